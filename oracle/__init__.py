@@ -1,0 +1,156 @@
+"""ORACLE — test infrastructure only.
+
+A plain single-thread CPU implementation of the edge-centric graphlet
+estimator (``lge_oracle.c``) plus a brute-force enumerator of all 3- and
+4-vertex subsets (``bruteforce.py``).  Only the tests, the smoke check and
+the benchmark's CPU-baseline leg may import this package; the product path
+never does, and this package imports nothing from the product.
+
+Pins (each checked by a ``-m "not gpu"`` test, see tests/test_oracle_*.py):
+  * exact counts == brute-force classification of every 3-/4-subset, the
+    classes identified by the Table 1 properties (edges, max degree,
+    components) stored in tests/golden/table1_graphlets.txt;
+  * closed forms on complete, complete bipartite, star, cycle and empty
+    graphs; trace identities tr(A^3)/6 and the closed-4-walk identity;
+  * exact unbiasedness of X and of the variance estimate by enumerating every
+    sample outcome on tiny graphs (Sec. 2.4);
+  * Philox4x32-10 known-answer vectors and a cross-check against an
+    independent Philox implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lge_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GRAPHLET_NAMES = [
+    None, "edge", "2-node-independent", "triangle", "2-star", "3-node-1-edge",
+    "3-node-independent", "4-clique", "chordal-cycle", "tailed-triangle", "4-cycle",
+    "3-star", "4-path", "4-node-1-triangle", "4-node-2-star", "4-node-2-edge",
+    "4-node-1-edge", "4-node-independent",
+]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("p", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("sampled", ctypes.c_uint64),
+        ("csum", _U128 * 18), ("zsum", _U128 * 18), ("qsum", _U128 * 18), ("exact", _U128 * 18),
+        ("estimate", ctypes.c_double * 18), ("variance", ctypes.c_double * 18),
+        ("lower95", ctypes.c_double * 18), ("upper95", ctypes.c_double * 18),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        lib.oracle_philox4x32_10.restype = None
+        lib.oracle_edge_sampled.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double]
+        lib.oracle_edge_sampled.restype = ctypes.c_int
+        lib.oracle_estimate.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_double, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_Result)]
+        lib.oracle_estimate.restype = ctypes.c_int
+        lib.oracle_edge_local.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_edge_local.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _u(x: _U128) -> int:
+    return (x.hi << 64) | x.lo
+
+
+def _s(x: _U128) -> int:
+    v = _u(x)
+    return v - (1 << 128) if v >> 127 else v
+
+
+def philox4x32_10(ctr, key):
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib.oracle_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def edge_sampled(seed: int, eid: int, p: float) -> bool:
+    return bool(_load().oracle_edge_sampled(seed, eid, p))
+
+
+def _csr(row_ptr, col):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    return rp, cl
+
+
+def estimate(row_ptr, col, p: float, seed: int = 0, mask=None) -> dict:
+    """Run the oracle.  Returns a dict with Python ints for every integer field
+    (``csum``, ``zsum`` signed, ``qsum``, ``exact``: lists indexed by graphlet
+    number 0..17, slot 0 unused) and float lists for the FP64 fields."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    n = rp.shape[0] - 1
+    res = _Result()
+    mptr = None
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mk.size == 0:
+            mk = np.zeros(1, dtype=np.uint8)
+        mptr = mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    rc = lib.oracle_estimate(n, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(p), int(seed),
+                             mptr, ctypes.byref(res))
+    if rc != 0:
+        raise RuntimeError("oracle_estimate failed: %d" % rc)
+    return {
+        "n": res.n, "m": res.m, "p": res.p, "seed": res.seed, "sampled": res.sampled,
+        "csum": [_u(res.csum[i]) for i in range(18)],
+        "zsum": [_s(res.zsum[i]) for i in range(18)],
+        "qsum": [_u(res.qsum[i]) for i in range(18)],
+        "exact": [_u(res.exact[i]) for i in range(18)],
+        "estimate": list(res.estimate), "variance": list(res.variance),
+        "lower95": list(res.lower95), "upper95": list(res.upper95),
+    }
+
+
+def edge_local(row_ptr, col, u: int, v: int) -> dict:
+    """Per-edge local quantities of Alg. 2-4 with u as the classified side."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    out = (ctypes.c_int64 * 7)()
+    rc = lib.oracle_edge_local(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(u), int(v), out)
+    if rc != 0:
+        raise RuntimeError("oracle_edge_local failed")
+    keys = ["t", "su", "sv", "r", "clique", "cycle", "f"]
+    return {k: int(out[i]) for i, k in enumerate(keys)}
