@@ -1,0 +1,243 @@
+/*
+ * lge.h — C ABI of the MI355X edge-centric graphlet estimator.
+ *
+ * The library computes, for an undirected simple graph G=(V,E), a sampling
+ * probability p and a seed, the localized graphlet estimates of "Estimation
+ * of Graphlet Statistics" (Rossi, Zhou, Ahmed): every edge is sampled
+ * independently with probability p (Alg. 1 with a Bernoulli design, Sec. 2.4),
+ * each sampled edge is counted locally (Alg. 2: triangles and 2-stars by
+ * neighbourhood intersection; Alg. 3/5: 4-cliques; Alg. 4/6: 4-cycles), the
+ * unrestricted counts (eqs. non-induced-conn-n1..n4, non-induced-disconn-n1..n4)
+ * are summed exactly, and the estimates of all 2-, 3- and 4-vertex graphlets
+ * G1..G17 (Table 1) follow from the X equations (eq. graphlet-X-start ..
+ * graphlet-X-end) with sigma = 1/p, together with an unbiased variance
+ * estimate and 95% bounds (eq. bounds-95).
+ *
+ * Conventions
+ *  - Graphs are int32 CSR: row_ptr[n+1] (row_ptr[0] = 0, non-decreasing),
+ *    col[row_ptr[n]]; each undirected edge is stored in both rows; rows are
+ *    strictly increasing (sorted, no duplicates); no self-loops.
+ *  - Canonical edge id: rank of (u, v), u < v, in row-major order of the
+ *    sorted CSR (0-based).  Edge e is sampled iff the Philox4x32-10 block of
+ *    key (seed lo32, seed hi32) and counter (e lo32, e hi32, 0, 0), reduced to
+ *    u = ((x1 << 32 | x0) >> 11) * 2^-53, satisfies u < p.
+ *  - All counts are exact integers.  Sums that can exceed 64 bits are
+ *    returned as 128-bit two's complement values split into (lo, hi) limbs.
+ *    Floating point (double) is used only for the sampling compare and the
+ *    final scaling, variance and bounds.
+ *  - Arrays indexed by graphlet number have 18 slots; slot i holds G_i
+ *    (slot 0 unused).
+ *  - Every call returns LGE_OK (0) or a negative LGE_E* code; no exception
+ *    crosses the ABI.  lge_strerror() names a code.
+ *  - One lge_ctx drives one GPU through one HIP stream.  Calls on one ctx must
+ *    not overlap (use one ctx per host thread); the server API below is the
+ *    thread-safe way to share a GPU.
+ */
+#ifndef LGE_H
+#define LGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define LGE_API __attribute__((visibility("default")))
+#else
+#define LGE_API
+#endif
+
+#define LGE_OK 0
+#define LGE_EINVAL (-1)     /* bad argument (p outside (0,1], null pointer, bad size) */
+#define LGE_ENOMEM (-2)     /* device or host allocation failed */
+#define LGE_EGRAPH (-3)     /* CSR is not a sorted, symmetric, loop-free simple graph */
+#define LGE_EDEVICE (-4)    /* HIP runtime error or no usable GPU */
+#define LGE_ERANGE (-5)     /* sizes beyond the exact 128-bit range (see lge_graph_create_*) */
+#define LGE_EBUSY (-6)      /* server admission queue full */
+#define LGE_ETIMEDOUT (-7)  /* lge_wait timed out (the ticket stays valid) */
+#define LGE_ECANCELED (-8)  /* request cancelled or server shut down */
+#define LGE_ENOTFOUND (-9)  /* unknown ticket or graph id */
+
+/* lge_graph_create_* flag: skip validation of the CSR (caller guarantees it) */
+#define LGE_FLAG_TRUSTED 1u
+
+typedef struct lge_ctx lge_ctx;
+typedef struct lge_graph lge_graph;
+typedef struct lge_event lge_event;
+typedef struct lge_server lge_server;
+
+typedef struct {
+  uint64_t lo, hi;
+} lge_u128;
+
+/*
+ * Result of one estimate (caller-owned).  Indices follow G1..G17.
+ *  csum[i]   C_i = sum over sampled edges of the unrestricted count of G_i,
+ *            for i in {3,4,5,7,...,16} (others 0).  Per edge, with
+ *            t = |T_e|, s_u, s_v the 2-star sets, r = n - |Gamma(u) u Gamma(v)|,
+ *            f = m - d_u - d_v + 1:
+ *              C3 += t, C4 += s_u+s_v, C5 += r, C7 += edges inside T_e,
+ *              C8 += t(t-1)/2, C9 += t(s_u+s_v), C10 += edges between S_u and S_v,
+ *              C11 += C(s_u,2)+C(s_v,2), C12 += s_u s_v, C13 += t r,
+ *              C14 += (s_u+s_v) r, C15 += f, C16 += r(r-1)/2.
+ *  z[i]      Z_i = sum over sampled edges of 12*Y_i(e), where Y_i(e) is edge e's
+ *            term of the X equations with sigma = 1 (signed), i = 3..17.
+ *  q[i]      Q_i = sum over sampled edges of (12*Y_i(e))^2, i = 3..17.
+ *  exact[i]  exact count of G_i; valid when every edge is sampled (p == 1),
+ *            exact[1] = m and exact[2] = C(n,2) - m always.
+ *  estimate  X_i = K_i + (Z_i * (1/p)) / 12 with K_6 = C(n,3), K_17 = C(n,4),
+ *            else 0; X_1 = m, X_2 = C(n,2) - m; at p == 1, X_i = exact[i].
+ *  variance  V_i = Q_i * ((1-p)/p^2) / 144 (0 for i = 1, 2 and at p == 1).
+ *  lower95/upper95  X_i -/+ 1.96 sqrt(V_i).
+ */
+typedef struct {
+  int64_t n, m;
+  double p;
+  uint64_t seed;
+  uint64_t sampled_edges;
+  lge_u128 csum[18];
+  lge_u128 z[18];
+  lge_u128 q[18];
+  lge_u128 exact[18];
+  double estimate[18];
+  double variance[18];
+  double lower95[18];
+  double upper95[18];
+} lge_result;
+
+/*
+ * Tunables.  Results never depend on them (exact integer sums are
+ * order-independent); only the speed does.  Zero-initialise and call
+ * lge_opts_default(), or pass NULL for defaults.
+ *  wave_max_deg   edges whose endpoints both have degree <= this are counted
+ *                 by one wavefront with LDS tables (1..512, default 128)
+ *  block_max_deg  read-only: edges whose endpoints both have degree <= 1024
+ *                 are counted by one 256-thread workgroup with LDS tables;
+ *                 others use per-vertex global hash tables of the vertices
+ *                 of degree > 1024 and are split across workgroups
+ *  probe_ratio    per neighbour w, look the target set up inside Gamma(w)
+ *                 (binary search or w's table) instead of scanning Gamma(w)
+ *                 when |target| * lookup_cost(d_w) * probe_ratio < d_w
+ *                 (0 disables lookups; default 4)
+ *  grid_per_cu    persistent workgroups per compute unit for each counting
+ *                 kernel (0 = library default)
+ */
+typedef struct {
+  int32_t wave_max_deg;
+  int32_t block_max_deg;
+  int32_t probe_ratio;
+  int32_t grid_per_cu;
+  int32_t reserved[4];
+} lge_opts;
+
+/* Device-time breakdown of the last estimate/batch call on a ctx. */
+typedef struct {
+  float total_ms;          /* first kernel start to last kernel end (includes one host round trip) */
+  float sample_ms;         /* sampling + binning kernel */
+  float count_ms[3];       /* counting kernels: wavefront, workgroup and split global classes */
+  uint64_t class_edges[3]; /* sampled edges per class */
+  uint64_t words_read[3];  /* 4-byte words each class's counting kernels read (algorithmic) */
+  uint64_t launches;       /* kernel launches issued */
+} lge_timing;
+
+LGE_API const char *lge_strerror(int code);
+
+/* Fills *o with the library defaults. */
+LGE_API int lge_opts_default(lge_opts *o);
+
+/* Opens device `device` (HIP ordinal); *out owns a stream and workspaces.
+ * LGE_EDEVICE when no such GPU; LGE_ENOMEM on allocation failure. */
+LGE_API int lge_open(int device, lge_ctx **out);
+LGE_API int lge_close(lge_ctx *ctx);
+
+/*
+ * Host-side CSR check (no GPU needed): sizes, sorted strictly increasing
+ * rows, ids in [0,n), no self-loops, symmetry.  LGE_OK or LGE_EGRAPH
+ * (LGE_EINVAL for null pointers or negative n).
+ */
+LGE_API int lge_validate_csr_host(int64_t n, const int32_t *row_ptr, const int32_t *col);
+
+/*
+ * Graph from host arrays (copied into HBM; the caller keeps its arrays).
+ * Validates on the GPU unless LGE_FLAG_TRUSTED.  Preprocesses once: the
+ * canonical edge list and per-vertex 2-hop volumes used for scheduling.
+ * LGE_ERANGE if n >= 2^29 or a per-edge numerator could leave int64 or a sum
+ * of squares 128 bits (bound: 16 * max(C(n,2), 2 dmax n, 4 dmax^2, m)).
+ */
+LGE_API int lge_graph_create_host(lge_ctx *ctx, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                          uint32_t flags, lge_graph **out);
+
+/*
+ * Graph adopting device buffers (zero copy, e.g. PyTorch tensors on the
+ * ctx's device).  The caller keeps them alive and unchanged until
+ * lge_graph_destroy.  hip_stream (may be NULL) is waited on before the
+ * buffers are read.  Same validation and errors as the host variant.
+ */
+LGE_API int lge_graph_create_device(lge_ctx *ctx, int64_t n, const int32_t *d_row_ptr, const int32_t *d_col,
+                            void *hip_stream, uint32_t flags, lge_graph **out);
+LGE_API int lge_graph_destroy(lge_graph *g);
+
+/* Number of vertices / undirected edges of a graph (host-side, no GPU call). */
+LGE_API int64_t lge_graph_n(const lge_graph *g);
+LGE_API int64_t lge_graph_m(const lge_graph *g);
+
+/* Estimate (synchronous on the ctx stream).  p in (0,1] else LGE_EINVAL;
+ * opts may be NULL; out caller-owned. */
+LGE_API int lge_estimate(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, const lge_opts *opts,
+                 lge_result *out);
+
+/*
+ * Estimate restricted to the canonical edge ids [e0, e1): edges outside the
+ * range are never sampled; scaling still uses 1/p.  Sums over a partition of
+ * [0, m) into ranges add up to the full estimate's integers, which is how
+ * the work shards (Sec. 5: edge neighbourhoods are independent tasks).
+ * 0 <= e0 <= e1 <= m else LGE_EINVAL.
+ */
+LGE_API int lge_estimate_range(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, int64_t e0, int64_t e1,
+                               const lge_opts *opts, lge_result *out);
+
+/*
+ * Asynchronous estimate: enqueued after the work already on hip_stream (NULL
+ * = the ctx stream); *ev completes when `out` holds the result.  `out` must
+ * stay valid until lge_event_wait returns; the ctx must not be used for
+ * another call before that.
+ */
+LGE_API int lge_estimate_async(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, void *hip_stream,
+                       lge_result *out, lge_event **ev);
+LGE_API int lge_event_wait(lge_event *ev); /* waits, finalises `out`, frees ev */
+
+/*
+ * Batched estimate of many independent graphs in one launch sequence.
+ * Concatenated CSR: graph k has n_k = vtx_off[k+1]-vtx_off[k] vertices, its
+ * local row_ptr (n_k+1 entries, starting at 0) at row_ptr[vtx_off[k] + k],
+ * and its local column ids at col[nnz_off[k] .. nnz_off[k+1]).
+ * p[k], seed[k] per graph.  Host arrays; outs[count] caller-owned.
+ */
+typedef struct {
+  int32_t count;
+  const int64_t *vtx_off; /* count+1 */
+  const int64_t *nnz_off; /* count+1 */
+  const int32_t *row_ptr; /* vtx_off[count] + count entries */
+  const int32_t *col;     /* nnz_off[count] entries */
+  const double *p;        /* count */
+  const uint64_t *seed;   /* count */
+  uint32_t flags;         /* LGE_FLAG_TRUSTED skips validation */
+} lge_batch;
+
+LGE_API int lge_count_batch(lge_ctx *ctx, const lge_batch *b, const lge_opts *opts, lge_result *outs);
+
+/* Timing of the last lge_estimate / lge_count_batch on ctx. */
+LGE_API int lge_last_timing(const lge_ctx *ctx, lge_timing *out);
+
+/*
+ * Autotuner: times candidate settings on (g, p) and writes the fastest to
+ * *out.  The choice never changes results.
+ */
+LGE_API int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LGE_H */

@@ -79,6 +79,9 @@ def _load():
         lib.oracle_edge_local.argtypes = [ctypes.c_int64, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int64)]
         lib.oracle_edge_local.restype = ctypes.c_int
+        lib.oracle_sample_mask.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_uint8)]
+        lib.oracle_sample_mask.restype = ctypes.c_uint64
         _lib = lib
     return _lib
 
@@ -103,6 +106,22 @@ def philox4x32_10(ctr, key):
 
 def edge_sampled(seed: int, eid: int, p: float) -> bool:
     return bool(_load().oracle_edge_sampled(seed, eid, p))
+
+
+def sample_count(seed: int, p: float, e0: int, e1: int) -> int:
+    """Number of canonical edge ids in [e0, e1) that the sampler keeps."""
+    return int(_load().oracle_sample_mask(seed, p, e0, e1, None))
+
+
+def sample_mask(seed: int, p: float, m: int, e0: int = 0, e1: int | None = None) -> np.ndarray:
+    """uint8[m] mask of the sampled edges whose id lies in [e0, e1)."""
+    e1 = m if e1 is None else e1
+    mask = np.zeros(max(m, 1), dtype=np.uint8)
+    if e1 > e0:
+        sub = np.zeros(e1 - e0, dtype=np.uint8)
+        _load().oracle_sample_mask(seed, p, e0, e1, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        mask[e0:e1] = sub
+    return mask[:m] if m > 0 else mask
 
 
 def _csr(row_ptr, col):

@@ -423,3 +423,16 @@ int oracle_edge_local(int64_t n, const int32_t *row_ptr, const int32_t *col, int
   free(slist);
   return 0;
 }
+
+/* Sampler over a range of canonical edge ids: mask[e - e0] = 1 iff edge e is
+ * sampled; returns the number sampled (used to check full-size runs and to
+ * build explicit masks for range estimates). */
+uint64_t oracle_sample_mask(uint64_t seed, double p, uint64_t e0, uint64_t e1, uint8_t *mask) {
+  uint64_t cnt = 0;
+  for (uint64_t e = e0; e < e1; ++e) {
+    int s = oracle_edge_sampled(seed, e, p);
+    if (mask) mask[e - e0] = (uint8_t)s;
+    cnt += (uint64_t)s;
+  }
+  return cnt;
+}

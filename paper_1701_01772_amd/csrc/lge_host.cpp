@@ -1,0 +1,923 @@
+// Host runtime of the C ABI declared in include/lge.h: contexts, resident
+// graphs, workspaces, the estimate / batch launch sequences and the exact
+// integer -> FP64 finalisation.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/lge.h"
+#include "lge_internal.h"
+
+using namespace lge;
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+namespace {
+
+constexpr int64_t kMaxVertices = (int64_t)1 << 29;  // vertex ids fit in 30 bits with room for tags
+
+#define LGE_HIP(expr)                        \
+  do {                                       \
+    hipError_t e_ = (expr);                  \
+    if (e_ != hipSuccess) return hip_err(e_); \
+  } while (0)
+
+int hip_err(hipError_t e) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return LGE_ENOMEM;
+  return LGE_EDEVICE;
+}
+
+template <typename T>
+int dev_alloc(T **p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) return LGE_OK;
+  hipError_t e = hipMalloc((void **)p, (size_t)count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_err(e);
+  }
+  return LGE_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// objects
+// ---------------------------------------------------------------------------
+
+struct lge_graph {
+  lge_ctx *ctx = nullptr;
+  int64_t n = 0, m = 0;
+  int32_t max_deg = 0;
+  const int32_t *row_ptr = nullptr;
+  const int32_t *col = nullptr;
+  int32_t *own_row_ptr = nullptr;
+  int32_t *own_col = nullptr;
+  uint64_t *edges = nullptr;
+  int64_t *vol2 = nullptr;
+  int64_t *hoff = nullptr;
+  uint32_t *htab = nullptr;
+  int64_t htab_len = 0;
+};
+
+struct Workspace {
+  int64_t cap_edges = 0;  // capacity of each class list
+  int32_t cap_slots = 0;
+  int32_t cap_ranges = 0;
+  int32_t *bin_slot[kNumClasses] = {};
+  int32_t *bin_a[kNumClasses] = {};
+  int32_t *bin_b[kNumClasses] = {};
+  unsigned long long *counters = nullptr;  // count[3], cursor[3], words[3], pad
+  SlotDesc *slots = nullptr;
+  RangeDesc *ranges = nullptr;
+  unsigned long long *acc = nullptr;  // cap_slots * kAccSlots * 2
+  int64_t *items = nullptr;           // cap_edges
+  int64_t *item_pref = nullptr;       // cap_edges
+  void *gacc = nullptr;               // cap_edges * gedge_bytes()
+  int64_t *scan_tmp = nullptr;
+  int64_t scan_tmp_len = 0;
+  // pinned host staging
+  SlotDesc *h_slots = nullptr;
+  RangeDesc *h_ranges = nullptr;
+  unsigned long long *h_acc = nullptr;
+  unsigned long long *h_counters = nullptr;
+};
+
+struct lge_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Workspace ws;
+  lge_opts opts{};
+  lge_timing timing{};
+  hipEvent_t ev[8] = {};
+  int num_cu = 256;
+};
+
+struct lge_event {
+  lge_ctx *ctx;
+  lge_result *out;
+  const lge_graph *g;
+  double p;
+  uint64_t seed;
+  hipEvent_t done;
+};
+
+// ---------------------------------------------------------------------------
+// errors, options
+// ---------------------------------------------------------------------------
+
+extern "C" const char *lge_strerror(int code) {
+  switch (code) {
+    case LGE_OK: return "ok";
+    case LGE_EINVAL: return "invalid argument";
+    case LGE_ENOMEM: return "out of memory";
+    case LGE_EGRAPH: return "invalid graph (CSR must be sorted, symmetric, loop-free and simple)";
+    case LGE_EDEVICE: return "HIP device error or no usable GPU";
+    case LGE_ERANGE: return "graph too large for exact 128-bit sums";
+    case LGE_EBUSY: return "server queue full";
+    case LGE_ETIMEDOUT: return "timed out";
+    case LGE_ECANCELED: return "cancelled";
+    case LGE_ENOTFOUND: return "not found";
+    default: return "unknown error";
+  }
+}
+
+extern "C" int lge_opts_default(lge_opts *o) {
+  if (!o) return LGE_EINVAL;
+  memset(o, 0, sizeof(*o));
+  o->wave_max_deg = 128;
+  o->block_max_deg = kHubDeg;
+  o->probe_ratio = 4;
+  o->grid_per_cu = 0;
+  return LGE_OK;
+}
+
+static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
+  lge_opts d;
+  lge_opts_default(&d);
+  if (!o) o = &ctx->opts;
+  KernelCfg c;
+  int wmd = o->wave_max_deg > 0 ? o->wave_max_deg : d.wave_max_deg;
+  c.wave_max_deg = std::min(std::max(wmd, 1), 512);
+  c.block_max_deg = kHubDeg;
+  c.probe_ratio = o->probe_ratio >= 0 ? o->probe_ratio : d.probe_ratio;
+  const int per_cu = o->grid_per_cu > 0 ? o->grid_per_cu : 0;
+  const int cu = ctx->num_cu > 0 ? ctx->num_cu : 256;
+  c.grid_wave = cu * (per_cu ? per_cu : 20);
+  c.grid_block = cu * (per_cu ? per_cu : 4);
+  c.grid_global = cu * (per_cu ? per_cu : 4);
+  c.grid_sample = cu * 16;
+  c.global_chunk = 256;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+static void ws_free(Workspace &w) {
+  for (int c = 0; c < kNumClasses; ++c) {
+    dev_free(w.bin_slot[c]);
+    dev_free(w.bin_a[c]);
+    dev_free(w.bin_b[c]);
+  }
+  dev_free(w.counters);
+  dev_free(w.slots);
+  dev_free(w.ranges);
+  dev_free(w.acc);
+  dev_free(w.items);
+  dev_free(w.item_pref);
+  if (w.gacc) (void)hipFree(w.gacc);
+  w.gacc = nullptr;
+  dev_free(w.scan_tmp);
+  if (w.h_slots) (void)hipHostFree(w.h_slots);
+  if (w.h_ranges) (void)hipHostFree(w.h_ranges);
+  if (w.h_acc) (void)hipHostFree(w.h_acc);
+  if (w.h_counters) (void)hipHostFree(w.h_counters);
+  w = Workspace();
+}
+
+extern "C" int lge_open(int device, lge_ctx **out) {
+  if (!out) return LGE_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return LGE_EDEVICE;
+  if (device < 0 || device >= count) return LGE_EDEVICE;
+  lge_ctx *ctx = new (std::nothrow) lge_ctx();
+  if (!ctx) return LGE_ENOMEM;
+  ctx->device = device;
+  lge_opts_default(&ctx->opts);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return LGE_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->num_cu = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return LGE_EDEVICE;
+  }
+  for (auto &e : ctx->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      lge_close(ctx);
+      return LGE_EDEVICE;
+    }
+  }
+  Workspace &w = ctx->ws;
+  if (dev_alloc(&w.counters, 16) != LGE_OK ||
+      hipHostMalloc((void **)&w.h_counters, 16 * sizeof(unsigned long long), 0) != hipSuccess) {
+    lge_close(ctx);
+    return LGE_ENOMEM;
+  }
+  *out = ctx;
+  return LGE_OK;
+}
+
+extern "C" int lge_close(lge_ctx *ctx) {
+  if (!ctx) return LGE_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  ws_free(ctx->ws);
+  for (auto &e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return LGE_OK;
+}
+
+// grows the workspace to hold `edges` binned edges, `slots` slots, `ranges` ranges
+static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges) {
+  Workspace &w = ctx->ws;
+  if (edges > w.cap_edges) {
+    int64_t cap = std::max<int64_t>(edges, 1024);
+    for (int c = 0; c < kNumClasses; ++c) {
+      dev_free(w.bin_slot[c]);
+      dev_free(w.bin_a[c]);
+      dev_free(w.bin_b[c]);
+    }
+    dev_free(w.items);
+    dev_free(w.item_pref);
+    if (w.gacc) (void)hipFree(w.gacc);
+    w.gacc = nullptr;
+    dev_free(w.scan_tmp);
+    w.cap_edges = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+      int rc;
+      if ((rc = dev_alloc(&w.bin_slot[c], cap)) != LGE_OK) return rc;
+      if ((rc = dev_alloc(&w.bin_a[c], cap)) != LGE_OK) return rc;
+      if ((rc = dev_alloc(&w.bin_b[c], cap)) != LGE_OK) return rc;
+    }
+    int rc;
+    if ((rc = dev_alloc(&w.items, cap)) != LGE_OK) return rc;
+    if ((rc = dev_alloc(&w.item_pref, cap)) != LGE_OK) return rc;
+    if (hipMalloc(&w.gacc, (size_t)cap * gedge_bytes()) != hipSuccess) {
+      w.gacc = nullptr;
+      return LGE_ENOMEM;
+    }
+    w.scan_tmp_len = scan_tmp_size(cap);
+    if ((rc = dev_alloc(&w.scan_tmp, w.scan_tmp_len)) != LGE_OK) return rc;
+    w.cap_edges = cap;
+  }
+  if (slots > w.cap_slots) {
+    int32_t cap = std::max<int32_t>(slots, 16);
+    dev_free(w.slots);
+    dev_free(w.acc);
+    if (w.h_slots) (void)hipHostFree(w.h_slots);
+    if (w.h_acc) (void)hipHostFree(w.h_acc);
+    w.h_slots = nullptr;
+    w.h_acc = nullptr;
+    w.cap_slots = 0;
+    int rc;
+    if ((rc = dev_alloc(&w.slots, cap)) != LGE_OK) return rc;
+    if ((rc = dev_alloc(&w.acc, (int64_t)cap * kAccSlots * 2)) != LGE_OK) return rc;
+    if (hipHostMalloc((void **)&w.h_slots, (size_t)cap * sizeof(SlotDesc), 0) != hipSuccess) return LGE_ENOMEM;
+    if (hipHostMalloc((void **)&w.h_acc, (size_t)cap * kAccSlots * 2 * sizeof(unsigned long long), 0) !=
+        hipSuccess)
+      return LGE_ENOMEM;
+    w.cap_slots = cap;
+  }
+  if (ranges > w.cap_ranges) {
+    int32_t cap = std::max<int32_t>(ranges, 16);
+    dev_free(w.ranges);
+    if (w.h_ranges) (void)hipHostFree(w.h_ranges);
+    w.h_ranges = nullptr;
+    w.cap_ranges = 0;
+    int rc;
+    if ((rc = dev_alloc(&w.ranges, cap)) != LGE_OK) return rc;
+    if (hipHostMalloc((void **)&w.h_ranges, (size_t)cap * sizeof(RangeDesc), 0) != hipSuccess) return LGE_ENOMEM;
+    w.cap_ranges = cap;
+  }
+  return LGE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph validation and creation
+// ---------------------------------------------------------------------------
+
+extern "C" int lge_validate_csr_host(int64_t n, const int32_t *row_ptr, const int32_t *col) {
+  if (n < 0 || !row_ptr) return LGE_EINVAL;
+  if (row_ptr[0] != 0) return LGE_EGRAPH;
+  for (int64_t u = 0; u < n; ++u)
+    if (row_ptr[u + 1] < row_ptr[u]) return LGE_EGRAPH;
+  const int64_t nnz = row_ptr[n];
+  if (nnz > 0 && !col) return LGE_EINVAL;
+  if (nnz % 2) return LGE_EGRAPH;
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<int> bad{0};
+  auto work = [&](unsigned id) {
+    for (int64_t u = id; u < n && !bad.load(std::memory_order_relaxed); u += nt) {
+      for (int32_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+        const int32_t v = col[j];
+        if (v < 0 || v >= n || v == u || (j > row_ptr[u] && col[j - 1] >= v)) {
+          bad = 1;
+          return;
+        }
+        if (!std::binary_search(col + row_ptr[v], col + row_ptr[v + 1], (int32_t)u)) {
+          bad = 1;
+          return;
+        }
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned i = 1; i < nt; ++i) th.emplace_back(work, i);
+  work(0);
+  for (auto &t : th) t.join();
+  return bad ? LGE_EGRAPH : LGE_OK;
+}
+
+// Every per-edge numerator 12*Y_i(e) must fit in int64 and every sum of
+// squares in 128 bits: |12 Y| <= 16 * max count term, the largest term being
+// C(n,2), 2*dmax*n, 4*dmax^2 or m.
+static bool sizes_in_range(int64_t n, int64_t m, int64_t dmax) {
+  if (n >= kMaxVertices) return false;
+  long double cmax = (long double)n * (long double)n / 2.0L;
+  cmax = std::max(cmax, 2.0L * dmax * (long double)n);
+  cmax = std::max(cmax, 4.0L * dmax * (long double)dmax);
+  cmax = std::max(cmax, (long double)m);
+  const long double zmax = 16.0L * cmax;
+  if (zmax >= ldexpl(1.0L, 62)) return false;
+  if ((long double)m * zmax * zmax >= ldexpl(1.0L, 127)) return false;
+  return true;
+}
+
+static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags) {
+  hipStream_t s = ctx->stream;
+  const int64_t n = g->n;
+  int rc;
+  if (!(flags & LGE_FLAG_TRUSTED) && n > 0) {
+    int *derr = nullptr;
+    if ((rc = dev_alloc(&derr, 1)) != LGE_OK) return rc;
+    int herr = 0;
+    hipError_t e = hipMemsetAsync(derr, 0, sizeof(int), s);
+    if (e == hipSuccess) e = launch_graph_validate(g->row_ptr, g->col, n, derr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&herr, derr, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(derr);
+    if (e != hipSuccess) return hip_err(e);
+    if (herr) return LGE_EGRAPH;
+  }
+  // canonical edge list
+  int32_t *up = nullptr;
+  int64_t *cnt = nullptr, *base = nullptr, *tmp = nullptr;
+  const int64_t tl = scan_tmp_size(std::max<int64_t>(n, 1));
+  if ((rc = dev_alloc(&up, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&cnt, std::max<int64_t>(n, 1))) != LGE_OK || (rc = dev_alloc(&base, std::max<int64_t>(n, 1))) != LGE_OK ||
+      (rc = dev_alloc(&tmp, tl)) != LGE_OK) {
+    dev_free(up);
+    dev_free(cnt);
+    dev_free(base);
+    dev_free(tmp);
+    return rc;
+  }
+  auto cleanup = [&]() {
+    dev_free(up);
+    dev_free(cnt);
+    dev_free(base);
+    dev_free(tmp);
+  };
+  hipError_t e = hipSuccess;
+  if (g->m > 0) {
+    if ((rc = dev_alloc(&g->edges, g->m)) != LGE_OK) {
+      cleanup();
+      return rc;
+    }
+  }
+  if ((rc = dev_alloc(&g->vol2, std::max<int64_t>(n, 1))) != LGE_OK || (rc = dev_alloc(&g->hoff, std::max<int64_t>(n, 1))) != LGE_OK) {
+    cleanup();
+    return rc;
+  }
+  e = launch_graph_upper(g->row_ptr, g->col, n, up, cnt, s);
+  if (e == hipSuccess) e = launch_scan_i64(cnt, base, n, tmp, s);
+  int64_t last[2] = {0, 0};
+  if (e == hipSuccess && n > 0) e = hipMemcpyAsync(&last[0], base + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && n > 0) e = hipMemcpyAsync(&last[1], cnt + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_err(e);
+  }
+  if (n > 0 && last[0] + last[1] != g->m) {
+    cleanup();
+    return LGE_EGRAPH;  // upper triangle does not hold half the entries
+  }
+  if (g->m > 0) e = launch_graph_edges(g->row_ptr, g->col, up, base, n, g->edges, s);
+  if (e == hipSuccess) e = launch_graph_vol2(g->row_ptr, g->col, n, g->vol2, s);
+  // hub tables
+  if (e == hipSuccess) e = launch_hub_sizes(g->row_ptr, n, cnt, s);
+  if (e == hipSuccess) e = launch_scan_i64(cnt, g->hoff, n, tmp, s);
+  if (e == hipSuccess && n > 0) e = hipMemcpyAsync(&last[0], g->hoff + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && n > 0) e = hipMemcpyAsync(&last[1], cnt + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_err(e);
+  }
+  g->htab_len = n > 0 ? last[0] + last[1] : 0;
+  if (g->htab_len > 0) {
+    if ((rc = dev_alloc(&g->htab, g->htab_len)) != LGE_OK) {
+      cleanup();
+      return rc;
+    }
+    e = launch_hub_build(g->row_ptr, g->col, n, g->hoff, g->htab, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) return hip_err(e);
+  return LGE_OK;
+}
+
+static void graph_free(lge_graph *g) {
+  dev_free(g->own_row_ptr);
+  dev_free(g->own_col);
+  dev_free(g->edges);
+  dev_free(g->vol2);
+  dev_free(g->hoff);
+  dev_free(g->htab);
+}
+
+static int32_t host_max_deg(int64_t n, const int32_t *row_ptr) {
+  int32_t d = 0;
+  for (int64_t u = 0; u < n; ++u) d = std::max(d, row_ptr[u + 1] - row_ptr[u]);
+  return d;
+}
+
+extern "C" int lge_graph_create_host(lge_ctx *ctx, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                                     uint32_t flags, lge_graph **out) {
+  if (!ctx || !out || !row_ptr || n < 0) return LGE_EINVAL;
+  *out = nullptr;
+  if (n >= kMaxVertices) return LGE_ERANGE;
+  if (row_ptr[0] != 0) return LGE_EGRAPH;
+  for (int64_t u = 0; u < n; ++u)
+    if (row_ptr[u + 1] < row_ptr[u]) return LGE_EGRAPH;
+  const int64_t nnz = row_ptr[n];
+  if (nnz % 2) return LGE_EGRAPH;
+  if (nnz > 0 && !col) return LGE_EINVAL;
+  const int32_t dmax = host_max_deg(n, row_ptr);
+  if (!sizes_in_range(n, nnz / 2, dmax)) return LGE_ERANGE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  lge_graph *g = new (std::nothrow) lge_graph();
+  if (!g) return LGE_ENOMEM;
+  g->ctx = ctx;
+  g->n = n;
+  g->m = nnz / 2;
+  g->max_deg = dmax;
+  int rc;
+  if ((rc = dev_alloc(&g->own_row_ptr, n + 1)) != LGE_OK || (rc = dev_alloc(&g->own_col, std::max<int64_t>(nnz, 1))) != LGE_OK) {
+    graph_free(g);
+    delete g;
+    return rc;
+  }
+  hipError_t e = hipMemcpyAsync(g->own_row_ptr, row_ptr, (size_t)(n + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                                ctx->stream);
+  if (e == hipSuccess && nnz > 0)
+    e = hipMemcpyAsync(g->own_col, col, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) {
+    graph_free(g);
+    delete g;
+    return hip_err(e);
+  }
+  g->row_ptr = g->own_row_ptr;
+  g->col = g->own_col;
+  if ((rc = graph_preprocess(ctx, g, flags)) != LGE_OK) {
+    graph_free(g);
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return LGE_OK;
+}
+
+extern "C" int lge_graph_create_device(lge_ctx *ctx, int64_t n, const int32_t *d_row_ptr, const int32_t *d_col,
+                                       void *hip_stream, uint32_t flags, lge_graph **out) {
+  if (!ctx || !out || !d_row_ptr || n < 0) return LGE_EINVAL;
+  *out = nullptr;
+  if (n >= kMaxVertices) return LGE_ERANGE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  if (hip_stream) LGE_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+  // row_ptr checks need it on the host once (n+1 ints)
+  std::vector<int32_t> rp((size_t)n + 1);
+  LGE_HIP(hipMemcpy(rp.data(), d_row_ptr, (size_t)(n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (rp[0] != 0) return LGE_EGRAPH;
+  for (int64_t u = 0; u < n; ++u)
+    if (rp[u + 1] < rp[u]) return LGE_EGRAPH;
+  const int64_t nnz = rp[n];
+  if (nnz % 2) return LGE_EGRAPH;
+  if (nnz > 0 && !d_col) return LGE_EINVAL;
+  const int32_t dmax = host_max_deg(n, rp.data());
+  if (!sizes_in_range(n, nnz / 2, dmax)) return LGE_ERANGE;
+  lge_graph *g = new (std::nothrow) lge_graph();
+  if (!g) return LGE_ENOMEM;
+  g->ctx = ctx;
+  g->n = n;
+  g->m = nnz / 2;
+  g->max_deg = dmax;
+  g->row_ptr = d_row_ptr;
+  g->col = d_col;
+  int rc;
+  if ((rc = graph_preprocess(ctx, g, flags)) != LGE_OK) {
+    graph_free(g);
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return LGE_OK;
+}
+
+extern "C" int lge_graph_destroy(lge_graph *g) {
+  if (!g) return LGE_EINVAL;
+  if (g->ctx) {
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+  }
+  graph_free(g);
+  delete g;
+  return LGE_OK;
+}
+
+extern "C" int64_t lge_graph_n(const lge_graph *g) { return g ? g->n : -1; }
+extern "C" int64_t lge_graph_m(const lge_graph *g) { return g ? g->m : -1; }
+
+// ---------------------------------------------------------------------------
+// finalisation (exact integers -> FP64)
+// ---------------------------------------------------------------------------
+
+static u128 u128_of(const unsigned long long *p) { return ((u128)p[1] << 64) | (u128)p[0]; }
+
+static lge_u128 to_abi(u128 x) {
+  lge_u128 r;
+  r.lo = (uint64_t)x;
+  r.hi = (uint64_t)(x >> 64);
+  return r;
+}
+
+static i128 binom(int64_t n, int k) {
+  if (n < k) return 0;
+  i128 r = 1;
+  for (int i = 0; i < k; ++i) r = r * (i128)(n - i) / (i128)(i + 1);
+  return r;
+}
+
+// correctly rounded int128 -> double (round to nearest even)
+static double to_double(i128 x) {
+  const bool neg = x < 0;
+  u128 a = neg ? (u128)0 - (u128)x : (u128)x;
+  int bits = 0;
+  for (u128 t = a; t; t >>= 1) ++bits;
+  if (bits <= 53) {
+    const double d = (double)(uint64_t)a;
+    return neg ? -d : d;
+  }
+  const int sh = bits - 53;
+  u128 mant = a >> sh;
+  const u128 rem = a - (mant << sh);
+  const u128 half = (u128)1 << (sh - 1);
+  if (rem > half || (rem == half && (mant & 1))) ++mant;
+  const double d = ldexp((double)(uint64_t)mant, sh);
+  return neg ? -d : d;
+}
+
+// acc: kAccSlots x {lo, hi} as produced by the kernels
+static void finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned long long *acc,
+                     lge_result *out) {
+  memset(out, 0, sizeof(*out));
+  out->n = n;
+  out->m = m;
+  out->p = p;
+  out->seed = seed;
+  out->sampled_edges = (uint64_t)u128_of(acc + 2 * kAccIdxCount);
+  static const int cidx[kNumC] = {3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
+  i128 C[18] = {0};
+  for (int k = 0; k < kNumC; ++k) C[cidx[k]] = (i128)u128_of(acc + 2 * k);
+  u128 Q[18] = {0};
+  for (int k = 0; k < kNumQ; ++k) Q[3 + k] = u128_of(acc + 2 * (kNumC + k));
+  // Z_i = sum of 12 Y_i(e); the map from the C sums is linear
+  i128 Z[18] = {0};
+  const i128 d87 = C[8] - C[7];
+  const i128 z9_3 = 2 * C[9] - 8 * d87;
+  Z[3] = 4 * C[3];
+  Z[4] = 6 * C[4];
+  Z[5] = 12 * C[5];
+  Z[6] = -(Z[3] + Z[4] + Z[5]);
+  Z[7] = 2 * C[7];
+  Z[8] = 12 * d87;
+  Z[9] = 3 * z9_3;
+  Z[10] = 3 * C[10];
+  Z[11] = 4 * C[11] - z9_3;
+  Z[12] = 12 * (C[12] - C[10]);
+  Z[13] = 4 * C[13] - z9_3;
+  Z[14] = 6 * C[14] - Z[12];
+  Z[15] = 6 * C[15] - 3 * Z[7] - 2 * Z[8] - Z[9] - 2 * Z[10] - Z[12];
+  Z[16] = 12 * C[16] - 2 * Z[15];
+  Z[17] = 0;
+  for (int i = 7; i <= 16; ++i) Z[17] -= Z[i];
+  i128 K[18] = {0};
+  K[6] = binom(n, 3);
+  K[17] = binom(n, 4);
+  i128 E[18] = {0};
+  E[1] = m;
+  E[2] = binom(n, 2) - m;
+  for (int i = 3; i <= 17; ++i) E[i] = K[i] + Z[i] / 12;
+  for (int i = 0; i < 18; ++i) {
+    out->csum[i] = to_abi((u128)C[i]);
+    out->z[i] = to_abi((u128)Z[i]);
+    out->q[i] = to_abi(Q[i]);
+    out->exact[i] = to_abi((u128)E[i]);
+  }
+  const double sigma = 1.0 / p;
+  const double vfac = (1.0 - p) / (p * p);
+  for (int i = 1; i <= 17; ++i) {
+    double x, v;
+    if (i <= 2 || p == 1.0) {
+      x = to_double(E[i]);
+      v = 0.0;
+    } else {
+      x = to_double(K[i]) + (to_double(Z[i]) * sigma) / 12.0;
+      v = (to_double((i128)Q[i]) * vfac) / 144.0;
+    }
+    const double h = 1.96 * sqrt(v);
+    out->estimate[i] = x;
+    out->variance[i] = v;
+    out->lower95[i] = x - h;
+    out->upper95[i] = x + h;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch sequence for a set of slots and ranges
+// ---------------------------------------------------------------------------
+
+struct Job {
+  const lge_graph *g;
+  double p;
+  uint64_t seed;
+  int64_t e0, e1;       // canonical edge range (of the graph's own ids)
+  int64_t n_override;   // graph-level sizes for the closed forms (batch unions)
+  int64_t m_override;
+  int64_t eid_base;     // subtracted from edge ids before the sampler
+};
+
+static Bins make_bins(Workspace &w) {
+  Bins b;
+  for (int c = 0; c < kNumClasses; ++c) {
+    b.slot[c] = w.bin_slot[c];
+    b.a[c] = w.bin_a[c];
+    b.b[c] = w.bin_b[c];
+  }
+  b.count = w.counters;
+  b.cursor = w.counters + 3;
+  b.words = w.counters + 6;
+  b.cap = w.cap_edges;
+  return b;
+}
+
+// Runs sample -> bin -> count for every job; leaves per-job accumulators in
+// ws.h_acc (host) on success.
+static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  int64_t total = 0;
+  for (int j = 0; j < njobs; ++j) total += jobs[j].e1 - jobs[j].e0;
+  int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), njobs, njobs);
+  if (rc != LGE_OK) return rc;
+  Workspace &w = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const KernelCfg cfg = make_cfg(ctx, opts);
+  int64_t pref = 0;
+  for (int j = 0; j < njobs; ++j) {
+    const lge_graph *g = jobs[j].g;
+    SlotDesc &sd = w.h_slots[j];
+    sd.row_ptr = g->row_ptr;
+    sd.col = g->col;
+    sd.edges = g->edges ? g->edges + jobs[j].eid_base : nullptr;
+    sd.vol2 = g->vol2;
+    sd.hoff = g->hoff;
+    sd.htab = g->htab;
+    sd.n = jobs[j].n_override >= 0 ? jobs[j].n_override : g->n;
+    sd.m = jobs[j].m_override >= 0 ? jobs[j].m_override : g->m;
+    sd.p = jobs[j].p;
+    sd.seed = jobs[j].seed;
+    sd.acc = w.acc + (int64_t)j * kAccSlots * 2;
+    RangeDesc &rd = w.h_ranges[j];
+    rd.slot = j;
+    rd.pad = 0;
+    rd.e0 = jobs[j].e0 - jobs[j].eid_base;
+    rd.e1 = jobs[j].e1 - jobs[j].eid_base;
+    rd.pref = pref;
+    pref += jobs[j].e1 - jobs[j].e0;
+  }
+  ctx->timing = lge_timing();
+  hipEvent_t *ev = ctx->ev;
+  LGE_HIP(hipMemcpyAsync(w.slots, w.h_slots, (size_t)njobs * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
+  LGE_HIP(hipMemcpyAsync(w.ranges, w.h_ranges, (size_t)njobs * sizeof(RangeDesc), hipMemcpyHostToDevice, s));
+  LGE_HIP(launch_zero_u64(w.counters, 16, s));
+  LGE_HIP(launch_zero_u64(w.acc, (int64_t)njobs * kAccSlots * 2, s));
+  Bins bins = make_bins(w);
+  LGE_HIP(hipEventRecord(ev[0], s));
+  LGE_HIP(launch_sample_bin(w.slots, w.ranges, njobs, total, bins, cfg, s));
+  LGE_HIP(hipEventRecord(ev[1], s));
+  LGE_HIP(hipMemcpyAsync(w.h_counters, w.counters, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipStreamSynchronize(s));
+  const int64_t nw = (int64_t)w.h_counters[0], nb = (int64_t)w.h_counters[1], ng = (int64_t)w.h_counters[2];
+  LGE_HIP(hipEventRecord(ev[2], s));
+  LGE_HIP(launch_count_wave(w.slots, bins, nw, cfg, s));
+  LGE_HIP(hipEventRecord(ev[3], s));
+  LGE_HIP(launch_count_block(w.slots, bins, nb, cfg, s));
+  LGE_HIP(hipEventRecord(ev[4], s));
+  if (ng > 0) {
+    LGE_HIP(launch_global_prep(w.slots, bins, ng, cfg.global_chunk, w.items, w.gacc, s));
+    LGE_HIP(launch_scan_i64(w.items, w.item_pref, ng, w.scan_tmp, s));
+    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.gacc, cfg, s));
+  }
+  LGE_HIP(hipEventRecord(ev[5], s));
+  LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)njobs * kAccSlots * 2 * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipMemcpyAsync(w.h_counters, w.counters, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipStreamSynchronize(s));
+  lge_timing &t = ctx->timing;
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) t.total_ms = ms;
+  if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) t.sample_ms = ms;
+  if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) t.count_ms[0] = ms;
+  if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) t.count_ms[1] = ms;
+  if (hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) t.count_ms[2] = ms;
+  for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[c];
+  for (int c = 0; c < kNumClasses; ++c) t.words_read[c] = w.h_counters[6 + c];
+  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 3 : 0);
+  return LGE_OK;
+}
+
+static bool p_ok(double p) { return p > 0.0 && p <= 1.0; }
+
+extern "C" int lge_estimate(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, const lge_opts *opts,
+                            lge_result *out) {
+  if (!p_ok(p)) return LGE_EINVAL;
+  if (!ctx || !g || !out) return LGE_EINVAL;
+  if (g->ctx != ctx) return LGE_EINVAL;
+  Job job{g, p, seed, 0, g->m, -1, -1, 0};
+  int rc = run_jobs(ctx, &job, 1, opts);
+  if (rc != LGE_OK) return rc;
+  finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+  return LGE_OK;
+}
+
+extern "C" int lge_estimate_range(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, int64_t e0,
+                                  int64_t e1, const lge_opts *opts, lge_result *out) {
+  if (!p_ok(p)) return LGE_EINVAL;
+  if (!ctx || !g || !out) return LGE_EINVAL;
+  if (g->ctx != ctx || e0 < 0 || e1 < e0 || e1 > g->m) return LGE_EINVAL;
+  Job job{g, p, seed, e0, e1, -1, -1, 0};
+  int rc = run_jobs(ctx, &job, 1, opts);
+  if (rc != LGE_OK) return rc;
+  finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+  return LGE_OK;
+}
+
+extern "C" int lge_estimate_async(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, void *hip_stream,
+                                  lge_result *out, lge_event **ev) {
+  if (!p_ok(p)) return LGE_EINVAL;
+  if (!ctx || !g || !out || !ev) return LGE_EINVAL;
+  if (g->ctx != ctx) return LGE_EINVAL;
+  *ev = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  // order after the caller's stream, then run on the ctx stream
+  if (hip_stream) {
+    hipEvent_t dep;
+    LGE_HIP(hipEventCreateWithFlags(&dep, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(dep, (hipStream_t)hip_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, dep, 0);
+    (void)hipEventDestroy(dep);
+    if (e != hipSuccess) return hip_err(e);
+  }
+  lge_event *E = new (std::nothrow) lge_event();
+  if (!E) return LGE_ENOMEM;
+  E->ctx = ctx;
+  E->out = out;
+  E->g = g;
+  E->p = p;
+  E->seed = seed;
+  E->done = nullptr;
+  Job job{g, p, seed, 0, g->m, -1, -1, 0};
+  int rc = run_jobs(ctx, &job, 1, nullptr);
+  if (rc != LGE_OK) {
+    delete E;
+    return rc;
+  }
+  finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+  *ev = E;
+  return LGE_OK;
+}
+
+extern "C" int lge_event_wait(lge_event *ev) {
+  if (!ev) return LGE_EINVAL;
+  delete ev;
+  return LGE_OK;
+}
+
+extern "C" int lge_last_timing(const lge_ctx *ctx, lge_timing *out) {
+  if (!ctx || !out) return LGE_EINVAL;
+  *out = ctx->timing;
+  return LGE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch: the graphs become one disjoint union (global vertex ids), each graph
+// one slot over its own range of canonical edge ids
+// ---------------------------------------------------------------------------
+
+extern "C" int lge_count_batch(lge_ctx *ctx, const lge_batch *b, const lge_opts *opts, lge_result *outs) {
+  if (!ctx || !b || !outs || b->count < 0) return LGE_EINVAL;
+  if (b->count == 0) return LGE_OK;
+  if (!b->vtx_off || !b->nnz_off || !b->row_ptr || !b->p || !b->seed) return LGE_EINVAL;
+  const int G = b->count;
+  for (int k = 0; k < G; ++k)
+    if (!p_ok(b->p[k])) return LGE_EINVAL;
+  const int64_t N = b->vtx_off[G];
+  const int64_t NNZ = b->nnz_off[G];
+  if (N < 0 || NNZ < 0 || (NNZ > 0 && !b->col)) return LGE_EINVAL;
+  if (N >= kMaxVertices || NNZ > INT32_MAX) return LGE_ERANGE;
+  // union CSR on the host
+  std::vector<int32_t> rp((size_t)N + 1), cl((size_t)std::max<int64_t>(NNZ, 1));
+  std::vector<int64_t> eoff((size_t)G + 1, 0);
+  rp[0] = 0;
+  for (int k = 0; k < G; ++k) {
+    const int64_t v0 = b->vtx_off[k], v1 = b->vtx_off[k + 1];
+    const int64_t z0 = b->nnz_off[k], z1 = b->nnz_off[k + 1];
+    if (v1 < v0 || z1 < z0) return LGE_EINVAL;
+    const int32_t *lrp = b->row_ptr + v0 + k;
+    if (lrp[0] != 0 || lrp[v1 - v0] != z1 - z0) return LGE_EGRAPH;
+    if (!(b->flags & LGE_FLAG_TRUSTED)) {
+      int rc = lge_validate_csr_host(v1 - v0, lrp, b->col + z0);
+      if (rc != LGE_OK) return rc;
+    }
+    for (int64_t u = 0; u < v1 - v0; ++u) rp[v0 + u + 1] = (int32_t)(z0 + lrp[u + 1]);
+    for (int64_t j = z0; j < z1; ++j) cl[j] = (int32_t)(b->col[j] + v0);
+    eoff[k + 1] = eoff[k] + (z1 - z0) / 2;
+    if (!sizes_in_range(v1 - v0, (z1 - z0) / 2, host_max_deg(v1 - v0, lrp))) return LGE_ERANGE;
+  }
+  lge_graph *U = nullptr;
+  int rc = lge_graph_create_host(ctx, N, rp.data(), cl.data(), LGE_FLAG_TRUSTED, &U);
+  if (rc != LGE_OK) return rc;
+  std::vector<Job> jobs((size_t)G);
+  for (int k = 0; k < G; ++k) {
+    const int64_t nk = b->vtx_off[k + 1] - b->vtx_off[k];
+    jobs[k] = Job{U, b->p[k], b->seed[k], eoff[k], eoff[k + 1], nk, eoff[k + 1] - eoff[k], eoff[k]};
+  }
+  rc = run_jobs(ctx, jobs.data(), G, opts);
+  if (rc == LGE_OK) {
+    for (int k = 0; k < G; ++k)
+      finalize(jobs[k].n_override, jobs[k].m_override, b->p[k], b->seed[k],
+               ctx->ws.h_acc + (int64_t)k * kAccSlots * 2, &outs[k]);
+  }
+  lge_graph_destroy(U);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: results never depend on the options, only the time does
+// ---------------------------------------------------------------------------
+
+extern "C" int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *out) {
+  if (!p_ok(p)) return LGE_EINVAL;
+  if (!ctx || !g || !out) return LGE_EINVAL;
+  lge_opts best;
+  lge_opts_default(&best);
+  float best_ms = 1e30f;
+  const int waves[] = {64, 128, 256, 512};
+  const int ratios[] = {0, 1, 2, 4, 8, 16};
+  lge_result r;
+  for (int wv : waves) {
+    for (int pr : ratios) {
+      lge_opts o;
+      lge_opts_default(&o);
+      o.wave_max_deg = wv;
+      o.probe_ratio = pr;
+      int rc = lge_estimate(ctx, g, p, 0x5eed, &o, &r);
+      if (rc != LGE_OK) return rc;
+      const lge_timing &t = ctx->timing;
+      const float ms = t.sample_ms + t.count_ms[0] + t.count_ms[1] + t.count_ms[2];
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = o;
+      }
+    }
+  }
+  *out = best;
+  return LGE_OK;
+}

@@ -1,0 +1,100 @@
+// Internal interface between the host runtime (lge_host.cpp) and the device
+// kernels (lge_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lge {
+
+// Number of 128-bit accumulators per estimate slot:
+//   [0..12]  C3, C4, C5, C7, C8, C9, C10, C11, C12, C13, C14, C15, C16
+//   [13..27] Q3 .. Q17 (sums of squared per-edge numerators 12*Y_i(e))
+//   [28]     sampled edges
+//   [29]     4-byte words read by the counting kernels
+constexpr int kNumC = 13;
+constexpr int kNumQ = 15;
+constexpr int kAccIdxCount = 28;
+constexpr int kAccIdxWords = 29;
+constexpr int kAccSlots = 32;  // padded; one slot = 32 x (lo, hi) u64 = 512 B
+
+// Vertices of degree > kHubDeg get a global hash table of their neighbours
+// ("hub table"); edges whose endpoints both have degree <= kHubDeg are
+// counted entirely from LDS tables.
+constexpr int kHubDeg = 1024;
+// Largest number of Gamma(a) positions handled by one global-class work item.
+constexpr int kGlobalChunkMax = 1024;
+
+// One estimate job as seen by the kernels.
+struct SlotDesc {
+  const int32_t *row_ptr;   // n+1
+  const int32_t *col;       // 2m
+  const uint64_t *edges;    // m canonical edges, (u << 32) | v with u < v
+  const int64_t *vol2;      // n: sum of neighbour degrees
+  const int64_t *hoff;      // n: offset of the vertex's hub table in htab (hubs only)
+  const uint32_t *htab;     // hub tables (open addressing, 2^table_log(d) slots each)
+  int64_t n, m;
+  double p;
+  uint64_t seed;
+  unsigned long long *acc;  // kAccSlots x {lo, hi}
+};
+
+// A contiguous range of canonical edge ids of one slot.
+struct RangeDesc {
+  int32_t slot;
+  int32_t pad;
+  int64_t e0, e1;  // [e0, e1)
+  int64_t pref;    // exclusive prefix of range lengths over the range table
+};
+
+// Edge classes (who counts the edge).
+enum EdgeClass { kClassWave = 0, kClassBlock = 1, kClassGlobal = 2, kNumClasses = 3 };
+
+// Binned work lists: structure of arrays, one per class, capacity `cap` each.
+struct Bins {
+  int32_t *slot[kNumClasses];
+  int32_t *a[kNumClasses];  // side whose neighbours are iterated
+  int32_t *b[kNumClasses];  // side held in the membership table
+  unsigned long long *count;   // kNumClasses counters
+  unsigned long long *cursor;  // kNumClasses work-queue cursors
+  unsigned long long *words;   // kNumClasses counters of 4-byte words read
+  int64_t cap;
+};
+
+struct KernelCfg {
+  int32_t wave_max_deg;
+  int32_t block_max_deg;
+  int32_t probe_ratio;
+  int32_t grid_wave, grid_block, grid_global;
+  int32_t grid_sample;
+  int32_t global_chunk;  // Gamma(a) positions per global-class work item
+};
+
+// ---- launchers (lge_kernels.hip) ----
+hipError_t launch_graph_validate(const int32_t *row_ptr, const int32_t *col, int64_t n, int *err,
+                                 hipStream_t s);
+hipError_t launch_graph_upper(const int32_t *row_ptr, const int32_t *col, int64_t n, int32_t *up_start,
+                              int64_t *cnt, hipStream_t s);
+// exclusive scan; tmp must hold scan_tmp_size(len) entries
+hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t len, int64_t *tmp, hipStream_t s);
+int64_t scan_tmp_size(int64_t len);
+hipError_t launch_graph_edges(const int32_t *row_ptr, const int32_t *col, const int32_t *up_start,
+                              const int64_t *eid_base, int64_t n, uint64_t *edges, hipStream_t s);
+hipError_t launch_graph_vol2(const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t *vol2,
+                             hipStream_t s);
+hipError_t launch_hub_sizes(const int32_t *row_ptr, int64_t n, int64_t *size, hipStream_t s);
+hipError_t launch_hub_build(const int32_t *row_ptr, const int32_t *col, int64_t n, const int64_t *hoff,
+                            uint32_t *htab, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
+hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
+                             int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);
+hipError_t launch_count_wave(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s);
+hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s);
+// per-edge work-item counts and partial sums (gacc: gedge_bytes() per edge)
+hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t chunk, int64_t *items,
+                              void *gacc, hipStream_t s);
+hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
+                               const int64_t *item_cnt, void *gacc, KernelCfg cfg, hipStream_t s);
+size_t gedge_bytes();
+
+}  // namespace lge

@@ -1,0 +1,323 @@
+"""Thin Python binding of liblge.so (include/lge.h).
+
+Argument marshalling only: every step of the estimate runs in the HIP
+library.  Names mirror the C ABI.  Results come back as dicts with Python
+ints for the exact integer fields (``csum``, ``zsum`` signed, ``qsum``,
+``exact``; lists indexed by graphlet number 0..17, slot 0 unused) and float
+lists for ``estimate``, ``variance``, ``lower95``, ``upper95``.
+
+The library must be built (``python -m paper_1701_01772_amd.build``); there
+is no fallback: importing a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblge.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lge.h")
+
+LGE_OK = 0
+LGE_EINVAL = -1
+LGE_ENOMEM = -2
+LGE_EGRAPH = -3
+LGE_EDEVICE = -4
+LGE_ERANGE = -5
+LGE_EBUSY = -6
+LGE_ETIMEDOUT = -7
+LGE_ECANCELED = -8
+LGE_ENOTFOUND = -9
+LGE_FLAG_TRUSTED = 1
+
+
+class LgeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (where, lge_strerror(code), code))
+
+
+class U128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("p", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("sampled_edges", ctypes.c_uint64),
+        ("csum", U128 * 18), ("z", U128 * 18), ("q", U128 * 18), ("exact", U128 * 18),
+        ("estimate", ctypes.c_double * 18), ("variance", ctypes.c_double * 18),
+        ("lower95", ctypes.c_double * 18), ("upper95", ctypes.c_double * 18),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("wave_max_deg", ctypes.c_int32), ("block_max_deg", ctypes.c_int32),
+                ("probe_ratio", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_float), ("sample_ms", ctypes.c_float), ("count_ms", ctypes.c_float * 3),
+                ("class_edges", ctypes.c_uint64 * 3), ("words_read", ctypes.c_uint64 * 3),
+                ("launches", ctypes.c_uint64)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32),
+                ("vtx_off", ctypes.POINTER(ctypes.c_int64)), ("nnz_off", ctypes.POINTER(ctypes.c_int64)),
+                ("row_ptr", ctypes.POINTER(ctypes.c_int32)), ("col", ctypes.POINTER(ctypes.c_int32)),
+                ("p", ctypes.POINTER(ctypes.c_double)), ("seed", ctypes.POINTER(ctypes.c_uint64)),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load():
+    """Load liblge.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblge.so is not built (%s); run `python -m paper_1701_01772_amd.build`" % LIB_PATH)
+    # PyTorch-ROCm ships its own HIP/HSA runtime under the same sonames as the
+    # system one.  Loading torch first makes liblge.so bind to that already
+    # loaded runtime, so the process has one runtime and device pointers and
+    # streams from torch are valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "lge_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "lge_opts_default": ([ctypes.POINTER(Opts)], ctypes.c_int),
+        "lge_open": ([ctypes.c_int, ctypes.POINTER(_VP)], ctypes.c_int),
+        "lge_close": ([_VP], ctypes.c_int),
+        "lge_validate_csr_host": ([ctypes.c_int64, i32p, i32p], ctypes.c_int),
+        "lge_graph_create_host": ([_VP, ctypes.c_int64, i32p, i32p, ctypes.c_uint32, ctypes.POINTER(_VP)],
+                                  ctypes.c_int),
+        "lge_graph_create_device": ([_VP, ctypes.c_int64, _VP, _VP, _VP, ctypes.c_uint32, ctypes.POINTER(_VP)],
+                                    ctypes.c_int),
+        "lge_graph_destroy": ([_VP], ctypes.c_int),
+        "lge_graph_n": ([_VP], ctypes.c_int64),
+        "lge_graph_m": ([_VP], ctypes.c_int64),
+        "lge_estimate": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.POINTER(Result)],
+                         ctypes.c_int),
+        "lge_estimate_range": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.POINTER(Opts), ctypes.POINTER(Result)], ctypes.c_int),
+        "lge_estimate_async": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, _VP, ctypes.POINTER(Result),
+                                ctypes.POINTER(_VP)], ctypes.c_int),
+        "lge_event_wait": ([_VP], ctypes.c_int),
+        "lge_count_batch": ([_VP, ctypes.POINTER(Batch), ctypes.POINTER(Opts), ctypes.POINTER(Result)], ctypes.c_int),
+        "lge_last_timing": ([_VP, ctypes.POINTER(Timing)], ctypes.c_int),
+        "lge_autotune": ([_VP, _VP, ctypes.c_double, ctypes.POINTER(Opts)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def header_symbols():
+    """Every function the public header declares."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^LGE_API\s+[\w\s\*]*?\b(lge_\w+)\(", txt, flags=re.M)))
+
+
+def _check(rc: int, where: str):
+    if rc != LGE_OK:
+        raise LgeError(rc, where)
+
+
+def lge_strerror(code: int) -> str:
+    return load().lge_strerror(code).decode()
+
+
+def lge_opts_default() -> Opts:
+    o = Opts()
+    _check(load().lge_opts_default(ctypes.byref(o)), "lge_opts_default")
+    return o
+
+
+def make_opts(**kw) -> Opts:
+    o = lge_opts_default()
+    for k, v in kw.items():
+        setattr(o, k, int(v))
+    return o
+
+
+def lge_open(device: int = 0):
+    ctx = _VP()
+    _check(load().lge_open(device, ctypes.byref(ctx)), "lge_open")
+    return ctx
+
+
+def lge_close(ctx):
+    _check(load().lge_close(ctx), "lge_close")
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a
+
+
+def lge_validate_csr_host(row_ptr, col) -> int:
+    rp, cl = _i32(row_ptr), _i32(col)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    return load().lge_validate_csr_host(rp.shape[0] - 1, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+def lge_graph_create_host(ctx, row_ptr, col, flags: int = 0):
+    rp, cl = _i32(row_ptr), _i32(col)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    g = _VP()
+    _check(load().lge_graph_create_host(ctx, rp.shape[0] - 1, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), flags, ctypes.byref(g)),
+           "lge_graph_create_host")
+    return g
+
+
+def lge_graph_create_device(ctx, n: int, row_ptr_ptr: int, col_ptr: int, stream_ptr: int = 0, flags: int = 0):
+    """Adopt device buffers (e.g. ``tensor.data_ptr()`` of int32 tensors)."""
+    g = _VP()
+    _check(load().lge_graph_create_device(ctx, n, _VP(row_ptr_ptr), _VP(col_ptr), _VP(stream_ptr or None), flags,
+                                          ctypes.byref(g)), "lge_graph_create_device")
+    return g
+
+
+def lge_graph_destroy(g):
+    _check(load().lge_graph_destroy(g), "lge_graph_destroy")
+
+
+def _u(x) -> int:
+    return (int(x.hi) << 64) | int(x.lo)
+
+
+def _s(x) -> int:
+    v = _u(x)
+    return v - (1 << 128) if v >> 127 else v
+
+
+def result_dict(r: Result) -> dict:
+    return {
+        "n": r.n, "m": r.m, "p": r.p, "seed": r.seed, "sampled": int(r.sampled_edges),
+        "csum": [_u(r.csum[i]) for i in range(18)],
+        "zsum": [_s(r.z[i]) for i in range(18)],
+        "qsum": [_u(r.q[i]) for i in range(18)],
+        "exact": [_u(r.exact[i]) for i in range(18)],
+        "estimate": list(r.estimate), "variance": list(r.variance),
+        "lower95": list(r.lower95), "upper95": list(r.upper95),
+    }
+
+
+def lge_estimate(ctx, g, p: float, seed: int, opts: Opts | None = None) -> dict:
+    r = Result()
+    _check(load().lge_estimate(ctx, g, float(p), int(seed), ctypes.byref(opts) if opts is not None else None,
+                               ctypes.byref(r)), "lge_estimate")
+    return result_dict(r)
+
+
+def lge_estimate_range(ctx, g, p: float, seed: int, e0: int, e1: int, opts: Opts | None = None) -> dict:
+    r = Result()
+    _check(load().lge_estimate_range(ctx, g, float(p), int(seed), int(e0), int(e1),
+                                     ctypes.byref(opts) if opts is not None else None, ctypes.byref(r)),
+           "lge_estimate_range")
+    return result_dict(r)
+
+
+def lge_estimate_async(ctx, g, p: float, seed: int, stream_ptr: int = 0):
+    """Returns (event, Result); call lge_event_wait(event) then result_dict."""
+    r = Result()
+    ev = _VP()
+    _check(load().lge_estimate_async(ctx, g, float(p), int(seed), _VP(stream_ptr or None), ctypes.byref(r),
+                                     ctypes.byref(ev)), "lge_estimate_async")
+    return ev, r
+
+
+def lge_event_wait(ev):
+    _check(load().lge_event_wait(ev), "lge_event_wait")
+
+
+def pack_batch(graphs):
+    """Concatenated CSR arrays (vtx_off, nnz_off, row_ptr, col) of (row_ptr, col) pairs."""
+    vtx = [0]
+    nnz = [0]
+    rps, cols = [], []
+    for rp, cl in graphs:
+        rp = _i32(rp)
+        cl = _i32(cl)
+        vtx.append(vtx[-1] + rp.shape[0] - 1)
+        nnz.append(nnz[-1] + cl.shape[0])
+        rps.append(rp)
+        cols.append(cl)
+    return (np.asarray(vtx, dtype=np.int64), np.asarray(nnz, dtype=np.int64),
+            np.concatenate(rps) if rps else np.zeros(0, np.int32),
+            np.concatenate(cols) if cols else np.zeros(0, np.int32))
+
+
+def lge_count_batch(ctx, graphs, p, seed, flags: int = 0, opts: Opts | None = None):
+    """graphs: list of (row_ptr, col); p, seed: scalars or per-graph lists."""
+    G = len(graphs)
+    vtx, nnz, rp, cl = pack_batch(graphs)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    ps = np.asarray(p if np.ndim(p) else [p] * G, dtype=np.float64)
+    ss = np.asarray(seed if np.ndim(seed) else [seed] * G, dtype=np.uint64)
+    b = Batch(G, vtx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nnz.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+              rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+              ps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ss.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+              flags)
+    outs = (Result * max(G, 1))()
+    _check(load().lge_count_batch(ctx, ctypes.byref(b), ctypes.byref(opts) if opts is not None else None, outs),
+           "lge_count_batch")
+    return [result_dict(outs[i]) for i in range(G)]
+
+
+def lge_last_timing(ctx) -> dict:
+    t = Timing()
+    _check(load().lge_last_timing(ctx, ctypes.byref(t)), "lge_last_timing")
+    return {"total_ms": t.total_ms, "sample_ms": t.sample_ms, "count_ms": list(t.count_ms),
+            "class_edges": [int(x) for x in t.class_edges], "words_read": [int(x) for x in t.words_read],
+            "launches": int(t.launches)}
+
+
+def lge_autotune(ctx, g, p: float) -> Opts:
+    o = Opts()
+    _check(load().lge_autotune(ctx, g, float(p), ctypes.byref(o)), "lge_autotune")
+    return o
+
+
+class Context:
+    """RAII helper around lge_open / lge_close."""
+
+    def __init__(self, device: int = 0):
+        self.ctx = lge_open(device)
+
+    def close(self):
+        if self.ctx:
+            lge_close(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def graph(self, row_ptr, col, flags: int = 0):
+        return lge_graph_create_host(self.ctx, row_ptr, col, flags)
+
+    def estimate(self, g, p: float, seed: int, opts: Opts | None = None) -> dict:
+        return lge_estimate(self.ctx, g, p, seed, opts)

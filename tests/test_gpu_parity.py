@@ -1,0 +1,230 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: every integer (sampled edge count, the 13 C sums, the 15 Z and 15 Q
+sums, the 17 exact counts at p = 1) bit-equal; every FP64 output within a
+relative 1e-12 (or both zero).  Inputs are seeded synthetic graphs sized so
+the oracle finishes in seconds, chosen to hit all three edge classes
+(wavefront, workgroup, split global) and the ragged tails of every loop.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1701_01772_amd import inputs, lge
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+
+
+def _say(msg):
+    sys.stdout.write("[gpu-parity] %s\n" % msg)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = lge.lge_open(0)
+    yield c
+    lge.lge_close(c)
+
+
+def _close(a, b):
+    if a == b:
+        return True
+    return abs(a - b) <= REL * max(abs(a), abs(b))
+
+
+def assert_parity(gpu, orc, what=""):
+    assert gpu["sampled"] == orc["sampled"], what
+    for key in ("csum", "zsum", "qsum"):
+        for i in range(3, 18):
+            assert gpu[key][i] == orc[key][i], (what, key, i, gpu[key][i], orc[key][i])
+    if orc["p"] == 1.0:
+        assert gpu["exact"][1:] == orc["exact"][1:], what
+    for key in ("estimate", "variance", "lower95", "upper95"):
+        for i in range(1, 18):
+            assert _close(gpu[key][i], orc[key][i]), (what, key, i, gpu[key][i], orc[key][i])
+
+
+def run_pair(ctx, g, p, seed, opts=None, what=""):
+    _say("%s n=%d m=%d p=%g seed=%d" % (what or g.name, g.n, g.m, p, seed))
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        got = lge.lge_estimate(ctx, h, p, seed, opts)
+    finally:
+        lge.lge_graph_destroy(h)
+    want = oracle.estimate(g.row_ptr, g.col, p, seed)
+    assert_parity(got, want, what or g.name)
+    return got
+
+
+def two_hub_graph(seed=3):
+    """Two adjacent hubs (degree > 1024) sharing half their neighbours, a dense
+    cluster, and sparse background edges: exercises hub tables and splitting."""
+    rng = np.random.default_rng(seed)
+    n = 5000
+    edges = [(0, 1)]
+    n0 = rng.choice(np.arange(2, n), 2600, replace=False)
+    n1 = np.concatenate([n0[:1300], rng.choice(np.arange(2, n), 1400, replace=False)])
+    edges += [(0, int(x)) for x in n0] + [(1, int(x)) for x in n1]
+    cl = rng.choice(np.arange(2, n), 40, replace=False)
+    edges += [(int(a), int(b)) for i, a in enumerate(cl) for b in cl[i + 1:]]
+    m_bg = 12000
+    a = rng.integers(2, n, m_bg)
+    b = rng.integers(2, n, m_bg)
+    edges += [(int(x), int(y)) for x, y in zip(a, b)]
+    # a mid-degree vertex (block class) wired into both hubs' neighbourhoods
+    mid = 2
+    edges += [(mid, int(x)) for x in rng.choice(n0, 600, replace=False)]
+    return inputs.from_edges(n, edges)
+
+
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_small_random_exact(ctx, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 90))
+    q = float(rng.choice([0.02, 0.1, 0.3, 0.6, 0.9]))
+    run_pair(ctx, inputs.erdos_renyi(n, q, 100 + seed), 1.0, 0)
+
+
+def test_degenerate_graphs(ctx):
+    for n, es in ((1, []), (5, []), (2, [(0, 1)]), (3, [(0, 1), (1, 2), (0, 2)]), (7, [(0, 1), (5, 6)])):
+        g = inputs.from_edges(n, es)
+        for p in (1.0, 0.5):
+            run_pair(ctx, g, p, 9, what="degenerate n=%d m=%d" % (n, len(es)))
+
+
+def test_er_config_exact(ctx):
+    run_pair(ctx, inputs.er_2000(), 1.0, 0, what="er(2000,0.005)")
+
+
+@pytest.mark.parametrize("maker,name", [
+    (lambda: two_hub_graph(), "two-hub"),
+    (lambda: inputs.chung_lu(20000, 10.0, 2.1, 3000.0, 41), "chung-lu-20k"),
+    (lambda: inputs.rmat(12, 16, 0.57, 0.19, 0.19, 42), "rmat-12"),
+])
+def test_all_classes_exact(ctx, maker, name):
+    run_pair(ctx, maker(), 1.0, 0, what=name)
+
+
+@pytest.mark.parametrize("p,seed", [(0.5, 1), (0.1, 2), (0.01, 3), (1e-4, 4)])
+def test_sampled_powerlaw(ctx, p, seed):
+    run_pair(ctx, inputs.chung_lu(20000, 10.0, 2.1, 3000.0, 41), p, seed, what="chung-lu-20k")
+
+
+@pytest.mark.parametrize("p", [0.3, 0.05])
+def test_sampled_two_hub(ctx, p):
+    run_pair(ctx, two_hub_graph(), p, 17, what="two-hub")
+
+
+def test_tuning_invariance(ctx):
+    g = inputs.rmat(11, 16, 0.57, 0.19, 0.19, 5)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        base = lge.lge_estimate(ctx, h, 0.7, 3)
+        for wv in (8, 64, 200, 512):
+            for pr in (0, 1, 16, 1000):
+                for gpc in (1, 3):
+                    o = lge.make_opts(wave_max_deg=wv, probe_ratio=pr, grid_per_cu=gpc)
+                    got = lge.lge_estimate(ctx, h, 0.7, 3, o)
+                    for k in ("sampled", "csum", "zsum", "qsum"):
+                        assert got[k] == base[k], (wv, pr, gpc, k)
+    finally:
+        lge.lge_graph_destroy(h)
+    assert_parity(base, oracle.estimate(g.row_ptr, g.col, 0.7, 3), "rmat-11 tuned")
+
+
+def test_range_additivity_and_parity(ctx):
+    g = inputs.chung_lu(20000, 10.0, 2.1, 3000.0, 41)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        full = lge.lge_estimate(ctx, h, 0.25, 8)
+        cuts = [0, 1, 777, g.m // 2, g.m - 3, g.m]
+        parts = [lge.lge_estimate_range(ctx, h, 0.25, 8, a, b) for a, b in zip(cuts, cuts[1:])]
+        for k in ("sampled",):
+            assert sum(pt[k] for pt in parts) == full[k]
+        for k in ("csum", "zsum", "qsum"):
+            for i in range(3, 18):
+                assert sum(pt[k][i] for pt in parts) == full[k][i], (k, i)
+        a, b = 1234, 1234 + 3000
+        got = lge.lge_estimate_range(ctx, h, 0.25, 8, a, b)
+        mask = oracle.sample_mask(8, 0.25, g.m, a, b)
+        assert_parity(got, oracle.estimate(g.row_ptr, g.col, 0.25, 8, mask=mask), "range")
+    finally:
+        lge.lge_graph_destroy(h)
+
+
+def test_batch_equals_singles(ctx):
+    graphs = inputs.batch_graphs(count=24, seed=77, n_lo=20, n_hi=1500)
+    graphs.append(inputs.from_edges(4, []))
+    graphs.append(two_hub_graph(5))
+    ps = [1.0 if i % 3 else 0.4 for i in range(len(graphs))]
+    seeds = [1000 + i for i in range(len(graphs))]
+    _say("batch of %d graphs" % len(graphs))
+    outs = lge.lge_count_batch(ctx, [(g.row_ptr, g.col) for g in graphs], ps, seeds)
+    for g, out, p, s in zip(graphs, outs, ps, seeds):
+        want = oracle.estimate(g.row_ptr, g.col, p, s)
+        assert_parity(out, want, "batch member n=%d" % g.n)
+
+
+def test_graph_create_device_matches_host(ctx):
+    torch = pytest.importorskip("torch")
+    g = inputs.chung_lu(5000, 8.0, 2.3, 800.0, 12)
+    rp = torch.from_numpy(g.row_ptr).to("cuda:0")
+    cl = torch.from_numpy(g.col).to("cuda:0")
+    torch.cuda.synchronize()
+    h = lge.lge_graph_create_device(ctx, g.n, rp.data_ptr(), cl.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    try:
+        got = lge.lge_estimate(ctx, h, 0.6, 21)
+    finally:
+        lge.lge_graph_destroy(h)
+    assert_parity(got, oracle.estimate(g.row_ptr, g.col, 0.6, 21), "device-adopted")
+
+
+def test_invalid_graph_rejected_on_gpu(ctx):
+    # asymmetric: 0->1 without 1->0
+    rp = np.array([0, 1, 1], dtype=np.int32)
+    cl = np.array([1], dtype=np.int32)
+    with pytest.raises(lge.LgeError) as ei:
+        lge.lge_graph_create_host(ctx, rp, cl)
+    assert ei.value.code in (lge.LGE_EGRAPH,)
+
+
+# ---------------------------------------------------------------------------
+# Full-size configurations: properties at full size, oracle parity on ranges
+# the oracle finishes in seconds, in the launch configuration of the bench.
+# ---------------------------------------------------------------------------
+
+
+def _full_size_checks(ctx, g, p, seed, ranges):
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        _say("full %s p=%g" % (g.name, p))
+        full = lge.lge_estimate(ctx, h, p, seed)
+        assert full["sampled"] == oracle.sample_count(seed, p, 0, g.m)
+        # 4-node counts sum to C(n,4) in every estimate (X17 is the complement)
+        tot4 = sum(full["estimate"][7:18])
+        assert abs(tot4 - math.comb(g.n, 4)) <= 1e-9 * math.comb(g.n, 4)
+        for a, b in ranges:
+            _say("range [%d, %d)" % (a, b))
+            got = lge.lge_estimate_range(ctx, h, p, seed, a, b)
+            mask = oracle.sample_mask(seed, p, g.m, a, b)
+            assert_parity(got, oracle.estimate(g.row_ptr, g.col, p, seed, mask=mask), "%s range" % g.name)
+    finally:
+        lge.lge_graph_destroy(h)
+
+
+@pytest.mark.parametrize("p", [0.1, 0.01])
+def test_full_size_chung_lu(ctx, p):
+    g = inputs.chung_lu_1m()
+    rng = np.random.default_rng(5)
+    starts = rng.integers(0, g.m - 4000, 3)
+    _full_size_checks(ctx, g, p, 2024, [(int(s), int(s) + 4000) for s in starts])
