@@ -24,7 +24,10 @@ typedef unsigned __int128 u128;
 
 namespace {
 
-constexpr int64_t kMaxVertices = (int64_t)1 << 29;  // vertex ids fit in 30 bits with room for tags
+// Co-degree table: at most this many ranked vertices (hc^2 * 4 bytes <= 1 GiB),
+// each of degree > kCodegMinDeg.
+constexpr int64_t kCodegMaxVertices = 16384;
+constexpr int32_t kCodegMinDeg = 32;
 
 #define LGE_HIP(expr)                        \
   do {                                       \
@@ -74,6 +77,10 @@ struct lge_graph {
   int64_t *hoff = nullptr;
   uint32_t *htab = nullptr;
   int64_t htab_len = 0;
+  int32_t *crank = nullptr;
+  uint32_t *codeg = nullptr;
+  int64_t hc = 0;
+  int32_t codeg_tau = 0;
 };
 
 struct Workspace {
@@ -89,6 +96,10 @@ struct Workspace {
   unsigned long long *acc = nullptr;  // cap_slots * kAccSlots * 2
   int64_t *items = nullptr;           // cap_edges
   int64_t *item_pref = nullptr;       // cap_edges
+  int64_t *tcap = nullptr;            // cap_edges
+  int64_t *tbase = nullptr;           // cap_edges
+  int32_t *tlist = nullptr;           // cap_tlist
+  int64_t cap_tlist = 0;
   void *gacc = nullptr;               // cap_edges * gedge_bytes()
   int64_t *scan_tmp = nullptr;
   int64_t scan_tmp_len = 0;
@@ -183,6 +194,9 @@ static void ws_free(Workspace &w) {
   dev_free(w.acc);
   dev_free(w.items);
   dev_free(w.item_pref);
+  dev_free(w.tcap);
+  dev_free(w.tbase);
+  dev_free(w.tlist);
   if (w.gacc) (void)hipFree(w.gacc);
   w.gacc = nullptr;
   dev_free(w.scan_tmp);
@@ -254,6 +268,8 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     }
     dev_free(w.items);
     dev_free(w.item_pref);
+    dev_free(w.tcap);
+    dev_free(w.tbase);
     if (w.gacc) (void)hipFree(w.gacc);
     w.gacc = nullptr;
     dev_free(w.scan_tmp);
@@ -267,6 +283,8 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     int rc;
     if ((rc = dev_alloc(&w.items, cap)) != LGE_OK) return rc;
     if ((rc = dev_alloc(&w.item_pref, cap)) != LGE_OK) return rc;
+    if ((rc = dev_alloc(&w.tcap, cap)) != LGE_OK) return rc;
+    if ((rc = dev_alloc(&w.tbase, cap)) != LGE_OK) return rc;
     if (hipMalloc(&w.gacc, (size_t)cap * gedge_bytes()) != hipSuccess) {
       w.gacc = nullptr;
       return LGE_ENOMEM;
@@ -304,6 +322,18 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     if (hipHostMalloc((void **)&w.h_ranges, (size_t)cap * sizeof(RangeDesc), 0) != hipSuccess) return LGE_ENOMEM;
     w.cap_ranges = cap;
   }
+  return LGE_OK;
+}
+
+static int ws_reserve_tlist(lge_ctx *ctx, int64_t len) {
+  Workspace &w = ctx->ws;
+  if (len <= w.cap_tlist) return LGE_OK;
+  dev_free(w.tlist);
+  w.cap_tlist = 0;
+  const int64_t cap = std::max<int64_t>(len + len / 4, 4096);
+  int rc = dev_alloc(&w.tlist, cap);
+  if (rc != LGE_OK) return rc;
+  w.cap_tlist = cap;
   return LGE_OK;
 }
 
@@ -358,7 +388,9 @@ static bool sizes_in_range(int64_t n, int64_t m, int64_t dmax) {
   return true;
 }
 
-static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags) {
+static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr);
+
+static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const int32_t *host_row_ptr) {
   hipStream_t s = ctx->stream;
   const int64_t n = g->n;
   int rc;
@@ -441,6 +473,70 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   if (e != hipSuccess) return hip_err(e);
+  return build_codeg(ctx, g, host_row_ptr);
+}
+
+// Co-degree table of the vertices of degree > tau, tau the smallest threshold
+// >= kCodegMinDeg that leaves at most kCodegMaxVertices of them.
+static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) {
+  const int64_t n = g->n;
+  g->hc = 0;
+  if (n <= 0) return LGE_OK;
+  std::vector<int32_t> deg((size_t)n);
+  for (int64_t u = 0; u < n; ++u) deg[u] = host_row_ptr[u + 1] - host_row_ptr[u];
+  int32_t tau = kCodegMinDeg;
+  if (n > kCodegMaxVertices) {
+    std::nth_element(deg.begin(), deg.begin() + kCodegMaxVertices, deg.end(), std::greater<int32_t>());
+    tau = std::max(tau, deg[kCodegMaxVertices]);
+  }
+  int64_t hc = 0;
+  for (int64_t u = 0; u < n; ++u) hc += (host_row_ptr[u + 1] - host_row_ptr[u]) > tau;
+  g->codeg_tau = tau;
+  if (hc < 2) return LGE_OK;
+  hipStream_t s = ctx->stream;
+  int64_t *flag = nullptr, *pref = nullptr, *cnt = nullptr, *off = nullptr, *tmp = nullptr;
+  int32_t *list = nullptr;
+  auto cleanup = [&]() {
+    dev_free(flag);
+    dev_free(pref);
+    dev_free(cnt);
+    dev_free(off);
+    dev_free(tmp);
+    dev_free(list);
+  };
+  int rc;
+  if ((rc = dev_alloc(&flag, n)) != LGE_OK || (rc = dev_alloc(&pref, n)) != LGE_OK ||
+      (rc = dev_alloc(&cnt, n)) != LGE_OK || (rc = dev_alloc(&off, n)) != LGE_OK ||
+      (rc = dev_alloc(&tmp, scan_tmp_size(n))) != LGE_OK || (rc = dev_alloc(&g->crank, n)) != LGE_OK ||
+      (rc = dev_alloc(&g->codeg, hc * hc)) != LGE_OK) {
+    cleanup();
+    return rc;
+  }
+  hipError_t e = launch_codeg_flags(g->row_ptr, n, tau, flag, s);
+  if (e == hipSuccess) e = launch_scan_i64(flag, pref, n, tmp, s);
+  if (e == hipSuccess) e = launch_codeg_rank(flag, pref, n, g->crank, s);
+  if (e == hipSuccess) e = launch_codeg_count(g->row_ptr, g->col, g->crank, n, cnt, s);
+  if (e == hipSuccess) e = launch_scan_i64(cnt, off, n, tmp, s);
+  int64_t last[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(&last[0], off + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&last[1], cnt + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_err(e);
+  }
+  const int64_t total = last[0] + last[1];
+  if ((rc = dev_alloc(&list, std::max<int64_t>(total, 1))) != LGE_OK) {
+    cleanup();
+    return rc;
+  }
+  e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, list, s);
+  if (e == hipSuccess) e = hipMemsetAsync(g->codeg, 0, (size_t)hc * (size_t)hc * sizeof(uint32_t), s);
+  if (e == hipSuccess) e = launch_codeg_pairs(off, cnt, list, n, hc, g->codeg, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  cleanup();
+  if (e != hipSuccess) return hip_err(e);
+  g->hc = hc;
   return LGE_OK;
 }
 
@@ -451,6 +547,8 @@ static void graph_free(lge_graph *g) {
   dev_free(g->vol2);
   dev_free(g->hoff);
   dev_free(g->htab);
+  dev_free(g->crank);
+  dev_free(g->codeg);
 }
 
 static int32_t host_max_deg(int64_t n, const int32_t *row_ptr) {
@@ -496,7 +594,7 @@ extern "C" int lge_graph_create_host(lge_ctx *ctx, int64_t n, const int32_t *row
   }
   g->row_ptr = g->own_row_ptr;
   g->col = g->own_col;
-  if ((rc = graph_preprocess(ctx, g, flags)) != LGE_OK) {
+  if ((rc = graph_preprocess(ctx, g, flags, row_ptr)) != LGE_OK) {
     graph_free(g);
     delete g;
     return rc;
@@ -532,7 +630,7 @@ extern "C" int lge_graph_create_device(lge_ctx *ctx, int64_t n, const int32_t *d
   g->row_ptr = d_row_ptr;
   g->col = d_col;
   int rc;
-  if ((rc = graph_preprocess(ctx, g, flags)) != LGE_OK) {
+  if ((rc = graph_preprocess(ctx, g, flags, rp.data())) != LGE_OK) {
     graph_free(g);
     delete g;
     return rc;
@@ -709,6 +807,9 @@ static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *op
     sd.vol2 = g->vol2;
     sd.hoff = g->hoff;
     sd.htab = g->htab;
+    sd.crank = g->crank;
+    sd.codeg = g->codeg;
+    sd.hc = g->hc;
     sd.n = jobs[j].n_override >= 0 ? jobs[j].n_override : g->n;
     sd.m = jobs[j].m_override >= 0 ? jobs[j].m_override : g->m;
     sd.p = jobs[j].p;
@@ -741,9 +842,16 @@ static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *op
   LGE_HIP(launch_count_block(w.slots, bins, nb, cfg, s));
   LGE_HIP(hipEventRecord(ev[4], s));
   if (ng > 0) {
-    LGE_HIP(launch_global_prep(w.slots, bins, ng, cfg.global_chunk, w.items, w.gacc, s));
+    LGE_HIP(launch_global_prep(w.slots, bins, ng, cfg.global_chunk, w.items, w.tcap, w.gacc, s));
     LGE_HIP(launch_scan_i64(w.items, w.item_pref, ng, w.scan_tmp, s));
-    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.gacc, cfg, s));
+    LGE_HIP(launch_scan_i64(w.tcap, w.tbase, ng, w.scan_tmp, s));
+    int64_t *hl = (int64_t *)w.h_counters + 10;
+    LGE_HIP(hipMemcpyAsync(hl, w.tbase + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LGE_HIP(hipMemcpyAsync(hl + 1, w.tcap + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LGE_HIP(hipStreamSynchronize(s));
+    if ((rc = ws_reserve_tlist(ctx, hl[0] + hl[1])) != LGE_OK) return rc;
+    LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
+    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
   LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)njobs * kAccSlots * 2 * sizeof(unsigned long long),
@@ -759,7 +867,7 @@ static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *op
   if (hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) t.count_ms[2] = ms;
   for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[c];
   for (int c = 0; c < kNumClasses; ++c) t.words_read[c] = w.h_counters[6 + c];
-  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 3 : 0);
+  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 5 : 0);
   return LGE_OK;
 }
 

@@ -24,6 +24,8 @@ constexpr int kAccSlots = 32;  // padded; one slot = 32 x (lo, hi) u64 = 512 B
 constexpr int kHubDeg = 1024;
 // Largest number of Gamma(a) positions handled by one global-class work item.
 constexpr int kGlobalChunkMax = 1024;
+// Vertex ids must stay below 2^29: the kernels keep three tag bits above them.
+constexpr int64_t kMaxVertices = (int64_t)1 << 29;
 
 // One estimate job as seen by the kernels.
 struct SlotDesc {
@@ -33,6 +35,9 @@ struct SlotDesc {
   const int64_t *vol2;      // n: sum of neighbour degrees
   const int64_t *hoff;      // n: offset of the vertex's hub table in htab (hubs only)
   const uint32_t *htab;     // hub tables (open addressing, 2^table_log(d) slots each)
+  const int32_t *crank;     // n: rank in the co-degree table, -1 if absent
+  const uint32_t *codeg;    // hc x hc: |Gamma(x) n Gamma(y)| at [min rank][max rank]
+  int64_t hc;               // ranked vertices (0: no table)
   int64_t n, m;
   double p;
   uint64_t seed;
@@ -85,16 +90,28 @@ hipError_t launch_graph_vol2(const int32_t *row_ptr, const int32_t *col, int64_t
 hipError_t launch_hub_sizes(const int32_t *row_ptr, int64_t n, int64_t *size, hipStream_t s);
 hipError_t launch_hub_build(const int32_t *row_ptr, const int32_t *col, int64_t n, const int64_t *hoff,
                             uint32_t *htab, hipStream_t s);
+hipError_t launch_codeg_flags(const int32_t *row_ptr, int64_t n, int32_t tau, int64_t *flag, hipStream_t s);
+hipError_t launch_codeg_rank(const int64_t *flag, const int64_t *pref, int64_t n, int32_t *crank, hipStream_t s);
+hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
+                              int64_t *cnt, hipStream_t s);
+hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
+                             const int64_t *off, int32_t *list, hipStream_t s);
+hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, int64_t n, int64_t hc,
+                              uint32_t *tab, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
                              int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);
 hipError_t launch_count_wave(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s);
 hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s);
-// per-edge work-item counts and partial sums (gacc: gedge_bytes() per edge)
+// global class: per-edge work items and T_e capacities, T_e lists, counting
 hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t chunk, int64_t *items,
-                              void *gacc, hipStream_t s);
+                              int64_t *tcap, void *gacc, hipStream_t s);
+hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
+                                  const int64_t *item_cnt, const int64_t *tbase, int32_t *tlist, void *gacc,
+                                  KernelCfg cfg, hipStream_t s);
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
-                               const int64_t *item_cnt, void *gacc, KernelCfg cfg, hipStream_t s);
+                               const int64_t *item_cnt, const int64_t *tbase, const int32_t *tlist, void *gacc,
+                               KernelCfg cfg, hipStream_t s);
 size_t gedge_bytes();
 
 }  // namespace lge

@@ -27,8 +27,7 @@ namespace lge {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kTag = 0x80000000u;
-constexpr uint32_t kProbe = 0x40000000u;
-constexpr uint32_t kIdMask = 0x3FFFFFFFu;
+constexpr uint32_t kIdMask = 0x1FFFFFFFu;  // vertex ids < 2^29; bits 29..31 carry tags
 constexpr int kWave = 64;
 
 typedef unsigned __int128 u128;
@@ -437,12 +436,96 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Co-degree table of the high-degree vertices: codeg[i][j] = |Gamma(x) n
+// Gamma(y)| for the vertices x, y of rank i < j among those with degree > tau.
+// Built once per graph by enumerating, for every vertex, the pairs of its
+// ranked neighbours (each common neighbour of x and y is seen once).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_codeg_flags(const int32_t *__restrict__ row_ptr, int64_t n, int32_t tau,
+                                                     int64_t *flag) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x)
+    flag[u] = (row_ptr[u + 1] - row_ptr[u]) > tau ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_codeg_rank(const int64_t *__restrict__ flag,
+                                                    const int64_t *__restrict__ pref, int64_t n, int32_t *crank) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x)
+    crank[u] = flag[u] ? (int32_t)pref[u] : -1;
+}
+
+// number of ranked neighbours of every vertex
+__global__ __launch_bounds__(256) void k_codeg_count(const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ crank, int64_t n, int64_t *cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = wave; u < n; u += nwaves) {
+    unsigned long long c = 0;
+    for (int32_t j = row_ptr[u] + lane; j < row_ptr[u + 1]; j += kWave) c += crank[col[j]] >= 0 ? 1ull : 0ull;
+    c = wave_sum_u64(c);
+    if (lane == 0) cnt[u] = (int64_t)c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_codeg_fill(const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const int32_t *__restrict__ crank, int64_t n,
+                                                    const int64_t *__restrict__ off, int32_t *list) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = wave; u < n; u += nwaves) {
+    int64_t pos = off[u];
+    const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
+    for (int32_t base = beg; base < end; base += kWave) {
+      const int32_t j = base + lane;
+      const int32_t r = j < end ? crank[col[j]] : -1;
+      const uint64_t m = __ballot(r >= 0);
+      if (r >= 0) list[pos + __popcll(m & lt_mask)] = r;
+      pos += __popcll(m);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_codeg_pairs(const int64_t *__restrict__ off,
+                                                     const int64_t *__restrict__ cnt,
+                                                     const int32_t *__restrict__ list, int64_t n, int64_t hc,
+                                                     uint32_t *tab) {
+  for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
+    const int64_t k = cnt[u];
+    if (k < 2) continue;  // uniform per block
+    const int32_t *l = list + off[u];
+    for (int64_t i = 0; i + 1 < k; ++i) {
+      const int32_t ri = l[i];
+      for (int64_t j = i + 1 + threadIdx.x; j < k; j += blockDim.x) {
+        const int32_t rj = l[j];
+        const int64_t lo = ri < rj ? ri : rj, hi = ri < rj ? rj : ri;
+        atomicAdd(&tab[lo * hc + hi], 1u);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t y, uint32_t *val) {
+  if (S.hc <= 0) return false;
+  const int32_t rx = S.crank[x], ry = S.crank[y];
+  if (rx < 0 || ry < 0) return false;
+  const int64_t lo = rx < ry ? rx : ry, hi = rx < ry ? ry : rx;
+  *val = S.codeg[lo * (int64_t)S.hc + hi];
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Block-level helpers for the counting kernels
 // ---------------------------------------------------------------------------
 
 template <int NT>
-__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
-                                                            unsigned long long *red) {
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long *red) {
   v = wave_sum_u64(v);
   if constexpr (NT == kWave) {
     return v;
@@ -468,7 +551,6 @@ __device__ int32_t block_scan_lds(int32_t *x, int len, int32_t *carry_sh) {
   for (int base = 0; base < len; base += NT) {
     const int i = base + (int)threadIdx.x;
     int32_t v = i < len ? x[i] : 0;
-    // inclusive wave scan
     int32_t s = v;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
@@ -496,8 +578,8 @@ __device__ int32_t block_scan_lds(int32_t *x, int len, int32_t *carry_sh) {
   return carry;
 }
 
-// Accumulates one edge's terms into the 32-lane register accumulator of wave 0
-// of the block; flushes to the slot when the slot changes.
+// Accumulates one edge's terms in the registers of wave 0 (lane k holds
+// accumulator k) and flushes them into the slot when the slot changes.
 struct SlotAcc {
   u128 acc;
   int32_t slot;
@@ -510,8 +592,8 @@ struct SlotAcc {
     if (slot >= 0 && lane < kAccSlots && acc != 0) atomic_add_u128(slots[slot].acc + 2 * lane, acc);
     acc = 0;
   }
-  __device__ void add(const SlotDesc *__restrict__ slots, int32_t s, int64_t n, int64_t m, int64_t da,
-                      int64_t db, int64_t t, int64_t k4, int64_t cyc) {
+  __device__ void add(const SlotDesc *__restrict__ slots, int32_t s, int64_t n, int64_t m, int64_t da, int64_t db,
+                      int64_t t, int64_t k4, int64_t cyc) {
     const int lane = threadIdx.x & 63;
     if (s != slot) {
       flush(slots);
@@ -522,20 +604,89 @@ struct SlotAcc {
 };
 
 // ---------------------------------------------------------------------------
+// Per-neighbour work modes.  For every w in Gamma(a) \ {b} the kernels pick
+// the cheapest of
+//   scan   : walk Gamma(w), test each r against the tables of b / T_e
+//            (neighbour iteration, Alg. 3/4)                  units = d_w
+//   lookT  : w in T_e: look each member of T_e up in Gamma(w)  units = t
+//            (restricted search, Alg. 5)
+//   lookS  : w in S_a: look each member of S_b up in Gamma(w)  units = |S_b source|
+//            (restricted search, Alg. 6)
+//   codeg  : w in S_a with w, b in the co-degree table:
+//            |Gamma(w) n S_b| = codeg(w,b) - 1 - |Gamma(w) n T_e|, the last term
+//            by looking T_e up in Gamma(w)                  units = t
+// "Look up x in Gamma(w)" uses w's hub table when d_w > kHubDeg, else a binary
+// search of the sorted list.  Costs are in quarter units: a scanned entry
+// costs 8 (a coalesced load and a table probe), a look-up 4*(2 + probe cost)
+// scaled by probe_ratio / 4.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kModeLook = 0x40000000u;
+constexpr uint32_t kModeCodeg = 0x20000000u;
+
+struct WMode {
+  uint32_t flags;
+  int32_t units;
+  int64_t base;  // added to the cycle count once (codeg mode)
+};
+
+__device__ __forceinline__ WMode choose_mode(bool isT, int dw, int t, int sb_src, bool codeg_ok, uint32_t cdeg,
+                                             int probe_ratio) {
+  WMode m;
+  m.flags = 0;
+  m.units = dw;
+  m.base = 0;
+  if (probe_ratio <= 0) return m;
+  const int64_t look = (int64_t)((dw > kHubDeg ? 1 : ceil_log2((uint32_t)dw + 1u)) + 2) * probe_ratio;
+  int64_t best = 8ll * dw;
+  if (isT) {
+    const int64_t c = (int64_t)t * look;
+    if (c < best) {
+      m.flags = kModeLook;
+      m.units = t;
+    }
+    return m;
+  }
+  const int64_t cs = (int64_t)sb_src * look;
+  if (cs < best) {
+    best = cs;
+    m.flags = kModeLook;
+    m.units = sb_src;
+  }
+  if (codeg_ok) {
+    const int64_t cc = (int64_t)t * look;
+    if (cc < best) {
+      m.flags = kModeLook | kModeCodeg;
+      m.units = t;
+      m.base = (int64_t)cdeg - 1;
+    }
+  }
+  return m;
+}
+
+// is x in Gamma(w)?  (w's hub table, or binary search of its sorted list)
+__device__ __forceinline__ bool w_has(const SlotDesc &S, int32_t w, int32_t wbeg, int dw, int32_t x,
+                                      uint32_t *steps) {
+  if (dw > kHubDeg) {
+    *steps += 2;
+    return table_find(S.htab + S.hoff[w], table_log(dw), (uint32_t)x) >= 0;
+  }
+  return sorted_has(S.col + wbeg, dw, x, steps);
+}
+
+// ---------------------------------------------------------------------------
 // LDS counting kernel: one edge per workgroup of NT threads, both endpoint
-// degrees <= CAP.  LDS: hash of Gamma(b)\{a} (tag = member of T_e), the list
-// of w in Gamma(a)\{b} with per-w unit prefix, and the target list
-// (T_e at the front, S_b at the back) for restricted searches.
+// degrees <= CAP.  LDS holds the hash of Gamma(b) \ {a} (bit 31 tags members
+// of T_e), the list of w in Gamma(a) \ {b} with their modes and unit prefix,
+// and the target list (T_e at the front, S_b at the back).
 // ---------------------------------------------------------------------------
 
 template <int NT, int CAP>
-__global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ slots,
-                                                  const int32_t *__restrict__ bslot,
-                                                  const int32_t *__restrict__ ba,
-                                                  const int32_t *__restrict__ bb, int64_t nedges,
-                                                  unsigned long long *cursor, unsigned long long *words_out,
-                                                  int32_t probe_ratio, int32_t chunk) {
-  constexpr int HS = 2 * CAP;  // max hash slots
+__global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot,
+                                                  const int32_t *__restrict__ ba, const int32_t *__restrict__ bb,
+                                                  int64_t nedges, unsigned long long *cursor,
+                                                  unsigned long long *words_out, int32_t probe_ratio, int32_t chunk) {
+  constexpr int HS = 2 * CAP;
   __shared__ uint32_t htab[HS];
   __shared__ uint32_t wl_v[CAP];
   __shared__ int32_t wl_beg[CAP];
@@ -574,7 +725,6 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       for (int i = tid; i < hs; i += NT) htab[i] = kEmpty;
       if (tid < 4) sh_cnt[tid] = 0;
       __syncthreads();
-      // Gamma(b) \ {a} into the hash
       for (int i = tid; i < db; i += NT) {
         const int32_t x = col[bbeg + i];
         if (x != a) lds_insert(htab, lg, (uint32_t)x);
@@ -585,7 +735,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       for (int base = 0; base < da; base += NT) {
         const int i = base + tid;
         bool valid = i < da;
-        int32_t x = valid ? col[abeg + i] : -1;
+        const int32_t x = valid ? col[abeg + i] : -1;
         valid = valid && x != b;
         bool isT = false;
         if (valid) {
@@ -596,9 +746,8 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           }
         }
         const uint64_t vm = __ballot(valid);
-        const int wcount = __popcll(vm);
         int pos0 = 0;
-        if (lane == 0 && wcount) pos0 = atomicAdd(&sh_cnt[0], wcount);
+        if (lane == 0 && vm) pos0 = atomicAdd(&sh_cnt[0], __popcll(vm));
         pos0 = __shfl(pos0, 0);
         if (valid) {
           const int pos = pos0 + __popcll(vm & lt_mask);
@@ -608,7 +757,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           wl_deg[pos] = we - wb;
         }
       }
-      words += (unsigned long long)da + 2ull * (unsigned long long)(da > 0 ? da - 1 : 0);
+      words += (unsigned long long)(3 * da);
       __syncthreads();
       // target lists from the hash: T_e at the front, S_b at the back
       for (int i = tid; i < hs; i += NT) {
@@ -623,34 +772,30 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       const int L = sh_cnt[0];
       const int t = sh_cnt[1];
       const int sbn = sh_cnt[2];
-      // per-w strategy and unit counts
+      // per-w modes
+      long long cyc_base = 0;
       for (int i = tid; i < L; i += NT) {
         const uint32_t v = wl_v[i];
-        const int dw = wl_deg[i];
-        const int tl = (v & kTag) ? t : sbn;
-        int units = dw;
-        if (probe_ratio > 0) {
-          const int cost = dw > kHubDeg ? 3 : ceil_log2((uint32_t)dw + 1u) + 1;
-          const long long pc = (long long)tl * (long long)cost * probe_ratio;
-          if (pc < dw) {
-            units = tl;
-            wl_v[i] = v | kProbe;
-          }
-        }
-        wl_pref[i] = units;
+        const bool isT = (v & kTag) != 0;
+        const int32_t w = (int32_t)(v & kIdMask);
+        uint32_t cdeg = 0;
+        const bool cok = !isT && codeg_pair(S, w, b, &cdeg);
+        const WMode md = choose_mode(isT, wl_deg[i], t, sbn, cok, cdeg, probe_ratio);
+        wl_v[i] = v | md.flags;
+        wl_pref[i] = md.units;
+        cyc_base += md.base;
       }
       __syncthreads();
       const int32_t total = block_scan_lds<NT>(wl_pref, L, carry_sh);
       if (tid == 0) wl_pref[L] = total;
       __syncthreads();
       // flattened (w, unit) loop
-      unsigned long long k4 = 0, cyc = 0;
+      unsigned long long k4 = 0, cyc = (unsigned long long)cyc_base;
       int cur = 0;
       uint32_t steps = 0;
       for (int base = 0; base < total; base += NT) {
         const int idx = base + tid;
         if (idx < total) {
-          // largest i with wl_pref[i] <= idx, searching upward from cur
           int lo = cur, hi = L - 1;
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -663,20 +808,14 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           const uint32_t v = wl_v[lo];
           const int off = idx - wl_pref[lo];
           const bool isT = (v & kTag) != 0;
-          if (v & kProbe) {
-            const int32_t x = isT ? tgt[off] : tgt[CAP - sbn + off];
-            const int32_t w = (int32_t)(v & kIdMask);
-            const int dw = wl_deg[lo];
-            bool found;
-            if (dw > kHubDeg) {
-              found = table_find(S.htab + S.hoff[w], table_log(dw), (uint32_t)x) >= 0;
-              steps += 2;
-            } else {
-              found = sorted_has(col + wl_beg[lo], dw, x, &steps);
-            }
-            if (found) {
+          if (v & kModeLook) {
+            const bool fromT = isT || (v & kModeCodeg);
+            const int32_t x = fromT ? tgt[off] : tgt[CAP - sbn + off];
+            if (w_has(S, (int32_t)(v & kIdMask), wl_beg[lo], wl_deg[lo], x, &steps)) {
               if (isT)
                 ++k4;
+              else if (v & kModeCodeg)
+                --cyc;
               else
                 ++cyc;
             }
@@ -692,7 +831,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           }
         }
       }
-      words += steps;
+      words += steps + 2ull * (unsigned long long)L;
       k4 = block_sum_u64<NT>(k4, red);
       cyc = block_sum_u64<NT>(cyc, red);
       if (tid < kWave) acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(k4 / 2), (int64_t)cyc);
@@ -705,49 +844,106 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// Global-class counting: edges with an endpoint of degree > kHubDeg.
-// Work item = (edge, chunk of kGlobalChunk positions of Gamma(a)).  Hub
-// endpoints use their global hub table; a non-hub endpoint is hashed into
-// LDS per item.  Per-edge partial sums meet in gacc; the item that completes
-// an edge folds it into the slot.
+// Global class: edges with an endpoint of degree > kHubDeg.  Work item =
+// (edge, chunk of Gamma(a) positions).  Three kernels:
+//   prep     : items and T_e capacity per edge, partial sums cleared
+//   classify : T_e of every edge into a global list (membership in Gamma(b)
+//              by b's hub table or binary search)
+//   count    : the per-w modes above over each chunk; per-edge partial sums
+//              meet in GEdge and the item that completes an edge folds it
+//              into its slot
+// Tables in LDS per item: Gamma(b) \ {a} when b is not a hub, T_e when
+// t <= kTHashCap (otherwise a's hub table serves).
 // ---------------------------------------------------------------------------
 
 constexpr int kGlobalNT = 256;
+constexpr int kTHashCap = 2048;
 
 struct GEdge {
   unsigned long long t, k4, cyc, done;
 };
 
 __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict__ slots,
-                                                     const int32_t *__restrict__ bslot,
-                                                     const int32_t *__restrict__ ba, int64_t nedges,
-                                                     int32_t chunk, int64_t *items, GEdge *gacc) {
+                                                     const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
+                                                     const int32_t *__restrict__ bb, int64_t nedges, int32_t chunk,
+                                                     int64_t *items, int64_t *tcap, GEdge *gacc) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
        e += (int64_t)gridDim.x * blockDim.x) {
     const SlotDesc &S = slots[bslot[e]];
-    const int32_t a = ba[e];
+    const int32_t a = ba[e], b = bb[e];
     const int da = S.row_ptr[a + 1] - S.row_ptr[a];
+    const int db = S.row_ptr[b + 1] - S.row_ptr[b];
     items[e] = (da + chunk - 1) / chunk;
+    tcap[e] = da < db ? da : db;
     gacc[e].t = gacc[e].k4 = gacc[e].cyc = gacc[e].done = 0ull;
   }
 }
 
-__device__ __forceinline__ bool side_has(bool hub, const uint32_t *lds_tab, int lds_lg, const uint32_t *htab,
-                                         int64_t off, int hlg, uint32_t x) {
-  if (hub) return table_find(htab + off, hlg, x) >= 0;
-  return table_find(lds_tab, lds_lg, x) >= 0;
+__device__ __forceinline__ int64_t find_item_edge(const int64_t *__restrict__ item_pref, int64_t nedges,
+                                                  int64_t item) {
+  int64_t lo = 0, hi = nedges - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (item_pref[mid] <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kGlobalNT) void k_global_classify(
+    const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
+    const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
+    const int64_t *__restrict__ item_cnt, const int64_t *__restrict__ tbase, int32_t *tlist, GEdge *gacc,
+    int32_t chunk) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
+  for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
+    const int64_t e = find_item_edge(item_pref, nedges, item);
+    const int64_t c = item - item_pref[e];
+    const SlotDesc &S = slots[bslot[e]];
+    const int32_t *__restrict__ rp = S.row_ptr;
+    const int32_t *__restrict__ col = S.col;
+    const int32_t a = ba[e], b = bb[e];
+    const int32_t abeg = rp[a], bbeg = rp[b];
+    const int da = rp[a + 1] - abeg, db = rp[b + 1] - bbeg;
+    const bool hb = db > kHubDeg;
+    const int p0 = (int)(c * chunk);
+    const int p1 = p0 + chunk < da ? p0 + chunk : da;
+    for (int base = p0; base < p1; base += kGlobalNT) {
+      const int i = base + (int)threadIdx.x;
+      bool isT = false;
+      int32_t x = -1;
+      if (i < p1) {
+        x = col[abeg + i];
+        if (x != b) {
+          uint32_t st = 0;
+          isT = hb ? table_find(S.htab + S.hoff[b], table_log(db), (uint32_t)x) >= 0
+                   : sorted_has(col + bbeg, db, x, &st);
+        }
+      }
+      const uint64_t tm = __ballot(isT);
+      unsigned long long pos0 = 0;
+      if (lane == 0 && tm) pos0 = atomicAdd(&gacc[e].t, (unsigned long long)__popcll(tm));
+      pos0 = __shfl(pos0, 0);
+      if (isT) tlist[tbase[e] + (int64_t)pos0 + __popcll(tm & lt_mask)] = x;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
-    const int64_t *__restrict__ item_cnt, GEdge *gacc, unsigned long long *cursor,
-    unsigned long long *words_out, int32_t probe_ratio, int32_t chunk) {
+    const int64_t *__restrict__ item_cnt, const int64_t *__restrict__ tbase, const int32_t *__restrict__ tlist,
+    GEdge *gacc, unsigned long long *cursor, unsigned long long *words_out, int32_t probe_ratio, int32_t chunk) {
   constexpr int NT = kGlobalNT;
   constexpr int CH = kGlobalChunkMax;
-  constexpr int HS = 2 * kHubDeg;
-  __shared__ uint32_t hA[HS];
-  __shared__ uint32_t hB[HS];
+  constexpr int HB = 2 * kHubDeg;
+  constexpr int HT = 2 * kTHashCap;
+  __shared__ uint32_t hB[HB];
+  __shared__ uint32_t hT[HT];
   __shared__ uint32_t wl_v[CH];
   __shared__ int32_t wl_beg[CH];
   __shared__ int32_t wl_deg[CH];
@@ -770,37 +966,28 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const int64_t item = sh_item;
     __syncthreads();
     if (item >= total_items) break;
-    // edge of this item
-    int64_t lo = 0, hi = nedges - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (item_pref[mid] <= item)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const int64_t e = lo;
+    const int64_t e = find_item_edge(item_pref, nedges, item);
     const int64_t c = item - item_pref[e];
     const int32_t slot = bslot[e];
     const SlotDesc &S = slots[slot];
     const int32_t *__restrict__ rp = S.row_ptr;
     const int32_t *__restrict__ col = S.col;
-    const int64_t *__restrict__ hoff = S.hoff;
-    const uint32_t *__restrict__ htab = S.htab;
     const int32_t a = ba[e], b = bb[e];
-    const int32_t abeg = rp[a], aend = rp[a + 1], bbeg = rp[b], bend = rp[b + 1];
-    const int da = aend - abeg, db = bend - bbeg;
+    const int32_t abeg = rp[a], bbeg = rp[b];
+    const int da = rp[a + 1] - abeg, db = rp[b + 1] - bbeg;
     const bool ha = da > kHubDeg, hb = db > kHubDeg;
-    const int alg = table_log(da), blg = table_log(db);
-    const int64_t aoff = ha ? hoff[a] : 0, boff = hb ? hoff[b] : 0;
+    const int blg = table_log(db), alg = table_log(da);
+    const uint32_t *__restrict__ btab = hb ? S.htab + S.hoff[b] : hB;
+    const uint32_t *__restrict__ atab = ha ? S.htab + S.hoff[a] : nullptr;
+    const int t = (int)gacc[e].t;
+    const int32_t *__restrict__ T = tlist + tbase[e];
+    const bool tl = t <= kTHashCap;
+    const int tlg = table_log(t);
     if (tid < 4) sh_cnt[tid] = 0;
-    // LDS tables for non-hub endpoints
-    if (!hb) {
+    if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
-    }
-    if (!ha) {
-      for (int i = tid; i < (1 << alg); i += NT) hA[i] = kEmpty;
-    }
+    if (tl)
+      for (int i = tid; i < (1 << tlg); i += NT) hT[i] = kEmpty;
     __syncthreads();
     if (!hb) {
       for (int i = tid; i < db; i += NT) {
@@ -809,15 +996,22 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       }
       words += (unsigned long long)db;
     }
-    if (!ha) {
-      for (int i = tid; i < da; i += NT) {
-        const int32_t x = col[abeg + i];
-        if (x != b) lds_insert(hA, alg, (uint32_t)x);
-      }
-      words += (unsigned long long)da;
+    if (tl) {
+      for (int i = tid; i < t; i += NT) lds_insert(hT, tlg, (uint32_t)T[i]);
+      words += (unsigned long long)t;
     }
     __syncthreads();
-    // classify this chunk's w
+    // membership helpers.  inB: r in Gamma(b) \ {a} (a's own id excluded
+    // by the callers where b's hub table holds it); inT_b: for r already in
+    // Gamma(b), r in T_e; inT: any r.
+    auto inB = [&](uint32_t r) -> bool { return table_find(btab, blg, r) >= 0; };
+    auto inT_b = [&](uint32_t r) -> bool {
+      return tl ? table_find(hT, tlg, r) >= 0 : table_find(atab, alg, r) >= 0;
+    };
+    auto inT = [&](uint32_t r) -> bool {
+      return tl ? table_find(hT, tlg, r) >= 0 : (table_find(atab, alg, r) >= 0 && inB(r));
+    };
+    // this chunk's w
     const int p0 = (int)(c * chunk);
     const int p1 = p0 + chunk < da ? p0 + chunk : da;
     for (int base = p0; base < p1; base += NT) {
@@ -825,15 +1019,10 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       bool valid = i < p1;
       const int32_t x = valid ? col[abeg + i] : -1;
       valid = valid && x != b;
-      bool isT = false;
-      if (valid) isT = side_has(hb, hB, blg, htab, boff, blg, (uint32_t)x);
+      const bool isT = valid && inB((uint32_t)x);  // x in Gamma(a): in T_e iff in Gamma(b)
       const uint64_t vm = __ballot(valid);
-      const uint64_t tm = __ballot(isT);
       int pos0 = 0;
-      if (lane == 0 && vm) {
-        pos0 = atomicAdd(&sh_cnt[0], __popcll(vm));
-        atomicAdd(&sh_cnt[1], __popcll(tm));
-      }
+      if (lane == 0 && vm) pos0 = atomicAdd(&sh_cnt[0], __popcll(vm));
       pos0 = __shfl(pos0, 0);
       if (valid) {
         const int pos = pos0 + __popcll(vm & lt_mask);
@@ -846,31 +1035,22 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     words += (unsigned long long)(3 * (p1 - p0) + 4);
     __syncthreads();
     const int L = sh_cnt[0];
-    const int tchunk = sh_cnt[1];
-    // per-w strategy: scan Gamma(w), or walk the target source list (T_e from
-    // the shorter of Gamma(a), Gamma(b); S_b from Gamma(b)) and look each
-    // member up in Gamma(w)
-    const int tsrc = da < db ? da : db;
+    long long cyc_base = 0;
     for (int i = tid; i < L; i += NT) {
       const uint32_t v = wl_v[i];
-      const int dw = wl_deg[i];
-      const int srcn = (v & kTag) ? tsrc : db;
-      int units = dw;
-      if (probe_ratio > 0) {
-        const int cost = dw > kHubDeg ? 3 : ceil_log2((uint32_t)dw + 1u) + 1;
-        const long long pc = (long long)srcn * (long long)cost * probe_ratio;
-        if (pc < dw) {
-          units = srcn;
-          wl_v[i] = v | kProbe;
-        }
-      }
-      wl_pref[i] = units;
+      const bool isT = (v & kTag) != 0;
+      uint32_t cdeg = 0;
+      const bool cok = !isT && codeg_pair(S, (int32_t)(v & kIdMask), b, &cdeg);
+      const WMode md = choose_mode(isT, wl_deg[i], t, db, cok, cdeg, probe_ratio);
+      wl_v[i] = v | md.flags;
+      wl_pref[i] = md.units;
+      cyc_base += md.base;
     }
     __syncthreads();
     const int32_t total = block_scan_lds<NT>(wl_pref, L, carry_sh);
     if (tid == 0) wl_pref[L] = total;
     __syncthreads();
-    unsigned long long k4 = 0, cyc = 0;
+    unsigned long long k4 = 0, cyc = (unsigned long long)cyc_base;
     uint32_t steps = 0;
     int cur = 0;
     for (int base = 0; base < total; base += NT) {
@@ -888,58 +1068,41 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
         const uint32_t v = wl_v[l2];
         const int off = idx - wl_pref[l2];
         const bool isT = (v & kTag) != 0;
-        if (v & kProbe) {
-          // candidate x from the source list, kept only if it is a target
+        const int32_t w = (int32_t)(v & kIdMask);
+        if (v & kModeLook) {
           int32_t x;
-          bool keep;
-          if (isT) {
-            if (da < db) {
-              x = col[abeg + off];
-              keep = x != b && side_has(hb, hB, blg, htab, boff, blg, (uint32_t)x);
-            } else {
-              x = col[bbeg + off];
-              keep = x != a && side_has(ha, hA, alg, htab, aoff, alg, (uint32_t)x);
-            }
+          bool keep = true;
+          if (isT || (v & kModeCodeg)) {
+            x = T[off];
           } else {
-            x = col[bbeg + off];
-            keep = x != a && !side_has(ha, hA, alg, htab, aoff, alg, (uint32_t)x);
+            x = col[bbeg + off];  // S_b candidate from Gamma(b)
+            keep = x != a && !inT_b((uint32_t)x);
           }
           ++steps;
-          if (keep) {
-            const int32_t w = (int32_t)(v & kIdMask);
-            const int dw = wl_deg[l2];
-            bool found;
-            if (dw > kHubDeg) {
-              found = table_find(htab + hoff[w], table_log(dw), (uint32_t)x) >= 0;
-              steps += 2;
-            } else {
-              found = sorted_has(col + wl_beg[l2], dw, x, &steps);
-            }
-            if (found) {
-              if (isT)
-                ++k4;
-              else
-                ++cyc;
-            }
+          if (keep && w_has(S, w, wl_beg[l2], wl_deg[l2], x, &steps)) {
+            if (isT)
+              ++k4;
+            else if (v & kModeCodeg)
+              --cyc;
+            else
+              ++cyc;
           }
         } else {
           const int32_t r = col[wl_beg[l2] + off];
           ++steps;
-          if (side_has(hb, hB, blg, htab, boff, blg, (uint32_t)r)) {
-            // r in Gamma(b) \ {a}; in T_e iff also in Gamma(a)
-            const bool rA = side_has(ha, hA, alg, htab, aoff, alg, (uint32_t)r);
-            if (isT && rA) ++k4;
-            if (!isT && !rA && r != a) ++cyc;
+          if (isT) {
+            if (inT((uint32_t)r)) ++k4;
+          } else if (r != a && inB((uint32_t)r) && !inT_b((uint32_t)r)) {
+            ++cyc;
           }
         }
       }
     }
-    words += steps;
+    words += steps + 2ull * (unsigned long long)L;
     k4 = block_sum_u64<NT>(k4, red);
     cyc = block_sum_u64<NT>(cyc, red);
     if (tid == 0) {
       GEdge *g = gacc + e;
-      if (tchunk) atomicAdd(&g->t, (unsigned long long)tchunk);
       if (k4) atomicAdd(&g->k4, k4);
       if (cyc) atomicAdd(&g->cyc, cyc);
       __threadfence();
@@ -950,11 +1113,10 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     if (sh_last && tid < kWave) {
       GEdge *g = gacc + e;
       __threadfence();
-      const int64_t tt = (int64_t)atomicAdd(&g->t, 0ull);
       const int64_t kk = (int64_t)atomicAdd(&g->k4, 0ull);
       const int64_t cc = (int64_t)atomicAdd(&g->cyc, 0ull);
       if (lane <= kAccIdxCount) {
-        const u128 v = edge_term(lane, S.n, S.m, da, db, tt, kk / 2, cc);
+        const u128 v = edge_term(lane, S.n, S.m, da, db, t, kk / 2, cc);
         if (v != 0) atomic_add_u128(S.acc + 2 * lane, v);
       }
     }
@@ -981,8 +1143,7 @@ static int grid_for(int64_t work, int per_block, int cap) {
   return (int)g;
 }
 
-hipError_t launch_graph_validate(const int32_t *row_ptr, const int32_t *col, int64_t n, int *err,
-                                 hipStream_t s) {
+hipError_t launch_graph_validate(const int32_t *row_ptr, const int32_t *col, int64_t n, int *err, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_graph_validate, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, n, err);
   return hipGetLastError();
@@ -991,8 +1152,7 @@ hipError_t launch_graph_validate(const int32_t *row_ptr, const int32_t *col, int
 hipError_t launch_graph_upper(const int32_t *row_ptr, const int32_t *col, int64_t n, int32_t *up_start,
                               int64_t *cnt, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_graph_upper, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, row_ptr, col, n,
-                     up_start, cnt);
+  hipLaunchKernelGGL(k_graph_upper, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, row_ptr, col, n, up_start, cnt);
   return hipGetLastError();
 }
 
@@ -1024,13 +1184,12 @@ int64_t scan_tmp_size(int64_t len) {
 hipError_t launch_graph_edges(const int32_t *row_ptr, const int32_t *col, const int32_t *up_start,
                               const int64_t *eid_base, int64_t n, uint64_t *edges, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_graph_edges, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, up_start,
-                     eid_base, n, edges);
+  hipLaunchKernelGGL(k_graph_edges, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, up_start, eid_base,
+                     n, edges);
   return hipGetLastError();
 }
 
-hipError_t launch_graph_vol2(const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t *vol2,
-                             hipStream_t s) {
+hipError_t launch_graph_vol2(const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t *vol2, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_graph_vol2, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, n, vol2);
   return hipGetLastError();
@@ -1046,6 +1205,39 @@ hipError_t launch_hub_build(const int32_t *row_ptr, const int32_t *col, int64_t 
                             uint32_t *htab, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hub_build, dim3(grid_for(n, 64, 8192)), dim3(256), 0, s, row_ptr, col, n, hoff, htab);
+  return hipGetLastError();
+}
+
+hipError_t launch_codeg_flags(const int32_t *row_ptr, int64_t n, int32_t tau, int64_t *flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_flags, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, row_ptr, n, tau, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_codeg_rank(const int64_t *flag, const int64_t *pref, int64_t n, int32_t *crank, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_rank, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, flag, pref, n, crank);
+  return hipGetLastError();
+}
+
+hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
+                              int64_t *cnt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_count, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, crank, n, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
+                             const int64_t *off, int32_t *list, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_fill, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, crank, n, off, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, int64_t n, int64_t hc,
+                              uint32_t *tab, hipStream_t s) {
+  if (n <= 0 || hc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_pairs, dim3(grid_for(n, 1, 16384)), dim3(256), 0, s, off, cnt, list, n, hc, tab);
   return hipGetLastError();
 }
 
@@ -1088,20 +1280,32 @@ hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t nedges, 
 }
 
 hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t chunk, int64_t *items,
-                              void *gacc, hipStream_t s) {
+                              int64_t *tcap, void *gacc, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_global_prep, dim3(grid_for(nedges, 256, 8192)), dim3(256), 0, s, slots,
-                     bins.slot[kClassGlobal], bins.a[kClassGlobal], nedges, chunk, items, (GEdge *)gacc);
+                     bins.slot[kClassGlobal], bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, chunk, items, tcap,
+                     (GEdge *)gacc);
+  return hipGetLastError();
+}
+
+hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
+                                  const int64_t *item_cnt, const int64_t *tbase, int32_t *tlist, void *gacc,
+                                  KernelCfg cfg, hipStream_t s) {
+  if (nedges <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
+                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, tbase, tlist,
+                     (GEdge *)gacc, cfg.global_chunk);
   return hipGetLastError();
 }
 
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
-                               const int64_t *item_cnt, void *gacc, KernelCfg cfg, hipStream_t s) {
+                               const int64_t *item_cnt, const int64_t *tbase, const int32_t *tlist, void *gacc,
+                               KernelCfg cfg, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots,
-                     bins.slot[kClassGlobal], bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref,
-                     item_cnt, (GEdge *)gacc, bins.cursor + kClassGlobal, bins.words + kClassGlobal,
-                     cfg.probe_ratio, cfg.global_chunk);
+  hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
+                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, tbase, tlist,
+                     (GEdge *)gacc, bins.cursor + kClassGlobal, bins.words + kClassGlobal, cfg.probe_ratio,
+                     cfg.global_chunk);
   return hipGetLastError();
 }
 
