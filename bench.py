@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (known bytes) to scale memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every box here has one MI355X; the path shards by "
@@ -101,7 +103,10 @@ def main():
     g, wname = make_workload(args.workload)
     log("graph n=%d m=%d" % (g.n, g.m))
     ctx = lge.lge_open(0)
+    t_create = time.perf_counter()
     h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    t_create = time.perf_counter() - t_create
+    log("graph resident in %.2f s (upload, validation, edge list, hub and co-degree tables)" % t_create)
     for i in range(args.warmup):
         lge.lge_estimate(ctx, h, p, args.seed + i)
         log("warmup %d/%d" % (i + 1, args.warmup))
@@ -144,14 +149,24 @@ def main():
         "config": {"workload": wname, "n": g.n, "m": g.m, "p": p, "seed0": args.seed + 100,
                    "path": "plain (one lge_estimate per step, graph resident)"},
         "device_ms": {"sample_bin": sum(t["sample_ms"] for t in tim) / k, "count_wave": cnt_ms[0],
-                      "count_block": cnt_ms[1], "count_global": cnt_ms[2]},
+                      "count_block": cnt_ms[1], "global_prep": sum(t["global_prep_ms"] for t in tim) / k,
+                      "count_global": cnt_ms[2]},
         "class_edges": [sum(t["class_edges"][c] for t in tim) // k for c in range(3)],
+        "graph_create_s": t_create,
         "roofline": {"bound": "hbm", "kernel": CLASS_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": 4.0 * words[dom]},
     }
     lge.lge_graph_destroy(h)
     lge.lge_close(ctx)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(g, p, args.seed + 100, args.cpu_seconds)

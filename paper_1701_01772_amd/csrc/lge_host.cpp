@@ -841,6 +841,7 @@ static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *op
   LGE_HIP(hipEventRecord(ev[3], s));
   LGE_HIP(launch_count_block(w.slots, bins, nb, cfg, s));
   LGE_HIP(hipEventRecord(ev[4], s));
+  if (ng == 0) LGE_HIP(hipEventRecord(ev[6], s));
   if (ng > 0) {
     LGE_HIP(launch_global_prep(w.slots, bins, ng, cfg.global_chunk, w.items, w.tcap, w.gacc, s));
     LGE_HIP(launch_scan_i64(w.items, w.item_pref, ng, w.scan_tmp, s));
@@ -851,6 +852,7 @@ static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *op
     LGE_HIP(hipStreamSynchronize(s));
     if ((rc = ws_reserve_tlist(ctx, hl[0] + hl[1])) != LGE_OK) return rc;
     LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
+    LGE_HIP(hipEventRecord(ev[6], s));
     LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
@@ -864,7 +866,8 @@ static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *op
   if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) t.sample_ms = ms;
   if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) t.count_ms[0] = ms;
   if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) t.count_ms[1] = ms;
-  if (hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) t.count_ms[2] = ms;
+  if (hipEventElapsedTime(&ms, ev[6], ev[5]) == hipSuccess) t.count_ms[2] = ms;
+  if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
   for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[c];
   for (int c = 0; c < kNumClasses; ++c) t.words_read[c] = w.h_counters[6 + c];
   t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 5 : 0);

@@ -62,6 +62,7 @@ class Opts(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_float), ("sample_ms", ctypes.c_float), ("count_ms", ctypes.c_float * 3),
+                ("global_prep_ms", ctypes.c_float),
                 ("class_edges", ctypes.c_uint64 * 3), ("words_read", ctypes.c_uint64 * 3),
                 ("launches", ctypes.c_uint64)]
 
@@ -289,6 +290,7 @@ def lge_last_timing(ctx) -> dict:
     t = Timing()
     _check(load().lge_last_timing(ctx, ctypes.byref(t)), "lge_last_timing")
     return {"total_ms": t.total_ms, "sample_ms": t.sample_ms, "count_ms": list(t.count_ms),
+            "global_prep_ms": t.global_prep_ms,
             "class_edges": [int(x) for x in t.class_edges], "words_read": [int(x) for x in t.words_read],
             "launches": int(t.launches)}
 
