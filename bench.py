@@ -76,6 +76,188 @@ def cpu_baseline(g, p, seed, target_s=15.0):
                 stride, sampled_ids.size, r["sampled"], dt)}
 
 
+def roofline_of(tim, workload):
+    k = len(tim)
+    cnt_ms = [sum(t["count_ms"][c] for t in tim) / k for c in range(3)]
+    words = [sum(t["words_read"][c] for t in tim) / k for c in range(3)]
+    dom = max(range(3), key=lambda c: cnt_ms[c])
+    achieved = 4.0 * words[dom] / (cnt_ms[dom] * 1e-3) / 1e9 if cnt_ms[dom] > 0 else 0.0
+    traffic = None
+    pmc_path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (workload, ["wave", "block", "global"][dom]))
+    if os.path.exists(pmc_path):
+        with open(pmc_path) as fh:
+            pmc = json.load(fh)
+        if pmc.get("kernel_hash") == kernel_source_hash():
+            traffic = pmc.get("traffic_bytes_per_launch")
+    device_ms = {"sample_bin": sum(t["sample_ms"] for t in tim) / k, "count_wave": cnt_ms[0],
+                 "count_block": cnt_ms[1], "global_prep": sum(t["global_prep_ms"] for t in tim) / k,
+                 "count_global": cnt_ms[2]}
+    roof = {"bound": "hbm", "kernel": CLASS_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": 4.0 * words[dom]}
+    return device_ms, roof
+
+
+def bench_batch(args):
+    """4096 small graphs: one lge_estimate_many launch sequence per step vs
+    one lge_estimate per graph (the plain path), graphs resident."""
+    import torch
+    from paper_1701_01772_amd import inputs, lge
+    log("generating 4096 graphs")
+    graphs = inputs.batch_graphs(4096, 4096)
+    tot_m = sum(g.m for g in graphs)
+    log("batch: %d graphs, %d vertices, %d edges" % (len(graphs), sum(g.n for g in graphs), tot_m))
+    ctx = lge.lge_open(0)
+    hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col) for g in graphs]
+    seeds = [args.seed + i for i in range(len(hs))]
+    p = args.p if args.p is not None else 1.0
+    lge.lge_estimate_many(ctx, hs, p, seeds)
+    for h in hs[:64]:
+        lge.lge_estimate(ctx, h, p, 1)
+    torch.cuda.synchronize()
+    # plain path: one estimate (one launch sequence) per graph
+    t0 = time.perf_counter()
+    plain_sampled = 0
+    for h, sd in zip(hs, seeds):
+        plain_sampled += lge.lge_estimate(ctx, h, p, sd)["sampled"]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log("plain: %.3f s" % t_plain)
+    sampled = 0
+    tim = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        outs = lge.lge_estimate_many(ctx, hs, p, seeds)
+        sampled += sum(o["sampled"] for o in outs)
+        tim.append(lge.lge_last_timing(ctx))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("batched: %d steps in %.3f s" % (args.steps, dt))
+    # end-to-end from host arrays (union upload + preprocessing + one launch)
+    t0 = time.perf_counter()
+    lge.lge_count_batch(ctx, [(g.row_ptr, g.col) for g in graphs], p, seeds)
+    t_e2e = time.perf_counter() - t0
+    for h in hs:
+        lge.lge_graph_destroy(h)
+    lge.lge_close(ctx)
+    device_ms, roof = roofline_of(tim, "batch")
+    return {
+        "metric": "sampled edges/s (all 3/4-node graphlets), batched",
+        "value": sampled / dt, "unit": "sampled edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "batch_4096_er_chunglu_n50_5000", "graphs": len(graphs), "m_total": tot_m, "p": p,
+                   "path": "batched (one lge_estimate_many per step, graphs resident)"},
+        "plain": {"value": plain_sampled / t_plain, "unit": "sampled edges/s", "s": t_plain,
+                  "path": "4096 lge_estimate calls, one launch sequence each"},
+        "batched_vs_plain": (sampled / dt) / (plain_sampled / t_plain),
+        "end_to_end_count_batch_s": t_e2e,
+        "device_ms": device_ms, "roofline": roof,
+    }
+
+
+def bench_serve(args):
+    """Poisson request stream over resident graphs served by lge_server
+    (continuous batching); rates at 50% and 80% of the plain path's measured
+    saturation throughput."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    import torch
+    from paper_1701_01772_amd import inputs, lge
+    log("generating 64 serving graphs (edge counts log-uniform in [1e3, %.0e])" % args.serve_m_hi)
+    graphs = inputs.serving_graphs(64, 64, 1e3, args.serve_m_hi)
+    log("serving set: %d edges total" % sum(g.m for g in graphs))
+    ctx = lge.lge_open(0)
+    hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col) for g in graphs]
+    rng = np.random.default_rng(args.seed)
+    n_req = args.serve_requests
+
+    def draw(k):
+        return [(int(rng.integers(0, len(hs))), float(rng.choice([1.0, 0.1, 0.01])), 10_000 + i) for i in range(k)]
+
+    # plain-path saturation: requests back to back, one lge_estimate each
+    cal = draw(n_req)
+    for gi, p, s in cal[:8]:
+        lge.lge_estimate(ctx, hs[gi], p, s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_edges = 0
+    for gi, p, s in cal:
+        plain_edges += lge.lge_estimate(ctx, hs[gi], p, s)["sampled"]
+    t_plain = time.perf_counter() - t0
+    sat_qps = len(cal) / t_plain
+    log("plain saturation: %.1f requests/s" % sat_qps)
+    out = {"plain": {"requests_per_s": sat_qps, "sampled_edges_per_s": plain_edges / t_plain}}
+    srv = lge.lge_server_create(ctx)
+    gids = [lge.lge_server_add_graph(srv, h) for h in hs]
+    try:
+        # closed loop on the same requests as the plain measurement: all
+        # submitted at once, drained by the server
+        st0 = lge.lge_server_get_stats(srv)
+        t0 = time.perf_counter()
+        tk = [lge.lge_submit(srv, gids[gi], p, s) for gi, p, s in cal]
+        burst_edges = sum(lge.lge_wait(srv, t, -1)["sampled"] for t in tk)
+        t_burst = time.perf_counter() - t0
+        st1 = lge.lge_server_get_stats(srv)
+        assert burst_edges == plain_edges
+        out["burst"] = {"requests_per_s": len(cal) / t_burst, "sampled_edges_per_s": burst_edges / t_burst,
+                        "steps": st1["steps"] - st0["steps"], "busy_s": st1["busy_s"] - st0["busy_s"],
+                        "vs_plain": t_plain / t_burst}
+        log("burst: %.1f requests/s (plain %.1f), %d steps" % (len(cal) / t_burst, sat_qps, out["burst"]["steps"]))
+        for frac in (0.5, 0.8):
+            reqs = draw(n_req)
+            qps = frac * sat_qps
+            gaps = rng.exponential(1.0 / qps, len(reqs))
+            lat = [None] * len(reqs)
+            sampled = [0] * len(reqs)
+            pool = ThreadPoolExecutor(64)
+
+            def waiter(i, ticket, t_sub):
+                r = lge.lge_wait(srv, ticket, -1)
+                lat[i] = time.perf_counter() - t_sub
+                sampled[i] = r["sampled"]
+
+            t_start = time.perf_counter()
+            t_next = t_start
+            futs = []
+            for i, ((gi, p, s), gap) in enumerate(zip(reqs, gaps)):
+                t_next += gap
+                d = t_next - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                t_sub = time.perf_counter()
+                ticket = lge.lge_submit(srv, gids[gi], p, s)
+                futs.append(pool.submit(waiter, i, ticket, t_sub))
+            for f in futs:
+                f.result()
+            span = time.perf_counter() - t_start
+            pool.shutdown()
+            la = np.array(lat) * 1e3
+            st = lge.lge_server_get_stats(srv)
+            key = "served_%d" % int(frac * 100)
+            out[key] = {"offered_qps": qps, "requests": len(reqs), "p50_ms": float(np.percentile(la, 50)),
+                        "p99_ms": float(np.percentile(la, 99)), "throughput_rps": len(reqs) / span,
+                        "sampled_edges_per_s": sum(sampled) / span, "steps_total": st["steps"]}
+            log("%s: p50 %.2f ms p99 %.2f ms" % (key, out[key]["p50_ms"], out[key]["p99_ms"]))
+    finally:
+        lge.lge_server_destroy(srv)
+    for h in hs:
+        lge.lge_graph_destroy(h)
+    lge.lge_close(ctx)
+    s80 = out["served_80"]
+    return {
+        "metric": "served p50/p99 latency and throughput (sampled edges/s)",
+        "value": s80["sampled_edges_per_s"], "unit": "sampled edges/s", "n_gpus": 1, "steps": n_req,
+        "warmup": 8, "ms_per_step": s80["p50_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "serving_64_graphs_chunglu_rmat_m1e3_%.0e" % args.serve_m_hi,
+                   "p_mix": [1.0, 0.1, 0.01], "arrivals": "poisson"},
+        "serving": out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +268,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-m-hi", type=float, default=2e6)
+    ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale memory counters")
     args = ap.parse_args()
@@ -94,6 +278,13 @@ def main():
               "canonical edge-id ranges (lge_estimate_range) but no multi-GPU run is part of this build",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args)))
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args)))
+        return
 
     import torch
     from paper_1701_01772_amd import lge
@@ -122,17 +313,7 @@ def main():
     dt = time.perf_counter() - t0
     log("timed %d steps in %.3f s" % (args.steps, dt))
     k = len(tim)
-    cnt_ms = [sum(t["count_ms"][c] for t in tim) / k for c in range(3)]
-    words = [sum(t["words_read"][c] for t in tim) / k for c in range(3)]
-    dom = max(range(3), key=lambda c: cnt_ms[c])
-    achieved = 4.0 * words[dom] / (cnt_ms[dom] * 1e-3) / 1e9 if cnt_ms[dom] > 0 else 0.0
-    traffic = None
-    pmc_path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (args.workload, ["wave", "block", "global"][dom]))
-    if os.path.exists(pmc_path):
-        with open(pmc_path) as fh:
-            pmc = json.load(fh)
-        if pmc.get("kernel_hash") == kernel_source_hash():
-            traffic = pmc.get("traffic_bytes_per_launch")
+    device_ms, roof = roofline_of(tim, args.workload)
     result = {
         "metric": "sampled edges/s (all 3/4-node graphlets)",
         "value": sampled / dt,
@@ -148,14 +329,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "n": g.n, "m": g.m, "p": p, "seed0": args.seed + 100,
                    "path": "plain (one lge_estimate per step, graph resident)"},
-        "device_ms": {"sample_bin": sum(t["sample_ms"] for t in tim) / k, "count_wave": cnt_ms[0],
-                      "count_block": cnt_ms[1], "global_prep": sum(t["global_prep_ms"] for t in tim) / k,
-                      "count_global": cnt_ms[2]},
+        "device_ms": device_ms,
         "class_edges": [sum(t["class_edges"][c] for t in tim) // k for c in range(3)],
         "graph_create_s": t_create,
-        "roofline": {"bound": "hbm", "kernel": CLASS_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": 4.0 * words[dom]},
+        "roofline": roof,
     }
     lge.lge_graph_destroy(h)
     lge.lge_close(ctx)

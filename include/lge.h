@@ -229,6 +229,14 @@ typedef struct {
 
 LGE_API int lge_count_batch(lge_ctx *ctx, const lge_batch *b, const lge_opts *opts, lge_result *outs);
 
+/*
+ * Many resident graphs (created on this ctx) estimated in one launch
+ * sequence: graph k with p[k], seed[k]; outs[count] caller-owned.  Results
+ * equal `count` separate lge_estimate calls.
+ */
+LGE_API int lge_estimate_many(lge_ctx *ctx, const lge_graph *const *graphs, const double *p, const uint64_t *seed,
+                              int32_t count, const lge_opts *opts, lge_result *outs);
+
 /* Timing of the last lge_estimate / lge_count_batch on ctx. */
 LGE_API int lge_last_timing(const lge_ctx *ctx, lge_timing *out);
 
@@ -237,6 +245,55 @@ LGE_API int lge_last_timing(const lge_ctx *ctx, lge_timing *out);
  * *out.  The choice never changes results.
  */
 LGE_API int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *out);
+
+/*
+ * Serving.  A server owns `ctx` (no other call may use that ctx while the
+ * server exists) and runs one scheduler thread.  Graphs are added once and
+ * stay resident.  Requests (graph, p, seed) queue FIFO; up to max_inflight of
+ * them run at once.  Every step the scheduler gives each running request the
+ * next chunk of its canonical edge-id range so that the step's device work
+ * lists fit hbm_budget_bytes (at least min_chunk_edges per chunk when the
+ * budget allows), runs all chunks in one launch sequence, and finalises the
+ * requests whose range is done.  Requests arriving meanwhile join at the next
+ * step (continuous batching).  A request's result equals lge_estimate on the
+ * same (graph, p, seed): exact sums do not depend on chunking or neighbours.
+ * lge_submit / lge_wait / lge_cancel / lge_server_get_stats are thread-safe; one
+ * thread may wait on a given ticket.
+ */
+typedef struct {
+  int32_t max_inflight;     /* requests running at once (default 64) */
+  int32_t queue_capacity;   /* queued + running requests before LGE_EBUSY (default 4096) */
+  int64_t hbm_budget_bytes; /* device work-list budget of one step (default 2 GiB) */
+  int64_t min_chunk_edges;  /* smallest edge-id chunk per request and step (default 65536) */
+  int32_t reserved[4];
+} lge_server_cfg;
+
+typedef struct {
+  uint64_t submitted, completed, canceled, rejected;
+  uint64_t steps;   /* launch sequences run */
+  uint64_t queued;  /* waiting for a running slot, now */
+  uint64_t running; /* admitted and not finished, now */
+  double busy_s;    /* wall time spent inside steps */
+} lge_server_stats;
+
+LGE_API int lge_server_cfg_default(lge_server_cfg *cfg);
+/* cfg may be NULL (defaults); zero fields take defaults; negative -> LGE_EINVAL. */
+LGE_API int lge_server_create(lge_ctx *ctx, const lge_server_cfg *cfg, lge_server **out);
+/* g must belong to the server's ctx and outlive the server; *gid names it. */
+LGE_API int lge_server_add_graph(lge_server *srv, const lge_graph *g, int32_t *gid);
+/* p in (0,1] else LGE_EINVAL; unknown gid LGE_ENOTFOUND; full LGE_EBUSY;
+ * after shutdown LGE_ECANCELED. */
+LGE_API int lge_submit(lge_server *srv, int32_t gid, double p, uint64_t seed, uint64_t *ticket);
+/* Waits up to timeout_us (< 0: forever).  LGE_OK fills *out and retires the
+ * ticket; LGE_ETIMEDOUT keeps it; LGE_ECANCELED (cancelled or shut down) and
+ * device errors retire it; unknown ticket LGE_ENOTFOUND. */
+LGE_API int lge_wait(lge_server *srv, uint64_t ticket, int64_t timeout_us, lge_result *out);
+/* Cancels a queued or running request (its wait returns LGE_ECANCELED). */
+LGE_API int lge_cancel(lge_server *srv, uint64_t ticket);
+LGE_API int lge_server_get_stats(lge_server *srv, lge_server_stats *out);
+/* Stops the scheduler after the step in flight, resolves every pending
+ * ticket with LGE_ECANCELED (threads blocked in lge_wait return), frees. */
+LGE_API int lge_server_destroy(lge_server *srv);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblge.so")
-SOURCES = [os.path.join(CSRC, "lge_kernels.hip"), os.path.join(CSRC, "lge_host.cpp")]
+SOURCES = [os.path.join(CSRC, "lge_kernels.hip"), os.path.join(CSRC, "lge_host.cpp"),
+           os.path.join(CSRC, "lge_server.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -16,6 +16,7 @@
 
 #include "../../include/lge.h"
 #include "lge_internal.h"
+#include "lge_runtime.h"
 
 using namespace lge;
 
@@ -63,62 +64,6 @@ void dev_free(T *&p) {
 // ---------------------------------------------------------------------------
 // objects
 // ---------------------------------------------------------------------------
-
-struct lge_graph {
-  lge_ctx *ctx = nullptr;
-  int64_t n = 0, m = 0;
-  int32_t max_deg = 0;
-  const int32_t *row_ptr = nullptr;
-  const int32_t *col = nullptr;
-  int32_t *own_row_ptr = nullptr;
-  int32_t *own_col = nullptr;
-  uint64_t *edges = nullptr;
-  int64_t *vol2 = nullptr;
-  int64_t *hoff = nullptr;
-  uint32_t *htab = nullptr;
-  int64_t htab_len = 0;
-  int32_t *crank = nullptr;
-  uint32_t *codeg = nullptr;
-  int64_t hc = 0;
-  int32_t codeg_tau = 0;
-};
-
-struct Workspace {
-  int64_t cap_edges = 0;  // capacity of each class list
-  int32_t cap_slots = 0;
-  int32_t cap_ranges = 0;
-  int32_t *bin_slot[kNumClasses] = {};
-  int32_t *bin_a[kNumClasses] = {};
-  int32_t *bin_b[kNumClasses] = {};
-  unsigned long long *counters = nullptr;  // count[3], cursor[3], words[3], pad
-  SlotDesc *slots = nullptr;
-  RangeDesc *ranges = nullptr;
-  unsigned long long *acc = nullptr;  // cap_slots * kAccSlots * 2
-  int64_t *items = nullptr;           // cap_edges
-  int64_t *item_pref = nullptr;       // cap_edges
-  int64_t *tcap = nullptr;            // cap_edges
-  int64_t *tbase = nullptr;           // cap_edges
-  int32_t *tlist = nullptr;           // cap_tlist
-  int64_t cap_tlist = 0;
-  void *gacc = nullptr;               // cap_edges * gedge_bytes()
-  int64_t *scan_tmp = nullptr;
-  int64_t scan_tmp_len = 0;
-  // pinned host staging
-  SlotDesc *h_slots = nullptr;
-  RangeDesc *h_ranges = nullptr;
-  unsigned long long *h_acc = nullptr;
-  unsigned long long *h_counters = nullptr;
-};
-
-struct lge_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  Workspace ws;
-  lge_opts opts{};
-  lge_timing timing{};
-  hipEvent_t ev[8] = {};
-  int num_cu = 256;
-};
 
 struct lge_event {
   lge_ctx *ctx;
@@ -693,7 +638,7 @@ static double to_double(i128 x) {
 }
 
 // acc: kAccSlots x {lo, hi} as produced by the kernels
-static void finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned long long *acc,
+void lge_finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned long long *acc,
                      lge_result *out) {
   memset(out, 0, sizeof(*out));
   out->n = n;
@@ -762,15 +707,7 @@ static void finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsign
 // launch sequence for a set of slots and ranges
 // ---------------------------------------------------------------------------
 
-struct Job {
-  const lge_graph *g;
-  double p;
-  uint64_t seed;
-  int64_t e0, e1;       // canonical edge range (of the graph's own ids)
-  int64_t n_override;   // graph-level sizes for the closed forms (batch unions)
-  int64_t m_override;
-  int64_t eid_base;     // subtracted from edge ids before the sampler
-};
+
 
 static Bins make_bins(Workspace &w) {
   Bins b;
@@ -788,7 +725,7 @@ static Bins make_bins(Workspace &w) {
 
 // Runs sample -> bin -> count for every job; leaves per-job accumulators in
 // ws.h_acc (host) on success.
-static int run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts) {
+int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts) {
   if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
   int64_t total = 0;
   for (int j = 0; j < njobs; ++j) total += jobs[j].e1 - jobs[j].e0;
@@ -882,9 +819,9 @@ extern "C" int lge_estimate(lge_ctx *ctx, const lge_graph *g, double p, uint64_t
   if (!ctx || !g || !out) return LGE_EINVAL;
   if (g->ctx != ctx) return LGE_EINVAL;
   Job job{g, p, seed, 0, g->m, -1, -1, 0};
-  int rc = run_jobs(ctx, &job, 1, opts);
+  int rc = lge_run_jobs(ctx, &job, 1, opts);
   if (rc != LGE_OK) return rc;
-  finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+  lge_finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
   return LGE_OK;
 }
 
@@ -894,9 +831,9 @@ extern "C" int lge_estimate_range(lge_ctx *ctx, const lge_graph *g, double p, ui
   if (!ctx || !g || !out) return LGE_EINVAL;
   if (g->ctx != ctx || e0 < 0 || e1 < e0 || e1 > g->m) return LGE_EINVAL;
   Job job{g, p, seed, e0, e1, -1, -1, 0};
-  int rc = run_jobs(ctx, &job, 1, opts);
+  int rc = lge_run_jobs(ctx, &job, 1, opts);
   if (rc != LGE_OK) return rc;
-  finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+  lge_finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
   return LGE_OK;
 }
 
@@ -925,12 +862,12 @@ extern "C" int lge_estimate_async(lge_ctx *ctx, const lge_graph *g, double p, ui
   E->seed = seed;
   E->done = nullptr;
   Job job{g, p, seed, 0, g->m, -1, -1, 0};
-  int rc = run_jobs(ctx, &job, 1, nullptr);
+  int rc = lge_run_jobs(ctx, &job, 1, nullptr);
   if (rc != LGE_OK) {
     delete E;
     return rc;
   }
-  finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+  lge_finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
   *ev = E;
   return LGE_OK;
 }
@@ -990,14 +927,31 @@ extern "C" int lge_count_batch(lge_ctx *ctx, const lge_batch *b, const lge_opts 
     const int64_t nk = b->vtx_off[k + 1] - b->vtx_off[k];
     jobs[k] = Job{U, b->p[k], b->seed[k], eoff[k], eoff[k + 1], nk, eoff[k + 1] - eoff[k], eoff[k]};
   }
-  rc = run_jobs(ctx, jobs.data(), G, opts);
+  rc = lge_run_jobs(ctx, jobs.data(), G, opts);
   if (rc == LGE_OK) {
     for (int k = 0; k < G; ++k)
-      finalize(jobs[k].n_override, jobs[k].m_override, b->p[k], b->seed[k],
+      lge_finalize(jobs[k].n_override, jobs[k].m_override, b->p[k], b->seed[k],
                ctx->ws.h_acc + (int64_t)k * kAccSlots * 2, &outs[k]);
   }
   lge_graph_destroy(U);
   return rc;
+}
+
+extern "C" int lge_estimate_many(lge_ctx *ctx, const lge_graph *const *graphs, const double *p,
+                                 const uint64_t *seed, int32_t count, const lge_opts *opts, lge_result *outs) {
+  if (!ctx || count < 0) return LGE_EINVAL;
+  if (count == 0) return LGE_OK;
+  if (!graphs || !p || !seed || !outs) return LGE_EINVAL;
+  std::vector<Job> jobs((size_t)count);
+  for (int32_t k = 0; k < count; ++k) {
+    if (!p_ok(p[k]) || !graphs[k] || graphs[k]->ctx != ctx) return LGE_EINVAL;
+    jobs[k] = Job{graphs[k], p[k], seed[k], 0, graphs[k]->m, -1, -1, 0};
+  }
+  int rc = lge_run_jobs(ctx, jobs.data(), count, opts);
+  if (rc != LGE_OK) return rc;
+  for (int32_t k = 0; k < count; ++k)
+    lge_finalize(graphs[k]->n, graphs[k]->m, p[k], seed[k], ctx->ws.h_acc + (int64_t)k * kAccSlots * 2, &outs[k]);
+  return LGE_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,92 @@
+// Host-runtime objects shared by the C ABI implementation (lge_host.cpp)
+// and the serving scheduler (lge_server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lge.h"
+#include "lge_internal.h"
+
+using lge::Bins;
+using lge::kNumClasses;
+using lge::RangeDesc;
+using lge::SlotDesc;
+
+struct lge_graph {
+  lge_ctx *ctx = nullptr;
+  int64_t n = 0, m = 0;
+  int32_t max_deg = 0;
+  const int32_t *row_ptr = nullptr;
+  const int32_t *col = nullptr;
+  int32_t *own_row_ptr = nullptr;
+  int32_t *own_col = nullptr;
+  uint64_t *edges = nullptr;
+  int64_t *vol2 = nullptr;
+  int64_t *hoff = nullptr;
+  uint32_t *htab = nullptr;
+  int64_t htab_len = 0;
+  int32_t *crank = nullptr;
+  uint32_t *codeg = nullptr;
+  int64_t hc = 0;
+  int32_t codeg_tau = 0;
+};
+
+struct Workspace {
+  int64_t cap_edges = 0;  // capacity of each class list
+  int32_t cap_slots = 0;
+  int32_t cap_ranges = 0;
+  int32_t *bin_slot[kNumClasses] = {};
+  int32_t *bin_a[kNumClasses] = {};
+  int32_t *bin_b[kNumClasses] = {};
+  unsigned long long *counters = nullptr;  // count[3], cursor[3], words[3], pad
+  SlotDesc *slots = nullptr;
+  RangeDesc *ranges = nullptr;
+  unsigned long long *acc = nullptr;  // cap_slots * kAccSlots * 2
+  int64_t *items = nullptr;           // cap_edges
+  int64_t *item_pref = nullptr;       // cap_edges
+  int64_t *tcap = nullptr;            // cap_edges
+  int64_t *tbase = nullptr;           // cap_edges
+  int32_t *tlist = nullptr;           // cap_tlist
+  int64_t cap_tlist = 0;
+  void *gacc = nullptr;               // cap_edges * gedge_bytes()
+  int64_t *scan_tmp = nullptr;
+  int64_t scan_tmp_len = 0;
+  // pinned host staging
+  SlotDesc *h_slots = nullptr;
+  RangeDesc *h_ranges = nullptr;
+  unsigned long long *h_acc = nullptr;
+  unsigned long long *h_counters = nullptr;
+};
+
+struct lge_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Workspace ws;
+  lge_opts opts{};
+  lge_timing timing{};
+  hipEvent_t ev[8] = {};
+  int num_cu = 256;
+};
+
+
+// One estimate job of a launch sequence: a canonical edge-id range of a
+// resident graph with its own p and seed.
+struct Job {
+  const lge_graph *g;
+  double p;
+  uint64_t seed;
+  int64_t e0, e1;       // canonical edge range (of the graph's own ids)
+  int64_t n_override;   // graph-level sizes for the closed forms (batch unions)
+  int64_t m_override;
+  int64_t eid_base;     // subtracted from edge ids before the sampler
+};
+
+// Runs sample -> bin -> count for the jobs in one launch sequence on the
+// ctx stream; on success the per-job accumulators (kAccSlots x {lo, hi}) are
+// in ctx->ws.h_acc.  Returns an LGE_* code.
+int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts);
+
+// Exact integers -> lge_result (C, Z, Q, exact counts, FP64 estimates,
+// variances, bounds) from one job's accumulators.
+void lge_finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned long long *acc, lge_result *out);

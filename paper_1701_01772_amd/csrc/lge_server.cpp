@@ -1,0 +1,320 @@
+// Serving loop: resident graphs, a request queue, footprint-bounded
+// continuous batching.
+//
+// One scheduler thread owns the ctx.  Every step it (1) admits queued
+// requests into free running slots, (2) hands every running request the next
+// chunk of its canonical edge-id range, the chunks together fitting the
+// step's HBM work-list budget, (3) runs all chunks in one launch sequence,
+// (4) adds each chunk's exact 128-bit accumulators into its request and
+// finalises requests whose range is exhausted.  Requests that arrive during
+// a step join at the next step, so their work overlaps on the device with
+// the requests already running.  Because the sampler is keyed by edge id
+// and the sums are exact integers, a request's result is independent of how
+// its range was chunked and of what ran beside it.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lge.h"
+#include "lge_internal.h"
+#include "lge_runtime.h"
+
+using namespace lge;
+
+namespace {
+
+// device bytes a step needs per canonical edge id it covers: three class
+// lists (3 x 12 B), global-class items, prefixes, T capacities and bases
+// (4 x 8 B) and per-edge partial sums (32 B), rounded up
+constexpr int64_t kStepBytesPerId = 128;
+
+struct Request {
+  uint64_t ticket = 0;
+  int32_t gid = 0;
+  double p = 1.0;
+  uint64_t seed = 0;
+  int64_t cursor = 0;  // next canonical edge id
+  int64_t m = 0;
+  bool canceled = false;
+  bool done = false;
+  int status = LGE_OK;
+  unsigned long long acc[kAccSlots * 2] = {};
+  lge_result result{};
+};
+
+void add_acc(unsigned long long *dst, const unsigned long long *src) {
+  for (int k = 0; k < kAccSlots; ++k) {
+    const unsigned long long lo = dst[2 * k] + src[2 * k];
+    const unsigned long long carry = lo < dst[2 * k] ? 1ull : 0ull;
+    dst[2 * k] = lo;
+    dst[2 * k + 1] += src[2 * k + 1] + carry;
+  }
+}
+
+}  // namespace
+
+struct lge_server {
+  lge_ctx *ctx = nullptr;
+  lge_server_cfg cfg{};
+  std::vector<const lge_graph *> graphs;
+  std::mutex mu;
+  std::condition_variable cv_work;  // scheduler waits for work
+  std::condition_variable cv_done;  // waiters wait for results
+  std::deque<Request *> queue;
+  std::vector<Request *> running;
+  std::unordered_map<uint64_t, Request *> all;
+  uint64_t next_ticket = 1;
+  size_t rotate = 0;
+  bool stop = false;
+  int waiters = 0;
+  lge_server_stats stats{};
+  std::thread th;
+
+  void finish(Request *r, int status) {
+    r->status = status;
+    r->done = true;
+    if (status == LGE_OK) ++stats.completed;
+    else if (status == LGE_ECANCELED) ++stats.canceled;
+  }
+
+  void loop() {
+    std::vector<Job> jobs;
+    std::vector<Request *> in_step;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
+        if (stop) return;
+        // admission: running slots free up as requests finish
+        while (!queue.empty() && (int32_t)running.size() < cfg.max_inflight) {
+          running.push_back(queue.front());
+          queue.pop_front();
+        }
+        // drop cancelled requests
+        bool any_done = false;
+        for (size_t i = 0; i < running.size();) {
+          if (running[i]->canceled) {
+            finish(running[i], LGE_ECANCELED);
+            running.erase(running.begin() + (long)i);
+            any_done = true;
+          } else {
+            ++i;
+          }
+        }
+        if (any_done) cv_done.notify_all();
+        if (running.empty()) continue;
+        // chunks for this step, starting at a rotating request
+        jobs.clear();
+        in_step.clear();
+        int64_t budget = std::max<int64_t>(cfg.hbm_budget_bytes / kStepBytesPerId, 1);
+        const size_t nr = running.size();
+        rotate %= nr;
+        for (size_t k = 0; k < nr && budget > 0; ++k) {
+          Request *r = running[(rotate + k) % nr];
+          const int64_t left = r->m - r->cursor;
+          const int64_t share = std::max<int64_t>(cfg.min_chunk_edges, budget / (int64_t)(nr - k));
+          const int64_t len = std::min(left, std::min(share, budget));
+          const lge_graph *g = graphs[(size_t)r->gid];
+          jobs.push_back(Job{g, r->p, r->seed, r->cursor, r->cursor + len, -1, -1, 0});
+          in_step.push_back(r);
+          budget -= std::max<int64_t>(len, 1);
+        }
+        rotate += 1;
+        ++stats.steps;
+      }
+      const auto t0 = std::chrono::steady_clock::now();
+      const int rc = lge_run_jobs(ctx, jobs.data(), (int)jobs.size(), nullptr);
+      const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        stats.busy_s += dt;
+        for (size_t j = 0; j < in_step.size(); ++j) {
+          Request *r = in_step[j];
+          if (rc != LGE_OK) {
+            finish(r, rc);
+          } else {
+            add_acc(r->acc, ctx->ws.h_acc + (int64_t)j * kAccSlots * 2);
+            r->cursor = jobs[j].e1;
+            if (r->canceled) {
+              finish(r, LGE_ECANCELED);
+            } else if (r->cursor >= r->m) {
+              const lge_graph *g = graphs[(size_t)r->gid];
+              lge_finalize(g->n, g->m, r->p, r->seed, r->acc, &r->result);
+              finish(r, LGE_OK);
+            }
+          }
+        }
+        running.erase(std::remove_if(running.begin(), running.end(), [](Request *r) { return r->done; }),
+                      running.end());
+        cv_done.notify_all();
+      }
+    }
+  }
+};
+
+extern "C" int lge_server_cfg_default(lge_server_cfg *c) {
+  if (!c) return LGE_EINVAL;
+  memset(c, 0, sizeof(*c));
+  c->max_inflight = 64;
+  c->queue_capacity = 4096;
+  c->hbm_budget_bytes = (int64_t)2 << 30;
+  c->min_chunk_edges = 1 << 16;
+  return LGE_OK;
+}
+
+extern "C" int lge_server_create(lge_ctx *ctx, const lge_server_cfg *cfg, lge_server **out) {
+  if (!ctx || !out) return LGE_EINVAL;
+  *out = nullptr;
+  lge_server_cfg c;
+  lge_server_cfg_default(&c);
+  if (cfg) {
+    if (cfg->max_inflight < 0 || cfg->queue_capacity < 0 || cfg->hbm_budget_bytes < 0 || cfg->min_chunk_edges < 0)
+      return LGE_EINVAL;
+    if (cfg->max_inflight) c.max_inflight = cfg->max_inflight;
+    if (cfg->queue_capacity) c.queue_capacity = cfg->queue_capacity;
+    if (cfg->hbm_budget_bytes) c.hbm_budget_bytes = cfg->hbm_budget_bytes;
+    if (cfg->min_chunk_edges) c.min_chunk_edges = cfg->min_chunk_edges;
+  }
+  if (c.hbm_budget_bytes < kStepBytesPerId) return LGE_EINVAL;
+  lge_server *s = new (std::nothrow) lge_server();
+  if (!s) return LGE_ENOMEM;
+  s->ctx = ctx;
+  s->cfg = c;
+  try {
+    s->th = std::thread([s] {
+      (void)hipSetDevice(s->ctx->device);
+      s->loop();
+    });
+  } catch (...) {
+    delete s;
+    return LGE_ENOMEM;
+  }
+  *out = s;
+  return LGE_OK;
+}
+
+extern "C" int lge_server_add_graph(lge_server *srv, const lge_graph *g, int32_t *gid) {
+  if (!srv || !g || !gid) return LGE_EINVAL;
+  if (g->ctx != srv->ctx) return LGE_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->stop) return LGE_ECANCELED;
+  *gid = (int32_t)srv->graphs.size();
+  srv->graphs.push_back(g);
+  return LGE_OK;
+}
+
+extern "C" int lge_submit(lge_server *srv, int32_t gid, double p, uint64_t seed, uint64_t *ticket) {
+  if (!(p > 0.0 && p <= 1.0)) return LGE_EINVAL;
+  if (!srv || !ticket) return LGE_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->stop) return LGE_ECANCELED;
+  if (gid < 0 || (size_t)gid >= srv->graphs.size()) return LGE_ENOTFOUND;
+  if ((int64_t)(srv->queue.size() + srv->running.size()) >= srv->cfg.queue_capacity) {
+    ++srv->stats.rejected;
+    return LGE_EBUSY;
+  }
+  Request *r = new (std::nothrow) Request();
+  if (!r) return LGE_ENOMEM;
+  r->ticket = srv->next_ticket++;
+  r->gid = gid;
+  r->p = p;
+  r->seed = seed;
+  r->m = srv->graphs[(size_t)gid]->m;
+  if (r->m == 0) {  // nothing to sample: result is immediate
+    const lge_graph *g = srv->graphs[(size_t)gid];
+    lge_finalize(g->n, g->m, p, seed, r->acc, &r->result);
+    srv->finish(r, LGE_OK);
+  } else {
+    srv->queue.push_back(r);
+  }
+  srv->all[r->ticket] = r;
+  ++srv->stats.submitted;
+  *ticket = r->ticket;
+  srv->cv_work.notify_one();
+  if (r->done) srv->cv_done.notify_all();
+  return LGE_OK;
+}
+
+extern "C" int lge_wait(lge_server *srv, uint64_t ticket, int64_t timeout_us, lge_result *out) {
+  if (!srv || !out) return LGE_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return LGE_ENOTFOUND;
+  Request *r = it->second;
+  ++srv->waiters;
+  bool ok = true;
+  if (timeout_us < 0) {
+    srv->cv_done.wait(lk, [&] { return r->done; });
+  } else {
+    ok = srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return r->done; });
+  }
+  --srv->waiters;
+  srv->cv_done.notify_all();
+  if (!ok) return LGE_ETIMEDOUT;
+  const int st = r->status;
+  if (st == LGE_OK) *out = r->result;
+  srv->all.erase(ticket);
+  delete r;
+  return st;
+}
+
+extern "C" int lge_cancel(lge_server *srv, uint64_t ticket) {
+  if (!srv) return LGE_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return LGE_ENOTFOUND;
+  Request *r = it->second;
+  if (r->done) return LGE_OK;
+  r->canceled = true;
+  auto q = std::find(srv->queue.begin(), srv->queue.end(), r);
+  if (q != srv->queue.end()) {  // never admitted: resolve now
+    srv->queue.erase(q);
+    srv->finish(r, LGE_ECANCELED);
+    srv->cv_done.notify_all();
+  }
+  srv->cv_work.notify_one();
+  return LGE_OK;
+}
+
+extern "C" int lge_server_get_stats(lge_server *srv, lge_server_stats *out) {
+  if (!srv || !out) return LGE_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *out = srv->stats;
+  out->queued = srv->queue.size();
+  out->running = srv->running.size();
+  return LGE_OK;
+}
+
+extern "C" int lge_server_destroy(lge_server *srv) {
+  if (!srv) return LGE_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    srv->cv_work.notify_all();
+  }
+  if (srv->th.joinable()) srv->th.join();  // the step in flight completes first
+  {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    for (auto &kv : srv->all)
+      if (!kv.second->done) srv->finish(kv.second, LGE_ECANCELED);
+    srv->queue.clear();
+    srv->running.clear();
+    srv->cv_done.notify_all();
+    // let threads blocked in lge_wait observe their result before freeing
+    srv->cv_done.wait(lk, [&] { return srv->waiters == 0; });
+    for (auto &kv : srv->all) delete kv.second;
+    srv->all.clear();
+  }
+  delete srv;
+  return LGE_OK;
+}

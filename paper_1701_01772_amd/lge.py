@@ -75,6 +75,18 @@ class Batch(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64), ("min_chunk_edges", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("running", ctypes.c_uint64), ("busy_s", ctypes.c_double)]
+
+
 _lib = None
 _VP = ctypes.c_void_p
 
@@ -117,8 +129,20 @@ def load():
                                 ctypes.POINTER(_VP)], ctypes.c_int),
         "lge_event_wait": ([_VP], ctypes.c_int),
         "lge_count_batch": ([_VP, ctypes.POINTER(Batch), ctypes.POINTER(Opts), ctypes.POINTER(Result)], ctypes.c_int),
+        "lge_estimate_many": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.POINTER(Opts),
+                               ctypes.POINTER(Result)], ctypes.c_int),
         "lge_last_timing": ([_VP, ctypes.POINTER(Timing)], ctypes.c_int),
         "lge_autotune": ([_VP, _VP, ctypes.c_double, ctypes.POINTER(Opts)], ctypes.c_int),
+        "lge_server_cfg_default": ([ctypes.POINTER(ServerCfg)], ctypes.c_int),
+        "lge_server_create": ([_VP, ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)], ctypes.c_int),
+        "lge_server_add_graph": ([_VP, _VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "lge_submit": ([_VP, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)],
+                       ctypes.c_int),
+        "lge_wait": ([_VP, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(Result)], ctypes.c_int),
+        "lge_cancel": ([_VP, ctypes.c_uint64], ctypes.c_int),
+        "lge_server_get_stats": ([_VP, ctypes.POINTER(ServerStats)], ctypes.c_int),
+        "lge_server_destroy": ([_VP], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -286,6 +310,19 @@ def lge_count_batch(ctx, graphs, p, seed, flags: int = 0, opts: Opts | None = No
     return [result_dict(outs[i]) for i in range(G)]
 
 
+def lge_estimate_many(ctx, graphs, p, seed, opts: Opts | None = None):
+    """graphs: list of graph handles on ctx; p, seed: scalars or per-graph lists."""
+    G = len(graphs)
+    arr = (_VP * max(G, 1))(*graphs)
+    ps = np.ascontiguousarray(p if np.ndim(p) else [p] * G, dtype=np.float64)
+    ss = np.ascontiguousarray(seed if np.ndim(seed) else [seed] * G, dtype=np.uint64)
+    outs = (Result * max(G, 1))()
+    _check(load().lge_estimate_many(ctx, arr, ps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ss.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), G,
+                                    ctypes.byref(opts) if opts is not None else None, outs), "lge_estimate_many")
+    return [result_dict(outs[i]) for i in range(G)]
+
+
 def lge_last_timing(ctx) -> dict:
     t = Timing()
     _check(load().lge_last_timing(ctx, ctypes.byref(t)), "lge_last_timing")
@@ -299,6 +336,59 @@ def lge_autotune(ctx, g, p: float) -> Opts:
     o = Opts()
     _check(load().lge_autotune(ctx, g, float(p), ctypes.byref(o)), "lge_autotune")
     return o
+
+
+def lge_server_cfg_default() -> ServerCfg:
+    c = ServerCfg()
+    _check(load().lge_server_cfg_default(ctypes.byref(c)), "lge_server_cfg_default")
+    return c
+
+
+def lge_server_create(ctx, cfg: ServerCfg | None = None):
+    s = _VP()
+    _check(load().lge_server_create(ctx, ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(s)),
+           "lge_server_create")
+    return s
+
+
+def lge_server_add_graph(srv, g) -> int:
+    gid = ctypes.c_int32()
+    _check(load().lge_server_add_graph(srv, g, ctypes.byref(gid)), "lge_server_add_graph")
+    return gid.value
+
+
+def lge_submit(srv, gid: int, p: float, seed: int) -> int:
+    """Returns the ticket; raises LgeError (e.g. LGE_EBUSY)."""
+    t = ctypes.c_uint64()
+    _check(load().lge_submit(srv, int(gid), float(p), int(seed), ctypes.byref(t)), "lge_submit")
+    return t.value
+
+
+def lge_wait(srv, ticket: int, timeout_us: int = -1) -> dict:
+    r = Result()
+    _check(load().lge_wait(srv, int(ticket), int(timeout_us), ctypes.byref(r)), "lge_wait")
+    return result_dict(r)
+
+
+def lge_wait_rc(srv, ticket: int, timeout_us: int = -1):
+    """(code, result-or-None) without raising."""
+    r = Result()
+    rc = load().lge_wait(srv, int(ticket), int(timeout_us), ctypes.byref(r))
+    return rc, (result_dict(r) if rc == LGE_OK else None)
+
+
+def lge_cancel(srv, ticket: int) -> int:
+    return load().lge_cancel(srv, int(ticket))
+
+
+def lge_server_get_stats(srv) -> dict:
+    st = ServerStats()
+    _check(load().lge_server_get_stats(srv, ctypes.byref(st)), "lge_server_get_stats")
+    return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+
+def lge_server_destroy(srv):
+    _check(load().lge_server_destroy(srv), "lge_server_destroy")
 
 
 class Context:

@@ -228,3 +228,21 @@ def test_full_size_chung_lu(ctx, p):
     rng = np.random.default_rng(5)
     starts = rng.integers(0, g.m - 4000, 3)
     _full_size_checks(ctx, g, p, 2024, [(int(s), int(s) + 4000) for s in starts])
+
+
+def test_estimate_many_equals_singles(ctx):
+    graphs = inputs.batch_graphs(count=16, seed=91, n_lo=30, n_hi=2500)
+    hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col) for g in graphs]
+    try:
+        ps = [1.0 if i % 2 else 0.35 for i in range(len(hs))]
+        seeds = [7 + 3 * i for i in range(len(hs))]
+        _say("estimate_many over %d resident graphs" % len(hs))
+        many = lge.lge_estimate_many(ctx, hs, ps, seeds)
+        for g, h, out, p, s in zip(graphs, hs, many, ps, seeds):
+            single = lge.lge_estimate(ctx, h, p, s)
+            for k in ("sampled", "csum", "zsum", "qsum", "exact", "estimate", "variance"):
+                assert out[k] == single[k], k
+            assert_parity(out, oracle.estimate(g.row_ptr, g.col, p, s), "many n=%d" % g.n)
+    finally:
+        for h in hs:
+            lge.lge_graph_destroy(h)
