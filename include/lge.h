@@ -251,9 +251,10 @@ LGE_API int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *o
  * server exists) and runs one scheduler thread.  Graphs are added once and
  * stay resident.  Requests (graph, p, seed) queue FIFO; up to max_inflight of
  * them run at once.  Every step the scheduler gives each running request the
- * next chunk of its canonical edge-id range so that the step's device work
- * lists fit hbm_budget_bytes (at least min_chunk_edges per chunk when the
- * budget allows), runs all chunks in one launch sequence, and finalises the
+ * next chunk of its canonical edge-id range: chunks share the step's work
+ * budget (measured work rate x target_step_us) equally, and together fit the
+ * step's device work lists into hbm_budget_bytes (the admission bound by HBM
+ * footprint); it runs all chunks in one launch sequence and finalises the
  * requests whose range is done.  Requests arriving meanwhile join at the next
  * step (continuous batching).  A request's result equals lge_estimate on the
  * same (graph, p, seed): exact sums do not depend on chunking or neighbours.
@@ -264,8 +265,10 @@ typedef struct {
   int32_t max_inflight;     /* requests running at once (default 64) */
   int32_t queue_capacity;   /* queued + running requests before LGE_EBUSY (default 4096) */
   int64_t hbm_budget_bytes; /* device work-list budget of one step (default 2 GiB) */
-  int64_t min_chunk_edges;  /* smallest edge-id chunk per request and step (default 65536) */
-  int32_t reserved[4];
+  int64_t min_chunk_edges;  /* smallest edge-id chunk per request and step (default 4096) */
+  int64_t target_step_us;   /* aimed duration of one step (default 20000); chunks are sized by each
+                               graph's per-edge work estimate and the measured work rate */
+  int32_t reserved[2];
 } lge_server_cfg;
 
 typedef struct {

@@ -397,6 +397,14 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   }
   if (g->m > 0) e = launch_graph_edges(g->row_ptr, g->col, up, base, n, g->edges, s);
   if (e == hipSuccess) e = launch_graph_vol2(g->row_ptr, g->col, n, g->vol2, s);
+  unsigned long long work_sum = 0;
+  if (e == hipSuccess && g->m > 0) {
+    e = hipMemsetAsync(tmp, 0, sizeof(int64_t), s);
+    if (e == hipSuccess) e = launch_graph_work(g->row_ptr, g->edges, g->vol2, g->m, (unsigned long long *)tmp, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&work_sum, tmp, sizeof(work_sum), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    g->work_per_id = g->m > 0 ? (double)work_sum / (double)g->m : 0.0;
+  }
   // hub tables
   if (e == hipSuccess) e = launch_hub_sizes(g->row_ptr, n, cnt, s);
   if (e == hipSuccess) e = launch_scan_i64(cnt, g->hoff, n, tmp, s);

@@ -30,6 +30,7 @@ struct lge_graph {
   uint32_t *codeg = nullptr;
   int64_t hc = 0;
   int32_t codeg_tau = 0;
+  double work_per_id = 0.0;  // scheduling weight per canonical edge id
 };
 
 struct Workspace {

@@ -75,6 +75,7 @@ struct lge_server {
   std::unordered_map<uint64_t, Request *> all;
   uint64_t next_ticket = 1;
   size_t rotate = 0;
+  double rate = 5e8;  // work units per second, updated after every step
   bool stop = false;
   int waiters = 0;
   lge_server_stats stats{};
@@ -86,6 +87,8 @@ struct lge_server {
     if (status == LGE_OK) ++stats.completed;
     else if (status == LGE_ECANCELED) ++stats.canceled;
   }
+
+  double step_work = 0.0;
 
   void loop() {
     std::vector<Job> jobs;
@@ -116,18 +119,26 @@ struct lge_server {
         // chunks for this step, starting at a rotating request
         jobs.clear();
         in_step.clear();
-        int64_t budget = std::max<int64_t>(cfg.hbm_budget_bytes / kStepBytesPerId, 1);
+        step_work = 0.0;
+        int64_t budget = std::max<int64_t>(cfg.hbm_budget_bytes / kStepBytesPerId, 1);  // edge ids
+        double wbudget = std::max(rate * (double)cfg.target_step_us * 1e-6, 1.0);       // work units
         const size_t nr = running.size();
         rotate %= nr;
         for (size_t k = 0; k < nr && budget > 0; ++k) {
           Request *r = running[(rotate + k) % nr];
-          const int64_t left = r->m - r->cursor;
-          const int64_t share = std::max<int64_t>(cfg.min_chunk_edges, budget / (int64_t)(nr - k));
-          const int64_t len = std::min(left, std::min(share, budget));
           const lge_graph *g = graphs[(size_t)r->gid];
+          const int64_t left = r->m - r->cursor;
+          // expected work of one edge id of this request
+          const double unit = std::max(r->p * g->work_per_id, 1e-9);
+          const double wshare = wbudget / (double)(nr - k);
+          const int64_t by_work = (int64_t)std::min(wshare / unit, 9.0e15);
+          const int64_t want = std::max<int64_t>(cfg.min_chunk_edges, by_work);
+          const int64_t len = std::min(left, std::min(want, budget));
           jobs.push_back(Job{g, r->p, r->seed, r->cursor, r->cursor + len, -1, -1, 0});
           in_step.push_back(r);
           budget -= std::max<int64_t>(len, 1);
+          wbudget -= std::min(wbudget, (double)len * unit);
+          step_work += (double)len * unit;
         }
         rotate += 1;
         ++stats.steps;
@@ -138,6 +149,8 @@ struct lge_server {
       {
         std::lock_guard<std::mutex> lk(mu);
         stats.busy_s += dt;
+        // work rate of the steps that were long enough to measure it
+        if (rc == LGE_OK && dt > 2e-3 && step_work > 0) rate = 0.7 * rate + 0.3 * (step_work / dt);
         for (size_t j = 0; j < in_step.size(); ++j) {
           Request *r = in_step[j];
           if (rc != LGE_OK) {
@@ -168,7 +181,8 @@ extern "C" int lge_server_cfg_default(lge_server_cfg *c) {
   c->max_inflight = 64;
   c->queue_capacity = 4096;
   c->hbm_budget_bytes = (int64_t)2 << 30;
-  c->min_chunk_edges = 1 << 16;
+  c->min_chunk_edges = 4096;
+  c->target_step_us = 20000;
   return LGE_OK;
 }
 
@@ -178,8 +192,10 @@ extern "C" int lge_server_create(lge_ctx *ctx, const lge_server_cfg *cfg, lge_se
   lge_server_cfg c;
   lge_server_cfg_default(&c);
   if (cfg) {
-    if (cfg->max_inflight < 0 || cfg->queue_capacity < 0 || cfg->hbm_budget_bytes < 0 || cfg->min_chunk_edges < 0)
+    if (cfg->max_inflight < 0 || cfg->queue_capacity < 0 || cfg->hbm_budget_bytes < 0 || cfg->min_chunk_edges < 0 ||
+        cfg->target_step_us < 0)
       return LGE_EINVAL;
+    if (cfg->target_step_us) c.target_step_us = cfg->target_step_us;
     if (cfg->max_inflight) c.max_inflight = cfg->max_inflight;
     if (cfg->queue_capacity) c.queue_capacity = cfg->queue_capacity;
     if (cfg->hbm_budget_bytes) c.hbm_budget_bytes = cfg->hbm_budget_bytes;
