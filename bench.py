@@ -258,6 +258,44 @@ def bench_serve(args):
     }
 
 
+def bench_sweep(args):
+    """Times option settings on one resident workload (results never depend
+    on them); prints one line per setting to stderr and a JSON summary."""
+    import torch
+    from paper_1701_01772_amd import lge
+    p = args.p if args.p is not None else 0.1
+    g, wname = make_workload(args.workload)
+    ctx = lge.lge_open(0)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    settings = []
+    for spec in args.sweep.split(";"):
+        kw = dict(kv.split("=") for kv in spec.split(",") if kv)
+        settings.append({k: int(v) for k, v in kw.items()})
+    rows = []
+    ref = None
+    for kw in settings:
+        o = lge.make_opts(**kw)
+        lge.lge_estimate(ctx, h, p, args.seed, o)
+        tim = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            r = lge.lge_estimate(ctx, h, p, args.seed + i, o)
+            tim.append(lge.lge_last_timing(ctx))
+            if i == 0:
+                key = (r["sampled"], tuple(r["csum"]), tuple(r["qsum"]))
+                ref = ref or key
+                assert key == ref, "results changed with options %s" % kw
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        dev, roof = roofline_of(tim, args.workload)
+        rows.append({"opts": kw, "ms_per_step": 1e3 * dt, "device_ms": dev})
+        log("%-60s %8.2f ms/step  global %8.2f  block %7.2f  wave %6.2f" % (
+            kw, 1e3 * dt, dev["count_global"], dev["count_block"], dev["count_wave"]))
+    lge.lge_graph_destroy(h)
+    lge.lge_close(ctx)
+    return {"sweep": rows, "workload": wname, "p": p}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +307,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-m-hi", type=float, default=2e6)
+    ap.add_argument("--sweep", default=None,
+                    help="';'-separated option settings, e.g. 'flags=0;flags=1,global_chunk=128'")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale memory counters")
@@ -279,6 +319,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.sweep:
+        print(json.dumps(bench_sweep(args)))
+        return
     if args.workload == "batch":
         print(json.dumps(bench_batch(args)))
         return

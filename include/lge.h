@@ -122,13 +122,24 @@ typedef struct {
  *                 (0 disables lookups; default 4)
  *  grid_per_cu    persistent workgroups per compute unit for each counting
  *                 kernel (0 = library default)
+ *  global_chunk   Gamma(a) positions per work item of the split class
+ *                 (1..512, default 256)
+ *  flags          LGE_OPT_SORT_HUB: order split-class edges by their
+ *                 table-side endpoint so consecutive work items share its
+ *                 hub table; LGE_OPT_XCD_LOCAL: each XCD (workgroups
+ *                 blockIdx % 8) takes work items from its own contiguous
+ *                 segment first, so each L2 sees a fraction of the tables
  */
+#define LGE_OPT_SORT_HUB 1u
+#define LGE_OPT_XCD_LOCAL 2u
 typedef struct {
   int32_t wave_max_deg;
   int32_t block_max_deg;
   int32_t probe_ratio;
   int32_t grid_per_cu;
-  int32_t reserved[4];
+  int32_t global_chunk;
+  uint32_t flags;
+  int32_t reserved[2];
 } lge_opts;
 
 /* Device-time breakdown of the last estimate/batch call on a ctx. */

@@ -101,6 +101,8 @@ extern "C" int lge_opts_default(lge_opts *o) {
   o->block_max_deg = kHubDeg;
   o->probe_ratio = 4;
   o->grid_per_cu = 0;
+  o->global_chunk = 256;
+  o->flags = 0;
   return LGE_OK;
 }
 
@@ -119,7 +121,8 @@ static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
   c.grid_block = cu * (per_cu ? per_cu : 4);
   c.grid_global = cu * (per_cu ? per_cu : 4);
   c.grid_sample = cu * 16;
-  c.global_chunk = 256;
+  c.global_chunk = o->global_chunk > 0 ? std::min<int32_t>(o->global_chunk, kGlobalChunkMax) : d.global_chunk;
+  c.flags = o->flags;
   return c;
 }
 
@@ -145,6 +148,12 @@ static void ws_free(Workspace &w) {
   if (w.gacc) (void)hipFree(w.gacc);
   w.gacc = nullptr;
   dev_free(w.scan_tmp);
+  dev_free(w.sort_slot);
+  dev_free(w.sort_a);
+  dev_free(w.sort_b);
+  dev_free(w.sort_hist);
+  dev_free(w.sort_off);
+  dev_free(w.sort_tmp);
   if (w.h_slots) (void)hipHostFree(w.h_slots);
   if (w.h_ranges) (void)hipHostFree(w.h_ranges);
   if (w.h_acc) (void)hipHostFree(w.h_acc);
@@ -180,8 +189,10 @@ extern "C" int lge_open(int device, lge_ctx **out) {
     }
   }
   Workspace &w = ctx->ws;
-  if (dev_alloc(&w.counters, 16) != LGE_OK ||
-      hipHostMalloc((void **)&w.h_counters, 16 * sizeof(unsigned long long), 0) != hipSuccess) {
+  if (dev_alloc(&w.counters, 32) != LGE_OK ||
+      hipHostMalloc((void **)&w.h_counters, 32 * sizeof(unsigned long long), 0) != hipSuccess ||
+      dev_alloc(&w.sort_hist, kSortKeys) != LGE_OK || dev_alloc(&w.sort_off, kSortKeys) != LGE_OK ||
+      dev_alloc(&w.sort_tmp, scan_tmp_size(kSortKeys)) != LGE_OK) {
     lge_close(ctx);
     return LGE_ENOMEM;
   }
@@ -218,6 +229,9 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     if (w.gacc) (void)hipFree(w.gacc);
     w.gacc = nullptr;
     dev_free(w.scan_tmp);
+    dev_free(w.sort_slot);
+    dev_free(w.sort_a);
+    dev_free(w.sort_b);
     w.cap_edges = 0;
     for (int c = 0; c < kNumClasses; ++c) {
       int rc;
@@ -236,6 +250,9 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     }
     w.scan_tmp_len = scan_tmp_size(cap);
     if ((rc = dev_alloc(&w.scan_tmp, w.scan_tmp_len)) != LGE_OK) return rc;
+    if ((rc = dev_alloc(&w.sort_slot, cap)) != LGE_OK) return rc;
+    if ((rc = dev_alloc(&w.sort_a, cap)) != LGE_OK) return rc;
+    if ((rc = dev_alloc(&w.sort_b, cap)) != LGE_OK) return rc;
     w.cap_edges = cap;
   }
   if (slots > w.cap_slots) {
@@ -727,6 +744,7 @@ static Bins make_bins(Workspace &w) {
   b.count = w.counters;
   b.cursor = w.counters + 3;
   b.words = w.counters + 6;
+  b.xcd_cursor = w.counters + 16;
   b.cap = w.cap_edges;
   return b;
 }
@@ -772,7 +790,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   hipEvent_t *ev = ctx->ev;
   LGE_HIP(hipMemcpyAsync(w.slots, w.h_slots, (size_t)njobs * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
   LGE_HIP(hipMemcpyAsync(w.ranges, w.h_ranges, (size_t)njobs * sizeof(RangeDesc), hipMemcpyHostToDevice, s));
-  LGE_HIP(launch_zero_u64(w.counters, 16, s));
+  LGE_HIP(launch_zero_u64(w.counters, 32, s));
   LGE_HIP(launch_zero_u64(w.acc, (int64_t)njobs * kAccSlots * 2, s));
   Bins bins = make_bins(w);
   LGE_HIP(hipEventRecord(ev[0], s));
@@ -788,6 +806,13 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   LGE_HIP(hipEventRecord(ev[4], s));
   if (ng == 0) LGE_HIP(hipEventRecord(ev[6], s));
   if (ng > 0) {
+    if (cfg.flags & kOptSortHub) {
+      LGE_HIP(launch_sort_global(w.slots, bins, ng, w.sort_slot, w.sort_a, w.sort_b, w.sort_hist, w.sort_off,
+                                 w.sort_tmp, s));
+      bins.slot[kClassGlobal] = w.sort_slot;
+      bins.a[kClassGlobal] = w.sort_a;
+      bins.b[kClassGlobal] = w.sort_b;
+    }
     LGE_HIP(launch_global_prep(w.slots, bins, ng, cfg.global_chunk, w.items, w.tcap, w.gacc, s));
     LGE_HIP(launch_scan_i64(w.items, w.item_pref, ng, w.scan_tmp, s));
     LGE_HIP(launch_scan_i64(w.tcap, w.tbase, ng, w.scan_tmp, s));

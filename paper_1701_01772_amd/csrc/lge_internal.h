@@ -23,7 +23,7 @@ constexpr int kAccSlots = 32;  // padded; one slot = 32 x (lo, hi) u64 = 512 B
 // counted entirely from LDS tables.
 constexpr int kHubDeg = 1024;
 // Largest number of Gamma(a) positions handled by one global-class work item.
-constexpr int kGlobalChunkMax = 1024;
+constexpr int kGlobalChunkMax = 512;
 // Vertex ids must stay below 2^29: the kernels keep three tag bits above them.
 constexpr int64_t kMaxVertices = (int64_t)1 << 29;
 
@@ -63,6 +63,7 @@ struct Bins {
   unsigned long long *count;   // kNumClasses counters
   unsigned long long *cursor;  // kNumClasses work-queue cursors
   unsigned long long *words;   // kNumClasses counters of 4-byte words read
+  unsigned long long *xcd_cursor;  // kXcds cursors of the XCD-local split-class queue
   int64_t cap;
 };
 
@@ -73,7 +74,15 @@ struct KernelCfg {
   int32_t grid_wave, grid_block, grid_global;
   int32_t grid_sample;
   int32_t global_chunk;  // Gamma(a) positions per global-class work item
+  uint32_t flags;        // LGE_OPT_* bits
 };
+
+// split-class edge ordering: key = rank of the table-side endpoint in the
+// co-degree table, kSortKeys - 1 for unranked endpoints
+constexpr int kSortKeys = 16385;
+constexpr int kXcds = 8;
+constexpr uint32_t kOptSortHub = 1u;
+constexpr uint32_t kOptXcdLocal = 2u;
 
 // ---- launchers (lge_kernels.hip) ----
 hipError_t launch_graph_validate(const int32_t *row_ptr, const int32_t *col, int64_t n, int *err,
@@ -111,6 +120,10 @@ hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, 
 hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                   const int64_t *item_cnt, const int64_t *tbase, int32_t *tlist, void *gacc,
                                   KernelCfg cfg, hipStream_t s);
+// counting sort of the split-class edges by key (see kSortKeys) into
+// (slot2, a2, b2); hist, off: kSortKeys int64 each; tmp: scan scratch
+hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t *slot2, int32_t *a2,
+                              int32_t *b2, int64_t *hist, int64_t *off, int64_t *tmp, hipStream_t s);
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                const int64_t *item_cnt, const int64_t *tbase, const int32_t *tlist, void *gacc,
                                KernelCfg cfg, hipStream_t s);

@@ -952,15 +952,35 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
   }
 }
 
+// Split-class counting in aggregate form.  With
+//   cbx(w) = |Gamma(w) n (Gamma(b) \ {a})|   for w in S_a,
+//   cax(x) = |Gamma(x) n (Gamma(a) \ {b})|   for x in T_e,
+//   degT(x) = |Gamma(x) n T_e|              for x in T_e,
+// the edges between S_a and S_b number
+//   cyc = sum_{w in S_a} cbx(w) - sum_{x in T_e} cax(x) + sum_{x in T_e} degT(x)
+// (each w in S_a is adjacent to a, and a's other neighbours split into T_e and
+// S_a), and the edges inside T_e number k4 = sum degT / 2.  cbx and cax are
+// pair co-degrees: one table read when both vertices are ranked.  Per vertex
+// the kernel picks the cheapest way to get its terms:
+//   w in S_a : codeg(w,b) - 1 | walk Gamma(w) testing Gamma(b) | look Gamma(b) up in Gamma(w)
+//   x in T_e : walk Gamma(x) testing T_e (and Gamma(a) when cax is not in the
+//              table) | look T_e (and Gamma(a)) up in Gamma(x)
+// Costs are in quarter units of one coalesced load.
+__device__ __forceinline__ int64_t lookup_cost(int dw) {
+  return dw > kHubDeg ? 16 : 8ll * (ceil_log2((uint32_t)dw + 1u) + 1);
+}
+
 __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
     const int64_t *__restrict__ item_cnt, const int64_t *__restrict__ tbase, const int32_t *__restrict__ tlist,
-    GEdge *gacc, unsigned long long *cursor, unsigned long long *words_out, int32_t probe_ratio, int32_t chunk) {
+    GEdge *gacc, unsigned long long *cursor, unsigned long long *xcd_cursor, unsigned long long *words_out,
+    int32_t probe_ratio, int32_t chunk, uint32_t flags) {
   constexpr int NT = kGlobalNT;
   constexpr int CH = kGlobalChunkMax;
   constexpr int HB = 2 * kHubDeg;
   constexpr int HT = 2 * kTHashCap;
+  __shared__ uint32_t hA[HB];
   __shared__ uint32_t hB[HB];
   __shared__ uint32_t hT[HT];
   __shared__ uint32_t wl_v[CH];
@@ -978,13 +998,36 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   unsigned long long words = 0;
   const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
+  // XCD-local queue: workgroups of XCD x = blockIdx % kXcds drain segment x
+  // of the item range first, then the following segments
+  const bool xcd_local = (flags & kOptXcdLocal) != 0;
+  const int my_seg = (int)(blockIdx.x % kXcds);
+  int seg_off = 0;
 
   for (;;) {
-    if (tid == 0) sh_item = (long long)atomicAdd(cursor, 1ull);
+    if (tid == 0) {
+      long long it = -1;
+      if (!xcd_local) {
+        it = (long long)atomicAdd(cursor, 1ull);
+        if (it >= total_items) it = -1;
+      } else {
+        while (seg_off < kXcds) {
+          const int sg = (my_seg + seg_off) % kXcds;
+          const int64_t lo = total_items * sg / kXcds, hi = total_items * (sg + 1) / kXcds;
+          const long long k = (long long)atomicAdd(&xcd_cursor[sg], 1ull);
+          if (lo + k < hi) {
+            it = lo + k;
+            break;
+          }
+          ++seg_off;
+        }
+      }
+      sh_item = it;
+    }
     __syncthreads();
     const int64_t item = sh_item;
     __syncthreads();
-    if (item >= total_items) break;
+    if (item < 0) break;
     const int64_t e = find_item_edge(item_pref, nedges, item);
     const int64_t c = item - item_pref[e];
     const int32_t slot = bslot[e];
@@ -997,7 +1040,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const bool ha = da > kHubDeg, hb = db > kHubDeg;
     const int blg = table_log(db), alg = table_log(da);
     const uint32_t *__restrict__ btab = hb ? S.htab + S.hoff[b] : hB;
-    const uint32_t *__restrict__ atab = ha ? S.htab + S.hoff[a] : nullptr;
+    const uint32_t *__restrict__ atab = ha ? S.htab + S.hoff[a] : hA;
     const int t = (int)gacc[e].t;
     const int32_t *__restrict__ T = tlist + tbase[e];
     const bool tl = t <= kTHashCap;
@@ -1005,6 +1048,8 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     if (tid < 4) sh_cnt[tid] = 0;
     if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
+    if (!ha)
+      for (int i = tid; i < (1 << alg); i += NT) hA[i] = kEmpty;
     if (tl)
       for (int i = tid; i < (1 << tlg); i += NT) hT[i] = kEmpty;
     __syncthreads();
@@ -1015,22 +1060,27 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       }
       words += (unsigned long long)db;
     }
+    if (!ha) {
+      for (int i = tid; i < da; i += NT) {
+        const int32_t x = col[abeg + i];
+        if (x != b) lds_insert(hA, alg, (uint32_t)x);
+      }
+      words += (unsigned long long)da;
+    }
     if (tl) {
       for (int i = tid; i < t; i += NT) lds_insert(hT, tlg, (uint32_t)T[i]);
       words += (unsigned long long)t;
     }
     __syncthreads();
-    // membership helpers.  inB: r in Gamma(b) \ {a} (a's own id excluded
-    // by the callers where b's hub table holds it); inT_b: for r already in
-    // Gamma(b), r in T_e; inT: any r.
-    auto inB = [&](uint32_t r) -> bool { return table_find(btab, blg, r) >= 0; };
-    auto inT_b = [&](uint32_t r) -> bool {
-      return tl ? table_find(hT, tlg, r) >= 0 : table_find(atab, alg, r) >= 0;
-    };
+    // r in Gamma(b) \ {a}; r in Gamma(a) \ {b}; r in T_e (the LDS tables
+    // exclude a and b already, the hub tables do not)
+    auto inBx = [&](uint32_t r) -> bool { return r != (uint32_t)a && table_find(btab, blg, r) >= 0; };
+    auto inAx = [&](uint32_t r) -> bool { return r != (uint32_t)b && table_find(atab, alg, r) >= 0; };
     auto inT = [&](uint32_t r) -> bool {
-      return tl ? table_find(hT, tlg, r) >= 0 : (table_find(atab, alg, r) >= 0 && inB(r));
+      return tl ? table_find(hT, tlg, r) >= 0 : (table_find(atab, alg, r) >= 0 && table_find(btab, blg, r) >= 0);
     };
-    // this chunk's w
+    const int64_t mB = hb ? 16 : 4, mA = ha ? 16 : 4, mT = tl ? 4 : 32;
+    // this chunk's vertices of Gamma(a) \ {b}
     const int p0 = (int)(c * chunk);
     const int p1 = p0 + chunk < da ? p0 + chunk : da;
     for (int base = p0; base < p1; base += NT) {
@@ -1038,7 +1088,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       bool valid = i < p1;
       const int32_t x = valid ? col[abeg + i] : -1;
       valid = valid && x != b;
-      const bool isT = valid && inB((uint32_t)x);  // x in Gamma(a): in T_e iff in Gamma(b)
+      const bool isT = valid && inBx((uint32_t)x);  // x in Gamma(a): in T_e iff in Gamma(b)
       const uint64_t vm = __ballot(valid);
       int pos0 = 0;
       if (lane == 0 && vm) pos0 = atomicAdd(&sh_cnt[0], __popcll(vm));
@@ -1058,18 +1108,55 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     for (int i = tid; i < L; i += NT) {
       const uint32_t v = wl_v[i];
       const bool isT = (v & kTag) != 0;
+      const int32_t w = (int32_t)(v & kIdMask);
+      const int dw = wl_deg[i];
+      const bool may_look = probe_ratio > 0;
+      const int64_t look = may_look ? ((4 + lookup_cost(dw)) * probe_ratio) / 4 : 0;
       uint32_t cdeg = 0;
-      const bool cok = !isT && codeg_pair(S, (int32_t)(v & kIdMask), b, &cdeg);
-      const WMode md = choose_mode(isT, wl_deg[i], t, db, cok, cdeg, probe_ratio);
-      wl_v[i] = v | md.flags;
-      wl_pref[i] = md.units;
-      cyc_base += md.base;
+      const bool cok = probe_ratio > 0 && codeg_pair(S, w, isT ? a : b, &cdeg);
+      uint32_t fl = 0;
+      int32_t units;
+      if (!isT) {
+        if (cok) {
+          fl = kModeCodeg;
+          units = 0;
+          cyc_base += (long long)cdeg - 1;
+        } else {
+          const int64_t scan = (int64_t)dw * (4 + mB), lk = (int64_t)db * look;
+          if (may_look && lk < scan) {
+            fl = kModeLook;
+            units = db;
+          } else {
+            units = dw;
+          }
+        }
+      } else {
+        int64_t scan, lk;
+        if (cok) {
+          fl = kModeCodeg;
+          cyc_base -= (long long)cdeg - 1;
+          scan = (int64_t)dw * (4 + mT);
+          lk = (int64_t)t * look;
+        } else {
+          scan = (int64_t)dw * (4 + mT + mA);
+          lk = (int64_t)(t + da) * look;
+        }
+        if (may_look && lk < scan) {
+          fl |= kModeLook;
+          units = cok ? t : t + da;
+        } else {
+          units = dw;
+        }
+      }
+      wl_v[i] = v | fl;
+      wl_pref[i] = units;
     }
     __syncthreads();
     const int32_t total = block_scan_lds<NT>(wl_pref, L, carry_sh);
     if (tid == 0) wl_pref[L] = total;
     __syncthreads();
-    unsigned long long k4 = 0, cyc = (unsigned long long)cyc_base;
+    unsigned long long kt = 0;                              // sum of degT over T_e members
+    unsigned long long cs = (unsigned long long)cyc_base;  // sum cbx - sum cax (mod 2^64)
     uint32_t steps = 0;
     int cur = 0;
     for (int base = 0; base < total; base += NT) {
@@ -1088,42 +1175,35 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
         const int off = idx - wl_pref[l2];
         const bool isT = (v & kTag) != 0;
         const int32_t w = (int32_t)(v & kIdMask);
-        if (v & kModeLook) {
-          int32_t x;
-          bool keep = true;
-          if (isT || (v & kModeCodeg)) {
-            x = T[off];
-          } else {
-            x = col[bbeg + off];  // S_b candidate from Gamma(b)
-            keep = x != a && !inT_b((uint32_t)x);
+        ++steps;
+        if (!isT) {
+          if (v & kModeLook) {  // cbx by looking Gamma(b) up in Gamma(w)
+            const int32_t x = col[bbeg + off];
+            if (x != a && w_has(S, w, wl_beg[l2], wl_deg[l2], x, &steps)) ++cs;
+          } else {  // cbx by walking Gamma(w)
+            if (inBx((uint32_t)col[wl_beg[l2] + off])) ++cs;
           }
-          ++steps;
-          if (keep && w_has(S, w, wl_beg[l2], wl_deg[l2], x, &steps)) {
-            if (isT)
-              ++k4;
-            else if (v & kModeCodeg)
-              --cyc;
-            else
-              ++cyc;
+        } else if (v & kModeLook) {
+          if (off < t) {  // degT: members of T_e in Gamma(w)
+            if (w_has(S, w, wl_beg[l2], wl_deg[l2], T[off], &steps)) ++kt;
+          } else {  // cax: members of Gamma(a) \ {b} in Gamma(w)
+            const int32_t y = col[abeg + (off - t)];
+            if (y != b && w_has(S, w, wl_beg[l2], wl_deg[l2], y, &steps)) --cs;
           }
-        } else {
-          const int32_t r = col[wl_beg[l2] + off];
-          ++steps;
-          if (isT) {
-            if (inT((uint32_t)r)) ++k4;
-          } else if (r != a && inB((uint32_t)r) && !inT_b((uint32_t)r)) {
-            ++cyc;
-          }
+        } else {  // walk Gamma(w): degT, and cax unless it came from the table
+          const uint32_t r = (uint32_t)col[wl_beg[l2] + off];
+          if (inT(r)) ++kt;
+          if (!(v & kModeCodeg) && inAx(r)) --cs;
         }
       }
     }
     words += steps + 2ull * (unsigned long long)L;
-    k4 = block_sum_u64<NT>(k4, red);
-    cyc = block_sum_u64<NT>(cyc, red);
+    kt = block_sum_u64<NT>(kt, red);
+    cs = block_sum_u64<NT>(cs, red);
     if (tid == 0) {
       GEdge *g = gacc + e;
-      if (k4) atomicAdd(&g->k4, k4);
-      if (cyc) atomicAdd(&g->cyc, cyc);
+      if (kt) atomicAdd(&g->k4, kt);
+      if (cs) atomicAdd(&g->cyc, cs);
       __threadfence();
       const unsigned long long d = atomicAdd(&g->done, 1ull);
       sh_last = (d + 1ull == (unsigned long long)item_cnt[e]) ? 1 : 0;
@@ -1132,10 +1212,10 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     if (sh_last && tid < kWave) {
       GEdge *g = gacc + e;
       __threadfence();
-      const int64_t kk = (int64_t)atomicAdd(&g->k4, 0ull);
-      const int64_t cc = (int64_t)atomicAdd(&g->cyc, 0ull);
+      const unsigned long long kk = atomicAdd(&g->k4, 0ull);
+      const unsigned long long cc = atomicAdd(&g->cyc, 0ull) + kk;
       if (lane <= kAccIdxCount) {
-        const u128 v = edge_term(lane, S.n, S.m, da, db, t, kk / 2, cc);
+        const u128 v = edge_term(lane, S.n, S.m, da, db, t, (int64_t)(kk / 2), (int64_t)cc);
         if (v != 0) atomic_add_u128(S.acc + 2 * lane, v);
       }
     }
@@ -1143,6 +1223,37 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
   }
   const unsigned long long wsum = block_sum_u64<NT>(words, red);
   if (tid == 0 && wsum) atomicAdd(words_out, wsum);
+}
+
+// ---------------------------------------------------------------------------
+// Ordering of the split class by table-side endpoint (counting sort)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int sort_key(const SlotDesc &S, int32_t b) {
+  if (S.hc <= 0) return kSortKeys - 1;
+  const int32_t r = S.crank[b];
+  return (r >= 0 && r < kSortKeys - 1) ? r : kSortKeys - 1;
+}
+
+__global__ __launch_bounds__(256) void k_sort_hist(const SlotDesc *__restrict__ slots,
+                                                   const int32_t *__restrict__ bslot, const int32_t *__restrict__ bb,
+                                                   int64_t n, int64_t *hist) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd((unsigned long long *)&hist[sort_key(slots[bslot[e]], bb[e])], 1ull);
+}
+
+__global__ __launch_bounds__(256) void k_sort_scatter(const SlotDesc *__restrict__ slots,
+                                                      const int32_t *__restrict__ bslot,
+                                                      const int32_t *__restrict__ ba, const int32_t *__restrict__ bb,
+                                                      int64_t n, int64_t *off, int32_t *slot2, int32_t *a2,
+                                                      int32_t *b2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t sl = bslot[e], b = bb[e];
+    const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&off[sort_key(slots[sl], b)], 1ull);
+    slot2[pos] = sl;
+    a2[pos] = ba[e];
+    b2[pos] = b;
+  }
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int64_t len) {
@@ -1324,14 +1435,28 @@ hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedg
   return hipGetLastError();
 }
 
+hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t *slot2, int32_t *a2,
+                              int32_t *b2, int64_t *hist, int64_t *off, int64_t *tmp, hipStream_t s) {
+  if (nedges <= 0) return hipSuccess;
+  hipError_t e = launch_zero_u64((unsigned long long *)hist, kSortKeys, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(nedges, 256, 4096)), dim3(256), 0, s, slots, bins.slot[kClassGlobal],
+                     bins.b[kClassGlobal], nedges, hist);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_scan_i64(hist, off, kSortKeys, tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_scatter, dim3(grid_for(nedges, 256, 4096)), dim3(256), 0, s, slots,
+                     bins.slot[kClassGlobal], bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, off, slot2, a2, b2);
+  return hipGetLastError();
+}
+
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                const int64_t *item_cnt, const int64_t *tbase, const int32_t *tlist, void *gacc,
                                KernelCfg cfg, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
                      bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, tbase, tlist,
-                     (GEdge *)gacc, bins.cursor + kClassGlobal, bins.words + kClassGlobal, cfg.probe_ratio,
-                     cfg.global_chunk);
+                     (GEdge *)gacc, bins.cursor + kClassGlobal, bins.xcd_cursor, bins.words + kClassGlobal,
+                     cfg.probe_ratio, cfg.global_chunk, cfg.flags);
   return hipGetLastError();
 }
 

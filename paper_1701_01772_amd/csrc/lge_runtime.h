@@ -53,6 +53,13 @@ struct Workspace {
   void *gacc = nullptr;               // cap_edges * gedge_bytes()
   int64_t *scan_tmp = nullptr;
   int64_t scan_tmp_len = 0;
+  // split-class edges reordered by table-side endpoint (cap_edges each)
+  int32_t *sort_slot = nullptr;
+  int32_t *sort_a = nullptr;
+  int32_t *sort_b = nullptr;
+  int64_t *sort_hist = nullptr;  // kSortKeys
+  int64_t *sort_off = nullptr;   // kSortKeys
+  int64_t *sort_tmp = nullptr;   // scan scratch for kSortKeys
   // pinned host staging
   SlotDesc *h_slots = nullptr;
   RangeDesc *h_ranges = nullptr;

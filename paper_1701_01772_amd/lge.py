@@ -32,6 +32,8 @@ LGE_ETIMEDOUT = -7
 LGE_ECANCELED = -8
 LGE_ENOTFOUND = -9
 LGE_FLAG_TRUSTED = 1
+LGE_OPT_SORT_HUB = 1
+LGE_OPT_XCD_LOCAL = 2
 
 
 class LgeError(RuntimeError):
@@ -57,7 +59,8 @@ class Result(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("wave_max_deg", ctypes.c_int32), ("block_max_deg", ctypes.c_int32),
                 ("probe_ratio", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("global_chunk", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Timing(ctypes.Structure):

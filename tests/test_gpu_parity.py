@@ -137,6 +137,13 @@ def test_tuning_invariance(ctx):
                     got = lge.lge_estimate(ctx, h, 0.7, 3, o)
                     for k in ("sampled", "csum", "zsum", "qsum"):
                         assert got[k] == base[k], (wv, pr, gpc, k)
+        for chunk in (1, 37, 256, 1024):
+            for flags in (0, lge.LGE_OPT_SORT_HUB, lge.LGE_OPT_XCD_LOCAL,
+                          lge.LGE_OPT_SORT_HUB | lge.LGE_OPT_XCD_LOCAL):
+                o = lge.make_opts(global_chunk=chunk, flags=flags)
+                got = lge.lge_estimate(ctx, h, 0.7, 3, o)
+                for k in ("sampled", "csum", "zsum", "qsum"):
+                    assert got[k] == base[k], (chunk, flags, k)
     finally:
         lge.lge_graph_destroy(h)
     assert_parity(base, oracle.estimate(g.row_ptr, g.col, 0.7, 3), "rmat-11 tuned")
