@@ -129,6 +129,7 @@ typedef struct {
  *                 hub table; LGE_OPT_XCD_LOCAL: each XCD (workgroups
  *                 blockIdx % 8) takes work items from its own contiguous
  *                 segment first, so each L2 sees a fraction of the tables
+ *                 (default: both)
  */
 #define LGE_OPT_SORT_HUB 1u
 #define LGE_OPT_XCD_LOCAL 2u

@@ -102,7 +102,7 @@ extern "C" int lge_opts_default(lge_opts *o) {
   o->probe_ratio = 4;
   o->grid_per_cu = 0;
   o->global_chunk = 256;
-  o->flags = 0;
+  o->flags = LGE_OPT_SORT_HUB | LGE_OPT_XCD_LOCAL;
   return LGE_OK;
 }
 
@@ -820,7 +820,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     LGE_HIP(hipMemcpyAsync(hl, w.tbase + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LGE_HIP(hipMemcpyAsync(hl + 1, w.tcap + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LGE_HIP(hipStreamSynchronize(s));
-    if ((rc = ws_reserve_tlist(ctx, hl[0] + hl[1])) != LGE_OK) return rc;
+    if ((rc = ws_reserve_tlist(ctx, 2 * (hl[0] + hl[1]))) != LGE_OK) return rc;  // (id, degree) pairs
     LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
     LGE_HIP(hipEventRecord(ev[6], s));
     LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));

@@ -876,7 +876,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
 // ---------------------------------------------------------------------------
 
 constexpr int kGlobalNT = 256;
-constexpr int kTHashCap = 2048;
+constexpr int kTHashCap = 1024;
 
 struct GEdge {
   unsigned long long t, k4, cyc, done;
@@ -947,7 +947,11 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
       unsigned long long pos0 = 0;
       if (lane == 0 && tm) pos0 = atomicAdd(&gacc[e].t, (unsigned long long)__popcll(tm));
       pos0 = __shfl(pos0, 0);
-      if (isT) tlist[tbase[e] + (int64_t)pos0 + __popcll(tm & lt_mask)] = x;
+      if (isT) {  // (id, degree) pairs
+        const int64_t pos = tbase[e] + (int64_t)pos0 + __popcll(tm & lt_mask);
+        tlist[2 * pos] = x;
+        tlist[2 * pos + 1] = rp[x + 1] - rp[x];
+      }
     }
   }
 }
@@ -963,12 +967,26 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
 // pair co-degrees: one table read when both vertices are ranked.  Per vertex
 // the kernel picks the cheapest way to get its terms:
 //   w in S_a : codeg(w,b) - 1 | walk Gamma(w) testing Gamma(b) | look Gamma(b) up in Gamma(w)
-//   x in T_e : walk Gamma(x) testing T_e (and Gamma(a) when cax is not in the
-//              table) | look T_e (and Gamma(a)) up in Gamma(x)
-// Costs are in quarter units of one coalesced load.
+//   x in T_e : degT by walking Gamma(x) against T_e or by looking T_e up in
+//              Gamma(x); cax from the table, or by walking Gamma(x) against
+//              Gamma(a), or by looking Gamma(a) up in Gamma(x)
+// A pair of T_e members that both look up is tested once, by the one of
+// smaller id, with weight 2 (the look-up choice depends only on (d_x, t) so
+// every workgroup agrees on it).  Costs are in quarter units of one
+// coalesced load.
 __device__ __forceinline__ int64_t lookup_cost(int dw) {
   return dw > kHubDeg ? 16 : 8ll * (ceil_log2((uint32_t)dw + 1u) + 1);
 }
+
+__device__ __forceinline__ bool t_looks(int dx, int t, int64_t mT, int probe_ratio) {
+  if (probe_ratio <= 0) return false;
+  return (int64_t)t * (((4 + lookup_cost(dx)) * probe_ratio) / 4) < (int64_t)dx * (4 + mT);
+}
+
+constexpr uint8_t kFLookT = 1;   // degT by look-ups of T_e
+constexpr uint8_t kFLookA = 2;   // cax by look-ups of Gamma(a)
+constexpr uint8_t kFCodeg = 4;   // co-degree from the table
+constexpr uint8_t kFLookB = 8;   // w in S_a: cbx by look-ups of Gamma(b)
 
 __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
@@ -984,6 +1002,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
   __shared__ uint32_t hB[HB];
   __shared__ uint32_t hT[HT];
   __shared__ uint32_t wl_v[CH];
+  __shared__ uint8_t wl_f[CH];
   __shared__ int32_t wl_beg[CH];
   __shared__ int32_t wl_deg[CH];
   __shared__ int32_t wl_pref[CH + 1];
@@ -1042,7 +1061,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const uint32_t *__restrict__ btab = hb ? S.htab + S.hoff[b] : hB;
     const uint32_t *__restrict__ atab = ha ? S.htab + S.hoff[a] : hA;
     const int t = (int)gacc[e].t;
-    const int32_t *__restrict__ T = tlist + tbase[e];
+    const int32_t *__restrict__ T = tlist + 2 * tbase[e];  // (id, degree) pairs
     const bool tl = t <= kTHashCap;
     const int tlg = table_log(t);
     if (tid < 4) sh_cnt[tid] = 0;
@@ -1068,8 +1087,8 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       words += (unsigned long long)da;
     }
     if (tl) {
-      for (int i = tid; i < t; i += NT) lds_insert(hT, tlg, (uint32_t)T[i]);
-      words += (unsigned long long)t;
+      for (int i = tid; i < t; i += NT) lds_insert(hT, tlg, (uint32_t)T[2 * i]);
+      words += 2ull * (unsigned long long)t;
     }
     __syncthreads();
     // r in Gamma(b) \ {a}; r in Gamma(a) \ {b}; r in T_e (the LDS tables
@@ -1113,42 +1132,35 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       const bool may_look = probe_ratio > 0;
       const int64_t look = may_look ? ((4 + lookup_cost(dw)) * probe_ratio) / 4 : 0;
       uint32_t cdeg = 0;
-      const bool cok = probe_ratio > 0 && codeg_pair(S, w, isT ? a : b, &cdeg);
-      uint32_t fl = 0;
+      const bool cok = may_look && codeg_pair(S, w, isT ? a : b, &cdeg);
+      uint8_t fl = 0;
       int32_t units;
       if (!isT) {
         if (cok) {
-          fl = kModeCodeg;
+          fl = kFCodeg;
           units = 0;
           cyc_base += (long long)cdeg - 1;
-        } else {
-          const int64_t scan = (int64_t)dw * (4 + mB), lk = (int64_t)db * look;
-          if (may_look && lk < scan) {
-            fl = kModeLook;
-            units = db;
-          } else {
-            units = dw;
-          }
-        }
-      } else {
-        int64_t scan, lk;
-        if (cok) {
-          fl = kModeCodeg;
-          cyc_base -= (long long)cdeg - 1;
-          scan = (int64_t)dw * (4 + mT);
-          lk = (int64_t)t * look;
-        } else {
-          scan = (int64_t)dw * (4 + mT + mA);
-          lk = (int64_t)(t + da) * look;
-        }
-        if (may_look && lk < scan) {
-          fl |= kModeLook;
-          units = cok ? t : t + da;
+        } else if (may_look && (int64_t)db * look < (int64_t)dw * (4 + mB)) {
+          fl = kFLookB;
+          units = db;
         } else {
           units = dw;
         }
+      } else {
+        const bool lt = t_looks(dw, t, mT, probe_ratio);
+        if (lt) fl |= kFLookT;
+        if (cok) {
+          fl |= kFCodeg;
+          cyc_base -= (long long)cdeg - 1;
+          units = lt ? t : dw;
+        } else {
+          const bool la = may_look && (int64_t)da * look < (int64_t)dw * (4 + mA);
+          if (la) fl |= kFLookA;
+          // one walk of Gamma(w) serves both terms when neither looks up
+          units = (!lt && !la) ? dw : (lt ? t : dw) + (la ? da : dw);
+        }
       }
-      wl_v[i] = v | fl;
+      wl_f[i] = fl;
       wl_pref[i] = units;
     }
     __syncthreads();
@@ -1162,38 +1174,59 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     for (int base = 0; base < total; base += NT) {
       const int idx = base + tid;
       if (idx < total) {
-        int l2 = cur, h2 = L - 1;
-        while (l2 < h2) {
-          const int mid = (l2 + h2 + 1) >> 1;
-          if (wl_pref[mid] <= idx)
-            l2 = mid;
-          else
-            h2 = mid - 1;
+        int l2 = cur;
+        if (wl_pref[l2 + 1] <= idx) {
+          int h2 = L - 1;
+          while (l2 < h2) {
+            const int mid = (l2 + h2 + 1) >> 1;
+            if (wl_pref[mid] <= idx)
+              l2 = mid;
+            else
+              h2 = mid - 1;
+          }
         }
         cur = l2;
         const uint32_t v = wl_v[l2];
+        const uint8_t fl = wl_f[l2];
         const int off = idx - wl_pref[l2];
         const bool isT = (v & kTag) != 0;
         const int32_t w = (int32_t)(v & kIdMask);
+        const int dw = wl_deg[l2];
         ++steps;
         if (!isT) {
-          if (v & kModeLook) {  // cbx by looking Gamma(b) up in Gamma(w)
+          if (fl & kFLookB) {  // cbx by looking Gamma(b) up in Gamma(w)
             const int32_t x = col[bbeg + off];
-            if (x != a && w_has(S, w, wl_beg[l2], wl_deg[l2], x, &steps)) ++cs;
+            if (x != a && w_has(S, w, wl_beg[l2], dw, x, &steps)) ++cs;
           } else {  // cbx by walking Gamma(w)
             if (inBx((uint32_t)col[wl_beg[l2] + off])) ++cs;
           }
-        } else if (v & kModeLook) {
-          if (off < t) {  // degT: members of T_e in Gamma(w)
-            if (w_has(S, w, wl_beg[l2], wl_deg[l2], T[off], &steps)) ++kt;
-          } else {  // cax: members of Gamma(a) \ {b} in Gamma(w)
-            const int32_t y = col[abeg + (off - t)];
-            if (y != b && w_has(S, w, wl_beg[l2], wl_deg[l2], y, &steps)) --cs;
+        } else {
+          const bool lt = (fl & kFLookT) != 0;
+          const bool both = !(fl & (kFCodeg | kFLookT | kFLookA));
+          const int part1 = lt ? t : dw;
+          if (both) {  // one walk of Gamma(w): degT and cax
+            const uint32_t r = (uint32_t)col[wl_beg[l2] + off];
+            if (inT(r)) ++kt;
+            if (inAx(r)) --cs;
+          } else if (off < part1) {  // degT
+            if (lt) {
+              const int32_t y = T[2 * off];
+              const int dy = T[2 * off + 1];
+              // pairs of look-up members are tested by the smaller id only
+              const int wgt = t_looks(dy, t, mT, probe_ratio) ? (y > w ? 2 : 0) : 1;
+              if (wgt && w_has(S, w, wl_beg[l2], dw, y, &steps)) kt += (unsigned long long)wgt;
+            } else {
+              if (inT((uint32_t)col[wl_beg[l2] + off])) ++kt;
+            }
+          } else {  // cax
+            const int o2 = off - part1;
+            if (fl & kFLookA) {
+              const int32_t y = col[abeg + o2];
+              if (y != b && w_has(S, w, wl_beg[l2], dw, y, &steps)) --cs;
+            } else {
+              if (inAx((uint32_t)col[wl_beg[l2] + o2])) --cs;
+            }
           }
-        } else {  // walk Gamma(w): degT, and cax unless it came from the table
-          const uint32_t r = (uint32_t)col[wl_beg[l2] + off];
-          if (inT(r)) ++kt;
-          if (!(v & kModeCodeg) && inAx(r)) --cs;
         }
       }
     }
