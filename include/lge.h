@@ -212,14 +212,15 @@ LGE_API int lge_estimate_range(lge_ctx *ctx, const lge_graph *g, double p, uint6
                                const lge_opts *opts, lge_result *out);
 
 /*
- * Asynchronous estimate: enqueued after the work already on hip_stream (NULL
- * = the ctx stream); *ev completes when `out` holds the result.  `out` must
- * stay valid until lge_event_wait returns; the ctx must not be used for
- * another call before that.
+ * Asynchronous estimate: returns at once; the launch sequence runs after the
+ * work already queued on hip_stream (NULL = none), driven by a worker thread
+ * of the library, and `out` is filled before lge_event_wait returns.  `out`
+ * must stay valid and the ctx must not be used for another call until then.
+ * lge_event_wait returns the estimate's status and frees ev.
  */
 LGE_API int lge_estimate_async(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, void *hip_stream,
                        lge_result *out, lge_event **ev);
-LGE_API int lge_event_wait(lge_event *ev); /* waits, finalises `out`, frees ev */
+LGE_API int lge_event_wait(lge_event *ev);
 
 /*
  * Batched estimate of many independent graphs in one launch sequence.

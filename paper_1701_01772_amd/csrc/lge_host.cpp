@@ -66,12 +66,8 @@ void dev_free(T *&p) {
 // ---------------------------------------------------------------------------
 
 struct lge_event {
-  lge_ctx *ctx;
-  lge_result *out;
-  const lge_graph *g;
-  double p;
-  uint64_t seed;
-  hipEvent_t done;
+  std::thread worker;  // runs the launch sequence and the finalisation
+  int status = LGE_OK;
 };
 
 // ---------------------------------------------------------------------------
@@ -877,7 +873,7 @@ extern "C" int lge_estimate_async(lge_ctx *ctx, const lge_graph *g, double p, ui
   if (g->ctx != ctx) return LGE_EINVAL;
   *ev = nullptr;
   if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
-  // order after the caller's stream, then run on the ctx stream
+  // order after the work already queued on the caller's stream
   if (hip_stream) {
     hipEvent_t dep;
     LGE_HIP(hipEventCreateWithFlags(&dep, hipEventDisableTiming));
@@ -888,27 +884,27 @@ extern "C" int lge_estimate_async(lge_ctx *ctx, const lge_graph *g, double p, ui
   }
   lge_event *E = new (std::nothrow) lge_event();
   if (!E) return LGE_ENOMEM;
-  E->ctx = ctx;
-  E->out = out;
-  E->g = g;
-  E->p = p;
-  E->seed = seed;
-  E->done = nullptr;
-  Job job{g, p, seed, 0, g->m, -1, -1, 0};
-  int rc = lge_run_jobs(ctx, &job, 1, nullptr);
-  if (rc != LGE_OK) {
+  try {
+    E->worker = std::thread([ctx, g, p, seed, out, E] {
+      (void)hipSetDevice(ctx->device);
+      Job job{g, p, seed, 0, g->m, -1, -1, 0};
+      E->status = lge_run_jobs(ctx, &job, 1, nullptr);
+      if (E->status == LGE_OK) lge_finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+    });
+  } catch (...) {
     delete E;
-    return rc;
+    return LGE_ENOMEM;
   }
-  lge_finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
   *ev = E;
   return LGE_OK;
 }
 
 extern "C" int lge_event_wait(lge_event *ev) {
   if (!ev) return LGE_EINVAL;
+  if (ev->worker.joinable()) ev->worker.join();
+  const int st = ev->status;
   delete ev;
-  return LGE_OK;
+  return st;
 }
 
 extern "C" int lge_last_timing(const lge_ctx *ctx, lge_timing *out) {

@@ -253,3 +253,20 @@ def test_estimate_many_equals_singles(ctx):
     finally:
         for h in hs:
             lge.lge_graph_destroy(h)
+
+
+def test_async_estimate_matches_sync(ctx):
+    torch = pytest.importorskip("torch")
+    g = inputs.chung_lu(20000, 10.0, 2.1, 3000.0, 41)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        sync = lge.lge_estimate(ctx, h, 0.3, 5)
+        x = torch.ones(1 << 20, device="cuda:0")
+        x.mul_(2.0)  # work queued on torch's stream before the estimate
+        ev, r = lge.lge_estimate_async(ctx, h, 0.3, 5, torch.cuda.current_stream().cuda_stream)
+        lge.lge_event_wait(ev)
+        got = lge.result_dict(r)
+        for k in ("sampled", "csum", "zsum", "qsum", "estimate", "variance"):
+            assert got[k] == sync[k], k
+    finally:
+        lge.lge_graph_destroy(h)
