@@ -114,8 +114,8 @@ typedef struct {
  *                 by one wavefront with LDS tables (1..512, default 128)
  *  block_max_deg  read-only: edges whose endpoints both have degree <= 1024
  *                 are counted by one 256-thread workgroup with LDS tables;
- *                 others use per-vertex global hash tables of the vertices
- *                 of degree > 1024 and are split across workgroups
+ *                 others are split across workgroups and use the per-vertex
+ *                 global hash tables kept for every vertex of degree > 256
  *  probe_ratio    per neighbour w, look the target set up inside Gamma(w)
  *                 (binary search or w's table) instead of scanning Gamma(w)
  *                 when |target| * lookup_cost(d_w) * probe_ratio < d_w
@@ -123,7 +123,7 @@ typedef struct {
  *  grid_per_cu    persistent workgroups per compute unit for each counting
  *                 kernel (0 = library default)
  *  global_chunk   Gamma(a) positions per work item of the split class
- *                 (1..512, default 256)
+ *                 (1..256, default 256)
  *  flags          LGE_OPT_SORT_HUB: order split-class edges by their
  *                 table-side endpoint so consecutive work items share its
  *                 hub table; LGE_OPT_XCD_LOCAL: each XCD (workgroups

@@ -114,8 +114,8 @@ static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
   const int per_cu = o->grid_per_cu > 0 ? o->grid_per_cu : 0;
   const int cu = ctx->num_cu > 0 ? ctx->num_cu : 256;
   c.grid_wave = cu * (per_cu ? per_cu : 20);
-  c.grid_block = cu * (per_cu ? per_cu : 4);
-  c.grid_global = cu * (per_cu ? per_cu : 4);
+  c.grid_block = cu * (per_cu ? per_cu : 8);
+  c.grid_global = cu * (per_cu ? per_cu : 8);
   c.grid_sample = cu * 16;
   c.global_chunk = o->global_chunk > 0 ? std::min<int32_t>(o->global_chunk, kGlobalChunkMax) : d.global_chunk;
   c.flags = o->flags;

@@ -18,12 +18,14 @@ constexpr int kAccIdxCount = 28;
 constexpr int kAccIdxWords = 29;
 constexpr int kAccSlots = 32;  // padded; one slot = 32 x (lo, hi) u64 = 512 B
 
-// Vertices of degree > kHubDeg get a global hash table of their neighbours
-// ("hub table"); edges whose endpoints both have degree <= kHubDeg are
-// counted entirely from LDS tables.
+// Edges whose endpoints both have degree <= kHubDeg are counted from LDS
+// tables by one workgroup; the others are split across workgroups.
 constexpr int kHubDeg = 1024;
+// Vertices of degree > kTableDeg get a global hash table of their neighbours
+// ("hub table"): O(1) membership tests instead of binary searches.
+constexpr int kTableDeg = 256;
 // Largest number of Gamma(a) positions handled by one global-class work item.
-constexpr int kGlobalChunkMax = 512;
+constexpr int kGlobalChunkMax = 256;
 // Vertex ids must stay below 2^29: the kernels keep three tag bits above them.
 constexpr int64_t kMaxVertices = (int64_t)1 << 29;
 

@@ -12,7 +12,8 @@
 //
 // Membership tables: the side b is held in an open-addressing hash of vertex
 // ids (bit 31 of a key tags "also in Gamma(a)", i.e. a member of T_e) —
-// in LDS when d_b <= kHubDeg, else in the per-vertex global hub table built
+// in LDS for the edges counted by one workgroup, else in the per-vertex global
+// hub table (every vertex of degree > kTableDeg has one) built
 // once per graph.  For every w in Gamma(a) \ {b} the kernel either scans
 // Gamma(w) against the table (the neighbour iteration of Alg. 3/4) or, when
 // Gamma(w) is much longer than the target set, looks each target up in
@@ -43,6 +44,10 @@ __device__ __forceinline__ int table_log(int len) {
   int l = ceil_log2((uint32_t)(2 * (len > 0 ? len : 1)));
   return l < 6 ? 6 : l;
 }
+
+// whether a vertex of degree d owns a global hub table (the single rule used
+// by the table sizing, the table build and every lookup)
+__device__ __forceinline__ bool has_table(int d) { return d > kTableDeg; }
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t x, int logsz) {
   return (x * 2654435761u) >> (32 - logsz);
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(256) void k_hub_sizes(const int32_t *__restrict__ r
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
        u += (int64_t)gridDim.x * blockDim.x) {
     const int d = row_ptr[u + 1] - row_ptr[u];
-    size[u] = d > kHubDeg ? ((int64_t)1 << table_log(d)) : 0;
+    size[u] = has_table(d) ? ((int64_t)1 << table_log(d)) : 0;
   }
 }
 
@@ -331,7 +336,7 @@ __global__ __launch_bounds__(256) void k_hub_build(const int32_t *__restrict__ r
   for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
     const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
     const int d = end - beg;
-    if (d <= kHubDeg) continue;  // uniform per block
+    if (!has_table(d)) continue;  // uniform per block
     const int lg = table_log(d);
     uint32_t *tab = htab + hoff[u];
     for (int j = threadIdx.x; j < (1 << lg); j += blockDim.x) tab[j] = kEmpty;
@@ -634,7 +639,7 @@ struct SlotAcc {
 //   codeg  : w in S_a with w, b in the co-degree table:
 //            |Gamma(w) n S_b| = codeg(w,b) - 1 - |Gamma(w) n T_e|, the last term
 //            by looking T_e up in Gamma(w)                  units = t
-// "Look up x in Gamma(w)" uses w's hub table when d_w > kHubDeg, else a binary
+// "Look up x in Gamma(w)" uses w's hub table when d_w > kTableDeg, else a binary
 // search of the sorted list.  Costs are in quarter units: a scanned entry
 // costs 8 (a coalesced load and a table probe), a look-up 4*(2 + probe cost)
 // scaled by probe_ratio / 4.
@@ -656,7 +661,7 @@ __device__ __forceinline__ WMode choose_mode(bool isT, int dw, int t, int sb_src
   m.units = dw;
   m.base = 0;
   if (probe_ratio <= 0) return m;
-  const int64_t look = (int64_t)((dw > kHubDeg ? 1 : ceil_log2((uint32_t)dw + 1u)) + 2) * probe_ratio;
+  const int64_t look = (int64_t)((has_table(dw) ? 1 : ceil_log2((uint32_t)dw + 1u)) + 2) * probe_ratio;
   int64_t best = 8ll * dw;
   if (isT) {
     const int64_t c = (int64_t)t * look;
@@ -686,7 +691,7 @@ __device__ __forceinline__ WMode choose_mode(bool isT, int dw, int t, int sb_src
 // is x in Gamma(w)?  (w's hub table, or binary search of its sorted list)
 __device__ __forceinline__ bool w_has(const SlotDesc &S, int32_t w, int32_t wbeg, int dw, int32_t x,
                                       uint32_t *steps) {
-  if (dw > kHubDeg) {
+  if (has_table(dw)) {
     *steps += 2;
     return table_find(S.htab + S.hoff[w], table_log(dw), (uint32_t)x) >= 0;
   }
@@ -876,7 +881,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
 // ---------------------------------------------------------------------------
 
 constexpr int kGlobalNT = 256;
-constexpr int kTHashCap = 1024;
+constexpr int kTHashCap = 512;
 
 struct GEdge {
   unsigned long long t, k4, cyc, done;
@@ -928,7 +933,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
     const int32_t a = ba[e], b = bb[e];
     const int32_t abeg = rp[a], bbeg = rp[b];
     const int da = rp[a + 1] - abeg, db = rp[b + 1] - bbeg;
-    const bool hb = db > kHubDeg;
+    const bool hb = has_table(db);
     const int p0 = (int)(c * chunk);
     const int p1 = p0 + chunk < da ? p0 + chunk : da;
     for (int base = p0; base < p1; base += kGlobalNT) {
@@ -975,7 +980,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
 // every workgroup agrees on it).  Costs are in quarter units of one
 // coalesced load.
 __device__ __forceinline__ int64_t lookup_cost(int dw) {
-  return dw > kHubDeg ? 16 : 8ll * (ceil_log2((uint32_t)dw + 1u) + 1);
+  return has_table(dw) ? 16 : 8ll * (ceil_log2((uint32_t)dw + 1u) + 1);
 }
 
 __device__ __forceinline__ bool t_looks(int dx, int t, int64_t mT, int probe_ratio) {
@@ -996,7 +1001,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     int32_t probe_ratio, int32_t chunk, uint32_t flags) {
   constexpr int NT = kGlobalNT;
   constexpr int CH = kGlobalChunkMax;
-  constexpr int HB = 2 * kHubDeg;
+  constexpr int HB = 2 * kTableDeg;
   constexpr int HT = 2 * kTHashCap;
   __shared__ uint32_t hA[HB];
   __shared__ uint32_t hB[HB];
@@ -1056,7 +1061,8 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const int32_t a = ba[e], b = bb[e];
     const int32_t abeg = rp[a], bbeg = rp[b];
     const int da = rp[a + 1] - abeg, db = rp[b + 1] - bbeg;
-    const bool ha = da > kHubDeg, hb = db > kHubDeg;
+    const bool ha = has_table(da), hb = has_table(db);
+    static_assert(2 * kTableDeg <= (1 << 9), "LDS tables of the split kernel hold degree <= kTableDeg");
     const int blg = table_log(db), alg = table_log(da);
     const uint32_t *__restrict__ btab = hb ? S.htab + S.hoff[b] : hB;
     const uint32_t *__restrict__ atab = ha ? S.htab + S.hoff[a] : hA;
