@@ -310,6 +310,7 @@ def main():
     ap.add_argument("--sweep", default=None,
                     help="';'-separated option settings, e.g. 'flags=0;flags=1,global_chunk=128'")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--quick", action="store_true", help="headline workload only (no batched / served legs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale memory counters")
     args = ap.parse_args()
@@ -390,6 +391,21 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(g, p, args.seed + 100, args.cpu_seconds)
+    if not args.quick and args.workload == "chung_lu" and not args.copy_calibration:
+        # the metric's other legs: batched vs plain, and served latency
+        bargs = argparse.Namespace(**vars(args))
+        bargs.steps, bargs.p = 3, None
+        b = bench_batch(bargs)
+        result["batched"] = {"workload": b["config"]["workload"], "value": b["value"], "unit": b["unit"],
+                             "plain_value": b["plain"]["value"], "batched_vs_plain": b["batched_vs_plain"],
+                             "ms_per_step": b["ms_per_step"]}
+        sv = bench_serve(bargs)["serving"]
+        result["served"] = {"workload": "serving_64_graphs_chunglu_rmat_m1e3_%.0e" % args.serve_m_hi,
+                            "plain_requests_per_s": sv["plain"]["requests_per_s"],
+                            "burst_vs_plain": sv["burst"]["vs_plain"],
+                            "p50_ms_at_50pct": sv["served_50"]["p50_ms"], "p99_ms_at_50pct": sv["served_50"]["p99_ms"],
+                            "p50_ms_at_80pct": sv["served_80"]["p50_ms"], "p99_ms_at_80pct": sv["served_80"]["p99_ms"],
+                            "throughput_rps_at_80pct": sv["served_80"]["throughput_rps"]}
     print(json.dumps(result))
 
 

@@ -250,6 +250,38 @@ LGE_API int lge_count_batch(lge_ctx *ctx, const lge_batch *b, const lge_opts *op
 LGE_API int lge_estimate_many(lge_ctx *ctx, const lge_graph *const *graphs, const double *p, const uint64_t *seed,
                               int32_t count, const lge_opts *opts, lge_result *outs);
 
+/*
+ * Adaptive estimation (Sec. 4, Alg. 8).  Starting from an empty sample,
+ * round t grows it by a fraction phi of the edges not yet sampled,
+ * p_t = p_{t-1} + phi (1 - p_{t-1}), and halves phi (phi0 = 0 picks
+ * 1/sqrt(m)); the loop stops when the largest relative change of the
+ * 4-vertex estimates G7..G17 between consecutive rounds is <= beta (a zero
+ * previous estimate with a non-zero new one counts as change 1), or after
+ * t_max rounds.  The samples are nested (one Philox uniform per edge against
+ * growing thresholds), so each round counts only its new edges and *out is
+ * exactly lge_estimate(g, p_T, seed) for the final p_T.  trace (may be NULL)
+ * records p_t, the change (-1 in the first round) and |J| per round.
+ */
+#define LGE_ADAPTIVE_MAX_ROUNDS 64
+typedef struct {
+  double beta;   /* tolerance on the max relative change (default 0.01) */
+  int32_t t_max; /* maximum rounds, 1..64 (default 20) */
+  int32_t pad;
+  double phi0;   /* initial growth fraction in (0, 1]; 0 = 1/sqrt(m) */
+} lge_adaptive_cfg;
+
+typedef struct {
+  int32_t rounds;
+  int32_t pad;
+  double p[LGE_ADAPTIVE_MAX_ROUNDS];
+  double delta[LGE_ADAPTIVE_MAX_ROUNDS];
+  uint64_t sampled[LGE_ADAPTIVE_MAX_ROUNDS];
+} lge_adaptive_trace;
+
+LGE_API int lge_adaptive_cfg_default(lge_adaptive_cfg *cfg);
+LGE_API int lge_estimate_adaptive(lge_ctx *ctx, const lge_graph *g, uint64_t seed, const lge_adaptive_cfg *cfg,
+                                  lge_result *out, lge_adaptive_trace *trace);
+
 /* Timing of the last lge_estimate / lge_count_batch on ctx. */
 LGE_API int lge_last_timing(const lge_ctx *ctx, lge_timing *out);
 

@@ -772,6 +772,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.n = jobs[j].n_override >= 0 ? jobs[j].n_override : g->n;
     sd.m = jobs[j].m_override >= 0 ? jobs[j].m_override : g->m;
     sd.p = jobs[j].p;
+    sd.p_lo = jobs[j].p_lo;
     sd.seed = jobs[j].seed;
     sd.acc = w.acc + (int64_t)j * kAccSlots * 2;
     RangeDesc &rd = w.h_ranges[j];
@@ -984,32 +985,135 @@ extern "C" int lge_estimate_many(lge_ctx *ctx, const lge_graph *const *graphs, c
 }
 
 // ---------------------------------------------------------------------------
+// Adaptive estimation (Sec. 4, Alg. 8).  Round t grows the sample by a
+// fraction phi of the edges not yet sampled, p_t = p_{t-1} + phi (1 - p_{t-1}),
+// then halves phi; because the sampler thresholds one uniform per edge, round
+// t only counts the edges with p_{t-1} <= uniform < p_t and adds their exact
+// sums, and its estimate is the plain Bernoulli(p_t) estimate.  The loop stops
+// once the largest relative change of the 4-vertex estimates (G7..G17)
+// between consecutive rounds is <= beta, or after t_max rounds.
+// ---------------------------------------------------------------------------
+
+extern "C" int lge_adaptive_cfg_default(lge_adaptive_cfg *c) {
+  if (!c) return LGE_EINVAL;
+  memset(c, 0, sizeof(*c));
+  c->beta = 0.01;
+  c->t_max = 20;
+  c->phi0 = 0.0;
+  return LGE_OK;
+}
+
+extern "C" int lge_estimate_adaptive(lge_ctx *ctx, const lge_graph *g, uint64_t seed, const lge_adaptive_cfg *cfg,
+                                     lge_result *out, lge_adaptive_trace *trace) {
+  if (!ctx || !g || !out) return LGE_EINVAL;
+  if (g->ctx != ctx) return LGE_EINVAL;
+  lge_adaptive_cfg c;
+  lge_adaptive_cfg_default(&c);
+  if (cfg) c = *cfg;
+  if (!(c.beta >= 0.0) || c.t_max < 1 || c.t_max > LGE_ADAPTIVE_MAX_ROUNDS || !(c.phi0 >= 0.0) || c.phi0 > 1.0)
+    return LGE_EINVAL;
+  double phi = c.phi0 > 0.0 ? c.phi0 : (g->m > 0 ? 1.0 / sqrt((double)g->m) : 1.0);
+  if (phi > 1.0) phi = 1.0;
+  unsigned long long acc[kAccSlots * 2] = {};
+  double p = 0.0;
+  lge_result prev;
+  bool have_prev = false;
+  if (trace) memset(trace, 0, sizeof(*trace));
+  for (int t = 0; t < c.t_max; ++t) {
+    const double p_new = p + phi * (1.0 - p);
+    Job job{g, p_new, seed, 0, g->m, -1, -1, 0};
+    job.p_lo = p;
+    const int rc = lge_run_jobs(ctx, &job, 1, nullptr);
+    if (rc != LGE_OK) return rc;
+    for (int k = 0; k < kAccSlots; ++k) {  // exact 128-bit accumulation
+      const unsigned long long *src = ctx->ws.h_acc + 2 * k;
+      const unsigned long long lo = acc[2 * k] + src[0];
+      acc[2 * k + 1] += src[1] + (lo < acc[2 * k] ? 1ull : 0ull);
+      acc[2 * k] = lo;
+    }
+    lge_finalize(g->n, g->m, p_new, seed, acc, out);
+    double delta = -1.0;
+    if (have_prev) {
+      delta = 0.0;
+      for (int i = 7; i <= 17; ++i) {
+        const double x0 = prev.estimate[i], x1 = out->estimate[i];
+        if (x0 != 0.0) delta = std::max(delta, fabs(x1 - x0) / fabs(x0));
+        else if (x1 != 0.0) delta = std::max(delta, 1.0);
+      }
+    }
+    if (trace) {
+      trace->p[t] = p_new;
+      trace->delta[t] = delta;
+      trace->sampled[t] = out->sampled_edges;
+      trace->rounds = t + 1;
+    }
+    prev = *out;
+    have_prev = true;
+    p = p_new;
+    phi *= 0.5;
+    if (delta >= 0.0 && delta <= c.beta) break;
+  }
+  return LGE_OK;
+}
+
+// ---------------------------------------------------------------------------
 // autotuner: results never depend on the options, only the time does
 // ---------------------------------------------------------------------------
 
 extern "C" int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *out) {
   if (!p_ok(p)) return LGE_EINVAL;
   if (!ctx || !g || !out) return LGE_EINVAL;
+  // coordinate descent over the knobs that matter, starting from the
+  // defaults; each candidate is timed on the device (sampling + counting)
   lge_opts best;
   lge_opts_default(&best);
-  float best_ms = 1e30f;
-  const int waves[] = {64, 128, 256, 512};
-  const int ratios[] = {0, 1, 2, 4, 8, 16};
   lge_result r;
-  for (int wv : waves) {
-    for (int pr : ratios) {
-      lge_opts o;
-      lge_opts_default(&o);
-      o.wave_max_deg = wv;
-      o.probe_ratio = pr;
-      int rc = lge_estimate(ctx, g, p, 0x5eed, &o, &r);
+  auto time_of = [&](const lge_opts &o, float *ms) -> int {
+    float t_best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      const int rc = lge_estimate(ctx, g, p, 0x5eedull + (uint64_t)rep, &o, &r);
       if (rc != LGE_OK) return rc;
       const lge_timing &t = ctx->timing;
-      const float ms = t.sample_ms + t.count_ms[0] + t.count_ms[1] + t.count_ms[2];
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = o;
-      }
+      t_best = std::min(t_best, t.sample_ms + t.count_ms[0] + t.count_ms[1] + t.global_prep_ms + t.count_ms[2]);
+    }
+    *ms = t_best;
+    return LGE_OK;
+  };
+  float best_ms;
+  int rc = time_of(best, &best_ms);
+  if (rc != LGE_OK) return rc;
+  const int waves[] = {64, 128, 256, 512};
+  const int ratios[] = {2, 4, 8};
+  const int grids[] = {4, 8, 12};
+  const int chunks[] = {128, 256};
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int v : waves) {
+      lge_opts o = best;
+      o.wave_max_deg = v;
+      float ms;
+      if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
+      if (ms < best_ms) best_ms = ms, best = o;
+    }
+    for (int v : ratios) {
+      lge_opts o = best;
+      o.probe_ratio = v;
+      float ms;
+      if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
+      if (ms < best_ms) best_ms = ms, best = o;
+    }
+    for (int v : grids) {
+      lge_opts o = best;
+      o.grid_per_cu = v;
+      float ms;
+      if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
+      if (ms < best_ms) best_ms = ms, best = o;
+    }
+    for (int v : chunks) {
+      lge_opts o = best;
+      o.global_chunk = v;
+      float ms;
+      if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
+      if (ms < best_ms) best_ms = ms, best = o;
     }
   }
   *out = best;

@@ -44,6 +44,7 @@ struct SlotDesc {
   double p;
   uint64_t seed;
   unsigned long long *acc;  // kAccSlots x {lo, hi}
+  double p_lo;              // sample edges with p_lo <= uniform < p (nested samples)
 };
 
 // A contiguous range of canonical edge ids of one slot.

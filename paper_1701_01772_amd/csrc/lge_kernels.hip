@@ -134,10 +134,13 @@ __device__ __forceinline__ uint64_t philox_bits(uint64_t seed, uint64_t ctr) {
   return ((uint64_t)c1 << 32) | (uint64_t)c0;
 }
 
-__device__ __forceinline__ bool edge_taken(uint64_t seed, uint64_t eid, double p) {
-  if (p >= 1.0) return true;  // the uniform is < 1 for every counter
+// edge eid is taken iff p_lo <= uniform < p (p_lo = 0 is the plain Bernoulli(p)
+// sample; thresholds of one uniform give nested samples)
+__device__ __forceinline__ bool edge_taken(uint64_t seed, uint64_t eid, double p_lo, double p) {
+  if (p >= 1.0 && p_lo <= 0.0) return true;  // the uniform is < 1 for every counter
   const uint64_t bits = philox_bits(seed, eid);
-  return (double)(bits >> 11) * 0x1.0p-53 < p;
+  const double u = (double)(bits >> 11) * 0x1.0p-53;
+  return u >= p_lo && u < p;
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
       slot = R.slot;
       const SlotDesc &S = slots[slot];
       const int64_t eid = R.e0 + (i - R.pref);
-      if (edge_taken(S.seed, (uint64_t)eid, S.p)) {
+      if (edge_taken(S.seed, (uint64_t)eid, S.p_lo, S.p)) {
         const uint64_t e = S.edges[eid];
         const int32_t u = (int32_t)(e >> 32), v = (int32_t)(uint32_t)e;
         const int32_t du = S.row_ptr[u + 1] - S.row_ptr[u];

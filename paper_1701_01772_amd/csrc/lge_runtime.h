@@ -88,6 +88,7 @@ struct Job {
   int64_t n_override;   // graph-level sizes for the closed forms (batch unions)
   int64_t m_override;
   int64_t eid_base;     // subtracted from edge ids before the sampler
+  double p_lo = 0.0;    // sample only edges whose uniform is >= p_lo (adaptive rounds)
 };
 
 // Runs sample -> bin -> count for the jobs in one launch sequence on the

@@ -90,6 +90,16 @@ class ServerStats(ctypes.Structure):
                 ("running", ctypes.c_uint64), ("busy_s", ctypes.c_double)]
 
 
+class AdaptiveCfg(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("t_max", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("phi0", ctypes.c_double)]
+
+
+class AdaptiveTrace(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("pad", ctypes.c_int32), ("p", ctypes.c_double * 64),
+                ("delta", ctypes.c_double * 64), ("sampled", ctypes.c_uint64 * 64)]
+
+
 _lib = None
 _VP = ctypes.c_void_p
 
@@ -137,6 +147,9 @@ def load():
                                ctypes.POINTER(Result)], ctypes.c_int),
         "lge_last_timing": ([_VP, ctypes.POINTER(Timing)], ctypes.c_int),
         "lge_autotune": ([_VP, _VP, ctypes.c_double, ctypes.POINTER(Opts)], ctypes.c_int),
+        "lge_adaptive_cfg_default": ([ctypes.POINTER(AdaptiveCfg)], ctypes.c_int),
+        "lge_estimate_adaptive": ([_VP, _VP, ctypes.c_uint64, ctypes.POINTER(AdaptiveCfg), ctypes.POINTER(Result),
+                                   ctypes.POINTER(AdaptiveTrace)], ctypes.c_int),
         "lge_server_cfg_default": ([ctypes.POINTER(ServerCfg)], ctypes.c_int),
         "lge_server_create": ([_VP, ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)], ctypes.c_int),
         "lge_server_add_graph": ([_VP, _VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -339,6 +352,18 @@ def lge_autotune(ctx, g, p: float) -> Opts:
     o = Opts()
     _check(load().lge_autotune(ctx, g, float(p), ctypes.byref(o)), "lge_autotune")
     return o
+
+
+def lge_estimate_adaptive(ctx, g, seed: int, beta: float = 0.01, t_max: int = 20, phi0: float = 0.0):
+    """Returns (result dict, trace dict with lists p, delta, sampled)."""
+    cfg = AdaptiveCfg(float(beta), int(t_max), 0, float(phi0))
+    r = Result()
+    tr = AdaptiveTrace()
+    _check(load().lge_estimate_adaptive(ctx, g, int(seed), ctypes.byref(cfg), ctypes.byref(r), ctypes.byref(tr)),
+           "lge_estimate_adaptive")
+    k = tr.rounds
+    return result_dict(r), {"rounds": k, "p": list(tr.p[:k]), "delta": list(tr.delta[:k]),
+                            "sampled": [int(x) for x in tr.sampled[:k]]}
 
 
 def lge_server_cfg_default() -> ServerCfg:

@@ -270,3 +270,40 @@ def test_async_estimate_matches_sync(ctx):
             assert got[k] == sync[k], k
     finally:
         lge.lge_graph_destroy(h)
+
+
+def test_autotune_changes_speed_not_results(ctx):
+    g = inputs.chung_lu(20000, 10.0, 2.1, 3000.0, 41)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        _say("autotune on chung-lu-20k")
+        o = lge.lge_autotune(ctx, h, 0.4)
+        assert 1 <= o.wave_max_deg <= 512 and o.probe_ratio > 0
+        tuned = lge.lge_estimate(ctx, h, 0.4, 77, o)
+        base = lge.lge_estimate(ctx, h, 0.4, 77)
+        for k in ("sampled", "csum", "zsum", "qsum", "estimate", "variance"):
+            assert tuned[k] == base[k], k
+    finally:
+        lge.lge_graph_destroy(h)
+
+
+@pytest.mark.parametrize("beta,phi0", [(0.05, 0.0), (0.0, 0.3), (0.01, 1.0)])
+def test_adaptive_equals_oracle_and_plain(ctx, beta, phi0):
+    from oracle import adaptive as oadaptive
+    g = inputs.chung_lu(8000, 10.0, 2.1, 1500.0, 17)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        _say("adaptive beta=%g phi0=%g on n=%d m=%d" % (beta, phi0, g.n, g.m))
+        got, tr = lge.lge_estimate_adaptive(ctx, h, 31, beta=beta, t_max=8, phi0=phi0)
+        want, otr = oadaptive.adaptive(g.row_ptr, g.col, 31, beta=beta, t_max=8, phi0=phi0)
+        assert tr["rounds"] == otr["rounds"]
+        assert tr["p"] == otr["p"] and tr["sampled"] == otr["sampled"]
+        for a, b in zip(tr["delta"], otr["delta"]):
+            assert _close(a, b), (a, b)
+        assert_parity(got, want, "adaptive")
+        # rounds add disjoint slices [p_{t-1}, p_t): the union is the plain sample at p_T
+        plain = lge.lge_estimate(ctx, h, tr["p"][-1], 31)
+        for k in ("sampled", "csum", "zsum", "qsum", "estimate", "variance"):
+            assert got[k] == plain[k], k
+    finally:
+        lge.lge_graph_destroy(h)
