@@ -82,6 +82,9 @@ def _load():
         lib.oracle_sample_mask.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_sample_mask.restype = ctypes.c_uint64
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_micro.argtypes = [ctypes.c_int64, i32p, i32p, i32p, i32p, ctypes.c_int64, i64p]
+        lib.oracle_micro.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -173,3 +176,35 @@ def edge_local(row_ptr, col, u: int, v: int) -> dict:
         raise RuntimeError("oracle_edge_local failed")
     keys = ["t", "su", "sv", "r", "clique", "cycle", "f"]
     return {k: int(out[i]) for i, k in enumerate(keys)}
+
+
+def canonical_edges(row_ptr, col):
+    """(us, vs) of every edge u < v, in canonical id order (row-major)."""
+    rp, cl = _csr(row_ptr, col)
+    cl = cl[:int(rp[-1])]
+    deg = np.diff(rp)
+    src = np.repeat(np.arange(rp.shape[0] - 1, dtype=np.int32), deg)
+    keep = cl > src
+    return src[keep], cl[keep]
+
+
+def micro(row_ptr, col, eids=None) -> np.ndarray:
+    """Micro-level graphlet statistics (Sec. 3, Alg. 7 with p_e = 1): one row
+    of 17 int64 per edge id in ``eids`` (default: every edge), column i-1 =
+    number of induced G_i containing both ends of the edge."""
+    lib = _load()
+    rp, cl = _csr(row_ptr, col)
+    us, vs = canonical_edges(rp, cl)
+    if eids is not None:
+        idx = np.asarray(eids, dtype=np.int64)
+        us, vs = us[idx], vs[idx]
+    us = np.ascontiguousarray(us, dtype=np.int32)
+    vs = np.ascontiguousarray(vs, dtype=np.int32)
+    out = np.zeros((us.shape[0], 17), dtype=np.int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    rc = lib.oracle_micro(rp.shape[0] - 1, rp.ctypes.data_as(i32p), cl.ctypes.data_as(i32p),
+                          us.ctypes.data_as(i32p), vs.ctypes.data_as(i32p), us.shape[0],
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise RuntimeError("oracle_micro failed")
+    return out

@@ -89,3 +89,20 @@ def census_csr(row_ptr, col, table):
     n = len(row_ptr) - 1
     edges = [(a, int(col[j])) for a in range(n) for j in range(row_ptr[a], row_ptr[a + 1]) if a < col[j]]
     return census(n, edges, table)
+
+
+def micro_census(n: int, edges, table, u: int, v: int):
+    """Per-edge census: counts of G1..G17 over the 2-, 3- and 4-vertex
+    subsets that contain both u and v (list indexed 0..17, slot 0 unused)."""
+    adj = [set() for _ in range(n)]
+    for a, b in edges:
+        if a != b:
+            adj[a].add(b)
+            adj[b].add(a)
+    cls = classifier(table)
+    counts = [0] * 18
+    rest = [x for x in range(n) if x != u and x != v]
+    for extra in (0, 1, 2):
+        for more in itertools.combinations(rest, extra):
+            counts[cls[signature((u, v) + more, adj)]] += 1
+    return counts

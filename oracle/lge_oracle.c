@@ -436,3 +436,115 @@ uint64_t oracle_sample_mask(uint64_t seed, double p, uint64_t e0, uint64_t e1, u
   }
   return cnt;
 }
+
+/* ---------------------------------------------------------------------------
+ * Micro-level graphlet statistics of single edges (Sec. 3, Alg. 7 with
+ * p_e = 1, every neighbour examined once).  y[i-1] is the number of induced
+ * k-vertex subgraphs of type G_i whose vertex set holds both ends of e
+ * (k = 2, 3, 4): G1 = 1 (e itself), and G2, G6, G17 (no edges) are 0.
+ *
+ * Plainly: mark u, v, T_e, S_u, S_v, then walk Gamma(w) of every w in
+ * T_e u S_u u S_v and tally where each neighbour r falls (T_e, S_u, S_v, or
+ * R = the vertices adjacent to neither end).  With those tallies every
+ * 4-vertex graphlet containing e is counted by the role e plays in it:
+ *   G7  4-clique       : edges inside T_e
+ *   G8  chordal cycle  : e the chord: C(t,2) - k4; e on the rim: edges T_e-S
+ *   G9  tailed triangle: e the tail: edges inside S_u and inside S_v;
+ *                        e next to the tail: t*s - edges T_e-S;
+ *                        e opposite the tail: edges T_e-R
+ *   G10 4-cycle        : edges S_u-S_v
+ *   G11 3-star         : C(s_u,2) - e(S_u) + C(s_v,2) - e(S_v)
+ *   G12 4-path         : e the middle: s_u s_v - e(S_u,S_v); e an end: edges S-R
+ *   G13 triangle + 1   : t*r - edges T_e-R
+ *   G14 2-star + 1     : s*r - edges S-R
+ *   G15 2 edges        : edges inside R
+ *   G16 1 edge         : C(r,2) - edges inside R
+ * where edges inside R = (edges sharing no end with e) - (edges inside
+ * T_e u S) - (edges T_e-R) - (edges S-R).
+ * The rows are pinned to a brute-force enumeration of the subsets that hold
+ * both ends of e, and their column sums to (edges of G_i) x (count of G_i).
+ * ------------------------------------------------------------------------ */
+enum { MK_T = 1, MK_SU = 2, MK_SV = 3, MK_END = 4 };
+
+static void micro_edge(int64_t n, int64_t m, const int32_t *row_ptr, const int32_t *col, int32_t u, int32_t v,
+                       int64_t *tag, int64_t *stamp, int64_t y[17]) {
+  const int64_t base = *stamp;
+  *stamp += 8;
+  /* tag values: base + MK_* (anything below base is "unmarked") */
+  for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) tag[col[j]] = base + MK_SV;
+  int64_t t = 0, su = 0, sv = 0;
+  for (int64_t j = row_ptr[u]; j < row_ptr[u + 1]; ++j) {
+    const int32_t w = col[j];
+    if (w == v) continue;
+    if (tag[w] == base + MK_SV) {
+      tag[w] = base + MK_T;
+      ++t;
+    } else {
+      tag[w] = base + MK_SU;
+      ++su;
+    }
+  }
+  tag[u] = base + MK_END;
+  tag[v] = base + MK_END;
+  sv = (row_ptr[v + 1] - row_ptr[v]) - 1 - t;
+  const int64_t du = row_ptr[u + 1] - row_ptr[u], dv = row_ptr[v + 1] - row_ptr[v];
+  /* tallies: [kind of w][kind of r] for kinds T, S_u, S_v, R */
+  int64_t tally[4][5];
+  memset(tally, 0, sizeof(tally));
+  for (int side = 0; side < 2; ++side) {
+    const int32_t x = side == 0 ? u : v;
+    for (int64_t j = row_ptr[x]; j < row_ptr[x + 1]; ++j) {
+      const int32_t w = col[j];
+      const int64_t tw = tag[w];
+      if (tw == base + MK_END) continue;
+      if (side == 1 && tw == base + MK_T) continue; /* T_e members are visited from u */
+      const int kw = (int)(tw - base); /* MK_T, MK_SU or MK_SV */
+      for (int64_t k = row_ptr[w]; k < row_ptr[w + 1]; ++k) {
+        const int64_t tr = tag[col[k]];
+        int kr;
+        if (tr == base + MK_END) continue; /* links to u or v */
+        if (tr >= base) kr = (int)(tr - base);
+        else kr = 0; /* R */
+        tally[kw][kr] += 1;
+      }
+    }
+  }
+  const int64_t r = n - (du + dv - t);
+  const int64_t s = su + sv;
+  const int64_t k4 = tally[MK_T][MK_T] / 2;
+  const int64_t ts = tally[MK_T][MK_SU] + tally[MK_T][MK_SV];
+  const int64_t tr_ = tally[MK_T][0];
+  const int64_t esu = tally[MK_SU][MK_SU] / 2, esv = tally[MK_SV][MK_SV] / 2;
+  const int64_t cyc = tally[MK_SU][MK_SV];
+  const int64_t sr = tally[MK_SU][0] + tally[MK_SV][0];
+  const int64_t f = m - du - dv + 1;
+  const int64_t inside = k4 + ts + esu + esv + cyc; /* edges inside T_e u S */
+  const int64_t er = f - inside - tr_ - sr;
+  for (int i = 0; i < 17; ++i) y[i] = 0;
+  y[0] = 1;
+  y[2] = t;
+  y[3] = s;
+  y[4] = r;
+  y[6] = k4;
+  y[7] = t * (t - 1) / 2 - k4 + ts;
+  y[8] = esu + esv + (t * s - ts) + tr_;
+  y[9] = cyc;
+  y[10] = su * (su - 1) / 2 - esu + sv * (sv - 1) / 2 - esv;
+  y[11] = su * sv - cyc + sr;
+  y[12] = t * r - tr_;
+  y[13] = s * r - sr;
+  y[14] = er;
+  y[15] = r * (r - 1) / 2 - er;
+}
+
+/* Rows for the edges (us[k], vs[k]), k < count; out is count x 17. */
+int oracle_micro(int64_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *us, const int32_t *vs,
+                 int64_t count, int64_t *out) {
+  const int64_t m = (int64_t)row_ptr[n] / 2;
+  int64_t *tag = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+  if (!tag) return -1;
+  int64_t stamp = 8;
+  for (int64_t k = 0; k < count; ++k) micro_edge(n, m, row_ptr, col, us[k], vs[k], tag, &stamp, out + 17 * k);
+  free(tag);
+  return 0;
+}
