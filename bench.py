@@ -8,7 +8,7 @@ roofline of the dominant counting kernel (device time from HIP events the
 library records on its own stream), and the CPU oracle timed on a bounded
 subsample of the same workload on this host.
 
-    python bench.py [--steps K] [--warmup W] [--workload chung_lu|rmat|er|batch] [--p P]
+    python bench.py [--steps K] [--warmup W] [--workload chung_lu|rmat|er|batch|serve|micro] [--p P]
 """
 import argparse
 import hashlib
@@ -296,6 +296,67 @@ def bench_sweep(args):
     return {"sweep": rows, "workload": wname, "p": p}
 
 
+def bench_micro(args):
+    """Micro-level rows (Sec. 3, Alg. 7 at p_e = 1) of every edge of the
+    Chung-Lu 1e6 graph: one lge_micro over all m edges per step, rows in a
+    resident m x 17 int64 device buffer."""
+    import torch
+    from paper_1701_01772_amd import lge
+    g, wname = make_workload("chung_lu")
+    ctx = lge.lge_open(0)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    rows = torch.empty((g.m, lge.LGE_MICRO_COLS), dtype=torch.int64, device="cuda:0")
+    for i in range(max(1, args.warmup)):
+        lge.lge_micro(ctx, h, 0, g.m, out=rows)
+        log("micro warmup %d" % (i + 1))
+    torch.cuda.synchronize()
+    tim = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, cm = lge.lge_micro(ctx, h, 0, g.m, out=rows)
+        tim.append(lge.lge_last_timing(ctx))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("micro: %d steps in %.3f s" % (args.steps, dt))
+    k = len(tim)
+    device_ms, roof = roofline_of(tim, "micro")
+    micro_ms = sum(t["micro_ms"] for t in tim) / k
+    device_ms["micro_rows"] = micro_ms
+    out_bytes = g.m * lge.LGE_MICRO_COLS * 8
+    res = {"metric": "micro rows/s (17 exact per-edge graphlet counts, every edge)", "value": g.m * args.steps / dt,
+           "unit": "edges/s", "steps": args.steps, "ms_per_step": 1e3 * dt / args.steps,
+           "config": {"workload": wname, "n": g.n, "m": g.m, "p": 1.0},
+           "device_ms": device_ms, "roofline": roof,
+           "micro_rows_kernel": {"ms": micro_ms, "row_bytes_written": out_bytes,
+                                 "write_GBps": out_bytes / (micro_ms * 1e-3) / 1e9 if micro_ms > 0 else None},
+           "colmax": cm}
+    del rows
+    lge.lge_graph_destroy(h)
+    lge.lge_close(ctx)
+    return res
+
+
+def bench_adaptive(args):
+    """Adaptive estimation (Sec. 4, Alg. 8) on the Chung-Lu 1e6 graph,
+    beta = 0.01, phi0 = 1/sqrt(m)."""
+    import torch
+    from paper_1701_01772_amd import lge
+    g, wname = make_workload("chung_lu")
+    ctx = lge.lge_open(0)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    lge.lge_estimate_adaptive(ctx, h, args.seed, beta=0.01)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, tr = lge.lge_estimate_adaptive(ctx, h, args.seed + 1, beta=0.01)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lge.lge_graph_destroy(h)
+    lge.lge_close(ctx)
+    return {"workload": wname, "beta": 0.01, "rounds": tr["rounds"], "final_p": tr["p"][-1],
+            "sampled": tr["sampled"][-1], "seconds": dt, "sampled_edges_per_s": tr["sampled"][-1] / dt,
+            "final_delta": tr["delta"][-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +389,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)))
+        return
+    if args.workload == "micro":
+        print(json.dumps(bench_micro(args)))
         return
 
     import torch
@@ -406,6 +470,11 @@ def main():
                             "p50_ms_at_50pct": sv["served_50"]["p50_ms"], "p99_ms_at_50pct": sv["served_50"]["p99_ms"],
                             "p50_ms_at_80pct": sv["served_80"]["p50_ms"], "p99_ms_at_80pct": sv["served_80"]["p99_ms"],
                             "throughput_rps_at_80pct": sv["served_80"]["throughput_rps"]}
+        mi = bench_micro(bargs)
+        result["micro"] = {"workload": mi["config"]["workload"], "value": mi["value"], "unit": mi["unit"],
+                           "ms_per_step": mi["ms_per_step"], "device_ms": mi["device_ms"],
+                           "micro_rows_kernel": mi["micro_rows_kernel"]}
+        result["adaptive"] = bench_adaptive(bargs)
     print(json.dumps(result))
 
 

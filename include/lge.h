@@ -58,6 +58,7 @@ extern "C" {
 #define LGE_ETIMEDOUT (-7)  /* lge_wait timed out (the ticket stays valid) */
 #define LGE_ECANCELED (-8)  /* request cancelled or server shut down */
 #define LGE_ENOTFOUND (-9)  /* unknown ticket or graph id */
+#define LGE_EINTERNAL (-10) /* a device-side consistency check failed (a library bug) */
 
 /* lge_graph_create_* flag: skip validation of the CSR (caller guarantees it) */
 #define LGE_FLAG_TRUSTED 1u
@@ -153,6 +154,8 @@ typedef struct {
   uint64_t class_edges[3]; /* sampled edges per class */
   uint64_t words_read[3];  /* 4-byte words each class's counting kernels read (algorithmic) */
   uint64_t launches;       /* kernel launches issued */
+  float micro_ms;          /* lge_micro only: the row kernel (after the counting pass) */
+  float pad;
 } lge_timing;
 
 LGE_API const char *lge_strerror(int code);
@@ -281,6 +284,32 @@ typedef struct {
 LGE_API int lge_adaptive_cfg_default(lge_adaptive_cfg *cfg);
 LGE_API int lge_estimate_adaptive(lge_ctx *ctx, const lge_graph *g, uint64_t seed, const lge_adaptive_cfg *cfg,
                                   lge_result *out, lge_adaptive_trace *trace);
+
+/*
+ * Micro-level graphlet statistics (Sec. 3, the micro problem and Alg. 7 with
+ * p_e = 1, every neighbour examined once): for every edge e = (u, v) with
+ * canonical id in [e0, e1), row e - e0 of `out` holds 17 int64, column i-1 =
+ * the number of induced k-vertex subgraphs of type G_i (k = 2, 3, 4, numbered
+ * as in Table 1) whose vertex set contains both u and v.  Column 0 (G1) is 1;
+ * G2, G6 and G17 (no edges) are 0.  Alg. 7 counts some graphlets with e in one
+ * role only (G8 with e as the chord, G9 with e as the tail, G12 with e in the
+ * middle) and leaves G13, G14, G16 unrestricted; these rows count every
+ * role, induced, so column i summed over all edges is (edges of G_i) x (number
+ * of G_i) for i >= 3.
+ *   out    : DEVICE pointer, (e1 - e0) x 17 int64, row-major, caller-owned;
+ *            may be NULL only when e1 == e0.  Overwritten; on error its
+ *            contents are unspecified.
+ *   colmax : HOST pointer to 18 int64 or NULL: colmax[i] = largest value of
+ *            column i-1 over the rows (the max graphlet statistic
+ *            Z_i = max_e X_i(e) of Sec. 5 over the range; 0 for an empty
+ *            range), colmax[0] = 0.
+ * Blocks until the rows are written.  The first call on a graph builds and
+ * caches per-arc triangle counts (8m + 8n bytes of device memory, freed with
+ * the graph).  Errors: LGE_EINVAL (null ctx/graph, foreign graph, bad range),
+ * LGE_ENOMEM, LGE_EDEVICE, LGE_EINTERNAL.
+ */
+#define LGE_MICRO_COLS 17
+LGE_API int lge_micro(lge_ctx *ctx, const lge_graph *g, int64_t e0, int64_t e1, int64_t *out, int64_t *colmax);
 
 /* Timing of the last lge_estimate / lge_count_batch on ctx. */
 LGE_API int lge_last_timing(const lge_ctx *ctx, lge_timing *out);

@@ -86,6 +86,7 @@ extern "C" const char *lge_strerror(int code) {
     case LGE_ETIMEDOUT: return "timed out";
     case LGE_ECANCELED: return "cancelled";
     case LGE_ENOTFOUND: return "not found";
+    case LGE_EINTERNAL: return "internal consistency check failed";
     default: return "unknown error";
   }
 }
@@ -515,6 +516,9 @@ static void graph_free(lge_graph *g) {
   dev_free(g->htab);
   dev_free(g->crank);
   dev_free(g->codeg);
+  dev_free(g->t_arc);
+  dev_free(g->tri);
+  dev_free(g->mred);
 }
 
 static int32_t host_max_deg(int64_t n, const int32_t *row_ptr) {
@@ -775,6 +779,9 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.p_lo = jobs[j].p_lo;
     sd.seed = jobs[j].seed;
     sd.acc = w.acc + (int64_t)j * kAccSlots * 2;
+    sd.micro = jobs[j].micro;
+    sd.micro_base = jobs[j].e0 - jobs[j].eid_base;
+    sd.micro_len = jobs[j].e1 - jobs[j].e0;
     RangeDesc &rd = w.h_ranges[j];
     rd.slot = j;
     rd.pad = 0;
@@ -1053,6 +1060,63 @@ extern "C" int lge_estimate_adaptive(lge_ctx *ctx, const lge_graph *g, uint64_t 
     phi *= 0.5;
     if (delta >= 0.0 && delta <= c.beta) break;
   }
+  return LGE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// micro-level statistics
+// ---------------------------------------------------------------------------
+
+static int ensure_micro(lge_ctx *ctx, lge_graph *g) {
+  if (g->mred) return LGE_OK;
+  dev_free(g->t_arc);  // left over from a failed earlier attempt
+  dev_free(g->tri);
+  int rc;
+  if ((rc = dev_alloc(&g->t_arc, std::max<int64_t>(2 * g->m, 1))) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&g->tri, std::max<int64_t>(g->n, 1))) != LGE_OK) return rc;
+  hipStream_t s = ctx->stream;
+  LGE_HIP(launch_micro_arc_tri(g->row_ptr, g->col, g->edges, g->hoff, g->htab, g->m, g->t_arc, s));
+  LGE_HIP(launch_micro_vertex_tri(g->row_ptr, g->t_arc, g->n, g->tri, s));
+  LGE_HIP(hipStreamSynchronize(s));
+  if ((rc = dev_alloc(&g->mred, 32)) != LGE_OK) return rc;  // last: marks the cache complete
+  return LGE_OK;
+}
+
+extern "C" int lge_micro(lge_ctx *ctx, const lge_graph *gc, int64_t e0, int64_t e1, int64_t *out, int64_t *colmax) {
+  if (!ctx || !gc) return LGE_EINVAL;
+  if (gc->ctx != ctx || e0 < 0 || e1 < e0 || e1 > gc->m) return LGE_EINVAL;
+  if (colmax)
+    for (int i = 0; i < 18; ++i) colmax[i] = 0;
+  if (e1 == e0) return LGE_OK;
+  if (!out) return LGE_EINVAL;
+  lge_graph *g = const_cast<lge_graph *>(gc);  // the cache is not part of the graph's value
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  int rc = ensure_micro(ctx, g);
+  if (rc != LGE_OK) return rc;
+  hipStream_t s = ctx->stream;
+  long long *rows = reinterpret_cast<long long *>(out);
+  LGE_HIP(launch_micro_mark(rows, e1 - e0, s));
+  // t, k4 and cyc of every edge of the range from the counting kernels (p = 1)
+  Job job{g, 1.0, 0, e0, e1, -1, -1, 0};
+  job.micro = rows;
+  if ((rc = lge_run_jobs(ctx, &job, 1, nullptr)) != LGE_OK) return rc;
+  LGE_HIP(launch_zero_u64(g->mred, 32, s));
+  int *err = reinterpret_cast<int *>(g->mred + 24);
+  LGE_HIP(hipEventRecord(ctx->ev[6], s));
+  LGE_HIP(launch_micro_rows(g->row_ptr, g->col, g->edges, g->vol2, g->t_arc, g->tri, g->n, g->m, e0, e1, rows,
+                            g->mred, err, ctx->num_cu * 8, s));
+  LGE_HIP(hipEventRecord(ctx->ev[7], s));
+  unsigned long long h[32];
+  LGE_HIP(hipMemcpyAsync(h, g->mred, sizeof(h), hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipStreamSynchronize(s));
+  int herr;
+  memcpy(&herr, &h[24], sizeof(herr));
+  if (herr != 0) return LGE_EINTERNAL;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]) == hipSuccess) ctx->timing.micro_ms = ms;
+  ctx->timing.launches += 3;
+  if (colmax)
+    for (int i = 0; i < LGE_MICRO_COLS; ++i) colmax[i + 1] = (int64_t)h[i];
   return LGE_OK;
 }
 

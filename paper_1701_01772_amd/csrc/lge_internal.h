@@ -45,7 +45,18 @@ struct SlotDesc {
   uint64_t seed;
   unsigned long long *acc;  // kAccSlots x {lo, hi}
   double p_lo;              // sample edges with p_lo <= uniform < p (nested samples)
+  // per-edge write-out (micro statistics; null otherwise): the counting
+  // kernels store t, k4, cyc of edge id e in row e - micro_base of a
+  // kMicroCols-wide int64 matrix, columns kMicroColT / K4 / Cyc
+  long long *micro;
+  int64_t micro_base, micro_len;
 };
+
+// micro statistics: one row of 17 int64 per edge, column i-1 = graphlet G_i
+constexpr int kMicroCols = 17;
+constexpr int kMicroColT = 2;    // G3 (triangles) = t
+constexpr int kMicroColK4 = 6;   // G7 (4-cliques) = k4
+constexpr int kMicroColCyc = 9;  // G10 (4-cycles) = cyc
 
 // A contiguous range of canonical edge ids of one slot.
 struct RangeDesc {
@@ -131,5 +142,16 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
                                const int64_t *item_cnt, const int64_t *tbase, const int32_t *tlist, void *gacc,
                                KernelCfg cfg, hipStream_t s);
 size_t gedge_bytes();
+// micro statistics: t of every arc (position j of col holds |Gamma(x) n
+// Gamma(col[j])| for the row x owning j), vertex triangle counts, the
+// per-edge sentinel fill, and the rows of edges [e0, e1)
+hipError_t launch_micro_arc_tri(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges,
+                                const int64_t *hoff, const uint32_t *htab, int64_t m, int32_t *t_arc, hipStream_t s);
+hipError_t launch_micro_vertex_tri(const int32_t *row_ptr, const int32_t *t_arc, int64_t n, int64_t *tri,
+                                   hipStream_t s);
+hipError_t launch_micro_mark(long long *out, int64_t rows, hipStream_t s);
+hipError_t launch_micro_rows(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges, const int64_t *vol2,
+                             const int32_t *t_arc, const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1,
+                             long long *out, unsigned long long *colmax, int *err, int grid, hipStream_t s);
 
 }  // namespace lge

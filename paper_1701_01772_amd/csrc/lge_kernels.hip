@@ -215,6 +215,30 @@ __device__ u128 edge_term(int k, int64_t n, int64_t m, int64_t da, int64_t db, i
   return 0;
 }
 
+// Per-edge write-out of (t, k4, cyc) for the micro statistics: the canonical
+// edge list is sorted by (u << 32 | v), so a binary search over the requested
+// id range gives the row.
+__device__ __forceinline__ void micro_put(const SlotDesc &S, int32_t a, int32_t b, int64_t t, int64_t k4,
+                                          int64_t cyc) {
+  if (!S.micro) return;
+  const uint64_t key = a < b ? (((uint64_t)(uint32_t)a << 32) | (uint32_t)b)
+                             : (((uint64_t)(uint32_t)b << 32) | (uint32_t)a);
+  int64_t lo = S.micro_base, hi = S.micro_base + S.micro_len;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (S.edges[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lo < S.micro_base + S.micro_len && S.edges[lo] == key) {
+    long long *row = S.micro + (lo - S.micro_base) * kMicroCols;
+    row[kMicroColT] = t;
+    row[kMicroColK4] = k4;
+    row[kMicroColCyc] = cyc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Graph preprocessing (once per resident graph)
 // ---------------------------------------------------------------------------
@@ -862,6 +886,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       k4 = block_sum_u64<NT>(k4, red);
       cyc = block_sum_u64<NT>(cyc, red);
       if (tid < kWave) acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(k4 / 2), (int64_t)cyc);
+      if (tid == 0) micro_put(S, a, b, t, (int64_t)(k4 / 2), (int64_t)cyc);
       __syncthreads();
     }
   }
@@ -1260,11 +1285,214 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
         const u128 v = edge_term(lane, S.n, S.m, da, db, t, (int64_t)(kk / 2), (int64_t)cc);
         if (v != 0) atomic_add_u128(S.acc + 2 * lane, v);
       }
+      if (lane == 0) micro_put(S, a, b, t, (int64_t)(kk / 2), (int64_t)cc);
     }
     __syncthreads();
   }
   const unsigned long long wsum = block_sum_u64<NT>(words, red);
   if (tid == 0 && wsum) atomicAdd(words_out, wsum);
+}
+
+// ---------------------------------------------------------------------------
+// Micro-level statistics (Sec. 3, Alg. 7 with p_e = 1): for every edge of a
+// range, the number of induced k-vertex subgraphs of each type G_i that hold
+// both ends of the edge.  The searches that need the neighbourhoods of the
+// neighbours (k4, cyc) come from the counting kernels above through
+// micro_put; everything else follows from per-arc triangle counts:
+//   tau_a   = sum over w in T_e of t(a, w)    (arcs a-w of the T_e members)
+//   omega   = edges T_e - (S_a u S_b)        = tau_a + tau_b - 2t - 4 k4
+//   e(S_a)  = edges inside S_a               = tri(a) - tau_a + k4
+//   RT      = edges T_e - R                  = sum_T d_w - 2t - 2k4 - omega
+//   RS      = edges (S_a u S_b) - R          = sum_S d_w - s - omega
+//                                               - 2(e(S_a) + e(S_b)) - 2 cyc
+//   e(R)    = edges inside R = f - (k4 + omega + e(S_a) + e(S_b) + cyc) - RT - RS
+// with R the vertices adjacent to neither end, f the edges that share no end
+// with e, tri(x) the triangles at x and sum_S d_w = vol2(a) + vol2(b)
+// - d_a - d_b - 2 sum_T d_w.  The row then reads
+//   G1 1, G3 t, G4 s, G5 r, G7 k4, G8 C(t,2) - k4 + omega,
+//   G9 e(S_a) + e(S_b) + t s - omega + RT, G10 cyc,
+//   G11 C(s_a,2) - e(S_a) + C(s_b,2) - e(S_b), G12 s_a s_b - cyc + RS,
+//   G13 t r - RT, G14 s r - RS, G15 e(R), G16 C(r,2) - e(R), G2 = G6 = G17 = 0.
+// ---------------------------------------------------------------------------
+
+// first position in the sorted list a[0, len) holding a value >= x
+__device__ __forceinline__ int row_lower(const int32_t *__restrict__ a, int len, int32_t x) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+constexpr int kMicroGroup = 16;  // lanes per edge
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = kMicroGroup / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kMicroGroup);
+  return v;
+}
+
+// t(u, v) of every edge, stored at both arcs
+__global__ __launch_bounds__(256) void k_micro_arc_tri(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       const uint64_t *__restrict__ edges,
+                                                       const int64_t *__restrict__ hoff,
+                                                       const uint32_t *__restrict__ htab, int64_t m,
+                                                       int32_t *__restrict__ t_arc) {
+  const int gl = threadIdx.x & (kMicroGroup - 1);
+  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kMicroGroup;
+  const int64_t ng = ((int64_t)gridDim.x * blockDim.x) / kMicroGroup;
+  for (int64_t e = g0; e < m; e += ng) {
+    const uint64_t key = edges[e];
+    const int32_t u = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
+    const int32_t ub = rp[u], du = rp[u + 1] - ub, vb = rp[v], dv = rp[v + 1] - vb;
+    const bool us = du <= dv;
+    const int32_t abeg = us ? ub : vb, da = us ? du : dv, b = us ? v : u;
+    const int32_t bbeg = us ? vb : ub, db = us ? dv : du;
+    const bool hb = has_table(db);
+    const uint32_t *btab = hb ? htab + hoff[b] : nullptr;
+    const int blg = table_log(db);
+    int cnt = 0;
+    for (int i = gl; i < da; i += kMicroGroup) {
+      const int32_t x = col[abeg + i];
+      if (x == b) continue;
+      bool in;
+      if (hb) {
+        in = table_find(btab, blg, (uint32_t)x) >= 0;
+      } else {
+        const int k = row_lower(col + bbeg, db, x);
+        in = k < db && col[bbeg + k] == x;
+      }
+      cnt += in ? 1 : 0;
+    }
+    cnt = group_sum(cnt);
+    if (gl == 0) {
+      const int pu = row_lower(col + ub, du, v), pv = row_lower(col + vb, dv, u);
+      if (pu < du) t_arc[ub + pu] = cnt;
+      if (pv < dv) t_arc[vb + pv] = cnt;
+    }
+  }
+}
+
+// tri(x) = half the sum of t over the arcs of x; one wavefront per vertex
+__global__ __launch_bounds__(256) void k_micro_vertex_tri(const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ t_arc, int64_t n,
+                                                          int64_t *__restrict__ tri) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t x = w0; x < n; x += nw) {
+    unsigned long long acc = 0;
+    const int32_t end = rp[x + 1];
+    for (int32_t j = rp[x] + lane; j < end; j += 64) acc += (unsigned long long)t_arc[j];
+    acc = wave_sum_u64(acc);
+    if (lane == 0) tri[x] = (int64_t)(acc / 2);
+  }
+}
+
+// sentinel -1 in the columns the counting kernels fill
+__global__ __launch_bounds__(256) void k_micro_mark(long long *__restrict__ out, int64_t rows) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+    long long *row = out + r * kMicroCols;
+    row[kMicroColT] = -1;
+    row[kMicroColK4] = -1;
+    row[kMicroColCyc] = -1;
+  }
+}
+
+__device__ __forceinline__ long long micro_pick(int c, const long long *y) {
+  long long v = 0;
+#pragma unroll
+  for (int i = 0; i < kMicroGroup; ++i)
+    if (c == i) v = y[i];
+  return v;
+}
+
+// the rows of edges [e0, e1); one group of kMicroGroup lanes per edge, lane c
+// writes column c (lane 0 also column 16); column maxima reduced per block
+__global__ __launch_bounds__(256) void k_micro_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                   const uint64_t *__restrict__ edges,
+                                                   const int64_t *__restrict__ vol2,
+                                                   const int32_t *__restrict__ t_arc,
+                                                   const int64_t *__restrict__ tri, int64_t n, int64_t m, int64_t e0,
+                                                   int64_t e1, long long *__restrict__ out,
+                                                   unsigned long long *__restrict__ colmax, int *__restrict__ err) {
+  __shared__ unsigned long long smax[kMicroCols];
+  if (threadIdx.x < kMicroCols) smax[threadIdx.x] = 0;
+  __syncthreads();
+  const int gl = threadIdx.x & (kMicroGroup - 1);
+  const int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kMicroGroup;
+  const int64_t ng = ((int64_t)gridDim.x * blockDim.x) / kMicroGroup;
+  unsigned long long mx = 0;
+  for (int64_t e = e0 + g0; e < e1; e += ng) {
+    const uint64_t key = edges[e];
+    const int32_t u = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
+    const int32_t ub = rp[u], du = rp[u + 1] - ub, vb = rp[v], dv = rp[v + 1] - vb;
+    const bool us = du <= dv;
+    const int32_t a = us ? u : v, b = us ? v : u;
+    const int32_t abeg = us ? ub : vb, da = us ? du : dv;
+    const int32_t bbeg = us ? vb : ub, db = us ? dv : du;
+    long long st = 0, sdt = 0, ta = 0, tb = 0;
+    for (int i = gl; i < da; i += kMicroGroup) {
+      const int32_t x = col[abeg + i];
+      if (x == b) continue;
+      const int k = row_lower(col + bbeg, db, x);
+      if (k < db && col[bbeg + k] == x) {
+        st += 1;
+        sdt += rp[x + 1] - rp[x];
+        ta += t_arc[abeg + i];
+        tb += t_arc[bbeg + k];
+      }
+    }
+    st = group_sum(st);
+    sdt = group_sum(sdt);
+    ta = group_sum(ta);
+    tb = group_sum(tb);
+    long long *row = out + (e - e0) * kMicroCols;
+    const long long t = row[kMicroColT], k4 = row[kMicroColK4], cyc = row[kMicroColCyc];
+    if (t != st || k4 < 0 || cyc < 0) {  // the counting pass missed this edge
+      if (gl == 0) atomicOr(err, 1);
+      continue;
+    }
+    const long long DA = da, DB = db;
+    const long long sa = DA - 1 - t, sb = DB - 1 - t, s = sa + sb;
+    const long long r = (long long)n - DA - DB + t;
+    const long long f = (long long)m - DA - DB + 1;
+    const long long omega = ta + tb - 2 * t - 4 * k4;
+    const long long esa = tri[a] - ta + k4, esb = tri[b] - tb + k4;
+    const long long rt = sdt - 2 * t - 2 * k4 - omega;
+    const long long sds = vol2[a] + vol2[b] - DA - DB - 2 * sdt;
+    const long long rs = sds - s - omega - 2 * (esa + esb) - 2 * cyc;
+    const long long er = f - (k4 + omega + esa + esb + cyc) - rt - rs;
+    long long y[kMicroGroup];
+    y[0] = 1;
+    y[1] = 0;
+    y[2] = t;
+    y[3] = s;
+    y[4] = r;
+    y[5] = 0;
+    y[6] = k4;
+    y[7] = t * (t - 1) / 2 - k4 + omega;
+    y[8] = esa + esb + t * s - omega + rt;
+    y[9] = cyc;
+    y[10] = sa * (sa - 1) / 2 - esa + sb * (sb - 1) / 2 - esb;
+    y[11] = sa * sb - cyc + rs;
+    y[12] = t * r - rt;
+    y[13] = s * r - rs;
+    y[14] = er;
+    y[15] = r * (r - 1) / 2 - er;
+    const long long val = micro_pick(gl, y);
+    row[gl] = val;
+    mx = (unsigned long long)val > mx ? (unsigned long long)val : mx;
+    if (gl == 0) row[16] = 0;  // G17: no independent set holds an edge
+  }
+  atomicMax(&smax[gl], mx);  // column 16 (G17) stays 0
+  __syncthreads();
+  if (threadIdx.x < kMicroCols && smax[threadIdx.x]) atomicMax(colmax + threadIdx.x, smax[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1503,5 +1731,38 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 }
 
 size_t gedge_bytes() { return sizeof(GEdge); }
+
+hipError_t launch_micro_arc_tri(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges,
+                                const int64_t *hoff, const uint32_t *htab, int64_t m, int32_t *t_arc, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_micro_arc_tri, dim3(grid_for(m, 256 / kMicroGroup, 16384)), dim3(256), 0, s, row_ptr, col,
+                     edges, hoff, htab, m, t_arc);
+  return hipGetLastError();
+}
+
+hipError_t launch_micro_vertex_tri(const int32_t *row_ptr, const int32_t *t_arc, int64_t n, int64_t *tri,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_micro_vertex_tri, dim3(grid_for(n, 4, 16384)), dim3(256), 0, s, row_ptr, t_arc, n, tri);
+  return hipGetLastError();
+}
+
+hipError_t launch_micro_mark(long long *out, int64_t rows, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_micro_mark, dim3(grid_for(rows, 256, 8192)), dim3(256), 0, s, out, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_micro_rows(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges, const int64_t *vol2,
+                             const int32_t *t_arc, const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1,
+                             long long *out, unsigned long long *colmax, int *err, int grid, hipStream_t s) {
+  if (e1 <= e0) return hipSuccess;
+  const int need = grid_for(e1 - e0, 256 / kMicroGroup, 1 << 20);
+  const int g = need < grid ? need : grid;
+  hipLaunchKernelGGL(k_micro_rows, dim3(g), dim3(256), 0, s, row_ptr, col, edges, vol2, t_arc, tri, n, m, e0, e1,
+                     out, colmax, err);
+  return hipGetLastError();
+}
+
 
 }  // namespace lge

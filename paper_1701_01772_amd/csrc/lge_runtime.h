@@ -31,6 +31,11 @@ struct lge_graph {
   int64_t hc = 0;
   int32_t codeg_tau = 0;
   double work_per_id = 0.0;  // scheduling weight per canonical edge id
+  // micro statistics, built on first use: t of every arc, triangles per
+  // vertex, and a small reduction buffer (column maxima, error flag)
+  int32_t *t_arc = nullptr;
+  int64_t *tri = nullptr;
+  unsigned long long *mred = nullptr;
 };
 
 struct Workspace {
@@ -89,6 +94,7 @@ struct Job {
   int64_t m_override;
   int64_t eid_base;     // subtracted from edge ids before the sampler
   double p_lo = 0.0;    // sample only edges whose uniform is >= p_lo (adaptive rounds)
+  long long *micro = nullptr;  // per-edge (t, k4, cyc) write-out rows for [e0, e1)
 };
 
 // Runs sample -> bin -> count for the jobs in one launch sequence on the

@@ -31,6 +31,8 @@ LGE_EBUSY = -6
 LGE_ETIMEDOUT = -7
 LGE_ECANCELED = -8
 LGE_ENOTFOUND = -9
+LGE_EINTERNAL = -10
+LGE_MICRO_COLS = 17
 LGE_FLAG_TRUSTED = 1
 LGE_OPT_SORT_HUB = 1
 LGE_OPT_XCD_LOCAL = 2
@@ -67,7 +69,7 @@ class Timing(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_float), ("sample_ms", ctypes.c_float), ("count_ms", ctypes.c_float * 3),
                 ("global_prep_ms", ctypes.c_float),
                 ("class_edges", ctypes.c_uint64 * 3), ("words_read", ctypes.c_uint64 * 3),
-                ("launches", ctypes.c_uint64)]
+                ("launches", ctypes.c_uint64), ("micro_ms", ctypes.c_float), ("pad", ctypes.c_float)]
 
 
 class Batch(ctypes.Structure):
@@ -150,6 +152,7 @@ def load():
         "lge_adaptive_cfg_default": ([ctypes.POINTER(AdaptiveCfg)], ctypes.c_int),
         "lge_estimate_adaptive": ([_VP, _VP, ctypes.c_uint64, ctypes.POINTER(AdaptiveCfg), ctypes.POINTER(Result),
                                    ctypes.POINTER(AdaptiveTrace)], ctypes.c_int),
+        "lge_micro": ([_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "lge_server_cfg_default": ([ctypes.POINTER(ServerCfg)], ctypes.c_int),
         "lge_server_create": ([_VP, ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)], ctypes.c_int),
         "lge_server_add_graph": ([_VP, _VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -345,7 +348,7 @@ def lge_last_timing(ctx) -> dict:
     return {"total_ms": t.total_ms, "sample_ms": t.sample_ms, "count_ms": list(t.count_ms),
             "global_prep_ms": t.global_prep_ms,
             "class_edges": [int(x) for x in t.class_edges], "words_read": [int(x) for x in t.words_read],
-            "launches": int(t.launches)}
+            "launches": int(t.launches), "micro_ms": t.micro_ms}
 
 
 def lge_autotune(ctx, g, p: float) -> Opts:
@@ -364,6 +367,27 @@ def lge_estimate_adaptive(ctx, g, seed: int, beta: float = 0.01, t_max: int = 20
     k = tr.rounds
     return result_dict(r), {"rounds": k, "p": list(tr.p[:k]), "delta": list(tr.delta[:k]),
                             "sampled": [int(x) for x in tr.sampled[:k]]}
+
+
+def lge_micro(ctx, g, e0: int = 0, e1: int | None = None, out=None, device: str = "cuda:0"):
+    """Micro-level graphlet statistics of the edges [e0, e1): returns (rows,
+    colmax) with rows a (e1-e0) x 17 int64 torch tensor on the device (the
+    one given as ``out`` if any) and colmax the 18 column maxima (index i =
+    graphlet G_i)."""
+    import torch
+    if e1 is None:
+        e1 = int(load().lge_graph_m(g))
+    nrows = max(int(e1) - int(e0), 0)
+    if out is None:
+        out = torch.empty((nrows, LGE_MICRO_COLS), dtype=torch.int64, device=device)
+    elif (out.dtype != torch.int64 or not out.is_cuda or not out.is_contiguous()
+          or tuple(out.shape) != (nrows, LGE_MICRO_COLS)):
+        raise ValueError("out must be a contiguous (e1-e0) x 17 int64 device tensor")
+    torch.cuda.synchronize(out.device)  # the library works on its own stream
+    cm = (ctypes.c_int64 * 18)()
+    _check(load().lge_micro(ctx, g, int(e0), int(e1), ctypes.c_void_p(out.data_ptr() if nrows else 0), cm),
+           "lge_micro")
+    return out, list(cm)
 
 
 def lge_server_cfg_default() -> ServerCfg:
