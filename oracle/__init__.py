@@ -15,7 +15,13 @@ Pins (each checked by a ``-m "not gpu"`` test, see tests/test_oracle_*.py):
   * exact unbiasedness of X and of the variance estimate by enumerating every
     sample outcome on tiny graphs (Sec. 2.4);
   * Philox4x32-10 known-answer vectors and a cross-check against an
-    independent Philox implementation.
+    independent Philox implementation;
+  * micro rows (``micro``) against a per-edge brute-force enumeration and
+    edge-weighted census sums;
+  * the adaptive loop (``adaptive.py``), the weighted and fixed-size designs
+    and k-core numbers (``designs.py``): schedule closed forms, brute-force
+    cores, exact unbiasedness by enumerating every sample outcome, planted
+    mistakes caught.
 """
 from __future__ import annotations
 
@@ -85,6 +91,9 @@ def _load():
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_micro.argtypes = [ctypes.c_int64, i32p, i32p, i32p, i32p, ctypes.c_int64, i64p]
         lib.oracle_micro.restype = ctypes.c_int
+        lib.oracle_philox_keys.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.POINTER(ctypes.c_uint64)]
+        lib.oracle_philox_keys.restype = None
         _lib = lib
     return _lib
 
@@ -125,6 +134,14 @@ def sample_mask(seed: int, p: float, m: int, e0: int = 0, e1: int | None = None)
         _load().oracle_sample_mask(seed, p, e0, e1, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
         mask[e0:e1] = sub
     return mask[:m] if m > 0 else mask
+
+
+def philox_keys(seed: int, m: int) -> np.ndarray:
+    """uint64[m]: the 64-bit Philox output (x1:x0) of every edge id."""
+    out = np.zeros(max(m, 1), dtype=np.uint64)
+    if m > 0:
+        _load().oracle_philox_keys(seed, 0, m, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return out[:m]
 
 
 def _csr(row_ptr, col):

@@ -548,3 +548,16 @@ int oracle_micro(int64_t n, const int32_t *row_ptr, const int32_t *col, const in
   free(tag);
   return 0;
 }
+
+/* The 64-bit Philox output (x1:x0) of every edge id in [e0, e1): the key
+ * whose top 53 bits are the edge's uniform (fixed-size samples take the K
+ * smallest keys). */
+void oracle_philox_keys(uint64_t seed, uint64_t e0, uint64_t e1, uint64_t *out) {
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (uint64_t e = e0; e < e1; ++e) {
+    uint32_t ctr[4] = {(uint32_t)e, (uint32_t)(e >> 32), 0u, 0u};
+    uint32_t x[4];
+    oracle_philox4x32_10(ctr, key, x);
+    out[e - e0] = ((uint64_t)x[1] << 32) | (uint64_t)x[0];
+  }
+}
