@@ -286,6 +286,66 @@ LGE_API int lge_estimate_adaptive(lge_ctx *ctx, const lge_graph *g, uint64_t see
                                   lge_result *out, lge_adaptive_trace *trace);
 
 /*
+ * Weighted edge sampling (Sec. 2.2: the edge neighbourhoods may be drawn by
+ * an arbitrary weighted distribution F, e.g. k-core numbers or degrees; Sec. 5
+ * biases the sample towards large k-cores).  Edge e has weight
+ *   LGE_WEIGHT_DEGREE : w_e = d_u + d_v - 2 (the edges sharing an end with e)
+ *   LGE_WEIGHT_KCORE  : w_e = min(core(u), core(v))
+ * quantised to 16 classes, class(e) = min(15, floor(log2 max(1, w_e))), and is
+ * kept iff its Philox uniform (as in lge_estimate) is below
+ * p_class = min(1, c 2^class), with c chosen so that the expected sample size
+ * is p_mean * m.  The estimate is the Horvitz-Thompson sum
+ * X_i = K_i + sum_{e in J} Y_i(e) / p_e, the variance estimate
+ * V_i = sum_{e in J} (1 - p_e) / p_e^2 Y_i(e)^2 (the Sec. 2.4 argument with a
+ * per-edge probability), both exact integers per class combined in FP64 in
+ * class order.  out->csum, z, q and sampled_edges are totals over the
+ * classes, out->p = p_mean.  info (may be NULL) receives the class
+ * probabilities, class sizes and sampled edges per class, and the graph's
+ * largest core number (k-core mode; -1 before it is computed).  The first
+ * call per mode builds and caches the classes (m bytes; k-core mode also the
+ * core numbers, 4n bytes).  Errors: LGE_EINVAL (mode, p_mean outside (0,1],
+ * null pointers), LGE_ENOMEM, LGE_EDEVICE, LGE_EINTERNAL.
+ */
+#define LGE_WEIGHT_DEGREE 1
+#define LGE_WEIGHT_KCORE 2
+#define LGE_WEIGHT_CLASSES 16
+typedef struct {
+  double p_level[LGE_WEIGHT_CLASSES];
+  uint64_t edges[LGE_WEIGHT_CLASSES];
+  uint64_t sampled[LGE_WEIGHT_CLASSES];
+  int32_t max_core;
+  int32_t pad;
+} lge_weight_info;
+
+LGE_API int lge_estimate_weighted(lge_ctx *ctx, const lge_graph *g, int32_t mode, double p_mean, uint64_t seed,
+                                  const lge_opts *opts, lge_result *out, lge_weight_info *info);
+
+/*
+ * k-core numbers (the weights of the Sec. 5 extremal estimation): core(v) is
+ * the largest k such that v survives the repeated deletion of vertices of
+ * degree < k.  core_out: DEVICE pointer to n int32 (may be NULL); max_core:
+ * host pointer (may be NULL).  Computed once per graph by level-synchronous
+ * peeling on the device and cached.  Errors: LGE_EINVAL, LGE_ENOMEM,
+ * LGE_EDEVICE, LGE_EINTERNAL.
+ */
+LGE_API int lge_core_numbers(lge_ctx *ctx, const lge_graph *g, int32_t *core_out, int32_t *max_core);
+
+/*
+ * Fixed-size sample (Alg. 1 with a sample size K) and the ratio estimator
+ * sigma = m / K (the printed p_i = |J| / |E| of Sec. 2.3): the K edges with
+ * the smallest 64-bit Philox keys (x1:x0 of the draw lge_estimate uses; ties
+ * broken by edge id) form a uniformly random K-subset;
+ * X_i = K_i + (m / K) sum_{e in J} Y_i(e) and the unbiased variance estimate
+ * of sampling without replacement V_i = m (m - K) s_i^2 / K, s_i^2 the sample
+ * variance of Y_i(e) (NaN for K = 1; 0 for K = m, where X is exact).  The
+ * numerator K Q_i - Z_i^2 is formed exactly in 256 bits.  out->p = K / m.
+ * Errors: LGE_EINVAL (K = 0 or K > m, null pointers), LGE_ENOMEM, LGE_EDEVICE,
+ * LGE_EINTERNAL.
+ */
+LGE_API int lge_estimate_fixed_k(lge_ctx *ctx, const lge_graph *g, uint64_t k, uint64_t seed, const lge_opts *opts,
+                                 lge_result *out);
+
+/*
  * Micro-level graphlet statistics (Sec. 3, the micro problem and Alg. 7 with
  * p_e = 1, every neighbour examined once): for every edge e = (u, v) with
  * canonical id in [e0, e1), row e - e0 of `out` holds 17 int64, column i-1 =

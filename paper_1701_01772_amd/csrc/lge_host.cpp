@@ -519,6 +519,9 @@ static void graph_free(lge_graph *g) {
   dev_free(g->t_arc);
   dev_free(g->tri);
   dev_free(g->mred);
+  dev_free(g->core);
+  dev_free(g->wlevel[0]);
+  dev_free(g->wlevel[1]);
 }
 
 static int32_t host_max_deg(int64_t n, const int32_t *row_ptr) {
@@ -663,21 +666,24 @@ static double to_double(i128 x) {
 }
 
 // acc: kAccSlots x {lo, hi} as produced by the kernels
-void lge_finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned long long *acc,
-                     lge_result *out) {
-  memset(out, 0, sizeof(*out));
-  out->n = n;
-  out->m = m;
-  out->p = p;
-  out->seed = seed;
-  out->sampled_edges = (uint64_t)u128_of(acc + 2 * kAccIdxCount);
+// The exact sums of one accumulator slot: C (unrestricted counts), Z (sums of
+// 12 Y_i(e), linear in C), Q (sums of (12 Y_i(e))^2) and the edge count.
+struct ExactSums {
+  i128 C[18];
+  i128 Z[18];
+  u128 Q[18];
+  uint64_t count;
+};
+
+static void sums_from_acc(const unsigned long long *acc, ExactSums *s) {
+  memset(s, 0, sizeof(*s));
+  s->count = (uint64_t)u128_of(acc + 2 * kAccIdxCount);
   static const int cidx[kNumC] = {3, 4, 5, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16};
-  i128 C[18] = {0};
+  i128 *C = s->C;
   for (int k = 0; k < kNumC; ++k) C[cidx[k]] = (i128)u128_of(acc + 2 * k);
-  u128 Q[18] = {0};
-  for (int k = 0; k < kNumQ; ++k) Q[3 + k] = u128_of(acc + 2 * (kNumC + k));
+  for (int k = 0; k < kNumQ; ++k) s->Q[3 + k] = u128_of(acc + 2 * (kNumC + k));
   // Z_i = sum of 12 Y_i(e); the map from the C sums is linear
-  i128 Z[18] = {0};
+  i128 *Z = s->Z;
   const i128 d87 = C[8] - C[7];
   const i128 z9_3 = 2 * C[9] - 8 * d87;
   Z[3] = 4 * C[3];
@@ -696,35 +702,64 @@ void lge_finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned 
   Z[16] = 12 * C[16] - 2 * Z[15];
   Z[17] = 0;
   for (int i = 7; i <= 16; ++i) Z[17] -= Z[i];
-  i128 K[18] = {0};
+}
+
+static void sums_add(ExactSums *a, const ExactSums &b) {
+  for (int i = 0; i < 18; ++i) {
+    a->C[i] += b.C[i];
+    a->Z[i] += b.Z[i];
+    a->Q[i] += b.Q[i];
+  }
+  a->count += b.count;
+}
+
+// Integer fields of a result from exact sums; K receives the constants
+// K_6 = C(n,3), K_17 = C(n,4), E the exact counts valid when every edge is in
+// the sample.
+static void fill_exact(int64_t n, int64_t m, double p, uint64_t seed, const ExactSums &t, lge_result *out,
+                       i128 K[18], i128 E[18]) {
+  memset(out, 0, sizeof(*out));
+  out->n = n;
+  out->m = m;
+  out->p = p;
+  out->seed = seed;
+  out->sampled_edges = t.count;
+  for (int i = 0; i < 18; ++i) K[i] = E[i] = 0;
   K[6] = binom(n, 3);
   K[17] = binom(n, 4);
-  i128 E[18] = {0};
   E[1] = m;
   E[2] = binom(n, 2) - m;
-  for (int i = 3; i <= 17; ++i) E[i] = K[i] + Z[i] / 12;
+  for (int i = 3; i <= 17; ++i) E[i] = K[i] + t.Z[i] / 12;
   for (int i = 0; i < 18; ++i) {
-    out->csum[i] = to_abi((u128)C[i]);
-    out->z[i] = to_abi((u128)Z[i]);
-    out->q[i] = to_abi(Q[i]);
+    out->csum[i] = to_abi((u128)t.C[i]);
+    out->z[i] = to_abi((u128)t.Z[i]);
+    out->q[i] = to_abi(t.Q[i]);
     out->exact[i] = to_abi((u128)E[i]);
   }
+}
+
+static void set_xv(lge_result *out, int i, double x, double v) {
+  const double h = 1.96 * sqrt(v);
+  out->estimate[i] = x;
+  out->variance[i] = v;
+  out->lower95[i] = x - h;
+  out->upper95[i] = x + h;
+}
+
+void lge_finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned long long *acc,
+                  lge_result *out) {
+  ExactSums t;
+  sums_from_acc(acc, &t);
+  i128 K[18], E[18];
+  fill_exact(n, m, p, seed, t, out, K, E);
   const double sigma = 1.0 / p;
   const double vfac = (1.0 - p) / (p * p);
   for (int i = 1; i <= 17; ++i) {
-    double x, v;
-    if (i <= 2 || p == 1.0) {
-      x = to_double(E[i]);
-      v = 0.0;
-    } else {
-      x = to_double(K[i]) + (to_double(Z[i]) * sigma) / 12.0;
-      v = (to_double((i128)Q[i]) * vfac) / 144.0;
-    }
-    const double h = 1.96 * sqrt(v);
-    out->estimate[i] = x;
-    out->variance[i] = v;
-    out->lower95[i] = x - h;
-    out->upper95[i] = x + h;
+    if (i <= 2 || p == 1.0)
+      set_xv(out, i, to_double(E[i]), 0.0);
+    else
+      set_xv(out, i, to_double(K[i]) + (to_double(t.Z[i]) * sigma) / 12.0,
+             (to_double((i128)t.Q[i]) * vfac) / 144.0);
   }
 }
 
@@ -751,19 +786,26 @@ static Bins make_bins(Workspace &w) {
 
 // Runs sample -> bin -> count for every job; leaves per-job accumulators in
 // ws.h_acc (host) on success.
+int lge_job_slots(const Job &j) { return j.design == kDesignWeighted ? kWeightLevels : 1; }
+
 int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts) {
   if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
   int64_t total = 0;
-  for (int j = 0; j < njobs; ++j) total += jobs[j].e1 - jobs[j].e0;
-  int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), njobs, njobs);
+  int nslots = 0;
+  for (int j = 0; j < njobs; ++j) {
+    total += jobs[j].e1 - jobs[j].e0;
+    nslots += lge_job_slots(jobs[j]);
+  }
+  int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), nslots, njobs);
   if (rc != LGE_OK) return rc;
   Workspace &w = ctx->ws;
   hipStream_t s = ctx->stream;
   const KernelCfg cfg = make_cfg(ctx, opts);
   int64_t pref = 0;
+  int slot0 = 0;
   for (int j = 0; j < njobs; ++j) {
     const lge_graph *g = jobs[j].g;
-    SlotDesc &sd = w.h_slots[j];
+    SlotDesc &sd = w.h_slots[slot0];
     sd.row_ptr = g->row_ptr;
     sd.col = g->col;
     sd.edges = g->edges ? g->edges + jobs[j].eid_base : nullptr;
@@ -778,12 +820,23 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.p = jobs[j].p;
     sd.p_lo = jobs[j].p_lo;
     sd.seed = jobs[j].seed;
-    sd.acc = w.acc + (int64_t)j * kAccSlots * 2;
+    sd.acc = w.acc + (int64_t)slot0 * kAccSlots * 2;
     sd.micro = jobs[j].micro;
     sd.micro_base = jobs[j].e0 - jobs[j].eid_base;
     sd.micro_len = jobs[j].e1 - jobs[j].e0;
+    sd.design = jobs[j].design;
+    sd.pad = 0;
+    sd.level = jobs[j].level;
+    sd.kkey = jobs[j].kkey;
+    sd.keid = jobs[j].keid;
+    for (int l = 0; l < kWeightLevels; ++l) sd.plev[l] = jobs[j].plev ? jobs[j].plev[l] : 0.0;
+    for (int l = 1; l < lge_job_slots(jobs[j]); ++l) {  // one accumulator slot per class
+      w.h_slots[slot0 + l] = sd;
+      w.h_slots[slot0 + l].acc = w.acc + (int64_t)(slot0 + l) * kAccSlots * 2;
+    }
     RangeDesc &rd = w.h_ranges[j];
-    rd.slot = j;
+    rd.slot = slot0;
+    slot0 += lge_job_slots(jobs[j]);
     rd.pad = 0;
     rd.e0 = jobs[j].e0 - jobs[j].eid_base;
     rd.e1 = jobs[j].e1 - jobs[j].eid_base;
@@ -792,10 +845,10 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   }
   ctx->timing = lge_timing();
   hipEvent_t *ev = ctx->ev;
-  LGE_HIP(hipMemcpyAsync(w.slots, w.h_slots, (size_t)njobs * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
+  LGE_HIP(hipMemcpyAsync(w.slots, w.h_slots, (size_t)nslots * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
   LGE_HIP(hipMemcpyAsync(w.ranges, w.h_ranges, (size_t)njobs * sizeof(RangeDesc), hipMemcpyHostToDevice, s));
   LGE_HIP(launch_zero_u64(w.counters, 32, s));
-  LGE_HIP(launch_zero_u64(w.acc, (int64_t)njobs * kAccSlots * 2, s));
+  LGE_HIP(launch_zero_u64(w.acc, (int64_t)nslots * kAccSlots * 2, s));
   Bins bins = make_bins(w);
   LGE_HIP(hipEventRecord(ev[0], s));
   LGE_HIP(launch_sample_bin(w.slots, w.ranges, njobs, total, bins, cfg, s));
@@ -830,7 +883,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
-  LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)njobs * kAccSlots * 2 * sizeof(unsigned long long),
+  LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)nslots * kAccSlots * 2 * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, s));
   LGE_HIP(hipMemcpyAsync(w.h_counters, w.counters, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   LGE_HIP(hipStreamSynchronize(s));
@@ -1117,6 +1170,342 @@ extern "C" int lge_micro(lge_ctx *ctx, const lge_graph *gc, int64_t e0, int64_t 
   ctx->timing.launches += 3;
   if (colmax)
     for (int i = 0; i < LGE_MICRO_COLS; ++i) colmax[i + 1] = (int64_t)h[i];
+  return LGE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sampling designs: k-core weighted / degree weighted classes, fixed size
+// ---------------------------------------------------------------------------
+
+// k-core numbers by level-synchronous peeling; every level ends when no alive
+// vertex has degree <= k, the next level starts at the smallest alive degree
+static int ensure_core(lge_ctx *ctx, lge_graph *g) {
+  if (g->max_core >= 0) return LGE_OK;
+  const int64_t n = g->n;
+  dev_free(g->core);
+  int rc;
+  if ((rc = dev_alloc(&g->core, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
+  if (n == 0) {
+    g->max_core = 0;
+    return LGE_OK;
+  }
+  int32_t *deg = nullptr, *state = nullptr, *fa = nullptr, *fb = nullptr;
+  unsigned long long *cnt = nullptr;
+  auto cleanup = [&] {
+    dev_free(deg);
+    dev_free(state);
+    dev_free(fa);
+    dev_free(fb);
+    dev_free(cnt);
+  };
+  if ((rc = dev_alloc(&deg, n)) != LGE_OK || (rc = dev_alloc(&state, n)) != LGE_OK ||
+      (rc = dev_alloc(&fa, n)) != LGE_OK || (rc = dev_alloc(&fb, n)) != LGE_OK || (rc = dev_alloc(&cnt, 4)) != LGE_OK) {
+    cleanup();
+    return rc;
+  }
+  hipStream_t s = ctx->stream;
+  unsigned long long *h = ctx->ws.h_counters + 24;  // pinned staging (4 words)
+  auto fail = [&](hipError_t e) {
+    cleanup();
+    return hip_err(e);
+  };
+  hipError_t e = launch_core_init(g->row_ptr, n, deg, state, s);
+  if (e != hipSuccess) return fail(e);
+  int64_t removed = 0;
+  int32_t k = 0, kmax = 0;
+  while (removed < n) {
+    const unsigned long long init[2] = {0ull, ~0ull};
+    if ((e = hipMemcpyAsync(cnt, init, sizeof(init), hipMemcpyHostToDevice, s)) != hipSuccess) return fail(e);
+    if ((e = launch_core_scan(n, k, deg, state, fa, cnt, cnt + 1, s)) != hipSuccess) return fail(e);
+    if ((e = hipMemcpyAsync(h, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return fail(e);
+    int64_t fn = (int64_t)h[0];
+    if (fn == 0) {  // nothing left at this level: jump to the smallest alive degree
+      if (h[1] == ~0ull) break;
+      k = std::max<int32_t>(k + 1, (int32_t)h[1]);
+      continue;
+    }
+    kmax = k;
+    int32_t *front = fa, *next = fb;
+    while (fn > 0) {
+      if ((e = launch_zero_u64(cnt + 2, 1, s)) != hipSuccess) return fail(e);
+      if ((e = launch_core_peel(g->row_ptr, g->col, front, fn, k, deg, state, g->core, next, cnt + 2, s)) !=
+          hipSuccess)
+        return fail(e);
+      removed += fn;
+      if ((e = hipMemcpyAsync(h + 2, cnt + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+          (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(e);
+      fn = (int64_t)h[2];
+      std::swap(front, next);
+    }
+    ++k;
+  }
+  cleanup();
+  if (removed != n) return LGE_EINTERNAL;
+  g->max_core = kmax;
+  return LGE_OK;
+}
+
+extern "C" int lge_core_numbers(lge_ctx *ctx, const lge_graph *gc, int32_t *core_out, int32_t *max_core) {
+  if (!ctx || !gc || gc->ctx != ctx) return LGE_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  lge_graph *g = const_cast<lge_graph *>(gc);  // the cache is not part of the graph's value
+  const int rc = ensure_core(ctx, g);
+  if (rc != LGE_OK) return rc;
+  if (core_out && g->n > 0) {
+    LGE_HIP(hipMemcpyAsync(core_out, g->core, (size_t)g->n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
+    LGE_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  if (max_core) *max_core = g->max_core;
+  return LGE_OK;
+}
+
+static int ensure_levels(lge_ctx *ctx, lge_graph *g, int32_t mode) {
+  uint8_t *&lv = g->wlevel[mode - 1];
+  if (lv) return LGE_OK;
+  int rc;
+  if (mode == LGE_WEIGHT_KCORE && (rc = ensure_core(ctx, g)) != LGE_OK) return rc;
+  uint8_t *buf = nullptr;
+  unsigned long long *hist = nullptr;
+  if ((rc = dev_alloc(&buf, std::max<int64_t>(g->m, 1))) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&hist, kWeightLevels)) != LGE_OK) {
+    dev_free(buf);
+    return rc;
+  }
+  hipStream_t s = ctx->stream;
+  unsigned long long h[kWeightLevels];
+  hipError_t e = launch_zero_u64(hist, kWeightLevels, s);
+  if (e == hipSuccess) e = launch_weight_levels(mode, g->row_ptr, g->edges, g->core, g->m, buf, hist, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(hist);
+  if (e != hipSuccess) {
+    dev_free(buf);
+    return hip_err(e);
+  }
+  for (int l = 0; l < kWeightLevels; ++l) g->whist[mode - 1][l] = h[l];
+  lv = buf;
+  return LGE_OK;
+}
+
+// Class probabilities p_l = min(1, c 2^l) with sum_l hist_l p_l = p_mean m:
+// the classes from j up are saturated for the first j, counting down from
+// kWeightLevels, whose c keeps every non-empty lower class below 1 and every
+// non-empty saturated class at or above 1.
+static bool plan_levels(const uint64_t *hist, double p_mean, int64_t m, double *pl) {
+  if (p_mean >= 1.0) {
+    for (int l = 0; l < kWeightLevels; ++l) pl[l] = 1.0;
+    return true;
+  }
+  const double target = p_mean * (double)m;
+  for (int j = kWeightLevels; j >= 1; --j) {
+    uint64_t sat = 0, wsum = 0;
+    for (int l = j; l < kWeightLevels; ++l) sat += hist[l];
+    for (int l = 0; l < j; ++l) wsum += hist[l] << l;
+    if (wsum == 0) continue;
+    const double c = (target - (double)sat) / (double)wsum;
+    if (c <= 0.0) continue;
+    bool ok = true;
+    for (int l = 0; l < kWeightLevels && ok; ++l) {
+      if (!hist[l]) continue;
+      const double q = c * ldexp(1.0, l);
+      ok = l < j ? q < 1.0 : q >= 1.0;
+    }
+    if (!ok) continue;
+    for (int l = 0; l < kWeightLevels; ++l) pl[l] = std::min(1.0, c * ldexp(1.0, l));
+    return true;
+  }
+  return false;
+}
+
+extern "C" int lge_estimate_weighted(lge_ctx *ctx, const lge_graph *gc, int32_t mode, double p_mean, uint64_t seed,
+                                     const lge_opts *opts, lge_result *out, lge_weight_info *info) {
+  if (!ctx || !gc || !out || gc->ctx != ctx) return LGE_EINVAL;
+  if (mode != LGE_WEIGHT_DEGREE && mode != LGE_WEIGHT_KCORE) return LGE_EINVAL;
+  if (!(p_mean > 0.0 && p_mean <= 1.0)) return LGE_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  lge_graph *g = const_cast<lge_graph *>(gc);
+  int rc = ensure_levels(ctx, g, mode);
+  if (rc != LGE_OK) return rc;
+  const uint64_t *hist = g->whist[mode - 1];
+  double pl[kWeightLevels];
+  if (g->m == 0) {
+    for (int l = 0; l < kWeightLevels; ++l) pl[l] = 1.0;
+  } else if (!plan_levels(hist, p_mean, g->m, pl)) {
+    return LGE_EINTERNAL;
+  }
+  Job job{g, p_mean, seed, 0, g->m, -1, -1, 0};
+  job.design = kDesignWeighted;
+  job.level = g->wlevel[mode - 1];
+  job.plev = pl;
+  if ((rc = lge_run_jobs(ctx, &job, 1, opts)) != LGE_OK) return rc;
+  ExactSums lev[kWeightLevels], tot;
+  memset(&tot, 0, sizeof(tot));
+  bool full = true;
+  for (int l = 0; l < kWeightLevels; ++l) {
+    sums_from_acc(ctx->ws.h_acc + (int64_t)l * kAccSlots * 2, &lev[l]);
+    sums_add(&tot, lev[l]);
+    if (hist[l] && pl[l] != 1.0) full = false;
+  }
+  i128 K[18], E[18];
+  fill_exact(g->n, g->m, p_mean, seed, tot, out, K, E);
+  for (int i = 1; i <= 17; ++i) {
+    if (i <= 2 || full) {
+      set_xv(out, i, to_double(E[i]), 0.0);
+      continue;
+    }
+    // Horvitz-Thompson over the classes, in class order
+    double x = to_double(K[i]), v = 0.0;
+    for (int l = 0; l < kWeightLevels; ++l) x += (to_double(lev[l].Z[i]) * (1.0 / pl[l])) / 12.0;
+    for (int l = 0; l < kWeightLevels; ++l)
+      v += (to_double((i128)lev[l].Q[i]) * ((1.0 - pl[l]) / (pl[l] * pl[l]))) / 144.0;
+    set_xv(out, i, x, v);
+  }
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    for (int l = 0; l < kWeightLevels; ++l) {
+      info->p_level[l] = pl[l];
+      info->edges[l] = hist[l];
+      info->sampled[l] = lev[l].count;
+    }
+    info->max_core = g->max_core;
+  }
+  return LGE_OK;
+}
+
+// 256-bit helpers for the fixed-size variance numerator K Q - Z^2
+struct U256 {
+  u128 hi, lo;
+};
+
+static U256 mul_u128(u128 a, u128 b) {
+  const u128 a0 = (uint64_t)a, a1 = a >> 64, b0 = (uint64_t)b, b1 = b >> 64;
+  const u128 p00 = a0 * b0, p01 = a0 * b1, p10 = a1 * b0, p11 = a1 * b1;
+  const u128 mid = (p00 >> 64) + (u128)(uint64_t)p01 + (u128)(uint64_t)p10;
+  U256 r;
+  r.lo = (mid << 64) | (u128)(uint64_t)p00;
+  r.hi = p11 + (p01 >> 64) + (p10 >> 64) + (mid >> 64);
+  return r;
+}
+
+static U256 sub_u256(U256 a, U256 b) {
+  U256 r;
+  r.lo = a.lo - b.lo;
+  r.hi = a.hi - b.hi - (a.lo < b.lo ? 1 : 0);
+  return r;
+}
+
+static int bitlen_u128(u128 x) {
+  int b = 0;
+  for (; x; x >>= 1) ++b;
+  return b;
+}
+
+// correctly rounded (to nearest, ties to even)
+static double u256_to_double(U256 a) {
+  const int bits = a.hi ? 128 + bitlen_u128(a.hi) : bitlen_u128(a.lo);
+  if (bits <= 53) return (double)(uint64_t)a.lo;
+  const int sh = bits - 53;  // 1 .. 203
+  u128 mant;
+  bool gt_half, eq_half;
+  if (sh < 128) {
+    mant = (a.hi << (128 - sh)) | (a.lo >> sh);
+    const u128 rem = a.lo & ((((u128)1) << sh) - 1);
+    const u128 h = (u128)1 << (sh - 1);
+    gt_half = rem > h;
+    eq_half = rem == h;
+  } else if (sh == 128) {
+    mant = a.hi;
+    const u128 h = (u128)1 << 127;
+    gt_half = a.lo > h;
+    eq_half = a.lo == h;
+  } else {
+    mant = a.hi >> (sh - 128);
+    const u128 rem_hi = a.hi & ((((u128)1) << (sh - 128)) - 1);
+    const u128 h_hi = (u128)1 << (sh - 129);
+    gt_half = rem_hi > h_hi || (rem_hi == h_hi && a.lo != 0);
+    eq_half = rem_hi == h_hi && a.lo == 0;
+  }
+  if (gt_half || (eq_half && (mant & 1))) ++mant;
+  return ldexp((double)(uint64_t)mant, sh);
+}
+
+// K-th smallest composite key (Philox key << 64 | edge id) by 16 radix passes
+static int select_kth(lge_ctx *ctx, int64_t m, uint64_t seed, uint64_t k, uint64_t *kkey, int64_t *keid) {
+  hipStream_t s = ctx->stream;
+  unsigned long long *hist = nullptr;
+  int rc;
+  if ((rc = dev_alloc(&hist, 256)) != LGE_OK) return rc;
+  unsigned long long h[256];
+  u128 chosen = 0;
+  uint64_t r = k;  // 1-based rank among the keys matching the prefix
+  hipError_t e = hipSuccess;
+  for (int pass = 0; pass < 16 && e == hipSuccess; ++pass) {
+    const int shift = 120 - 8 * pass, top = shift + 8;
+    uint64_t pre_hi = 0, pre_lo = 0;
+    if (top >= 128) {
+    } else if (top >= 64) {
+      pre_hi = (uint64_t)chosen;
+    } else {
+      const u128 full = chosen << top;
+      pre_hi = (uint64_t)(full >> 64);
+      pre_lo = (uint64_t)full >> top;
+    }
+    if ((e = launch_zero_u64(hist, 256, s)) != hipSuccess) break;
+    if ((e = launch_select_hist(seed, m, shift, pre_hi, pre_lo, hist, s)) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    int d = 0;
+    while (d < 256 && h[d] < r) r -= h[d++];
+    if (d == 256) {
+      dev_free(hist);
+      return LGE_EINTERNAL;
+    }
+    chosen = (chosen << 8) | (u128)d;
+  }
+  dev_free(hist);
+  if (e != hipSuccess) return hip_err(e);
+  *kkey = (uint64_t)(chosen >> 64);
+  *keid = (int64_t)(uint64_t)chosen;
+  return LGE_OK;
+}
+
+extern "C" int lge_estimate_fixed_k(lge_ctx *ctx, const lge_graph *g, uint64_t k, uint64_t seed,
+                                    const lge_opts *opts, lge_result *out) {
+  if (!ctx || !g || !out || g->ctx != ctx) return LGE_EINVAL;
+  if (k < 1 || k > (uint64_t)g->m) return LGE_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  const int64_t m = g->m;
+  Job job{g, (double)k / (double)m, seed, 0, m, -1, -1, 0};
+  job.design = kDesignFixedK;
+  int rc = select_kth(ctx, m, seed, k, &job.kkey, &job.keid);
+  if (rc != LGE_OK) return rc;
+  if ((rc = lge_run_jobs(ctx, &job, 1, opts)) != LGE_OK) return rc;
+  ExactSums t;
+  sums_from_acc(ctx->ws.h_acc, &t);
+  if (t.count != k) return LGE_EINTERNAL;
+  i128 K[18], E[18];
+  fill_exact(g->n, m, (double)k / (double)m, seed, t, out, K, E);
+  const bool full = (int64_t)k == m;
+  const double sigma = (double)m / (double)k;
+  const double gfac = k >= 2 ? (double)m * (double)(m - (int64_t)k) / ((double)k * (double)k * (double)(k - 1)) : 0.0;
+  for (int i = 1; i <= 17; ++i) {
+    if (i <= 2 || full) {
+      set_xv(out, i, to_double(E[i]), 0.0);
+      continue;
+    }
+    const double x = to_double(K[i]) + (to_double(t.Z[i]) * sigma) / 12.0;
+    double v = NAN;
+    if (k >= 2) {
+      // sample variance numerator K Q - Z^2 >= 0, exact in 256 bits
+      const u128 az = t.Z[i] < 0 ? (u128)0 - (u128)t.Z[i] : (u128)t.Z[i];
+      const U256 num = sub_u256(mul_u128((u128)k, t.Q[i]), mul_u128(az, az));
+      v = (u256_to_double(num) * gfac) / 144.0;
+    }
+    set_xv(out, i, x, v);
+  }
   return LGE_OK;
 }
 

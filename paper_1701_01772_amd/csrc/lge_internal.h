@@ -50,7 +50,19 @@ struct SlotDesc {
   // kMicroCols-wide int64 matrix, columns kMicroColT / K4 / Cyc
   long long *micro;
   int64_t micro_base, micro_len;
+  // sampling design (kDesignBernoulli: p_lo <= uniform < p)
+  int32_t design;
+  int32_t pad;
+  const uint8_t *level;     // kDesignWeighted: class of every edge id; class l is
+                            //   kept iff uniform < plev[l] and binned to slot + l
+  uint64_t kkey;            // kDesignFixedK: kept iff (Philox key, id) <= (kkey, keid)
+  int64_t keid;
+  double plev[16];
 };
+
+enum SampleDesign { kDesignBernoulli = 0, kDesignWeighted = 1, kDesignFixedK = 2 };
+// weighted sampling: edge weights quantised to this many classes
+constexpr int kWeightLevels = 16;
 
 // micro statistics: one row of 17 int64 per edge, column i-1 = graphlet G_i
 constexpr int kMicroCols = 17;
@@ -145,6 +157,25 @@ size_t gedge_bytes();
 // micro statistics: t of every arc (position j of col holds |Gamma(x) n
 // Gamma(col[j])| for the row x owning j), vertex triangle counts, the
 // per-edge sentinel fill, and the rows of edges [e0, e1)
+// k-core peeling (one level k): scan pushes alive vertices of degree <= k
+// (state 0 -> 2) and lowers *minalive to the smallest degree above k; peel
+// assigns core = k to the frontier, decrements alive neighbours and pushes
+// those that reach k, then retires the frontier (state 1)
+hipError_t launch_core_init(const int32_t *row_ptr, int64_t n, int32_t *deg, int32_t *state, hipStream_t s);
+hipError_t launch_core_scan(int64_t n, int32_t k, int32_t *deg, int32_t *state, int32_t *front,
+                            unsigned long long *cnt, unsigned long long *minalive, hipStream_t s);
+hipError_t launch_core_peel(const int32_t *row_ptr, const int32_t *col, const int32_t *front, int64_t fn, int32_t k,
+                            int32_t *deg, int32_t *state, int32_t *core, int32_t *next, unsigned long long *ncnt,
+                            hipStream_t s);
+// weight classes of every edge (mode 1: d_u + d_v - 2, mode 2: min core) and
+// their histogram (kWeightLevels counters, added to)
+hipError_t launch_weight_levels(int32_t mode, const int32_t *row_ptr, const uint64_t *edges, const int32_t *core,
+                                int64_t m, uint8_t *level, unsigned long long *hist, hipStream_t s);
+// one radix-select pass over the composite keys (Philox key << 64 | id) of
+// ids [0, m): histogram of the 8-bit digit at `shift` among the keys whose
+// bits above `shift + 8` equal (pre_hi, pre_lo) there
+hipError_t launch_select_hist(uint64_t seed, int64_t m, int32_t shift, uint64_t pre_hi, uint64_t pre_lo,
+                              unsigned long long *hist, hipStream_t s);
 hipError_t launch_micro_arc_tri(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges,
                                 const int64_t *hoff, const uint32_t *htab, int64_t m, int32_t *t_arc, hipStream_t s);
 hipError_t launch_micro_vertex_tri(const int32_t *row_ptr, const int32_t *t_arc, int64_t n, int64_t *tri,

@@ -455,7 +455,18 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
       slot = R.slot;
       const SlotDesc &S = slots[slot];
       const int64_t eid = R.e0 + (i - R.pref);
-      if (edge_taken(S.seed, (uint64_t)eid, S.p_lo, S.p)) {
+      bool take;
+      if (S.design == kDesignBernoulli) {
+        take = edge_taken(S.seed, (uint64_t)eid, S.p_lo, S.p);
+      } else if (S.design == kDesignWeighted) {
+        const int l = S.level[eid];
+        take = edge_taken(S.seed, (uint64_t)eid, 0.0, S.plev[l]);
+        slot += l;
+      } else {
+        const uint64_t key = philox_bits(S.seed, (uint64_t)eid);
+        take = key < S.kkey || (key == S.kkey && eid <= S.keid);
+      }
+      if (take) {
         const uint64_t e = S.edges[eid];
         const int32_t u = (int32_t)(e >> 32), v = (int32_t)(uint32_t)e;
         const int32_t du = S.row_ptr[u + 1] - S.row_ptr[u];
@@ -1496,6 +1507,124 @@ __global__ __launch_bounds__(256) void k_micro_rows(const int32_t *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// k-core numbers by level-synchronous peeling (once per graph), edge weight
+// classes, and the radix select of fixed-size samples
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_core_init(const int32_t *__restrict__ rp, int64_t n, int32_t *deg,
+                                                   int32_t *state) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    deg[v] = rp[v + 1] - rp[v];
+    state[v] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_core_scan(int64_t n, int32_t k, int32_t *deg, int32_t *state,
+                                                   int32_t *front, unsigned long long *cnt,
+                                                   unsigned long long *minalive) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long mn = ~0ull;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = base + threadIdx.x;
+    bool push = false;
+    if (v < n && state[v] == 0) {
+      const int32_t d = deg[v];
+      if (d <= k) {
+        push = true;
+        state[v] = 2;
+      } else if ((unsigned long long)d < mn) {
+        mn = (unsigned long long)d;
+      }
+    }
+    const uint64_t pm = __ballot(push);
+    unsigned long long pos0 = 0;
+    if (lane == 0 && pm) pos0 = atomicAdd(cnt, (unsigned long long)__popcll(pm));
+    pos0 = __shfl(pos0, 0);
+    if (push) front[pos0 + __popcll(pm & lt_mask)] = (int32_t)v;
+  }
+  if (mn != ~0ull) atomicMin(minalive, mn);
+}
+
+__global__ __launch_bounds__(256) void k_core_peel(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                   const int32_t *__restrict__ front, int64_t fn, int32_t k,
+                                                   int32_t *deg, int32_t *state, int32_t *core, int32_t *next,
+                                                   unsigned long long *ncnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = w0; i < fn; i += nw) {
+    const int32_t v = front[i];
+    const int32_t beg = rp[v], end = rp[v + 1];
+    for (int32_t j = beg + lane; j < end; j += 64) {
+      const int32_t w = col[j];
+      if (__atomic_load_n(&state[w], __ATOMIC_RELAXED) != 0) continue;
+      const int32_t old = atomicSub(&deg[w], 1);
+      if (old == k + 1) {  // w just reached degree k: it belongs to this level
+        state[w] = 2;
+        next[atomicAdd(ncnt, 1ull)] = w;
+      }
+    }
+    if (lane == 0) {
+      core[v] = k;
+      state[v] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_weight_levels(int32_t mode, const int32_t *__restrict__ rp,
+                                                       const uint64_t *__restrict__ edges,
+                                                       const int32_t *__restrict__ core, int64_t m,
+                                                       uint8_t *__restrict__ level,
+                                                       unsigned long long *__restrict__ hist) {
+  __shared__ unsigned long long sh[kWeightLevels];
+  if (threadIdx.x < kWeightLevels) sh[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = edges[e];
+    const int32_t u = (int32_t)(key >> 32), v = (int32_t)(uint32_t)key;
+    int64_t w;
+    if (mode == 1) {
+      w = (int64_t)(rp[u + 1] - rp[u]) + (int64_t)(rp[v + 1] - rp[v]) - 2;
+    } else {
+      const int32_t cu = core[u], cv = core[v];
+      w = cu < cv ? cu : cv;
+    }
+    int l = 0;
+    if (w >= 2) l = 63 - __clzll((unsigned long long)w);
+    if (l > kWeightLevels - 1) l = kWeightLevels - 1;
+    level[e] = (uint8_t)l;
+    atomicAdd(&sh[l], 1ull);
+  }
+  __syncthreads();
+  if (threadIdx.x < kWeightLevels && sh[threadIdx.x]) atomicAdd(hist + threadIdx.x, sh[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_select_hist(uint64_t seed, int64_t m, int32_t shift, uint64_t pre_hi,
+                                                     uint64_t pre_lo, unsigned long long *hist) {
+  __shared__ unsigned long long sh[256];
+  sh[threadIdx.x] = 0;
+  __syncthreads();
+  const int top = shift + 8;  // bits [top, 128) must match the prefix
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t hi = philox_bits(seed, (uint64_t)e), lo = (uint64_t)e;
+    bool match;
+    if (top >= 128) {
+      match = true;
+    } else if (top >= 64) {
+      match = (hi >> (top - 64)) == pre_hi;
+    } else {
+      match = hi == pre_hi && (top == 0 || (lo >> top) == pre_lo);
+    }
+    if (!match) continue;
+    const uint32_t dig = shift >= 64 ? (uint32_t)((hi >> (shift - 64)) & 0xFFu) : (uint32_t)((lo >> shift) & 0xFFu);
+    atomicAdd(&sh[dig], 1ull);
+  }
+  __syncthreads();
+  if (sh[threadIdx.x]) atomicAdd(hist + threadIdx.x, sh[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
 // Ordering of the split class by table-side endpoint (counting sort)
 // ---------------------------------------------------------------------------
 
@@ -1731,6 +1860,46 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 }
 
 size_t gedge_bytes() { return sizeof(GEdge); }
+
+hipError_t launch_core_init(const int32_t *row_ptr, int64_t n, int32_t *deg, int32_t *state, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_core_init, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, n, deg, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_scan(int64_t n, int32_t k, int32_t *deg, int32_t *state, int32_t *front,
+                            unsigned long long *cnt, unsigned long long *minalive, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_core_scan, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, k, deg, state, front, cnt,
+                     minalive);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_peel(const int32_t *row_ptr, const int32_t *col, const int32_t *front, int64_t fn, int32_t k,
+                            int32_t *deg, int32_t *state, int32_t *core, int32_t *next, unsigned long long *ncnt,
+                            hipStream_t s) {
+  if (fn <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_core_peel, dim3(grid_for(fn, 4, 16384)), dim3(256), 0, s, row_ptr, col, front, fn, k, deg,
+                     state, core, next, ncnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_levels(int32_t mode, const int32_t *row_ptr, const uint64_t *edges, const int32_t *core,
+                                int64_t m, uint8_t *level, unsigned long long *hist, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_weight_levels, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, mode, row_ptr, edges, core, m,
+                     level, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_hist(uint64_t seed, int64_t m, int32_t shift, uint64_t pre_hi, uint64_t pre_lo,
+                              unsigned long long *hist, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select_hist, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, seed, m, shift, pre_hi, pre_lo,
+                     hist);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_micro_arc_tri(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges,
                                 const int64_t *hoff, const uint32_t *htab, int64_t m, int32_t *t_arc, hipStream_t s) {

@@ -36,6 +36,12 @@ struct lge_graph {
   int32_t *t_arc = nullptr;
   int64_t *tri = nullptr;
   unsigned long long *mred = nullptr;
+  // weighted sampling, built on first use: k-core numbers, and per weight
+  // mode (1 degree, 2 k-core) the class of every edge and the class sizes
+  int32_t *core = nullptr;
+  int32_t max_core = -1;
+  uint8_t *wlevel[2] = {nullptr, nullptr};
+  uint64_t whist[2][16] = {};
 };
 
 struct Workspace {
@@ -95,11 +101,21 @@ struct Job {
   int64_t eid_base;     // subtracted from edge ids before the sampler
   double p_lo = 0.0;    // sample only edges whose uniform is >= p_lo (adaptive rounds)
   long long *micro = nullptr;  // per-edge (t, k4, cyc) write-out rows for [e0, e1)
+  int32_t design = 0;          // lge::SampleDesign
+  const uint8_t *level = nullptr;
+  const double *plev = nullptr;  // kWeightLevels class probabilities (host)
+  uint64_t kkey = 0;
+  int64_t keid = -1;
 };
 
+// Slot of job j's first accumulator: jobs take one slot each, weighted jobs
+// kWeightLevels (one per class).
+int lge_job_slots(const Job &j);
+
 // Runs sample -> bin -> count for the jobs in one launch sequence on the
-// ctx stream; on success the per-job accumulators (kAccSlots x {lo, hi}) are
-// in ctx->ws.h_acc.  Returns an LGE_* code.
+// ctx stream; on success the per-slot accumulators (kAccSlots x {lo, hi}) are
+// in ctx->ws.h_acc, job j's from slot sum_{i<j} lge_job_slots(job i).
+// Returns an LGE_* code.
 int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts);
 
 // Exact integers -> lge_result (C, Z, Q, exact counts, FP64 estimates,

@@ -33,6 +33,9 @@ LGE_ECANCELED = -8
 LGE_ENOTFOUND = -9
 LGE_EINTERNAL = -10
 LGE_MICRO_COLS = 17
+LGE_WEIGHT_DEGREE = 1
+LGE_WEIGHT_KCORE = 2
+LGE_WEIGHT_CLASSES = 16
 LGE_FLAG_TRUSTED = 1
 LGE_OPT_SORT_HUB = 1
 LGE_OPT_XCD_LOCAL = 2
@@ -70,6 +73,11 @@ class Timing(ctypes.Structure):
                 ("global_prep_ms", ctypes.c_float),
                 ("class_edges", ctypes.c_uint64 * 3), ("words_read", ctypes.c_uint64 * 3),
                 ("launches", ctypes.c_uint64), ("micro_ms", ctypes.c_float), ("pad", ctypes.c_float)]
+
+
+class WeightInfo(ctypes.Structure):
+    _fields_ = [("p_level", ctypes.c_double * 16), ("edges", ctypes.c_uint64 * 16),
+                ("sampled", ctypes.c_uint64 * 16), ("max_core", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Batch(ctypes.Structure):
@@ -153,6 +161,11 @@ def load():
         "lge_estimate_adaptive": ([_VP, _VP, ctypes.c_uint64, ctypes.POINTER(AdaptiveCfg), ctypes.POINTER(Result),
                                    ctypes.POINTER(AdaptiveTrace)], ctypes.c_int),
         "lge_micro": ([_VP, _VP, ctypes.c_int64, ctypes.c_int64, _VP, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "lge_estimate_weighted": ([_VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(Opts),
+                                   ctypes.POINTER(Result), ctypes.POINTER(WeightInfo)], ctypes.c_int),
+        "lge_core_numbers": ([_VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "lge_estimate_fixed_k": ([_VP, _VP, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(Result)], ctypes.c_int),
         "lge_server_cfg_default": ([ctypes.POINTER(ServerCfg)], ctypes.c_int),
         "lge_server_create": ([_VP, ctypes.POINTER(ServerCfg), ctypes.POINTER(_VP)], ctypes.c_int),
         "lge_server_add_graph": ([_VP, _VP, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -388,6 +401,37 @@ def lge_micro(ctx, g, e0: int = 0, e1: int | None = None, out=None, device: str 
     _check(load().lge_micro(ctx, g, int(e0), int(e1), ctypes.c_void_p(out.data_ptr() if nrows else 0), cm),
            "lge_micro")
     return out, list(cm)
+
+
+def lge_estimate_weighted(ctx, g, mode: int, p_mean: float, seed: int, opts: Opts | None = None):
+    """Returns (result dict, info dict with p_level, edges, sampled per class
+    and max_core)."""
+    r = Result()
+    info = WeightInfo()
+    _check(load().lge_estimate_weighted(ctx, g, int(mode), float(p_mean), int(seed),
+                                        ctypes.byref(opts) if opts is not None else None, ctypes.byref(r),
+                                        ctypes.byref(info)), "lge_estimate_weighted")
+    return result_dict(r), {"p_level": list(info.p_level), "edges": [int(x) for x in info.edges],
+                            "sampled": [int(x) for x in info.sampled], "max_core": int(info.max_core)}
+
+
+def lge_core_numbers(ctx, g, device: str = "cuda:0"):
+    """Returns (int32 torch tensor of the n core numbers on the device, max core)."""
+    import torch
+    n = int(load().lge_graph_n(g))
+    out = torch.empty(max(n, 0), dtype=torch.int32, device=device)
+    mc = ctypes.c_int32()
+    torch.cuda.synchronize(out.device)
+    _check(load().lge_core_numbers(ctx, g, ctypes.c_void_p(out.data_ptr() if n else 0), ctypes.byref(mc)),
+           "lge_core_numbers")
+    return out, mc.value
+
+
+def lge_estimate_fixed_k(ctx, g, k: int, seed: int, opts: Opts | None = None) -> dict:
+    r = Result()
+    _check(load().lge_estimate_fixed_k(ctx, g, int(k), int(seed), ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.byref(r)), "lge_estimate_fixed_k")
+    return result_dict(r)
 
 
 def lge_server_cfg_default() -> ServerCfg:
