@@ -8,7 +8,7 @@ roofline of the dominant counting kernel (device time from HIP events the
 library records on its own stream), and the CPU oracle timed on a bounded
 subsample of the same workload on this host.
 
-    python bench.py [--steps K] [--warmup W] [--workload chung_lu|rmat|er|batch|serve|micro] [--p P]
+    python bench.py [--steps K] [--warmup W] [--workload chung_lu|rmat|er|batch|serve|micro|designs] [--p P]
 """
 import argparse
 import hashlib
@@ -357,6 +357,44 @@ def bench_adaptive(args):
             "final_delta": tr["delta"][-1]}
 
 
+def bench_designs(args):
+    """The other sampling designs on the Chung-Lu 1e6 graph: k-core and
+    degree weighted Bernoulli samples (mean probability 0.1) and a fixed-size
+    sample of 0.1 m edges with the ratio estimator."""
+    import torch
+    from paper_1701_01772_amd import lge
+    g, wname = make_workload("chung_lu")
+    ctx = lge.lge_open(0)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    out = {"workload": wname}
+    t0 = time.perf_counter()
+    _, mc = lge.lge_core_numbers(ctx, h)
+    out["core_numbers_s"] = time.perf_counter() - t0
+    out["max_core"] = mc
+    steps = max(1, args.steps // 2)
+    for name, mode in (("kcore", lge.LGE_WEIGHT_KCORE), ("degree", lge.LGE_WEIGHT_DEGREE)):
+        lge.lge_estimate_weighted(ctx, h, mode, 0.1, args.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sampled = 0
+        for i in range(steps):
+            r, _ = lge.lge_estimate_weighted(ctx, h, mode, 0.1, args.seed + 100 + i)
+            sampled += r["sampled"]
+        dt = time.perf_counter() - t0
+        out["weighted_" + name] = {"sampled_edges_per_s": sampled / dt, "ms_per_step": 1e3 * dt / steps}
+    k = g.m // 10
+    lge.lge_estimate_fixed_k(ctx, h, k, args.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        lge.lge_estimate_fixed_k(ctx, h, k, args.seed + 100 + i)
+    dt = time.perf_counter() - t0
+    out["fixed_k"] = {"k": k, "sampled_edges_per_s": k * steps / dt, "ms_per_step": 1e3 * dt / steps}
+    lge.lge_graph_destroy(h)
+    lge.lge_close(ctx)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +430,9 @@ def main():
         return
     if args.workload == "micro":
         print(json.dumps(bench_micro(args)))
+        return
+    if args.workload == "designs":
+        print(json.dumps(bench_designs(args)))
         return
 
     import torch
@@ -475,6 +516,7 @@ def main():
                            "ms_per_step": mi["ms_per_step"], "device_ms": mi["device_ms"],
                            "micro_rows_kernel": mi["micro_rows_kernel"]}
         result["adaptive"] = bench_adaptive(bargs)
+        result["designs"] = bench_designs(bargs)
     print(json.dumps(result))
 
 

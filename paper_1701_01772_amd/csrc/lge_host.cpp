@@ -27,7 +27,7 @@ namespace {
 
 // Co-degree table: at most this many ranked vertices (hc^2 * 4 bytes <= 1 GiB),
 // each of degree > kCodegMinDeg.
-constexpr int64_t kCodegMaxVertices = 16384;
+constexpr int64_t kCodegMaxVertices = kMaxRanked;
 constexpr int32_t kCodegMinDeg = 32;
 
 #define LGE_HIP(expr)                        \
@@ -497,13 +497,21 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) 
     cleanup();
     return rc;
   }
+  const int64_t hcw = (hc + 63) / 64;
+  if ((rc = dev_alloc(&g->hbits, hc * hcw)) != LGE_OK) {
+    cleanup();
+    return rc;
+  }
   e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, list, s);
   if (e == hipSuccess) e = hipMemsetAsync(g->codeg, 0, (size_t)hc * (size_t)hc * sizeof(uint32_t), s);
   if (e == hipSuccess) e = launch_codeg_pairs(off, cnt, list, n, hc, g->codeg, s);
+  if (e == hipSuccess) e = launch_zero_u64(g->hbits, hc * hcw, s);
+  if (e == hipSuccess) e = launch_codeg_bits(g->row_ptr, g->col, g->crank, n, hcw, g->hbits, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   if (e != hipSuccess) return hip_err(e);
   g->hc = hc;
+  g->hcw = hcw;
   return LGE_OK;
 }
 
@@ -516,6 +524,7 @@ static void graph_free(lge_graph *g) {
   dev_free(g->htab);
   dev_free(g->crank);
   dev_free(g->codeg);
+  dev_free(g->hbits);
   dev_free(g->t_arc);
   dev_free(g->tri);
   dev_free(g->mred);
@@ -815,6 +824,8 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.crank = g->crank;
     sd.codeg = g->codeg;
     sd.hc = g->hc;
+    sd.hbits = g->hbits;
+    sd.hcw = g->hcw;
     sd.n = jobs[j].n_override >= 0 ? jobs[j].n_override : g->n;
     sd.m = jobs[j].m_override >= 0 ? jobs[j].m_override : g->m;
     sd.p = jobs[j].p;
@@ -877,7 +888,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     LGE_HIP(hipMemcpyAsync(hl, w.tbase + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LGE_HIP(hipMemcpyAsync(hl + 1, w.tcap + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LGE_HIP(hipStreamSynchronize(s));
-    if ((rc = ws_reserve_tlist(ctx, 2 * (hl[0] + hl[1]))) != LGE_OK) return rc;  // (id, degree) pairs
+    if ((rc = ws_reserve_tlist(ctx, 3 * (hl[0] + hl[1]))) != LGE_OK) return rc;  // (id, degree, rank)
     LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
     LGE_HIP(hipEventRecord(ev[6], s));
     LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));

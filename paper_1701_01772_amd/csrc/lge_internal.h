@@ -24,6 +24,10 @@ constexpr int kHubDeg = 1024;
 // Vertices of degree > kTableDeg get a global hash table of their neighbours
 // ("hub table"): O(1) membership tests instead of binary searches.
 constexpr int kTableDeg = 256;
+// Ranked (co-degree table) vertices at most, and the 64-bit words of one
+// adjacency bit row over them.
+constexpr int kMaxRanked = 16384;
+constexpr int kBitsWords = kMaxRanked / 64;
 // Largest number of Gamma(a) positions handled by one global-class work item.
 constexpr int kGlobalChunkMax = 256;
 // Vertex ids must stay below 2^29: the kernels keep three tag bits above them.
@@ -40,6 +44,8 @@ struct SlotDesc {
   const int32_t *crank;     // n: rank in the co-degree table, -1 if absent
   const uint32_t *codeg;    // hc x hc: |Gamma(x) n Gamma(y)| at [min rank][max rank]
   int64_t hc;               // ranked vertices (0: no table)
+  const unsigned long long *hbits;  // hc x hcw bit rows: bit ry of row rx = (x, y) adjacent
+  int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
   int64_t n, m;
   double p;
   uint64_t seed;
@@ -133,6 +139,9 @@ hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const 
                               int64_t *cnt, hipStream_t s);
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
                              const int64_t *off, int32_t *list, hipStream_t s);
+// adjacency bit rows among the ranked vertices (bits zeroed by the caller)
+hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,
+                             unsigned long long *bits, hipStream_t s);
 hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, int64_t n, int64_t hc,
                               uint32_t *tab, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);

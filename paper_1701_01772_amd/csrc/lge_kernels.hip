@@ -573,6 +573,23 @@ __global__ __launch_bounds__(256) void k_codeg_pairs(const int64_t *__restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                    const int32_t *__restrict__ crank, int64_t n, int64_t hcw,
+                                                    unsigned long long *bits) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t x = w0; x < n; x += nw) {
+    const int32_t rx = crank[x];
+    if (rx < 0) continue;  // uniform per wavefront
+    unsigned long long *row = bits + (int64_t)rx * hcw;
+    for (int32_t j = rp[x] + lane; j < rp[x + 1]; j += 64) {
+      const int32_t ry = crank[col[j]];
+      if (ry >= 0) atomicOr(row + (ry >> 6), 1ull << (ry & 63));
+    }
+  }
+}
+
 __device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t y, uint32_t *val) {
   if (S.hc <= 0) return false;
   const int32_t rx = S.crank[x], ry = S.crank[y];
@@ -991,10 +1008,11 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
       unsigned long long pos0 = 0;
       if (lane == 0 && tm) pos0 = atomicAdd(&gacc[e].t, (unsigned long long)__popcll(tm));
       pos0 = __shfl(pos0, 0);
-      if (isT) {  // (id, degree) pairs
+      if (isT) {  // (id, degree, rank) triples; rank -1 when not ranked
         const int64_t pos = tbase[e] + (int64_t)pos0 + __popcll(tm & lt_mask);
-        tlist[2 * pos] = x;
-        tlist[2 * pos + 1] = rp[x + 1] - rp[x];
+        tlist[3 * pos] = x;
+        tlist[3 * pos + 1] = rp[x + 1] - rp[x];
+        tlist[3 * pos + 2] = S.hc > 0 ? S.crank[x] : -1;
       }
     }
   }
@@ -1031,6 +1049,8 @@ constexpr uint8_t kFLookT = 1;   // degT by look-ups of T_e
 constexpr uint8_t kFLookA = 2;   // cax by look-ups of Gamma(a)
 constexpr uint8_t kFCodeg = 4;   // co-degree from the table
 constexpr uint8_t kFLookB = 8;   // w in S_a: cbx by look-ups of Gamma(b)
+constexpr uint8_t kFBits = 16;   // ranked w in T_e: degT over ranked members from bit rows
+constexpr uint32_t kRTag = 0x40000000u;  // T_e hash key tag: member is ranked
 
 __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
@@ -1055,6 +1075,9 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
   __shared__ unsigned long long red[NT / kWave];
   __shared__ long long sh_item;
   __shared__ int sh_last;
+  __shared__ unsigned long long tbits[kBitsWords];  // ranked members of T_e
+  __shared__ int16_t twidx[kBitsWords];            // indices of its non-zero words
+  __shared__ int32_t wl_rank[CH];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1106,10 +1129,12 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const uint32_t *__restrict__ btab = hb ? S.htab + S.hoff[b] : hB;
     const uint32_t *__restrict__ atab = ha ? S.htab + S.hoff[a] : hA;
     const int t = (int)gacc[e].t;
-    const int32_t *__restrict__ T = tlist + 2 * tbase[e];  // (id, degree) pairs
+    const int32_t *__restrict__ T = tlist + 3 * tbase[e];  // (id, degree, rank) triples
     const bool tl = t <= kTHashCap;
     const int tlg = table_log(t);
+    const int hcw = S.hc > 0 ? (int)S.hcw : 0;  // 0: no ranked vertices, no bit rows
     if (tid < 4) sh_cnt[tid] = 0;
+    for (int i = tid; i < hcw; i += NT) tbits[i] = 0ull;
     if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
     if (!ha)
@@ -1131,17 +1156,34 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       }
       words += (unsigned long long)da;
     }
-    if (tl) {
-      for (int i = tid; i < t; i += NT) lds_insert(hT, tlg, (uint32_t)T[2 * i]);
-      words += 2ull * (unsigned long long)t;
+    if (tl || hcw) {
+      for (int i = tid; i < t; i += NT) {
+        const int32_t y = T[3 * i], ry = T[3 * i + 2];
+        if (tl) lds_insert(hT, tlg, (uint32_t)y | (ry >= 0 ? kRTag : 0u));
+        if (ry >= 0) atomicOr(&tbits[ry >> 6], 1ull << (ry & 63));
+      }
+      words += 3ull * (unsigned long long)t;
     }
     __syncthreads();
+    for (int i = tid; i < hcw; i += NT)
+      if (tbits[i]) twidx[atomicAdd(&sh_cnt[1], 1)] = (int16_t)i;
+    __syncthreads();
+    const int nzw = sh_cnt[1];
     // r in Gamma(b) \ {a}; r in Gamma(a) \ {b}; r in T_e (the LDS tables
     // exclude a and b already, the hub tables do not)
     auto inBx = [&](uint32_t r) -> bool { return r != (uint32_t)a && table_find(btab, blg, r) >= 0; };
     auto inAx = [&](uint32_t r) -> bool { return r != (uint32_t)b && table_find(atab, alg, r) >= 0; };
-    auto inT = [&](uint32_t r) -> bool {
-      return tl ? table_find(hT, tlg, r) >= 0 : (table_find(atab, alg, r) >= 0 && table_find(btab, blg, r) >= 0);
+    // 0: r not in T_e; 1: unranked member; 2: ranked member.  The weight is
+    // the pair's share of the edges inside T_e counted from this side: a
+    // ranked member counts only its ranked partners (bit rows), so the
+    // unranked side counts a mixed pair twice.
+    auto tmemb = [&](uint32_t r) -> int {
+      if (tl) {
+        const int sl = table_find(hT, tlg, r);
+        return sl < 0 ? 0 : ((hT[sl] & kRTag) ? 2 : 1);
+      }
+      if (table_find(atab, alg, r) < 0 || table_find(btab, blg, r) < 0) return 0;
+      return (hcw && S.crank[r] >= 0) ? 2 : 1;
     };
     const int64_t mB = hb ? 16 : 4, mA = ha ? 16 : 4, mT = tl ? 4 : 32;
     // this chunk's vertices of Gamma(a) \ {b}
@@ -1178,6 +1220,8 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       const int64_t look = may_look ? ((4 + lookup_cost(dw)) * probe_ratio) / 4 : 0;
       uint32_t cdeg = 0;
       const bool cok = may_look && codeg_pair(S, w, isT ? a : b, &cdeg);
+      const int32_t rw = hcw ? S.crank[w] : -1;
+      wl_rank[i] = rw;
       uint8_t fl = 0;
       int32_t units;
       if (!isT) {
@@ -1192,17 +1236,20 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
           units = dw;
         }
       } else {
-        const bool lt = t_looks(dw, t, mT, probe_ratio);
+        const bool bits = rw >= 0;
+        const bool lt = !bits && t_looks(dw, t, mT, probe_ratio);
         if (lt) fl |= kFLookT;
+        if (bits) fl |= kFBits;
+        const int part1 = bits ? nzw : (lt ? t : dw);
         if (cok) {
           fl |= kFCodeg;
           cyc_base -= (long long)cdeg - 1;
-          units = lt ? t : dw;
+          units = part1;
         } else {
           const bool la = may_look && (int64_t)da * look < (int64_t)dw * (4 + mA);
           if (la) fl |= kFLookA;
-          // one walk of Gamma(w) serves both terms when neither looks up
-          units = (!lt && !la) ? dw : (lt ? t : dw) + (la ? da : dw);
+          // one walk of Gamma(w) serves both terms when nothing else is used
+          units = (!bits && !lt && !la) ? dw : part1 + (la ? da : dw);
         }
       }
       wl_f[i] = fl;
@@ -1247,21 +1294,26 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
           }
         } else {
           const bool lt = (fl & kFLookT) != 0;
-          const bool both = !(fl & (kFCodeg | kFLookT | kFLookA));
-          const int part1 = lt ? t : dw;
+          const bool bits = (fl & kFBits) != 0;
+          const bool both = !(fl & (kFCodeg | kFLookT | kFLookA | kFBits));
+          const int part1 = bits ? nzw : (lt ? t : dw);
           if (both) {  // one walk of Gamma(w): degT and cax
             const uint32_t r = (uint32_t)col[wl_beg[l2] + off];
-            if (inT(r)) ++kt;
+            kt += (unsigned long long)tmemb(r);
             if (inAx(r)) --cs;
           } else if (off < part1) {  // degT
-            if (lt) {
-              const int32_t y = T[2 * off];
-              const int dy = T[2 * off + 1];
-              // pairs of look-up members are tested by the smaller id only
-              const int wgt = t_looks(dy, t, mT, probe_ratio) ? (y > w ? 2 : 0) : 1;
+            if (bits) {  // ranked partners: AND of w's bit row with the ranked members of T_e
+              const int j = twidx[off];
+              kt += (unsigned long long)__popcll(S.hbits[(int64_t)wl_rank[l2] * S.hcw + j] & tbits[j]);
+            } else if (lt) {
+              const int32_t y = T[3 * off];
+              const int dy = T[3 * off + 1];
+              // ranked members count only ranked partners; pairs of unranked
+              // look-up members are tested by the smaller id only
+              const int wgt = T[3 * off + 2] >= 0 ? 2 : (t_looks(dy, t, mT, probe_ratio) ? (y > w ? 2 : 0) : 1);
               if (wgt && w_has(S, w, wl_beg[l2], dw, y, &steps)) kt += (unsigned long long)wgt;
             } else {
-              if (inT((uint32_t)col[wl_beg[l2] + off])) ++kt;
+              kt += (unsigned long long)tmemb((uint32_t)col[wl_beg[l2] + off]);
             }
           } else {  // cax
             const int o2 = off - part1;
@@ -1860,6 +1912,14 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 }
 
 size_t gedge_bytes() { return sizeof(GEdge); }
+
+hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,
+                             unsigned long long *bits, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_bits, dim3(grid_for(n, 4, 16384)), dim3(256), 0, s, row_ptr, col, crank, n, hcw, bits);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_core_init(const int32_t *row_ptr, int64_t n, int32_t *deg, int32_t *state, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -29,6 +29,8 @@ struct lge_graph {
   int32_t *crank = nullptr;
   uint32_t *codeg = nullptr;
   int64_t hc = 0;
+  unsigned long long *hbits = nullptr;  // hc x hcw adjacency bit rows of the ranked vertices
+  int64_t hcw = 0;
   int32_t codeg_tau = 0;
   double work_per_id = 0.0;  // scheduling weight per canonical edge id
   // micro statistics, built on first use: t of every arc, triangles per
