@@ -77,11 +77,20 @@ def cpu_baseline(g, p, seed, target_s=15.0):
 
 
 def roofline_of(tim, workload):
+    """Roofline of the dominant counting kernel.  achieved = the neighbour-
+    iteration bytes of the sampled edges it counts (per edge
+    16 + 4(d_u + d_v) + sum over w in Gamma(a)\\{b} of (8 + 4 d_w), summed by
+    the sampling kernel) / its mean launch time; the kernel's tables let it
+    read far fewer bytes, so this "effective" figure can exceed the HBM peak.
+    traffic = HBM-side bytes per launch from the committed rocprofv3 counter
+    profile of the same kernel source (null when the source has changed)."""
     k = len(tim)
     cnt_ms = [sum(t["count_ms"][c] for t in tim) / k for c in range(3)]
     words = [sum(t["words_read"][c] for t in tim) / k for c in range(3)]
+    alg = [sum(t["alg_bytes"][c] for t in tim) / k for c in range(3)]
     dom = max(range(3), key=lambda c: cnt_ms[c])
-    achieved = 4.0 * words[dom] / (cnt_ms[dom] * 1e-3) / 1e9 if cnt_ms[dom] > 0 else 0.0
+    sec = cnt_ms[dom] * 1e-3
+    achieved = alg[dom] / sec / 1e9 if sec > 0 else 0.0
     traffic = None
     pmc_path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (workload, ["wave", "block", "global"][dom]))
     if os.path.exists(pmc_path):
@@ -94,7 +103,11 @@ def roofline_of(tim, workload):
                  "count_global": cnt_ms[2]}
     roof = {"bound": "hbm", "kernel": CLASS_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "algorithmic_bytes_per_launch": 4.0 * words[dom]}
+            "algorithmic_bytes_per_launch": alg[dom], "issued_bytes_per_launch": 4.0 * words[dom],
+            "launch_ms": cnt_ms[dom]}
+    if traffic is not None and sec > 0:
+        roof["traffic_GBps"] = traffic / sec / 1e9
+        roof["traffic_frac"] = traffic / sec / 1e9 / HBM_PEAK_GBS
     return device_ms, roof
 
 

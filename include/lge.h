@@ -156,6 +156,8 @@ typedef struct {
   uint64_t launches;       /* kernel launches issued */
   float micro_ms;          /* lge_micro only: the row kernel (after the counting pass) */
   float pad;
+  uint64_t alg_bytes[3];   /* per class: bytes the neighbour iteration of Alg. 2-4 would read for the
+                              sampled edges, 16 + 4(d_u + d_v) + sum over w in Gamma(a)\{b} of (8 + 4 d_w) */
 } lge_timing;
 
 LGE_API const char *lge_strerror(int code);

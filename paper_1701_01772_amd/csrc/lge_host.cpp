@@ -142,6 +142,9 @@ static void ws_free(Workspace &w) {
   dev_free(w.tcap);
   dev_free(w.tbase);
   dev_free(w.tlist);
+  dev_free(w.tbw);
+  dev_free(w.tbi);
+  dev_free(w.item_edge);
   if (w.gacc) (void)hipFree(w.gacc);
   w.gacc = nullptr;
   dev_free(w.scan_tmp);
@@ -284,14 +287,32 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
   return LGE_OK;
 }
 
+static int ws_reserve_items(lge_ctx *ctx, int64_t len) {
+  Workspace &w = ctx->ws;
+  if (len <= w.cap_items) return LGE_OK;
+  dev_free(w.item_edge);
+  w.cap_items = 0;
+  const int64_t cap = std::max<int64_t>(len + len / 4, 4096);
+  const int rc = dev_alloc(&w.item_edge, cap);
+  if (rc != LGE_OK) return rc;
+  w.cap_items = cap;
+  return LGE_OK;
+}
+
+// room for `len` T_e entries: (id, degree, rank) triples plus the compact
+// bit-set words
 static int ws_reserve_tlist(lge_ctx *ctx, int64_t len) {
   Workspace &w = ctx->ws;
   if (len <= w.cap_tlist) return LGE_OK;
   dev_free(w.tlist);
+  dev_free(w.tbw);
+  dev_free(w.tbi);
   w.cap_tlist = 0;
   const int64_t cap = std::max<int64_t>(len + len / 4, 4096);
-  int rc = dev_alloc(&w.tlist, cap);
-  if (rc != LGE_OK) return rc;
+  int rc;
+  if ((rc = dev_alloc(&w.tlist, 3 * cap)) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&w.tbw, cap)) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&w.tbi, cap)) != LGE_OK) return rc;
   w.cap_tlist = cap;
   return LGE_OK;
 }
@@ -788,6 +809,7 @@ static Bins make_bins(Workspace &w) {
   b.count = w.counters;
   b.cursor = w.counters + 3;
   b.words = w.counters + 6;
+  b.alg = w.counters + 12;
   b.xcd_cursor = w.counters + 16;
   b.cap = w.cap_edges;
   return b;
@@ -884,19 +906,26 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     LGE_HIP(launch_global_prep(w.slots, bins, ng, cfg.global_chunk, w.items, w.tcap, w.gacc, s));
     LGE_HIP(launch_scan_i64(w.items, w.item_pref, ng, w.scan_tmp, s));
     LGE_HIP(launch_scan_i64(w.tcap, w.tbase, ng, w.scan_tmp, s));
-    int64_t *hl = (int64_t *)w.h_counters + 10;
+    int64_t *hl = (int64_t *)w.h_counters + 16;
     LGE_HIP(hipMemcpyAsync(hl, w.tbase + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LGE_HIP(hipMemcpyAsync(hl + 1, w.tcap + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LGE_HIP(hipMemcpyAsync(hl + 2, w.item_pref + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LGE_HIP(hipMemcpyAsync(hl + 3, w.items + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     LGE_HIP(hipStreamSynchronize(s));
-    if ((rc = ws_reserve_tlist(ctx, 3 * (hl[0] + hl[1]))) != LGE_OK) return rc;  // (id, degree, rank)
-    LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
+    if ((rc = ws_reserve_tlist(ctx, hl[0] + hl[1])) != LGE_OK) return rc;
+    if ((rc = ws_reserve_items(ctx, hl[2] + hl[3])) != LGE_OK) return rc;
+    LGE_HIP(launch_item_fill(w.item_pref, w.items, ng, w.item_edge, s));
+    LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.gacc,
+                                   cfg, s));
+    LGE_HIP(launch_global_tbits(w.slots, bins, ng, w.tbase, w.tlist, w.tbw, w.tbi, w.gacc, s));
     LGE_HIP(hipEventRecord(ev[6], s));
-    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.tbase, w.tlist, w.gacc, cfg, s));
+    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.tbw,
+                                w.tbi, w.gacc, cfg, s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
   LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)nslots * kAccSlots * 2 * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, s));
-  LGE_HIP(hipMemcpyAsync(w.h_counters, w.counters, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipMemcpyAsync(w.h_counters, w.counters, 15 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   LGE_HIP(hipStreamSynchronize(s));
   lge_timing &t = ctx->timing;
   float ms = 0;
@@ -908,7 +937,8 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
   for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[c];
   for (int c = 0; c < kNumClasses; ++c) t.words_read[c] = w.h_counters[6 + c];
-  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 5 : 0);
+  for (int c = 0; c < kNumClasses; ++c) t.alg_bytes[c] = w.h_counters[12 + c];
+  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 6 : 0);
   return LGE_OK;
 }
 

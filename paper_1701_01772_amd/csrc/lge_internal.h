@@ -95,6 +95,7 @@ struct Bins {
   unsigned long long *count;   // kNumClasses counters
   unsigned long long *cursor;  // kNumClasses work-queue cursors
   unsigned long long *words;   // kNumClasses counters of 4-byte words read
+  unsigned long long *alg;     // kNumClasses counters of neighbour-iteration bytes of the sampled edges
   unsigned long long *xcd_cursor;  // kXcds cursors of the XCD-local split-class queue
   int64_t cap;
 };
@@ -152,15 +153,23 @@ hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t nedges, 
 // global class: per-edge work items and T_e capacities, T_e lists, counting
 hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t chunk, int64_t *items,
                               int64_t *tcap, void *gacc, hipStream_t s);
+// work item -> edge map (item_edge holds the total number of items)
+hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, int64_t nedges, int32_t *item_edge,
+                            hipStream_t s);
 hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
-                                  const int64_t *item_cnt, const int64_t *tbase, int32_t *tlist, void *gacc,
-                                  KernelCfg cfg, hipStream_t s);
+                                  const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
+                                  int32_t *tlist, void *gacc, KernelCfg cfg, hipStream_t s);
 // counting sort of the split-class edges by key (see kSortKeys) into
 // (slot2, a2, b2); hist, off: kSortKeys int64 each; tmp: scan scratch
 hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t *slot2, int32_t *a2,
                               int32_t *b2, int64_t *hist, int64_t *off, int64_t *tmp, hipStream_t s);
+// the compact ranked-member bit sets of every edge's T_e (non-zero words and
+// their indices at the T_e offsets), then the counting
+hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *tbase,
+                               const int32_t *tlist, unsigned long long *tbw, int16_t *tbi, void *gacc, hipStream_t s);
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
-                               const int64_t *item_cnt, const int64_t *tbase, const int32_t *tlist, void *gacc,
+                               const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
+                               const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi, void *gacc,
                                KernelCfg cfg, hipStream_t s);
 size_t gedge_bytes();
 // micro statistics: t of every arc (position j of col holds |Gamma(x) n

@@ -442,6 +442,7 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
     const int64_t i = base + threadIdx.x;
     int cls = -1;
     int32_t slot = 0, a = 0, b = 0;
+    unsigned long long alg = 0;
     if (i < total) {
       int lo = 0, hi = nranges - 1;
       while (lo < hi) {
@@ -478,14 +479,24 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
         b = ua ? v : u;
         const int32_t dmax = du > dv ? du : dv;
         cls = dmax <= cfg.wave_max_deg ? kClassWave : (dmax <= kHubDeg ? kClassBlock : kClassGlobal);
+        // bytes the neighbour iteration of Alg. 2-4 reads for this edge:
+        // both row_ptr pairs, both rows, and for every w in Gamma(a) \ {b}
+        // its row_ptr pair and row
+        const int64_t da = ua ? du : dv, db = ua ? dv : du, wa = ua ? wu : wv;
+        alg = 16ull + 4ull * (unsigned long long)(du + dv) + 8ull * (unsigned long long)(da - 1) +
+              4ull * (unsigned long long)(wa - db);
       }
     }
     for (int c = 0; c < kNumClasses; ++c) {
       const uint64_t msk = __ballot(cls == c);
       if (msk == 0ull) continue;
       const int leader = __ffsll((unsigned long long)msk) - 1;
+      const unsigned long long ab = wave_sum_u64(cls == c ? alg : 0ull);
       unsigned long long pos0 = 0;
-      if (lane == leader) pos0 = atomicAdd(&bins.count[c], (unsigned long long)__popcll(msk));
+      if (lane == leader) {
+        pos0 = atomicAdd(&bins.count[c], (unsigned long long)__popcll(msk));
+        atomicAdd(&bins.alg[c], ab);
+      }
       pos0 = __shfl(pos0, leader);
       if (cls == c) {
         const int64_t pos = (int64_t)pos0 + __popcll(msk & lt_mask);
@@ -940,7 +951,7 @@ constexpr int kGlobalNT = 256;
 constexpr int kTHashCap = 512;
 
 struct GEdge {
-  unsigned long long t, k4, cyc, done;
+  unsigned long long t, k4, cyc, done, nzw;
 };
 
 __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict__ slots,
@@ -955,33 +966,31 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
     const int db = S.row_ptr[b + 1] - S.row_ptr[b];
     items[e] = (da + chunk - 1) / chunk;
     tcap[e] = da < db ? da : db;
-    gacc[e].t = gacc[e].k4 = gacc[e].cyc = gacc[e].done = 0ull;
+    gacc[e].t = gacc[e].k4 = gacc[e].cyc = gacc[e].done = gacc[e].nzw = 0ull;
   }
 }
 
-__device__ __forceinline__ int64_t find_item_edge(const int64_t *__restrict__ item_pref, int64_t nedges,
-                                                  int64_t item) {
-  int64_t lo = 0, hi = nedges - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (item_pref[mid] <= item)
-      lo = mid;
-    else
-      hi = mid - 1;
+// the work item -> edge map: item_pref[e] .. item_pref[e] + items[e] - 1 -> e
+__global__ __launch_bounds__(256) void k_item_fill(const int64_t *__restrict__ item_pref,
+                                                   const int64_t *__restrict__ items, int64_t nedges,
+                                                   int32_t *__restrict__ item_edge) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = item_pref[e], k = items[e];
+    for (int64_t i = 0; i < k; ++i) item_edge[b + i] = (int32_t)e;
   }
-  return lo;
 }
 
 __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
-    const int64_t *__restrict__ item_cnt, const int64_t *__restrict__ tbase, int32_t *tlist, GEdge *gacc,
-    int32_t chunk) {
+    const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
+    int32_t *tlist, GEdge *gacc, int32_t chunk) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
   for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
-    const int64_t e = find_item_edge(item_pref, nedges, item);
+    const int64_t e = item_edge[item];
     const int64_t c = item - item_pref[e];
     const SlotDesc &S = slots[bslot[e]];
     const int32_t *__restrict__ rp = S.row_ptr;
@@ -1015,6 +1024,45 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
         tlist[3 * pos + 2] = S.hc > 0 ? S.crank[x] : -1;
       }
     }
+  }
+}
+
+// The ranked members of every split-class edge's T_e as a bit set over the
+// ranks, stored compactly (non-zero words and their indices) at the edge's
+// T_e offset; one workgroup per edge, once per launch.
+__global__ __launch_bounds__(kGlobalNT) void k_global_tbits(const SlotDesc *__restrict__ slots,
+                                                            const int32_t *__restrict__ bslot, int64_t nedges,
+                                                            const int64_t *__restrict__ tbase,
+                                                            const int32_t *__restrict__ tlist, GEdge *gacc,
+                                                            unsigned long long *__restrict__ tbw,
+                                                            int16_t *__restrict__ tbi) {
+  __shared__ unsigned long long bits[kBitsWords];
+  __shared__ int cnt;
+  for (int64_t e = blockIdx.x; e < nedges; e += gridDim.x) {
+    const SlotDesc &S = slots[bslot[e]];
+    const int hcw = S.hc > 0 ? (int)S.hcw : 0;
+    const int t = (int)gacc[e].t;
+    if (hcw == 0 || t == 0) continue;  // uniform per block; nzw stays 0
+    for (int i = threadIdx.x; i < hcw; i += kGlobalNT) bits[i] = 0ull;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int32_t *T = tlist + 3 * tbase[e];
+    for (int i = threadIdx.x; i < t; i += kGlobalNT) {
+      const int32_t r = T[3 * i + 2];
+      if (r >= 0) atomicOr(&bits[r >> 6], 1ull << (r & 63));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < hcw; i += kGlobalNT) {
+      const unsigned long long wv = bits[i];
+      if (wv) {
+        const int k = atomicAdd(&cnt, 1);
+        tbw[tbase[e] + k] = wv;
+        tbi[tbase[e] + k] = (int16_t)i;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) gacc[e].nzw = (unsigned long long)cnt;
+    __syncthreads();
   }
 }
 
@@ -1052,12 +1100,14 @@ constexpr uint8_t kFLookB = 8;   // w in S_a: cbx by look-ups of Gamma(b)
 constexpr uint8_t kFBits = 16;   // ranked w in T_e: degT over ranked members from bit rows
 constexpr uint32_t kRTag = 0x40000000u;  // T_e hash key tag: member is ranked
 
-__global__ __launch_bounds__(kGlobalNT) void k_count_global(
+__global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_global(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
-    const int64_t *__restrict__ item_cnt, const int64_t *__restrict__ tbase, const int32_t *__restrict__ tlist,
-    GEdge *gacc, unsigned long long *cursor, unsigned long long *xcd_cursor, unsigned long long *words_out,
-    int32_t probe_ratio, int32_t chunk, uint32_t flags) {
+    const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
+    const int32_t *__restrict__ tlist, const unsigned long long *__restrict__ tbw, const int16_t *__restrict__ tbi,
+    GEdge *gacc,
+    unsigned long long *cursor, unsigned long long *xcd_cursor, unsigned long long *words_out, int32_t probe_ratio,
+    int32_t chunk, uint32_t flags) {
   constexpr int NT = kGlobalNT;
   constexpr int CH = kGlobalChunkMax;
   constexpr int HB = 2 * kTableDeg;
@@ -1075,14 +1125,16 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
   __shared__ unsigned long long red[NT / kWave];
   __shared__ long long sh_item;
   __shared__ int sh_last;
-  __shared__ unsigned long long tbits[kBitsWords];  // ranked members of T_e
-  __shared__ int16_t twidx[kBitsWords];            // indices of its non-zero words
+  __shared__ unsigned long long tbits[kBitsWords];  // non-zero words of the ranked members of T_e
+  __shared__ int16_t twidx[kBitsWords];            // and their indices
   __shared__ int32_t wl_rank[CH];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   unsigned long long words = 0;
+  SlotAcc acc;
+  acc.init();
   const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
   // XCD-local queue: workgroups of XCD x = blockIdx % kXcds drain segment x
   // of the item range first, then the following segments
@@ -1114,7 +1166,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const int64_t item = sh_item;
     __syncthreads();
     if (item < 0) break;
-    const int64_t e = find_item_edge(item_pref, nedges, item);
+    const int64_t e = item_edge[item];
     const int64_t c = item - item_pref[e];
     const int32_t slot = bslot[e];
     const SlotDesc &S = slots[slot];
@@ -1133,8 +1185,12 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
     const bool tl = t <= kTHashCap;
     const int tlg = table_log(t);
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;  // 0: no ranked vertices, no bit rows
+    const int nzw = hcw ? (int)gacc[e].nzw : 0;
     if (tid < 4) sh_cnt[tid] = 0;
-    for (int i = tid; i < hcw; i += NT) tbits[i] = 0ull;
+    for (int i = tid; i < nzw; i += NT) {
+      tbits[i] = tbw[tbase[e] + i];
+      twidx[i] = tbi[tbase[e] + i];
+    }
     if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
     if (!ha)
@@ -1156,19 +1212,15 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       }
       words += (unsigned long long)da;
     }
-    if (tl || hcw) {
+    if (tl) {
       for (int i = tid; i < t; i += NT) {
         const int32_t y = T[3 * i], ry = T[3 * i + 2];
-        if (tl) lds_insert(hT, tlg, (uint32_t)y | (ry >= 0 ? kRTag : 0u));
-        if (ry >= 0) atomicOr(&tbits[ry >> 6], 1ull << (ry & 63));
+        lds_insert(hT, tlg, (uint32_t)y | (ry >= 0 ? kRTag : 0u));
       }
-      words += 3ull * (unsigned long long)t;
+      words += 2ull * (unsigned long long)t;
     }
+    words += 3ull * (unsigned long long)nzw;
     __syncthreads();
-    for (int i = tid; i < hcw; i += NT)
-      if (tbits[i]) twidx[atomicAdd(&sh_cnt[1], 1)] = (int16_t)i;
-    __syncthreads();
-    const int nzw = sh_cnt[1];
     // r in Gamma(b) \ {a}; r in Gamma(a) \ {b}; r in T_e (the LDS tables
     // exclude a and b already, the hub tables do not)
     auto inBx = [&](uint32_t r) -> bool { return r != (uint32_t)a && table_find(btab, blg, r) >= 0; };
@@ -1303,8 +1355,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
             if (inAx(r)) --cs;
           } else if (off < part1) {  // degT
             if (bits) {  // ranked partners: AND of w's bit row with the ranked members of T_e
-              const int j = twidx[off];
-              kt += (unsigned long long)__popcll(S.hbits[(int64_t)wl_rank[l2] * S.hcw + j] & tbits[j]);
+              kt += (unsigned long long)__popcll(S.hbits[(int64_t)wl_rank[l2] * S.hcw + twidx[off]] & tbits[off]);
             } else if (lt) {
               const int32_t y = T[3 * off];
               const int dy = T[3 * off + 1];
@@ -1344,14 +1395,13 @@ __global__ __launch_bounds__(kGlobalNT) void k_count_global(
       __threadfence();
       const unsigned long long kk = atomicAdd(&g->k4, 0ull);
       const unsigned long long cc = atomicAdd(&g->cyc, 0ull) + kk;
-      if (lane <= kAccIdxCount) {
-        const u128 v = edge_term(lane, S.n, S.m, da, db, t, (int64_t)(kk / 2), (int64_t)cc);
-        if (v != 0) atomic_add_u128(S.acc + 2 * lane, v);
-      }
+      // per-lane register sums, flushed into the slot when it changes
+      acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(kk / 2), (int64_t)cc);
       if (lane == 0) micro_put(S, a, b, t, (int64_t)(kk / 2), (int64_t)cc);
     }
     __syncthreads();
   }
+  if (tid < kWave) acc.flush(slots);
   const unsigned long long wsum = block_sum_u64<NT>(words, red);
   if (tid == 0 && wsum) atomicAdd(words_out, wsum);
 }
@@ -1876,13 +1926,21 @@ hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, 
   return hipGetLastError();
 }
 
+hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, int64_t nedges, int32_t *item_edge,
+                            hipStream_t s) {
+  if (nedges <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_fill, dim3(grid_for(nedges, 256, 8192)), dim3(256), 0, s, item_pref, items, nedges,
+                     item_edge);
+  return hipGetLastError();
+}
+
 hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
-                                  const int64_t *item_cnt, const int64_t *tbase, int32_t *tlist, void *gacc,
-                                  KernelCfg cfg, hipStream_t s) {
+                                  const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
+                                  int32_t *tlist, void *gacc, KernelCfg cfg, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
-                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, tbase, tlist,
-                     (GEdge *)gacc, cfg.global_chunk);
+                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
+                     tlist, (GEdge *)gacc, cfg.global_chunk);
   return hipGetLastError();
 }
 
@@ -1900,13 +1958,22 @@ hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, 
   return hipGetLastError();
 }
 
+hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *tbase,
+                               const int32_t *tlist, unsigned long long *tbw, int16_t *tbi, void *gacc, hipStream_t s) {
+  if (nedges <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_global_tbits, dim3(grid_for(nedges, 1, 8192)), dim3(kGlobalNT), 0, s, slots,
+                     bins.slot[kClassGlobal], nedges, tbase, tlist, (GEdge *)gacc, tbw, tbi);
+  return hipGetLastError();
+}
+
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
-                               const int64_t *item_cnt, const int64_t *tbase, const int32_t *tlist, void *gacc,
+                               const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
+                               const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi, void *gacc,
                                KernelCfg cfg, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
-                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, tbase, tlist,
-                     (GEdge *)gacc, bins.cursor + kClassGlobal, bins.xcd_cursor, bins.words + kClassGlobal,
+                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
+                     tlist, tbw, tbi, (GEdge *)gacc, bins.cursor + kClassGlobal, bins.xcd_cursor, bins.words + kClassGlobal,
                      cfg.probe_ratio, cfg.global_chunk, cfg.flags);
   return hipGetLastError();
 }

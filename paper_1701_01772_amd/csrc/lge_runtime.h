@@ -61,8 +61,12 @@ struct Workspace {
   int64_t *item_pref = nullptr;       // cap_edges
   int64_t *tcap = nullptr;            // cap_edges
   int64_t *tbase = nullptr;           // cap_edges
-  int32_t *tlist = nullptr;           // cap_tlist
-  int64_t cap_tlist = 0;
+  int32_t *item_edge = nullptr;       // cap_items: split-class work item -> edge
+  int64_t cap_items = 0;
+  int32_t *tlist = nullptr;           // 3 * cap_tlist: (id, degree, rank) of T_e members
+  unsigned long long *tbw = nullptr;  // cap_tlist: non-zero words of the ranked-member bit sets
+  int16_t *tbi = nullptr;             // cap_tlist: their word indices
+  int64_t cap_tlist = 0;              // T_e entries
   void *gacc = nullptr;               // cap_edges * gedge_bytes()
   int64_t *scan_tmp = nullptr;
   int64_t scan_tmp_len = 0;

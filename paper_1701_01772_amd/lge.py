@@ -72,7 +72,8 @@ class Timing(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_float), ("sample_ms", ctypes.c_float), ("count_ms", ctypes.c_float * 3),
                 ("global_prep_ms", ctypes.c_float),
                 ("class_edges", ctypes.c_uint64 * 3), ("words_read", ctypes.c_uint64 * 3),
-                ("launches", ctypes.c_uint64), ("micro_ms", ctypes.c_float), ("pad", ctypes.c_float)]
+                ("launches", ctypes.c_uint64), ("micro_ms", ctypes.c_float), ("pad", ctypes.c_float),
+                ("alg_bytes", ctypes.c_uint64 * 3)]
 
 
 class WeightInfo(ctypes.Structure):
@@ -361,7 +362,8 @@ def lge_last_timing(ctx) -> dict:
     return {"total_ms": t.total_ms, "sample_ms": t.sample_ms, "count_ms": list(t.count_ms),
             "global_prep_ms": t.global_prep_ms,
             "class_edges": [int(x) for x in t.class_edges], "words_read": [int(x) for x in t.words_read],
-            "launches": int(t.launches), "micro_ms": t.micro_ms}
+            "launches": int(t.launches), "micro_ms": t.micro_ms,
+            "alg_bytes": [int(x) for x in t.alg_bytes]}
 
 
 def lge_autotune(ctx, g, p: float) -> Opts:
