@@ -28,6 +28,12 @@ namespace {
 // Co-degree table: at most this many ranked vertices (hc^2 * 4 bytes <= 1 GiB),
 // each of degree > kCodegMinDeg.
 constexpr int64_t kCodegMaxVertices = kMaxRanked;
+// Vertices above this degree get a co-degree row over all unranked vertices
+// (largest degrees first, while the build work, the sum of their 2-hop
+// volumes, and the memory stay within these budgets).
+constexpr int32_t kRowDeg = 1024;
+constexpr double kRowBudgetOps = 4e9;
+constexpr double kRowBudgetBytes = 4e9;
 constexpr int32_t kCodegMinDeg = 32;
 
 #define LGE_HIP(expr)                        \
@@ -369,6 +375,7 @@ static bool sizes_in_range(int64_t n, int64_t m, int64_t dmax) {
 }
 
 static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr);
+static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr);
 
 static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const int32_t *host_row_ptr) {
   hipStream_t s = ctx->stream;
@@ -461,7 +468,8 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   if (e != hipSuccess) return hip_err(e);
-  return build_codeg(ctx, g, host_row_ptr);
+  if ((rc = build_codeg(ctx, g, host_row_ptr)) != LGE_OK) return rc;
+  return build_rows(ctx, g, host_row_ptr);
 }
 
 // Co-degree table of the vertices of degree > tau, tau the smallest threshold
@@ -536,6 +544,65 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) 
   return LGE_OK;
 }
 
+// Co-degree rows: for the chosen vertices y, |Gamma(y) n Gamma(w)| for every
+// unranked w (ranked pairs use the co-degree table).  Counts of unranked w
+// are at most the ranking threshold, so 16 bits hold them.
+static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) {
+  g->nrows = 0;
+  const int64_t n = g->n;
+  if (n <= 0 || g->hc <= 0 || g->codeg_tau >= 65535) return LGE_OK;
+  std::vector<std::pair<int32_t, int32_t>> cand;
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t d = host_row_ptr[v + 1] - host_row_ptr[v];
+    if (d > kRowDeg) cand.push_back({d, (int32_t)v});
+  }
+  if (cand.empty()) return LGE_OK;
+  std::sort(cand.begin(), cand.end(), [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
+    return x.first != y.first ? x.first > y.first : x.second < y.second;
+  });
+  std::vector<int64_t> vol2((size_t)n);
+  hipStream_t s = ctx->stream;
+  LGE_HIP(hipMemcpyAsync(vol2.data(), g->vol2, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipStreamSynchronize(s));
+  const int64_t stride = (n + 1) & ~(int64_t)1;
+  std::vector<int32_t> hubs;
+  double ops = 0.0;
+  for (const auto &c : cand) {
+    const double bytes = (double)(hubs.size() + 1) * (double)stride * 2.0;
+    if (ops + (double)vol2[c.second] > kRowBudgetOps || bytes > kRowBudgetBytes) break;
+    ops += (double)vol2[c.second];
+    hubs.push_back(c.second);
+  }
+  if (hubs.empty()) return LGE_OK;
+  const int64_t nh = (int64_t)hubs.size();
+  std::vector<int32_t> hrow((size_t)n, -1);
+  for (int64_t h = 0; h < nh; ++h) hrow[hubs[h]] = (int32_t)h;
+  int32_t *dhubs = nullptr;
+  int rc;
+  if ((rc = dev_alloc(&dhubs, nh)) != LGE_OK) return rc;
+  const int64_t nent = (nh * stride + 3) & ~(int64_t)3;  // whole 64-bit words for the zero fill
+  if ((rc = dev_alloc(&g->hrow, n)) != LGE_OK || (rc = dev_alloc(&g->rows, nent)) != LGE_OK) {
+    dev_free(dhubs);
+    dev_free(g->hrow);
+    dev_free(g->rows);
+    return rc;
+  }
+  hipError_t e = hipMemcpyAsync(dhubs, hubs.data(), (size_t)nh * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->hrow, hrow.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_zero_u64((unsigned long long *)g->rows, nent / 4, s);
+  if (e == hipSuccess) e = launch_rows_build(g->row_ptr, g->col, g->crank, dhubs, nh, stride, g->rows, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(dhubs);
+  if (e != hipSuccess) {
+    dev_free(g->hrow);
+    dev_free(g->rows);
+    return hip_err(e);
+  }
+  g->nrows = nh;
+  g->rows_stride = stride;
+  return LGE_OK;
+}
+
 static void graph_free(lge_graph *g) {
   dev_free(g->own_row_ptr);
   dev_free(g->own_col);
@@ -546,6 +613,8 @@ static void graph_free(lge_graph *g) {
   dev_free(g->crank);
   dev_free(g->codeg);
   dev_free(g->hbits);
+  dev_free(g->hrow);
+  dev_free(g->rows);
   dev_free(g->t_arc);
   dev_free(g->tri);
   dev_free(g->mred);
@@ -848,6 +917,9 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.hc = g->hc;
     sd.hbits = g->hbits;
     sd.hcw = g->hcw;
+    sd.hrow = g->nrows > 0 ? g->hrow : nullptr;
+    sd.rows = g->rows;
+    sd.rows_stride = g->rows_stride;
     sd.n = jobs[j].n_override >= 0 ? jobs[j].n_override : g->n;
     sd.m = jobs[j].m_override >= 0 ? jobs[j].m_override : g->m;
     sd.p = jobs[j].p;

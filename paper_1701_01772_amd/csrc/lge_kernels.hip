@@ -584,6 +584,29 @@ __global__ __launch_bounds__(256) void k_codeg_pairs(const int64_t *__restrict__
   }
 }
 
+// One workgroup per row: for x in Gamma(b), for unranked w in Gamma(x), count
+// w once more.  A row belongs to one workgroup, so workgroup-scope atomics
+// on its packed 16-bit counters suffice.
+__global__ __launch_bounds__(256) void k_rows_build(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                    const int32_t *__restrict__ crank,
+                                                    const int32_t *__restrict__ hubs, int64_t nh, int64_t stride,
+                                                    uint16_t *rows) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    const int32_t b = hubs[h];
+    uint32_t *row = reinterpret_cast<uint32_t *>(rows + h * stride);
+    for (int32_t j = rp[b] + wv; j < rp[b + 1]; j += (int32_t)(blockDim.x >> 6)) {
+      const int32_t x = col[j];
+      for (int32_t k = rp[x] + lane; k < rp[x + 1]; k += 64) {
+        const int32_t w = col[k];
+        if (crank[w] >= 0) continue;
+        __hip_atomic_fetch_add(row + (w >> 1), 1u << ((w & 1) * 16), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ crank, int64_t n, int64_t hcw,
                                                     unsigned long long *bits) {
@@ -1271,9 +1294,16 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       const bool may_look = probe_ratio > 0;
       const int64_t look = may_look ? ((4 + lookup_cost(dw)) * probe_ratio) / 4 : 0;
       uint32_t cdeg = 0;
-      const bool cok = may_look && codeg_pair(S, w, isT ? a : b, &cdeg);
+      bool cok = may_look && codeg_pair(S, w, isT ? a : b, &cdeg);
       const int32_t rw = hcw ? S.crank[w] : -1;
       wl_rank[i] = rw;
+      if (!cok && may_look && S.hrow && rw < 0) {  // unranked w against a vertex with a co-degree row
+        const int32_t hr = S.hrow[isT ? a : b];
+        if (hr >= 0) {
+          cdeg = S.rows[(int64_t)hr * S.rows_stride + w];
+          cok = true;
+        }
+      }
       uint8_t fl = 0;
       int32_t units;
       if (!isT) {
@@ -1979,6 +2009,15 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 }
 
 size_t gedge_bytes() { return sizeof(GEdge); }
+
+hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,
+                             int64_t nh, int64_t stride, uint16_t *rows, hipStream_t s) {
+  if (nh <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_build, dim3(grid_for(nh, 1, 65536)), dim3(256), 0, s, row_ptr, col, crank, hubs, nh,
+                     stride, rows);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,
                              unsigned long long *bits, hipStream_t s) {
