@@ -842,7 +842,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
         const int32_t x = col[bbeg + i];
         if (x != a) lds_insert(htab, lg, (uint32_t)x);
       }
-      words += (unsigned long long)(db + 4);
+      if (tid == 0) words += (unsigned long long)(db + 4);  // per-edge terms counted once
       __syncthreads();
       // classify Gamma(a) \ {b}: in the hash -> T_e (tag it), else S_a
       for (int base = 0; base < da; base += NT) {
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           wl_deg[pos] = we - wb;
         }
       }
-      words += (unsigned long long)(3 * da);
+      if (tid == 0) words += (unsigned long long)(3 * da);
       __syncthreads();
       // target lists from the hash: T_e at the front, S_b at the back
       for (int i = tid; i < hs; i += NT) {
@@ -944,7 +944,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           }
         }
       }
-      words += steps + 2ull * (unsigned long long)L;
+      words += steps + (tid == 0 ? 2ull * (unsigned long long)L : 0ull);
       k4 = block_sum_u64<NT>(k4, red);
       cyc = block_sum_u64<NT>(cyc, red);
       if (tid < kWave) acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(k4 / 2), (int64_t)cyc);
@@ -1151,6 +1151,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   __shared__ unsigned long long tbits[kBitsWords];  // non-zero words of the ranked members of T_e
   __shared__ int16_t twidx[kBitsWords];            // and their indices
   __shared__ int32_t wl_rank[CH];
+  __shared__ int32_t bx_rank[CH];  // ranked members of T_e in this chunk
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1226,23 +1227,23 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         const int32_t x = col[bbeg + i];
         if (x != a) lds_insert(hB, blg, (uint32_t)x);
       }
-      words += (unsigned long long)db;
+      if (tid == 0) words += (unsigned long long)db;  // per-item terms counted once
     }
     if (!ha) {
       for (int i = tid; i < da; i += NT) {
         const int32_t x = col[abeg + i];
         if (x != b) lds_insert(hA, alg, (uint32_t)x);
       }
-      words += (unsigned long long)da;
+      if (tid == 0) words += (unsigned long long)da;
     }
     if (tl) {
       for (int i = tid; i < t; i += NT) {
         const int32_t y = T[3 * i], ry = T[3 * i + 2];
         lds_insert(hT, tlg, (uint32_t)y | (ry >= 0 ? kRTag : 0u));
       }
-      words += 2ull * (unsigned long long)t;
+      if (tid == 0) words += 2ull * (unsigned long long)t;
     }
-    words += 3ull * (unsigned long long)nzw;
+    if (tid == 0) words += 3ull * (unsigned long long)nzw;
     __syncthreads();
     // r in Gamma(b) \ {a}; r in Gamma(a) \ {b}; r in T_e (the LDS tables
     // exclude a and b already, the hub tables do not)
@@ -1282,7 +1283,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         wl_deg[pos] = we - wb;
       }
     }
-    words += (unsigned long long)(3 * (p1 - p0) + 4);
+    if (tid == 0) words += (unsigned long long)(3 * (p1 - p0) + 4);
     __syncthreads();
     const int L = sh_cnt[0];
     long long cyc_base = 0;
@@ -1321,8 +1322,11 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         const bool bits = rw >= 0;
         const bool lt = !bits && t_looks(dw, t, mT, probe_ratio);
         if (lt) fl |= kFLookT;
-        if (bits) fl |= kFBits;
-        const int part1 = bits ? nzw : (lt ? t : dw);
+        if (bits) {  // degT over ranked partners in the bit-row phase below
+          fl |= kFBits;
+          bx_rank[atomicAdd(&sh_cnt[2], 1)] = rw;
+        }
+        const int part1 = bits ? 0 : (lt ? t : dw);
         if (cok) {
           fl |= kFCodeg;
           cyc_base -= (long long)cdeg - 1;
@@ -1378,15 +1382,13 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
           const bool lt = (fl & kFLookT) != 0;
           const bool bits = (fl & kFBits) != 0;
           const bool both = !(fl & (kFCodeg | kFLookT | kFLookA | kFBits));
-          const int part1 = bits ? nzw : (lt ? t : dw);
+          const int part1 = bits ? 0 : (lt ? t : dw);
           if (both) {  // one walk of Gamma(w): degT and cax
             const uint32_t r = (uint32_t)col[wl_beg[l2] + off];
             kt += (unsigned long long)tmemb(r);
             if (inAx(r)) --cs;
           } else if (off < part1) {  // degT
-            if (bits) {  // ranked partners: AND of w's bit row with the ranked members of T_e
-              kt += (unsigned long long)__popcll(S.hbits[(int64_t)wl_rank[l2] * S.hcw + twidx[off]] & tbits[off]);
-            } else if (lt) {
+            if (lt) {
               const int32_t y = T[3 * off];
               const int dy = T[3 * off + 1];
               // ranked members count only ranked partners; pairs of unranked
@@ -1408,7 +1410,37 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         }
       }
     }
-    words += steps + 2ull * (unsigned long long)L;
+    words += steps + (tid == 0 ? 2ull * (unsigned long long)L : 0ull);
+    // bit-row phase: for every ranked member x of T_e in this chunk, the
+    // ranked partners |Gamma(x) n T_e n ranked| = popcount of x's bit row AND
+    // the ranked-member set, over its non-zero words; one wavefront per
+    // member, lanes over the words, two members in flight per wavefront
+    {
+      const int nb = sh_cnt[2];
+      const int wv = tid >> 6;
+      constexpr int NW = NT / kWave;
+      unsigned long long bsum = 0;
+      int xi = wv;
+      for (; xi + NW < nb; xi += 2 * NW) {
+        const unsigned long long *r0 = S.hbits + (int64_t)bx_rank[xi] * S.hcw;
+        const unsigned long long *r1 = S.hbits + (int64_t)bx_rank[xi + NW] * S.hcw;
+        for (int k = lane; k < nzw; k += kWave) {
+          const int j = twidx[k];
+          const unsigned long long tb = tbits[k];
+          const unsigned long long v0 = r0[j], v1 = r1[j];
+          bsum += (unsigned long long)(__popcll(v0 & tb) + __popcll(v1 & tb));
+          words += 4;
+        }
+      }
+      for (; xi < nb; xi += NW) {
+        const unsigned long long *r0 = S.hbits + (int64_t)bx_rank[xi] * S.hcw;
+        for (int k = lane; k < nzw; k += kWave) {
+          bsum += (unsigned long long)__popcll(r0[twidx[k]] & tbits[k]);
+          words += 2;
+        }
+      }
+      kt += bsum;
+    }
     kt = block_sum_u64<NT>(kt, red);
     cs = block_sum_u64<NT>(cs, red);
     if (tid == 0) {
