@@ -986,7 +986,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     LGE_HIP(hipStreamSynchronize(s));
     if ((rc = ws_reserve_tlist(ctx, hl[0] + hl[1])) != LGE_OK) return rc;
     if ((rc = ws_reserve_items(ctx, hl[2] + hl[3])) != LGE_OK) return rc;
-    LGE_HIP(launch_item_fill(w.item_pref, w.items, ng, w.item_edge, s));
+    LGE_HIP(launch_item_fill(w.item_pref, w.items, w.tbase, ng, w.item_edge, w.gacc, s));
     LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.gacc,
                                    cfg, s));
     LGE_HIP(launch_global_tbits(w.slots, bins, ng, w.tbase, w.tlist, w.tbw, w.tbi, w.gacc, s));

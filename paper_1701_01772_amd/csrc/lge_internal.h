@@ -161,8 +161,8 @@ hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t nedges, 
 hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t chunk, int64_t *items,
                               int64_t *tcap, void *gacc, hipStream_t s);
 // work item -> edge map (item_edge holds the total number of items)
-hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, int64_t nedges, int32_t *item_edge,
-                            hipStream_t s);
+hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, const int64_t *tbase, int64_t nedges,
+                            int32_t *item_edge, void *gacc, hipStream_t s);
 hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                   const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
                                   int32_t *tlist, void *gacc, KernelCfg cfg, hipStream_t s);

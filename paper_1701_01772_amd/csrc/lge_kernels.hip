@@ -973,9 +973,17 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
 constexpr int kGlobalNT = 256;
 constexpr int kTHashCap = 512;
 
+// Per split-class edge: counters (t by classify, nzw by the bit-set kernel,
+// k4 / cyc / done by the counting items) and the edge's descriptor, written
+// once per launch so a work item finds everything in one 128-byte record.
 struct GEdge {
   unsigned long long t, k4, cyc, done, nzw;
+  int32_t a, b, slot, da, db, abeg, bbeg, ra;  // ra / rb: ranks (-1 when unranked)
+  int32_t rb, hra, hrb, pad;                   // hra / hrb: co-degree rows (-1 when none)
+  int64_t hoffa, hoffb;                        // hub-table offsets (-1 when no table)
+  int64_t tbase, ipref, icnt;                  // T_e offset, first work item, work items
 };
+static_assert(sizeof(GEdge) == 128, "one GEdge per 128 bytes");
 
 __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict__ slots,
                                                      const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
@@ -983,24 +991,45 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
                                                      int64_t *items, int64_t *tcap, GEdge *gacc) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const SlotDesc &S = slots[bslot[e]];
+    const int32_t slot = bslot[e];
+    const SlotDesc &S = slots[slot];
     const int32_t a = ba[e], b = bb[e];
-    const int da = S.row_ptr[a + 1] - S.row_ptr[a];
-    const int db = S.row_ptr[b + 1] - S.row_ptr[b];
+    const int32_t abeg = S.row_ptr[a], bbeg = S.row_ptr[b];
+    const int da = S.row_ptr[a + 1] - abeg;
+    const int db = S.row_ptr[b + 1] - bbeg;
     items[e] = (da + chunk - 1) / chunk;
     tcap[e] = da < db ? da : db;
-    gacc[e].t = gacc[e].k4 = gacc[e].cyc = gacc[e].done = gacc[e].nzw = 0ull;
+    GEdge &G = gacc[e];
+    G.t = G.k4 = G.cyc = G.done = G.nzw = 0ull;
+    G.a = a;
+    G.b = b;
+    G.slot = slot;
+    G.da = da;
+    G.db = db;
+    G.abeg = abeg;
+    G.bbeg = bbeg;
+    G.ra = S.hc > 0 ? S.crank[a] : -1;
+    G.rb = S.hc > 0 ? S.crank[b] : -1;
+    G.hra = S.hrow ? S.hrow[a] : -1;
+    G.hrb = S.hrow ? S.hrow[b] : -1;
+    G.pad = 0;
+    G.hoffa = has_table(da) ? S.hoff[a] : -1;
+    G.hoffb = has_table(db) ? S.hoff[b] : -1;
   }
 }
 
 // the work item -> edge map: item_pref[e] .. item_pref[e] + items[e] - 1 -> e
 __global__ __launch_bounds__(256) void k_item_fill(const int64_t *__restrict__ item_pref,
-                                                   const int64_t *__restrict__ items, int64_t nedges,
-                                                   int32_t *__restrict__ item_edge) {
+                                                   const int64_t *__restrict__ items,
+                                                   const int64_t *__restrict__ tbase, int64_t nedges,
+                                                   int32_t *__restrict__ item_edge, GEdge *gacc) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = item_pref[e], k = items[e];
     for (int64_t i = 0; i < k; ++i) item_edge[b + i] = (int32_t)e;
+    gacc[e].tbase = tbase[e];
+    gacc[e].ipref = b;
+    gacc[e].icnt = k;
   }
 }
 
@@ -1150,7 +1179,6 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   __shared__ int sh_last;
   __shared__ unsigned long long tbits[kBitsWords];  // non-zero words of the ranked members of T_e
   __shared__ int16_t twidx[kBitsWords];            // and their indices
-  __shared__ int32_t wl_rank[CH];
   __shared__ int32_t bx_rank[CH];  // ranked members of T_e in this chunk
 
   const int tid = threadIdx.x;
@@ -1165,55 +1193,55 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   const bool xcd_local = (flags & kOptXcdLocal) != 0;
   const int my_seg = (int)(blockIdx.x % kXcds);
   int seg_off = 0;
+  // the next work item (-1: none left); thread 0 asks for item k+1 while the
+  // workgroup counts item k
+  auto next_item = [&]() -> long long {
+    if (!xcd_local) {
+      const long long it = (long long)atomicAdd(cursor, 1ull);
+      return it < total_items ? it : -1;
+    }
+    while (seg_off < kXcds) {
+      const int sg = (my_seg + seg_off) % kXcds;
+      const int64_t lo = total_items * sg / kXcds, hi = total_items * (sg + 1) / kXcds;
+      const long long k = (long long)atomicAdd(&xcd_cursor[sg], 1ull);
+      if (lo + k < hi) return lo + k;
+      ++seg_off;
+    }
+    return -1;
+  };
+  if (tid == 0) sh_item = next_item();
+  __syncthreads();
 
   for (;;) {
-    if (tid == 0) {
-      long long it = -1;
-      if (!xcd_local) {
-        it = (long long)atomicAdd(cursor, 1ull);
-        if (it >= total_items) it = -1;
-      } else {
-        while (seg_off < kXcds) {
-          const int sg = (my_seg + seg_off) % kXcds;
-          const int64_t lo = total_items * sg / kXcds, hi = total_items * (sg + 1) / kXcds;
-          const long long k = (long long)atomicAdd(&xcd_cursor[sg], 1ull);
-          if (lo + k < hi) {
-            it = lo + k;
-            break;
-          }
-          ++seg_off;
-        }
-      }
-      sh_item = it;
-    }
-    __syncthreads();
     const int64_t item = sh_item;
     __syncthreads();
     if (item < 0) break;
+    long long upcoming = -1;
+    if (tid == 0) upcoming = next_item();
     const int64_t e = item_edge[item];
-    const int64_t c = item - item_pref[e];
-    const int32_t slot = bslot[e];
+    const GEdge &G = gacc[e];
+    const int32_t a = G.a, b = G.b, slot = G.slot, da = G.da, db = G.db, abeg = G.abeg, bbeg = G.bbeg;
+    const int32_t ra = G.ra, rb = G.rb, hra = G.hra, hrb = G.hrb;
+    const int64_t hoffa = G.hoffa, hoffb = G.hoffb, tb0 = G.tbase, icnt = G.icnt;
+    const int64_t c = item - G.ipref;
+    const int t = (int)G.t;
     const SlotDesc &S = slots[slot];
     const int32_t *__restrict__ rp = S.row_ptr;
     const int32_t *__restrict__ col = S.col;
-    const int32_t a = ba[e], b = bb[e];
-    const int32_t abeg = rp[a], bbeg = rp[b];
-    const int da = rp[a + 1] - abeg, db = rp[b + 1] - bbeg;
-    const bool ha = has_table(da), hb = has_table(db);
+    const bool ha = hoffa >= 0, hb = hoffb >= 0;
     static_assert(2 * kTableDeg <= (1 << 9), "LDS tables of the split kernel hold degree <= kTableDeg");
     const int blg = table_log(db), alg = table_log(da);
-    const uint32_t *__restrict__ btab = hb ? S.htab + S.hoff[b] : hB;
-    const uint32_t *__restrict__ atab = ha ? S.htab + S.hoff[a] : hA;
-    const int t = (int)gacc[e].t;
-    const int32_t *__restrict__ T = tlist + 3 * tbase[e];  // (id, degree, rank) triples
+    const uint32_t *__restrict__ btab = hb ? S.htab + hoffb : hB;
+    const uint32_t *__restrict__ atab = ha ? S.htab + hoffa : hA;
+    const int32_t *__restrict__ T = tlist + 3 * tb0;  // (id, degree, rank) triples
     const bool tl = t <= kTHashCap;
     const int tlg = table_log(t);
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;  // 0: no ranked vertices, no bit rows
-    const int nzw = hcw ? (int)gacc[e].nzw : 0;
+    const int nzw = hcw ? (int)G.nzw : 0;
     if (tid < 4) sh_cnt[tid] = 0;
     for (int i = tid; i < nzw; i += NT) {
-      tbits[i] = tbw[tbase[e] + i];
-      twidx[i] = tbi[tbase[e] + i];
+      tbits[i] = tbw[tb0 + i];
+      twidx[i] = tbi[tb0 + i];
     }
     if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
@@ -1222,28 +1250,20 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     if (tl)
       for (int i = tid; i < (1 << tlg); i += NT) hT[i] = kEmpty;
     __syncthreads();
-    if (!hb) {
-      for (int i = tid; i < db; i += NT) {
-        const int32_t x = col[bbeg + i];
-        if (x != a) lds_insert(hB, blg, (uint32_t)x);
+    {  // the LDS tables: Gamma(b) \ {a}, Gamma(a) \ {b} (non-hub sides), T_e (small)
+      const int nB = hb ? 0 : db, nA = ha ? 0 : da, nT = tl ? t : 0;
+      const int nmax = nB > nA ? (nB > nT ? nB : nT) : (nA > nT ? nA : nT);
+      for (int i = tid; i < nmax; i += NT) {
+        const int32_t xb = i < nB ? col[bbeg + i] : -1;
+        const int32_t xa = i < nA ? col[abeg + i] : -1;
+        const int32_t ty = i < nT ? T[3 * i] : -1;
+        const int32_t tr = i < nT ? T[3 * i + 2] : -1;
+        if (xb >= 0 && xb != a) lds_insert(hB, blg, (uint32_t)xb);
+        if (xa >= 0 && xa != b) lds_insert(hA, alg, (uint32_t)xa);
+        if (ty >= 0) lds_insert(hT, tlg, (uint32_t)ty | (tr >= 0 ? kRTag : 0u));
       }
-      if (tid == 0) words += (unsigned long long)db;  // per-item terms counted once
+      if (tid == 0) words += (unsigned long long)(nB + nA + 2 * nT + 3 * nzw + 32);  // per-item terms once
     }
-    if (!ha) {
-      for (int i = tid; i < da; i += NT) {
-        const int32_t x = col[abeg + i];
-        if (x != b) lds_insert(hA, alg, (uint32_t)x);
-      }
-      if (tid == 0) words += (unsigned long long)da;
-    }
-    if (tl) {
-      for (int i = tid; i < t; i += NT) {
-        const int32_t y = T[3 * i], ry = T[3 * i + 2];
-        lds_insert(hT, tlg, (uint32_t)y | (ry >= 0 ? kRTag : 0u));
-      }
-      if (tid == 0) words += 2ull * (unsigned long long)t;
-    }
-    if (tid == 0) words += 3ull * (unsigned long long)nzw;
     __syncthreads();
     // r in Gamma(b) \ {a}; r in Gamma(a) \ {b}; r in T_e (the LDS tables
     // exclude a and b already, the hub tables do not)
@@ -1262,85 +1282,93 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       return (hcw && S.crank[r] >= 0) ? 2 : 1;
     };
     const int64_t mB = hb ? 16 : 4, mA = ha ? 16 : 4, mT = tl ? 4 : 32;
-    // this chunk's vertices of Gamma(a) \ {b}
+    // this chunk's vertices w of Gamma(a) \ {b}, each with its mode: the loads
+    // that depend only on w (row, rank, membership in Gamma(b)) go out
+    // together, then the co-degree read
     const int p0 = (int)(c * chunk);
     const int p1 = p0 + chunk < da ? p0 + chunk : da;
+    long long cyc_base = 0;
+    const bool may_look = probe_ratio > 0;
     for (int base = p0; base < p1; base += NT) {
       const int i = base + tid;
       bool valid = i < p1;
       const int32_t x = valid ? col[abeg + i] : -1;
       valid = valid && x != b;
-      const bool isT = valid && inBx((uint32_t)x);  // x in Gamma(a): in T_e iff in Gamma(b)
+      int32_t wb = 0, we = 0, rw = -1;
+      bool isT = false;
+      if (valid) {
+        wb = rp[x];
+        we = rp[x + 1];
+        if (hcw) rw = S.crank[x];
+        isT = table_find(btab, blg, (uint32_t)x) >= 0;  // x in Gamma(a): in T_e iff in Gamma(b)
+      }
+      const int dw = we - wb;
+      // |Gamma(x) n Gamma(y)|, y = a for T_e members, b otherwise: the table
+      // for ranked pairs, y's co-degree row for unranked x
+      uint32_t cdeg = 0;
+      bool cok = false;
+      if (valid && may_look) {
+        const int32_t ry = isT ? ra : rb, hr = isT ? hra : hrb;
+        if (rw >= 0 && ry >= 0) {
+          const int64_t lo = rw < ry ? rw : ry, hi = rw < ry ? ry : rw;
+          cdeg = S.codeg[lo * S.hc + hi];
+          cok = true;
+        } else if (rw < 0 && hr >= 0) {
+          cdeg = S.rows[(int64_t)hr * S.rows_stride + x];
+          cok = true;
+        }
+      }
+      uint8_t fl = 0;
+      int32_t units = 0;
+      if (valid) {
+        const int64_t look = may_look ? ((4 + lookup_cost(dw)) * probe_ratio) / 4 : 0;
+        if (!isT) {
+          if (cok) {
+            fl = kFCodeg;
+            cyc_base += (long long)cdeg - 1;
+          } else if (may_look && (int64_t)db * look < (int64_t)dw * (4 + mB)) {
+            fl = kFLookB;
+            units = db;
+          } else {
+            units = dw;
+          }
+        } else {
+          const bool bits = rw >= 0;
+          const bool lt = !bits && t_looks(dw, t, mT, probe_ratio);
+          if (lt) fl |= kFLookT;
+          if (bits) {  // degT over ranked partners in the bit-row phase below
+            fl |= kFBits;
+            bx_rank[atomicAdd(&sh_cnt[2], 1)] = rw;
+          }
+          const int part1 = bits ? 0 : (lt ? t : dw);
+          if (cok) {
+            fl |= kFCodeg;
+            cyc_base -= (long long)cdeg - 1;
+            units = part1;
+          } else {
+            const bool la = may_look && (int64_t)da * look < (int64_t)dw * (4 + mA);
+            if (la) fl |= kFLookA;
+            // one walk of Gamma(w) serves both terms when nothing else is used
+            units = (!bits && !lt && !la) ? dw : part1 + (la ? da : dw);
+          }
+        }
+      }
       const uint64_t vm = __ballot(valid);
       int pos0 = 0;
       if (lane == 0 && vm) pos0 = atomicAdd(&sh_cnt[0], __popcll(vm));
       pos0 = __shfl(pos0, 0);
       if (valid) {
         const int pos = pos0 + __popcll(vm & lt_mask);
-        const int32_t wb = rp[x], we = rp[x + 1];
         wl_v[pos] = (uint32_t)x | (isT ? kTag : 0u);
         wl_beg[pos] = wb;
-        wl_deg[pos] = we - wb;
+        wl_deg[pos] = dw;
+        wl_f[pos] = fl;
+        wl_pref[pos] = units;
       }
     }
-    if (tid == 0) words += (unsigned long long)(3 * (p1 - p0) + 4);
+    if (tid == 0) words += (unsigned long long)(6 * (p1 - p0));
     __syncthreads();
     const int L = sh_cnt[0];
-    long long cyc_base = 0;
-    for (int i = tid; i < L; i += NT) {
-      const uint32_t v = wl_v[i];
-      const bool isT = (v & kTag) != 0;
-      const int32_t w = (int32_t)(v & kIdMask);
-      const int dw = wl_deg[i];
-      const bool may_look = probe_ratio > 0;
-      const int64_t look = may_look ? ((4 + lookup_cost(dw)) * probe_ratio) / 4 : 0;
-      uint32_t cdeg = 0;
-      bool cok = may_look && codeg_pair(S, w, isT ? a : b, &cdeg);
-      const int32_t rw = hcw ? S.crank[w] : -1;
-      wl_rank[i] = rw;
-      if (!cok && may_look && S.hrow && rw < 0) {  // unranked w against a vertex with a co-degree row
-        const int32_t hr = S.hrow[isT ? a : b];
-        if (hr >= 0) {
-          cdeg = S.rows[(int64_t)hr * S.rows_stride + w];
-          cok = true;
-        }
-      }
-      uint8_t fl = 0;
-      int32_t units;
-      if (!isT) {
-        if (cok) {
-          fl = kFCodeg;
-          units = 0;
-          cyc_base += (long long)cdeg - 1;
-        } else if (may_look && (int64_t)db * look < (int64_t)dw * (4 + mB)) {
-          fl = kFLookB;
-          units = db;
-        } else {
-          units = dw;
-        }
-      } else {
-        const bool bits = rw >= 0;
-        const bool lt = !bits && t_looks(dw, t, mT, probe_ratio);
-        if (lt) fl |= kFLookT;
-        if (bits) {  // degT over ranked partners in the bit-row phase below
-          fl |= kFBits;
-          bx_rank[atomicAdd(&sh_cnt[2], 1)] = rw;
-        }
-        const int part1 = bits ? 0 : (lt ? t : dw);
-        if (cok) {
-          fl |= kFCodeg;
-          cyc_base -= (long long)cdeg - 1;
-          units = part1;
-        } else {
-          const bool la = may_look && (int64_t)da * look < (int64_t)dw * (4 + mA);
-          if (la) fl |= kFLookA;
-          // one walk of Gamma(w) serves both terms when nothing else is used
-          units = (!bits && !lt && !la) ? dw : part1 + (la ? da : dw);
-        }
-      }
-      wl_f[i] = fl;
-      wl_pref[i] = units;
-    }
     __syncthreads();
     const int32_t total = block_scan_lds<NT>(wl_pref, L, carry_sh);
     if (tid == 0) wl_pref[L] = total;
@@ -1443,24 +1471,32 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     }
     kt = block_sum_u64<NT>(kt, red);
     cs = block_sum_u64<NT>(cs, red);
-    if (tid == 0) {
-      GEdge *g = gacc + e;
-      if (kt) atomicAdd(&g->k4, kt);
-      if (cs) atomicAdd(&g->cyc, cs);
-      __threadfence();
-      const unsigned long long d = atomicAdd(&g->done, 1ull);
-      sh_last = (d + 1ull == (unsigned long long)item_cnt[e]) ? 1 : 0;
+    if (icnt == 1) {  // the edge's only item: no partial sums to meet
+      if (tid < kWave) {
+        // per-lane register sums, flushed into the slot when it changes
+        acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(kt / 2), (int64_t)(cs + kt));
+        if (lane == 0) micro_put(S, a, b, t, (int64_t)(kt / 2), (int64_t)(cs + kt));
+      }
+    } else {
+      if (tid == 0) {
+        GEdge *g = gacc + e;
+        if (kt) atomicAdd(&g->k4, kt);
+        if (cs) atomicAdd(&g->cyc, cs);
+        __threadfence();
+        const unsigned long long d = atomicAdd(&g->done, 1ull);
+        sh_last = (d + 1ull == (unsigned long long)icnt) ? 1 : 0;
+      }
+      __syncthreads();
+      if (sh_last && tid < kWave) {
+        GEdge *g = gacc + e;
+        __threadfence();
+        const unsigned long long kk = atomicAdd(&g->k4, 0ull);
+        const unsigned long long cc = atomicAdd(&g->cyc, 0ull) + kk;
+        acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(kk / 2), (int64_t)cc);
+        if (lane == 0) micro_put(S, a, b, t, (int64_t)(kk / 2), (int64_t)cc);
+      }
     }
-    __syncthreads();
-    if (sh_last && tid < kWave) {
-      GEdge *g = gacc + e;
-      __threadfence();
-      const unsigned long long kk = atomicAdd(&g->k4, 0ull);
-      const unsigned long long cc = atomicAdd(&g->cyc, 0ull) + kk;
-      // per-lane register sums, flushed into the slot when it changes
-      acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(kk / 2), (int64_t)cc);
-      if (lane == 0) micro_put(S, a, b, t, (int64_t)(kk / 2), (int64_t)cc);
-    }
+    if (tid == 0) sh_item = upcoming;
     __syncthreads();
   }
   if (tid < kWave) acc.flush(slots);
@@ -1988,11 +2024,11 @@ hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, 
   return hipGetLastError();
 }
 
-hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, int64_t nedges, int32_t *item_edge,
-                            hipStream_t s) {
+hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, const int64_t *tbase, int64_t nedges,
+                            int32_t *item_edge, void *gacc, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_item_fill, dim3(grid_for(nedges, 256, 8192)), dim3(256), 0, s, item_pref, items, nedges,
-                     item_edge);
+  hipLaunchKernelGGL(k_item_fill, dim3(grid_for(nedges, 256, 8192)), dim3(256), 0, s, item_pref, items, tbase,
+                     nedges, item_edge, (GEdge *)gacc);
   return hipGetLastError();
 }
 
