@@ -534,6 +534,7 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) 
   e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, list, s);
   if (e == hipSuccess) e = hipMemsetAsync(g->codeg, 0, (size_t)hc * (size_t)hc * sizeof(uint32_t), s);
   if (e == hipSuccess) e = launch_codeg_pairs(off, cnt, list, n, hc, g->codeg, s);
+  if (e == hipSuccess) e = launch_codeg_mirror(hc, g->codeg, s);
   if (e == hipSuccess) e = launch_zero_u64(g->hbits, hc * hcw, s);
   if (e == hipSuccess) e = launch_codeg_bits(g->row_ptr, g->col, g->crank, n, hcw, g->hbits, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

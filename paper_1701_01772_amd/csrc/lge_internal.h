@@ -42,7 +42,7 @@ struct SlotDesc {
   const int64_t *hoff;      // n: offset of the vertex's hub table in htab (hubs only)
   const uint32_t *htab;     // hub tables (open addressing, 2^table_log(d) slots each)
   const int32_t *crank;     // n: rank in the co-degree table, -1 if absent
-  const uint32_t *codeg;    // hc x hc: |Gamma(x) n Gamma(y)| at [min rank][max rank]
+  const uint32_t *codeg;    // hc x hc, symmetric: |Gamma(x) n Gamma(y)| at [rank x][rank y]
   int64_t hc;               // ranked vertices (0: no table)
   const unsigned long long *hbits;  // hc x hcw bit rows: bit ry of row rx = (x, y) adjacent
   int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
@@ -150,6 +150,8 @@ hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const i
 // adjacency bit rows among the ranked vertices (bits zeroed by the caller)
 hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,
                              unsigned long long *bits, hipStream_t s);
+// copy the upper triangle of the hc x hc co-degree table into the lower one
+hipError_t launch_codeg_mirror(int64_t hc, uint32_t *tab, hipStream_t s);
 hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, int64_t n, int64_t hc,
                               uint32_t *tab, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);

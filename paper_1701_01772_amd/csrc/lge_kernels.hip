@@ -510,9 +510,10 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
 
 // ---------------------------------------------------------------------------
 // Co-degree table of the high-degree vertices: codeg[i][j] = |Gamma(x) n
-// Gamma(y)| for the vertices x, y of rank i < j among those with degree > tau.
+// Gamma(y)| for the vertices x, y of ranks i, j among those with degree > tau.
 // Built once per graph by enumerating, for every vertex, the pairs of its
-// ranked neighbours (each common neighbour of x and y is seen once).
+// ranked neighbours (each common neighbour of x and y is seen once) into the
+// upper triangle, then mirrored so that each vertex's co-degrees form a row.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_codeg_flags(const int32_t *__restrict__ row_ptr, int64_t n, int32_t tau,
@@ -584,6 +585,30 @@ __global__ __launch_bounds__(256) void k_codeg_pairs(const int64_t *__restrict__
   }
 }
 
+// Mirror the upper triangle into the lower one, so that every vertex's
+// co-degrees are one contiguous row: 64 x 64 tiles through LDS, one
+// workgroup per tile above (or on) the diagonal.
+__global__ __launch_bounds__(256) void k_codeg_mirror(int64_t hc, uint32_t *tab) {
+  __shared__ uint32_t tile[64][65];
+  const int64_t nt = (hc + 63) / 64;
+  for (int64_t k = blockIdx.x; k < nt * nt; k += gridDim.x) {
+    const int64_t ti = k / nt, tj = k % nt;
+    if (tj < ti) continue;  // uniform per block
+    for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
+      const int r = q >> 6, c = q & 63;
+      const int64_t i = ti * 64 + r, j = tj * 64 + c;
+      tile[r][c] = (i < hc && j < hc && i < j) ? tab[i * hc + j] : 0u;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
+      const int r = q >> 6, c = q & 63;  // destination (j, i) = (tj*64 + r, ti*64 + c)
+      const int64_t i = ti * 64 + c, j = tj * 64 + r;
+      if (i < hc && j < hc && i < j) tab[j * hc + i] = tile[c][r];
+    }
+    __syncthreads();
+  }
+}
+
 // One workgroup per row: for x in Gamma(b), for unranked w in Gamma(x), count
 // w once more.  A row belongs to one workgroup, so workgroup-scope atomics
 // on its packed 16-bit counters suffice.
@@ -628,8 +653,7 @@ __device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t
   if (S.hc <= 0) return false;
   const int32_t rx = S.crank[x], ry = S.crank[y];
   if (rx < 0 || ry < 0) return false;
-  const int64_t lo = rx < ry ? rx : ry, hi = rx < ry ? ry : rx;
-  *val = S.codeg[lo * (int64_t)S.hc + hi];
+  *val = S.codeg[(int64_t)ry * S.hc + rx];  // the table is symmetric: y's row
   return true;
 }
 
@@ -652,6 +676,32 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
     for (int i = 0; i < NT / kWave; ++i) s += red[i];
     __syncthreads();
     return s;
+  }
+}
+
+// two block sums with one round of barriers (red holds 2 * NT / kWave words)
+template <int NT>
+__device__ __forceinline__ void block_sum2_u64(unsigned long long &x, unsigned long long &y,
+                                               unsigned long long *red) {
+  x = wave_sum_u64(x);
+  y = wave_sum_u64(y);
+  if constexpr (NT != kWave) {
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      red[w] = x;
+      red[NT / kWave + w] = y;
+    }
+    __syncthreads();
+    unsigned long long sx = 0, sy = 0;
+#pragma unroll
+    for (int i = 0; i < NT / kWave; ++i) {
+      sx += red[i];
+      sy += red[NT / kWave + i];
+    }
+    __syncthreads();
+    x = sx;
+    y = sy;
   }
 }
 
@@ -1174,7 +1224,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   __shared__ int32_t wl_pref[CH + 1];
   __shared__ int32_t sh_cnt[4];
   __shared__ int32_t carry_sh[NT / kWave + 1];
-  __shared__ unsigned long long red[NT / kWave];
+  __shared__ unsigned long long red[2 * NT / kWave];
   __shared__ long long sh_item;
   __shared__ int sh_last;
   __shared__ unsigned long long tbits[kBitsWords];  // non-zero words of the ranked members of T_e
@@ -1310,8 +1360,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       if (valid && may_look) {
         const int32_t ry = isT ? ra : rb, hr = isT ? hra : hrb;
         if (rw >= 0 && ry >= 0) {
-          const int64_t lo = rw < ry ? rw : ry, hi = rw < ry ? ry : rw;
-          cdeg = S.codeg[lo * S.hc + hi];
+          cdeg = S.codeg[(int64_t)ry * S.hc + rw];  // symmetric table: the row of the item's fixed end
           cok = true;
         } else if (rw < 0 && hr >= 0) {
           cdeg = S.rows[(int64_t)hr * S.rows_stride + x];
@@ -1469,8 +1518,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       }
       kt += bsum;
     }
-    kt = block_sum_u64<NT>(kt, red);
-    cs = block_sum_u64<NT>(cs, red);
+    block_sum2_u64<NT>(kt, cs, red);
     if (icnt == 1) {  // the edge's only item: no partial sums to meet
       if (tid < kWave) {
         // per-lane register sums, flushed into the slot when it changes
@@ -1967,6 +2015,13 @@ hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const i
                              const int64_t *off, int32_t *list, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_codeg_fill, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, crank, n, off, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_codeg_mirror(int64_t hc, uint32_t *tab, hipStream_t s) {
+  if (hc <= 1) return hipSuccess;
+  const int64_t nt = (hc + 63) / 64;
+  hipLaunchKernelGGL(k_codeg_mirror, dim3(grid_for(nt * nt, 1, 65536)), dim3(256), 0, s, hc, tab);
   return hipGetLastError();
 }
 
