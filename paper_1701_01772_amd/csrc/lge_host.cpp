@@ -151,6 +151,7 @@ static void ws_free(Workspace &w) {
   dev_free(w.tbw);
   dev_free(w.tbi);
   dev_free(w.item_edge);
+  dev_free(w.tmask);
   if (w.gacc) (void)hipFree(w.gacc);
   w.gacc = nullptr;
   dev_free(w.scan_tmp);
@@ -297,10 +298,12 @@ static int ws_reserve_items(lge_ctx *ctx, int64_t len) {
   Workspace &w = ctx->ws;
   if (len <= w.cap_items) return LGE_OK;
   dev_free(w.item_edge);
+  dev_free(w.tmask);
   w.cap_items = 0;
   const int64_t cap = std::max<int64_t>(len + len / 4, 4096);
-  const int rc = dev_alloc(&w.item_edge, cap);
+  int rc = dev_alloc(&w.item_edge, cap);
   if (rc != LGE_OK) return rc;
+  if ((rc = dev_alloc(&w.tmask, cap * (kGlobalChunkMax / 64))) != LGE_OK) return rc;
   w.cap_items = cap;
   return LGE_OK;
 }
@@ -469,6 +472,8 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   cleanup();
   if (e != hipSuccess) return hip_err(e);
   if ((rc = build_codeg(ctx, g, host_row_ptr)) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
+  LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, n, g->vinfo, s));
   return build_rows(ctx, g, host_row_ptr);
 }
 
@@ -616,6 +621,7 @@ static void graph_free(lge_graph *g) {
   dev_free(g->hbits);
   dev_free(g->hrow);
   dev_free(g->rows);
+  dev_free(g->vinfo);
   dev_free(g->t_arc);
   dev_free(g->tri);
   dev_free(g->mred);
@@ -918,6 +924,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.hc = g->hc;
     sd.hbits = g->hbits;
     sd.hcw = g->hcw;
+    sd.vinfo = g->vinfo;
     sd.hrow = g->nrows > 0 ? g->hrow : nullptr;
     sd.rows = g->rows;
     sd.rows_stride = g->rows_stride;
@@ -988,12 +995,12 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     if ((rc = ws_reserve_tlist(ctx, hl[0] + hl[1])) != LGE_OK) return rc;
     if ((rc = ws_reserve_items(ctx, hl[2] + hl[3])) != LGE_OK) return rc;
     LGE_HIP(launch_item_fill(w.item_pref, w.items, w.tbase, ng, w.item_edge, w.gacc, s));
-    LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.gacc,
-                                   cfg, s));
+    LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.tmask,
+                                   w.gacc, cfg, s));
     LGE_HIP(launch_global_tbits(w.slots, bins, ng, w.tbase, w.tlist, w.tbw, w.tbi, w.gacc, s));
     LGE_HIP(hipEventRecord(ev[6], s));
     LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.tbw,
-                                w.tbi, w.gacc, cfg, s));
+                                w.tbi, w.tmask, w.gacc, cfg, s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
   LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)nslots * kAccSlots * 2 * sizeof(unsigned long long),

@@ -46,6 +46,7 @@ struct SlotDesc {
   int64_t hc;               // ranked vertices (0: no table)
   const unsigned long long *hbits;  // hc x hcw bit rows: bit ry of row rx = (x, y) adjacent
   int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
+  const int4 *vinfo;        // n: (row start, degree, rank or -1, 0)
   const int32_t *hrow;      // n: co-degree row of the vertex, -1 if none (null: no rows)
   const uint16_t *rows;     // rows x rows_stride: |Gamma(y) n Gamma(w)| at [hrow[y]][w], unranked w only
   int64_t rows_stride;
@@ -143,6 +144,8 @@ hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const 
                               int64_t *cnt, hipStream_t s);
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
                              const int64_t *off, int32_t *list, hipStream_t s);
+// per-vertex (row start, degree, rank or -1, 0) records (crank may be null)
+hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, int64_t n, int4 *vinfo, hipStream_t s);
 // co-degree rows of the vertices `hubs` over the unranked vertices (rows
 // zeroed by the caller; stride even, in uint16)
 hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,
@@ -165,9 +168,12 @@ hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, 
 // work item -> edge map (item_edge holds the total number of items)
 hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, const int64_t *tbase, int64_t nedges,
                             int32_t *item_edge, void *gacc, hipStream_t s);
+// T_e lists, and per work item the T_e membership of its positions of
+// Gamma(a) (kGlobalChunkMax / 64 words per item)
 hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                   const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
-                                  int32_t *tlist, void *gacc, KernelCfg cfg, hipStream_t s);
+                                  int32_t *tlist, unsigned long long *tmask, void *gacc, KernelCfg cfg,
+                                  hipStream_t s);
 // counting sort of the split-class edges by key (see kSortKeys) into
 // (slot2, a2, b2); hist, off: kSortKeys int64 each; tmp: scan scratch
 hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t *slot2, int32_t *a2,
@@ -178,8 +184,8 @@ hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges,
                                const int32_t *tlist, unsigned long long *tbw, int16_t *tbi, void *gacc, hipStream_t s);
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
-                               const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi, void *gacc,
-                               KernelCfg cfg, hipStream_t s);
+                               const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi,
+                               const unsigned long long *tmask, void *gacc, KernelCfg cfg, hipStream_t s);
 size_t gedge_bytes();
 // micro statistics: t of every arc (position j of col holds |Gamma(x) n
 // Gamma(col[j])| for the row x owning j), vertex triangle counts, the

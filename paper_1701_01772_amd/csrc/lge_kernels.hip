@@ -632,6 +632,13 @@ __global__ __launch_bounds__(256) void k_rows_build(const int32_t *__restrict__ 
   }
 }
 
+// (row start, degree, rank or -1, 0) of every vertex
+__global__ __launch_bounds__(256) void k_vinfo(const int32_t *__restrict__ rp, const int32_t *__restrict__ crank,
+                                               int64_t n, int4 *__restrict__ vinfo) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    vinfo[v] = make_int4(rp[v], rp[v + 1] - rp[v], crank ? crank[v] : -1, 0);
+}
+
 __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ crank, int64_t n, int64_t hcw,
                                                     unsigned long long *bits) {
@@ -1022,6 +1029,8 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
 
 constexpr int kGlobalNT = 256;
 constexpr int kTHashCap = 512;
+constexpr int kMaskWords = kGlobalChunkMax / 64;  // T_e membership words per work item
+static_assert(kGlobalChunkMax <= kGlobalNT, "one pass over an item's positions");
 
 // Per split-class edge: counters (t by classify, nzw by the bit-set kernel,
 // k4 / cyc / done by the counting items) and the edge's descriptor, written
@@ -1087,7 +1096,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
     const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
-    int32_t *tlist, GEdge *gacc, int32_t chunk) {
+    int32_t *tlist, unsigned long long *__restrict__ tmask, GEdge *gacc, int32_t chunk) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
@@ -1116,6 +1125,8 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
         }
       }
       const uint64_t tm = __ballot(isT);
+      // membership of this wavefront's 64 positions, for the counting items
+      if (lane == 0) tmask[item * kMaskWords + ((base - p0) >> 6) + (threadIdx.x >> 6)] = tm;
       unsigned long long pos0 = 0;
       if (lane == 0 && tm) pos0 = atomicAdd(&gacc[e].t, (unsigned long long)__popcll(tm));
       pos0 = __shfl(pos0, 0);
@@ -1207,7 +1218,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
     const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
     const int32_t *__restrict__ tlist, const unsigned long long *__restrict__ tbw, const int16_t *__restrict__ tbi,
-    GEdge *gacc,
+    const unsigned long long *__restrict__ tmask, GEdge *gacc,
     unsigned long long *cursor, unsigned long long *xcd_cursor, unsigned long long *words_out, int32_t probe_ratio,
     int32_t chunk, uint32_t flags) {
   constexpr int NT = kGlobalNT;
@@ -1289,10 +1300,6 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;  // 0: no ranked vertices, no bit rows
     const int nzw = hcw ? (int)G.nzw : 0;
     if (tid < 4) sh_cnt[tid] = 0;
-    for (int i = tid; i < nzw; i += NT) {
-      tbits[i] = tbw[tb0 + i];
-      twidx[i] = tbi[tb0 + i];
-    }
     if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
     if (!ha)
@@ -1302,12 +1309,19 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     __syncthreads();
     {  // the LDS tables: Gamma(b) \ {a}, Gamma(a) \ {b} (non-hub sides), T_e (small)
       const int nB = hb ? 0 : db, nA = ha ? 0 : da, nT = tl ? t : 0;
-      const int nmax = nB > nA ? (nB > nT ? nB : nT) : (nA > nT ? nA : nT);
-      for (int i = tid; i < nmax; i += NT) {
+      int nmax = nB > nA ? (nB > nT ? nB : nT) : (nA > nT ? nA : nT);
+      nmax = nmax > nzw ? nmax : nzw;
+      for (int i = tid; i < nmax; i += NT) {  // all loads first, then the LDS writes
         const int32_t xb = i < nB ? col[bbeg + i] : -1;
         const int32_t xa = i < nA ? col[abeg + i] : -1;
         const int32_t ty = i < nT ? T[3 * i] : -1;
         const int32_t tr = i < nT ? T[3 * i + 2] : -1;
+        const unsigned long long bw = i < nzw ? tbw[tb0 + i] : 0ull;
+        const int16_t bi = i < nzw ? tbi[tb0 + i] : (int16_t)0;
+        if (i < nzw) {
+          tbits[i] = bw;
+          twidx[i] = bi;
+        }
         if (xb >= 0 && xb != a) lds_insert(hB, blg, (uint32_t)xb);
         if (xa >= 0 && xa != b) lds_insert(hA, alg, (uint32_t)xa);
         if (ty >= 0) lds_insert(hT, tlg, (uint32_t)ty | (tr >= 0 ? kRTag : 0u));
@@ -1347,10 +1361,12 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       int32_t wb = 0, we = 0, rw = -1;
       bool isT = false;
       if (valid) {
-        wb = rp[x];
-        we = rp[x + 1];
-        if (hcw) rw = S.crank[x];
-        isT = table_find(btab, blg, (uint32_t)x) >= 0;  // x in Gamma(a): in T_e iff in Gamma(b)
+        const int4 vi = S.vinfo[x];  // row start, degree, rank in one 16-byte read
+        wb = vi.x;
+        we = vi.x + vi.y;
+        rw = hcw ? vi.z : -1;
+        // x in Gamma(a) is in T_e iff in Gamma(b): the classify pass's bit
+        isT = ((tmask[item * kMaskWords + ((i - p0) >> 6)] >> ((i - p0) & 63)) & 1ull) != 0;
       }
       const int dw = we - wb;
       // |Gamma(x) n Gamma(y)|, y = a for T_e members, b otherwise: the table
@@ -1490,31 +1506,27 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     words += steps + (tid == 0 ? 2ull * (unsigned long long)L : 0ull);
     // bit-row phase: for every ranked member x of T_e in this chunk, the
     // ranked partners |Gamma(x) n T_e n ranked| = popcount of x's bit row AND
-    // the ranked-member set, over its non-zero words; one wavefront per
-    // member, lanes over the words, two members in flight per wavefront
+    // the ranked-member set, over its non-zero words.  The (member, word)
+    // pairs are spread over the whole workgroup, two loads in flight per
+    // thread; consecutive pairs are consecutive words of one row.
     {
       const int nb = sh_cnt[2];
-      const int wv = tid >> 6;
-      constexpr int NW = NT / kWave;
+      const int P = nb * nzw;
       unsigned long long bsum = 0;
-      int xi = wv;
-      for (; xi + NW < nb; xi += 2 * NW) {
-        const unsigned long long *r0 = S.hbits + (int64_t)bx_rank[xi] * S.hcw;
-        const unsigned long long *r1 = S.hbits + (int64_t)bx_rank[xi + NW] * S.hcw;
-        for (int k = lane; k < nzw; k += kWave) {
-          const int j = twidx[k];
-          const unsigned long long tb = tbits[k];
-          const unsigned long long v0 = r0[j], v1 = r1[j];
-          bsum += (unsigned long long)(__popcll(v0 & tb) + __popcll(v1 & tb));
-          words += 4;
-        }
-      }
-      for (; xi < nb; xi += NW) {
-        const unsigned long long *r0 = S.hbits + (int64_t)bx_rank[xi] * S.hcw;
-        for (int k = lane; k < nzw; k += kWave) {
-          bsum += (unsigned long long)__popcll(r0[twidx[k]] & tbits[k]);
+      for (int q0 = tid; q0 < P; q0 += 2 * NT) {
+        const int q1 = q0 + NT;
+        const int x0 = q0 / nzw, k0 = q0 - x0 * nzw;
+        const unsigned long long v0 = S.hbits[(int64_t)bx_rank[x0] * S.hcw + twidx[k0]];
+        unsigned long long v1 = 0;
+        int k1 = 0;
+        if (q1 < P) {
+          const int x1 = q1 / nzw;
+          k1 = q1 - x1 * nzw;
+          v1 = S.hbits[(int64_t)bx_rank[x1] * S.hcw + twidx[k1]];
           words += 2;
         }
+        bsum += (unsigned long long)(__popcll(v0 & tbits[k0]) + (q1 < P ? __popcll(v1 & tbits[k1]) : 0));
+        words += 2;
       }
       kt += bsum;
     }
@@ -2089,11 +2101,12 @@ hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, cons
 
 hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                   const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
-                                  int32_t *tlist, void *gacc, KernelCfg cfg, hipStream_t s) {
+                                  int32_t *tlist, unsigned long long *tmask, void *gacc, KernelCfg cfg,
+                                  hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
                      bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
-                     tlist, (GEdge *)gacc, cfg.global_chunk);
+                     tlist, tmask, (GEdge *)gacc, cfg.global_chunk);
   return hipGetLastError();
 }
 
@@ -2121,17 +2134,23 @@ hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges,
 
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
-                               const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi, void *gacc,
-                               KernelCfg cfg, hipStream_t s) {
+                               const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi,
+                               const unsigned long long *tmask, void *gacc, KernelCfg cfg, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
                      bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
-                     tlist, tbw, tbi, (GEdge *)gacc, bins.cursor + kClassGlobal, bins.xcd_cursor, bins.words + kClassGlobal,
+                     tlist, tbw, tbi, tmask, (GEdge *)gacc, bins.cursor + kClassGlobal, bins.xcd_cursor, bins.words + kClassGlobal,
                      cfg.probe_ratio, cfg.global_chunk, cfg.flags);
   return hipGetLastError();
 }
 
 size_t gedge_bytes() { return sizeof(GEdge); }
+
+hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, int64_t n, int4 *vinfo, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, n, vinfo);
+  return hipGetLastError();
+}
 
 hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,
                              int64_t nh, int64_t stride, uint16_t *rows, hipStream_t s) {

@@ -31,6 +31,7 @@ struct lge_graph {
   int64_t hc = 0;
   unsigned long long *hbits = nullptr;  // hc x hcw adjacency bit rows of the ranked vertices
   int64_t hcw = 0;
+  int4 *vinfo = nullptr;     // n: (row start, degree, rank or -1, 0)
   int32_t *hrow = nullptr;   // n: co-degree row index, -1 if none
   uint16_t *rows = nullptr;  // nrows x rows_stride co-degree rows over the unranked vertices
   int64_t nrows = 0, rows_stride = 0;
@@ -65,6 +66,7 @@ struct Workspace {
   int64_t *tcap = nullptr;            // cap_edges
   int64_t *tbase = nullptr;           // cap_edges
   int32_t *item_edge = nullptr;       // cap_items: split-class work item -> edge
+  unsigned long long *tmask = nullptr;  // cap_items x kGlobalChunkMax/64: T_e membership of item positions
   int64_t cap_items = 0;
   int32_t *tlist = nullptr;           // 3 * cap_tlist: (id, degree, rank) of T_e members
   unsigned long long *tbw = nullptr;  // cap_tlist: non-zero words of the ranked-member bit sets
