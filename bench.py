@@ -203,7 +203,10 @@ def bench_serve(args):
     sat_qps = len(cal) / t_plain
     log("plain saturation: %.1f requests/s" % sat_qps)
     out = {"plain": {"requests_per_s": sat_qps, "sampled_edges_per_s": plain_edges / t_plain}}
-    srv = lge.lge_server_create(ctx)
+    scfg = lge.lge_server_cfg_default()
+    if args.serve_step_us:
+        scfg.target_step_us = int(args.serve_step_us)
+    srv = lge.lge_server_create(ctx, scfg)
     gids = [lge.lge_server_add_graph(srv, h) for h in hs]
     try:
         # closed loop on the same requests as the plain measurement: all
@@ -422,6 +425,7 @@ def main():
     ap.add_argument("--sweep", default=None,
                     help="';'-separated option settings, e.g. 'flags=0;flags=1,global_chunk=128'")
     ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-step-us", type=int, default=0, help="server target step time (0: library default)")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no batched / served legs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale memory counters")

@@ -384,27 +384,31 @@ LGE_API int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *o
 
 /*
  * Serving.  A server owns `ctx` (no other call may use that ctx while the
- * server exists) and runs one scheduler thread.  Graphs are added once and
- * stay resident.  Requests (graph, p, seed) queue FIFO; up to max_inflight of
- * them run at once.  Every step the scheduler gives each running request the
- * next chunk of its canonical edge-id range: chunks share the step's work
- * budget (measured work rate x target_step_us) equally, and together fit the
- * step's device work lists into hbm_budget_bytes (the admission bound by HBM
- * footprint); it runs all chunks in one launch sequence and finalises the
- * requests whose range is done.  Requests arriving meanwhile join at the next
- * step (continuous batching).  A request's result equals lge_estimate on the
- * same (graph, p, seed): exact sums do not depend on chunking or neighbours.
- * lge_submit / lge_wait / lge_cancel / lge_server_get_stats are thread-safe; one
- * thread may wait on a given ticket.
+ * server exists) and runs `workers` step threads: the first steps on ctx,
+ * the others on contexts the server opens on the same device (own stream and
+ * workspace), so one step's host round trips and tail overlap another step's
+ * kernels.  Graphs are added once and stay resident.  Requests (graph, p,
+ * seed) queue FIFO; up to max_inflight of them run at once.  Every step a
+ * worker gives running requests the next chunks of their canonical edge-id
+ * ranges: chunks share the step's work budget (measured work rate x
+ * target_step_us) equally, and together fit the step's device work lists into
+ * hbm_budget_bytes (the admission bound by HBM footprint); it runs all chunks
+ * in one launch sequence and finalises the requests whose range is done and
+ * whose chunks have all returned.  Requests arriving meanwhile join at the
+ * next step (continuous batching).  A request's result equals lge_estimate on
+ * the same (graph, p, seed): exact sums do not depend on chunking, order or
+ * neighbours.  lge_submit / lge_wait / lge_cancel / lge_server_get_stats are
+ * thread-safe; one thread may wait on a given ticket.
  */
 typedef struct {
   int32_t max_inflight;     /* requests running at once (default 64) */
   int32_t queue_capacity;   /* queued + running requests before LGE_EBUSY (default 4096) */
   int64_t hbm_budget_bytes; /* device work-list budget of one step (default 2 GiB) */
   int64_t min_chunk_edges;  /* smallest edge-id chunk per request and step (default 4096) */
-  int64_t target_step_us;   /* aimed duration of one step (default 20000); chunks are sized by each
+  int64_t target_step_us;   /* aimed duration of one step (default 100000); chunks are sized by each
                                graph's per-edge work estimate and the measured work rate */
-  int32_t reserved[2];
+  int32_t workers;          /* step threads, 1..4 (default 2; 0 = default) */
+  int32_t reserved;
 } lge_server_cfg;
 
 typedef struct {

@@ -1,16 +1,19 @@
 // Serving loop: resident graphs, a request queue, footprint-bounded
 // continuous batching.
 //
-// One scheduler thread owns the ctx.  Every step it (1) admits queued
-// requests into free running slots, (2) hands every running request the next
-// chunk of its canonical edge-id range, the chunks together fitting the
-// step's HBM work-list budget, (3) runs all chunks in one launch sequence,
-// (4) adds each chunk's exact 128-bit accumulators into its request and
-// finalises requests whose range is exhausted.  Requests that arrive during
-// a step join at the next step, so their work overlaps on the device with
-// the requests already running.  Because the sampler is keyed by edge id
-// and the sums are exact integers, a request's result is independent of how
-// its range was chunked and of what ran beside it.
+// A server has `workers` step threads, each with its own context (stream
+// and workspace; the first is the caller's).  Every step a worker (1) admits
+// queued requests into free running slots, (2) hands running requests the
+// next chunks of their canonical edge-id ranges, the chunks together fitting
+// the step's HBM work-list budget and work target, (3) runs all chunks in one
+// launch sequence, (4) adds each chunk's exact 128-bit accumulators into its
+// request and finalises requests whose range is exhausted and whose chunks
+// have all returned.  Requests that arrive during a step join at the next
+// step, and with two workers one step's set-up, host round trips and tail
+// overlap the other step's kernels on the device.  Because the sampler is
+// keyed by edge id and the sums are exact integers, a request's result is
+// independent of how its range was chunked, of the order chunks return in and
+// of what ran beside it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -37,17 +40,20 @@ namespace {
 // lists (3 x 12 B), global-class items, prefixes, T capacities and bases
 // (4 x 8 B) and per-edge partial sums (32 B), rounded up
 constexpr int64_t kStepBytesPerId = 128;
+constexpr int32_t kMaxWorkers = 4;
 
 struct Request {
   uint64_t ticket = 0;
   int32_t gid = 0;
   double p = 1.0;
   uint64_t seed = 0;
-  int64_t cursor = 0;  // next canonical edge id
+  int64_t cursor = 0;  // next canonical edge id to hand out
   int64_t m = 0;
+  int32_t inflight = 0;  // chunks running on some worker
   bool canceled = false;
   bool done = false;
   int status = LGE_OK;
+  int error = LGE_OK;  // first failed chunk
   unsigned long long acc[kAccSlots * 2] = {};
   lge_result result{};
 };
@@ -64,22 +70,28 @@ void add_acc(unsigned long long *dst, const unsigned long long *src) {
 }  // namespace
 
 struct lge_server {
+  struct Worker {
+    lge_ctx *ctx = nullptr;
+    bool owned = false;  // opened by the server
+    std::thread th;
+  };
   lge_ctx *ctx = nullptr;
   lge_server_cfg cfg{};
   std::vector<const lge_graph *> graphs;
   std::mutex mu;
-  std::condition_variable cv_work;  // scheduler waits for work
+  std::condition_variable cv_work;  // workers wait for assignable work
   std::condition_variable cv_done;  // waiters wait for results
   std::deque<Request *> queue;
   std::vector<Request *> running;
   std::unordered_map<uint64_t, Request *> all;
   uint64_t next_ticket = 1;
   size_t rotate = 0;
-  double rate = 5e8;  // work units per second, updated after every step
+  double rate = 5e8;  // work units per second and worker, updated after every step
   bool stop = false;
   int waiters = 0;
   lge_server_stats stats{};
-  std::thread th;
+  Worker workers[kMaxWorkers];
+  int nworkers = 0;
 
   void finish(Request *r, int status) {
     r->status = status;
@@ -88,44 +100,56 @@ struct lge_server {
     else if (status == LGE_ECANCELED) ++stats.canceled;
   }
 
-  double step_work = 0.0;
+  // resolve a running request once it has nothing left to hand out and no
+  // chunk in flight; true if it finished
+  bool try_complete(Request *r) {
+    if (r->done || r->inflight > 0) return r->done;
+    if (r->error != LGE_OK) {
+      finish(r, r->error);
+    } else if (r->canceled) {
+      finish(r, LGE_ECANCELED);
+    } else if (r->cursor >= r->m) {
+      const lge_graph *g = graphs[(size_t)r->gid];
+      lge_finalize(g->n, g->m, r->p, r->seed, r->acc, &r->result);
+      finish(r, LGE_OK);
+    }
+    return r->done;
+  }
 
-  void loop() {
+  bool assignable() const {
+    if (!queue.empty() && (int32_t)running.size() < cfg.max_inflight) return true;
+    for (const Request *r : running)
+      if (!r->canceled && r->error == LGE_OK && r->cursor < r->m) return true;
+    return false;
+  }
+
+  void loop(lge_ctx *wctx) {
     std::vector<Job> jobs;
     std::vector<Request *> in_step;
     for (;;) {
+      double step_work = 0.0;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
+        cv_work.wait(lk, [&] { return stop || assignable(); });
         if (stop) return;
         // admission: running slots free up as requests finish
         while (!queue.empty() && (int32_t)running.size() < cfg.max_inflight) {
           running.push_back(queue.front());
           queue.pop_front();
         }
-        // drop cancelled requests
-        bool any_done = false;
-        for (size_t i = 0; i < running.size();) {
-          if (running[i]->canceled) {
-            finish(running[i], LGE_ECANCELED);
-            running.erase(running.begin() + (long)i);
-            any_done = true;
-          } else {
-            ++i;
-          }
-        }
-        if (any_done) cv_done.notify_all();
-        if (running.empty()) continue;
         // chunks for this step, starting at a rotating request
         jobs.clear();
         in_step.clear();
-        step_work = 0.0;
         int64_t budget = std::max<int64_t>(cfg.hbm_budget_bytes / kStepBytesPerId, 1);  // edge ids
         double wbudget = std::max(rate * (double)cfg.target_step_us * 1e-6, 1.0);       // work units
-        const size_t nr = running.size();
+        std::vector<Request *> open;
+        for (Request *r : running)
+          if (!r->canceled && r->error == LGE_OK && r->cursor < r->m) open.push_back(r);
+        const size_t nr = open.size();
+        if (nr == 0) continue;
         rotate %= nr;
         for (size_t k = 0; k < nr && budget > 0; ++k) {
-          Request *r = running[(rotate + k) % nr];
+          Request *r = open[(rotate + k) % nr];
           const lge_graph *g = graphs[(size_t)r->gid];
           const int64_t left = r->m - r->cursor;
           // expected work of one edge id of this request
@@ -136,15 +160,18 @@ struct lge_server {
           const int64_t len = std::min(left, std::min(want, budget));
           jobs.push_back(Job{g, r->p, r->seed, r->cursor, r->cursor + len, -1, -1, 0});
           in_step.push_back(r);
+          r->cursor += len;
+          r->inflight += 1;
           budget -= std::max<int64_t>(len, 1);
           wbudget -= std::min(wbudget, (double)len * unit);
           step_work += (double)len * unit;
         }
         rotate += 1;
         ++stats.steps;
+        if (assignable()) cv_work.notify_one();  // more work for an idle worker
       }
       const auto t0 = std::chrono::steady_clock::now();
-      const int rc = lge_run_jobs(ctx, jobs.data(), (int)jobs.size(), nullptr);
+      const int rc = lge_run_jobs(wctx, jobs.data(), (int)jobs.size(), nullptr);
       const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       {
         std::lock_guard<std::mutex> lk(mu);
@@ -153,23 +180,19 @@ struct lge_server {
         if (rc == LGE_OK && dt > 2e-3 && step_work > 0) rate = 0.7 * rate + 0.3 * (step_work / dt);
         for (size_t j = 0; j < in_step.size(); ++j) {
           Request *r = in_step[j];
+          r->inflight -= 1;
           if (rc != LGE_OK) {
-            finish(r, rc);
+            if (r->error == LGE_OK) r->error = rc;
           } else {
-            add_acc(r->acc, ctx->ws.h_acc + (int64_t)j * kAccSlots * 2);
-            r->cursor = jobs[j].e1;
-            if (r->canceled) {
-              finish(r, LGE_ECANCELED);
-            } else if (r->cursor >= r->m) {
-              const lge_graph *g = graphs[(size_t)r->gid];
-              lge_finalize(g->n, g->m, r->p, r->seed, r->acc, &r->result);
-              finish(r, LGE_OK);
-            }
+            add_acc(r->acc, wctx->ws.h_acc + (int64_t)j * kAccSlots * 2);
           }
         }
+        // cancelled requests and finished ranges resolve once nothing is in flight
+        for (Request *r : running) try_complete(r);
         running.erase(std::remove_if(running.begin(), running.end(), [](Request *r) { return r->done; }),
                       running.end());
         cv_done.notify_all();
+        cv_work.notify_all();
       }
     }
   }
@@ -182,7 +205,8 @@ extern "C" int lge_server_cfg_default(lge_server_cfg *c) {
   c->queue_capacity = 4096;
   c->hbm_budget_bytes = (int64_t)2 << 30;
   c->min_chunk_edges = 4096;
-  c->target_step_us = 20000;
+  c->target_step_us = 100000;
+  c->workers = 2;
   return LGE_OK;
 }
 
@@ -193,25 +217,52 @@ extern "C" int lge_server_create(lge_ctx *ctx, const lge_server_cfg *cfg, lge_se
   lge_server_cfg_default(&c);
   if (cfg) {
     if (cfg->max_inflight < 0 || cfg->queue_capacity < 0 || cfg->hbm_budget_bytes < 0 || cfg->min_chunk_edges < 0 ||
-        cfg->target_step_us < 0)
+        cfg->target_step_us < 0 || cfg->workers < 0 || cfg->workers > kMaxWorkers)
       return LGE_EINVAL;
     if (cfg->target_step_us) c.target_step_us = cfg->target_step_us;
     if (cfg->max_inflight) c.max_inflight = cfg->max_inflight;
     if (cfg->queue_capacity) c.queue_capacity = cfg->queue_capacity;
     if (cfg->hbm_budget_bytes) c.hbm_budget_bytes = cfg->hbm_budget_bytes;
     if (cfg->min_chunk_edges) c.min_chunk_edges = cfg->min_chunk_edges;
+    if (cfg->workers) c.workers = cfg->workers;
   }
   if (c.hbm_budget_bytes < kStepBytesPerId) return LGE_EINVAL;
   lge_server *s = new (std::nothrow) lge_server();
   if (!s) return LGE_ENOMEM;
   s->ctx = ctx;
   s->cfg = c;
+  // worker 0 steps on the caller's context, the others on contexts of their
+  // own (same device, own stream and workspace); a context that cannot be
+  // opened leaves fewer workers
+  s->workers[0].ctx = ctx;
+  s->nworkers = 1;
+  for (int k = 1; k < c.workers; ++k) {
+    lge_ctx *wc = nullptr;
+    if (lge_open(ctx->device, &wc) != LGE_OK) break;
+    wc->opts = ctx->opts;
+    s->workers[k].ctx = wc;
+    s->workers[k].owned = true;
+    s->nworkers = k + 1;
+  }
+  s->cfg.workers = s->nworkers;
   try {
-    s->th = std::thread([s] {
-      (void)hipSetDevice(s->ctx->device);
-      s->loop();
-    });
+    for (int k = 0; k < s->nworkers; ++k) {
+      lge_ctx *wc = s->workers[k].ctx;
+      s->workers[k].th = std::thread([s, wc] {
+        (void)hipSetDevice(wc->device);
+        s->loop(wc);
+      });
+    }
   } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+      s->cv_work.notify_all();
+    }
+    for (int k = 0; k < s->nworkers; ++k) {
+      if (s->workers[k].th.joinable()) s->workers[k].th.join();
+      if (s->workers[k].owned) lge_close(s->workers[k].ctx);
+    }
     delete s;
     return LGE_ENOMEM;
   }
@@ -256,7 +307,7 @@ extern "C" int lge_submit(lge_server *srv, int32_t gid, double p, uint64_t seed,
   srv->all[r->ticket] = r;
   ++srv->stats.submitted;
   *ticket = r->ticket;
-  srv->cv_work.notify_one();
+  srv->cv_work.notify_all();
   if (r->done) srv->cv_done.notify_all();
   return LGE_OK;
 }
@@ -296,9 +347,11 @@ extern "C" int lge_cancel(lge_server *srv, uint64_t ticket) {
   if (q != srv->queue.end()) {  // never admitted: resolve now
     srv->queue.erase(q);
     srv->finish(r, LGE_ECANCELED);
-    srv->cv_done.notify_all();
+  } else if (srv->try_complete(r)) {  // running, no chunk in flight
+    srv->running.erase(std::remove(srv->running.begin(), srv->running.end(), r), srv->running.end());
   }
-  srv->cv_work.notify_one();
+  if (r->done) srv->cv_done.notify_all();
+  srv->cv_work.notify_all();
   return LGE_OK;
 }
 
@@ -318,7 +371,10 @@ extern "C" int lge_server_destroy(lge_server *srv) {
     srv->stop = true;
     srv->cv_work.notify_all();
   }
-  if (srv->th.joinable()) srv->th.join();  // the step in flight completes first
+  for (int k = 0; k < srv->nworkers; ++k)  // steps in flight complete first
+    if (srv->workers[k].th.joinable()) srv->workers[k].th.join();
+  for (int k = 0; k < srv->nworkers; ++k)
+    if (srv->workers[k].owned) lge_close(srv->workers[k].ctx);
   {
     std::unique_lock<std::mutex> lk(srv->mu);
     for (auto &kv : srv->all)

@@ -92,7 +92,7 @@ class Batch(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("min_chunk_edges", ctypes.c_int64),
-                ("target_step_us", ctypes.c_int64), ("reserved", ctypes.c_int32 * 2)]
+                ("target_step_us", ctypes.c_int64), ("workers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
