@@ -32,8 +32,13 @@ constexpr int64_t kCodegMaxVertices = kMaxRanked;
 // (largest degrees first, while the build work, the sum of their 2-hop
 // volumes, and the memory stay within these budgets).
 constexpr int32_t kRowDeg = 1024;
-constexpr double kRowBudgetOps = 4e9;
-constexpr double kRowBudgetBytes = 4e9;
+// co-degree rows: build work (sum of 2-hop volumes) and HBM per graph; the
+// byte budget is also capped at a quarter of the free HBM at creation.
+// LGE_FLAG_COMPACT keeps the small budget for callers holding many graphs.
+constexpr double kRowBudgetOps = 6e10;
+constexpr double kRowBudgetBytes = 32e9;
+constexpr double kRowBudgetOpsCompact = 4e9;
+constexpr double kRowBudgetBytesCompact = 4e9;
 constexpr int32_t kCodegMinDeg = 32;
 
 #define LGE_HIP(expr)                        \
@@ -378,7 +383,7 @@ static bool sizes_in_range(int64_t n, int64_t m, int64_t dmax) {
 }
 
 static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr);
-static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr);
+static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags);
 
 static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const int32_t *host_row_ptr) {
   hipStream_t s = ctx->stream;
@@ -474,7 +479,7 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   if ((rc = build_codeg(ctx, g, host_row_ptr)) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
   LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, n, g->vinfo, s));
-  return build_rows(ctx, g, host_row_ptr);
+  return build_rows(ctx, g, host_row_ptr, flags);
 }
 
 // Co-degree table of the vertices of degree > tau, tau the smallest threshold
@@ -553,7 +558,7 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) 
 // Co-degree rows: for the chosen vertices y, |Gamma(y) n Gamma(w)| for every
 // unranked w (ranked pairs use the co-degree table).  Counts of unranked w
 // are at most the ranking threshold, so 16 bits hold them.
-static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) {
+static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags) {
   g->nrows = 0;
   const int64_t n = g->n;
   if (n <= 0 || g->hc <= 0 || g->codeg_tau >= 65535) return LGE_OK;
@@ -571,11 +576,16 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) {
   LGE_HIP(hipMemcpyAsync(vol2.data(), g->vol2, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   LGE_HIP(hipStreamSynchronize(s));
   const int64_t stride = (n + 1) & ~(int64_t)1;
+  const bool compact = (flags & LGE_FLAG_COMPACT) != 0;
+  const double budget_ops = compact ? kRowBudgetOpsCompact : kRowBudgetOps;
+  double budget_bytes = compact ? kRowBudgetBytesCompact : kRowBudgetBytes;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget_bytes = std::min(budget_bytes, 0.25 * (double)free_b);
   std::vector<int32_t> hubs;
   double ops = 0.0;
   for (const auto &c : cand) {
     const double bytes = (double)(hubs.size() + 1) * (double)stride * 2.0;
-    if (ops + (double)vol2[c.second] > kRowBudgetOps || bytes > kRowBudgetBytes) break;
+    if (ops + (double)vol2[c.second] > budget_ops || bytes > budget_bytes) break;
     ops += (double)vol2[c.second];
     hubs.push_back(c.second);
   }

@@ -37,6 +37,7 @@ LGE_WEIGHT_DEGREE = 1
 LGE_WEIGHT_KCORE = 2
 LGE_WEIGHT_CLASSES = 16
 LGE_FLAG_TRUSTED = 1
+LGE_FLAG_COMPACT = 2
 LGE_OPT_SORT_HUB = 1
 LGE_OPT_XCD_LOCAL = 2
 

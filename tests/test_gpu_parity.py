@@ -307,3 +307,33 @@ def test_adaptive_equals_oracle_and_plain(ctx, beta, phi0):
             assert got[k] == plain[k], k
     finally:
         lge.lge_graph_destroy(h)
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    _say("generating R-MAT scale 22")
+    return inputs.rmat_22()
+
+
+@pytest.mark.parametrize("p", [0.01, 0.1])
+def test_full_size_rmat(ctx, rmat22, p):
+    g = rmat22
+    rng = np.random.default_rng(6 if p == 0.1 else 7)
+    starts = rng.integers(0, g.m - 4000, 3)
+    _full_size_checks(ctx, g, p, 2025, [(int(s), int(s) + 4000) for s in starts])
+
+
+def test_compact_graph_same_results(ctx, rmat22):
+    # R-MAT scale 22 has ~12k vertices of degree > 1024: the compact budget
+    # builds co-degree rows for far fewer of them than the default
+    g = rmat22
+    outs = []
+    for flags in (0, lge.LGE_FLAG_COMPACT):
+        _say("R-MAT scale 22 flags=%d p=0.005" % flags)
+        h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col, flags)
+        try:
+            outs.append(lge.lge_estimate(ctx, h, 0.005, 99))
+        finally:
+            lge.lge_graph_destroy(h)
+    for k in ("sampled", "csum", "zsum", "qsum", "estimate", "variance"):
+        assert outs[0][k] == outs[1][k], k
