@@ -483,7 +483,11 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
 }
 
 // Co-degree table of the vertices of degree > tau, tau the smallest threshold
-// >= kCodegMinDeg that leaves at most kCodegMaxVertices of them.
+// >= kCodegMinDeg that leaves at most kCodegMaxVertices of them.  Ranks go
+// by increasing degree (ties by id): the split kernel counts each edge
+// between two ranked members of T_e once, from its lower-rank end, over the
+// bit-row words above that rank, and high-degree members, the common ones,
+// then have few words above them.
 static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) {
   const int64_t n = g->n;
   g->hc = 0;
@@ -492,35 +496,36 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) 
   for (int64_t u = 0; u < n; ++u) deg[u] = host_row_ptr[u + 1] - host_row_ptr[u];
   int32_t tau = kCodegMinDeg;
   if (n > kCodegMaxVertices) {
-    std::nth_element(deg.begin(), deg.begin() + kCodegMaxVertices, deg.end(), std::greater<int32_t>());
-    tau = std::max(tau, deg[kCodegMaxVertices]);
+    std::vector<int32_t> tmpd(deg);
+    std::nth_element(tmpd.begin(), tmpd.begin() + kCodegMaxVertices, tmpd.end(), std::greater<int32_t>());
+    tau = std::max(tau, tmpd[kCodegMaxVertices]);
   }
-  int64_t hc = 0;
-  for (int64_t u = 0; u < n; ++u) hc += (host_row_ptr[u + 1] - host_row_ptr[u]) > tau;
+  std::vector<int32_t> ranked;
+  for (int64_t u = 0; u < n; ++u)
+    if (deg[u] > tau) ranked.push_back((int32_t)u);
+  const int64_t hc = (int64_t)ranked.size();
   g->codeg_tau = tau;
   if (hc < 2) return LGE_OK;
+  std::stable_sort(ranked.begin(), ranked.end(), [&](int32_t x, int32_t y) { return deg[x] < deg[y]; });
+  std::vector<int32_t> hrank((size_t)n, -1);
+  for (int64_t r = 0; r < hc; ++r) hrank[ranked[r]] = (int32_t)r;
   hipStream_t s = ctx->stream;
-  int64_t *flag = nullptr, *pref = nullptr, *cnt = nullptr, *off = nullptr, *tmp = nullptr;
+  int64_t *cnt = nullptr, *off = nullptr, *tmp = nullptr;
   int32_t *list = nullptr;
   auto cleanup = [&]() {
-    dev_free(flag);
-    dev_free(pref);
     dev_free(cnt);
     dev_free(off);
     dev_free(tmp);
     dev_free(list);
   };
   int rc;
-  if ((rc = dev_alloc(&flag, n)) != LGE_OK || (rc = dev_alloc(&pref, n)) != LGE_OK ||
-      (rc = dev_alloc(&cnt, n)) != LGE_OK || (rc = dev_alloc(&off, n)) != LGE_OK ||
+  if ((rc = dev_alloc(&cnt, n)) != LGE_OK || (rc = dev_alloc(&off, n)) != LGE_OK ||
       (rc = dev_alloc(&tmp, scan_tmp_size(n))) != LGE_OK || (rc = dev_alloc(&g->crank, n)) != LGE_OK ||
       (rc = dev_alloc(&g->codeg, hc * hc)) != LGE_OK) {
     cleanup();
     return rc;
   }
-  hipError_t e = launch_codeg_flags(g->row_ptr, n, tau, flag, s);
-  if (e == hipSuccess) e = launch_scan_i64(flag, pref, n, tmp, s);
-  if (e == hipSuccess) e = launch_codeg_rank(flag, pref, n, g->crank, s);
+  hipError_t e = hipMemcpyAsync(g->crank, hrank.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_codeg_count(g->row_ptr, g->col, g->crank, n, cnt, s);
   if (e == hipSuccess) e = launch_scan_i64(cnt, off, n, tmp, s);
   int64_t last[2] = {0, 0};

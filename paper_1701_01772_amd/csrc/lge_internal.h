@@ -138,8 +138,6 @@ hipError_t launch_graph_work(const int32_t *row_ptr, const uint64_t *edges, cons
 hipError_t launch_hub_sizes(const int32_t *row_ptr, int64_t n, int64_t *size, hipStream_t s);
 hipError_t launch_hub_build(const int32_t *row_ptr, const int32_t *col, int64_t n, const int64_t *hoff,
                             uint32_t *htab, hipStream_t s);
-hipError_t launch_codeg_flags(const int32_t *row_ptr, int64_t n, int32_t tau, int64_t *flag, hipStream_t s);
-hipError_t launch_codeg_rank(const int64_t *flag, const int64_t *pref, int64_t n, int32_t *crank, hipStream_t s);
 hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
                               int64_t *cnt, hipStream_t s);
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,

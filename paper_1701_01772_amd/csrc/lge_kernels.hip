@@ -516,20 +516,6 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
 // upper triangle, then mirrored so that each vertex's co-degrees form a row.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_codeg_flags(const int32_t *__restrict__ row_ptr, int64_t n, int32_t tau,
-                                                     int64_t *flag) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-       u += (int64_t)gridDim.x * blockDim.x)
-    flag[u] = (row_ptr[u + 1] - row_ptr[u]) > tau ? 1 : 0;
-}
-
-__global__ __launch_bounds__(256) void k_codeg_rank(const int64_t *__restrict__ flag,
-                                                    const int64_t *__restrict__ pref, int64_t n, int32_t *crank) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
-       u += (int64_t)gridDim.x * blockDim.x)
-    crank[u] = flag[u] ? (int32_t)pref[u] : -1;
-}
-
 // number of ranked neighbours of every vertex
 __global__ __launch_bounds__(256) void k_codeg_count(const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col,
@@ -1141,8 +1127,9 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
 }
 
 // The ranked members of every split-class edge's T_e as a bit set over the
-// ranks, stored compactly (non-zero words and their indices) at the edge's
-// T_e offset; one workgroup per edge, once per launch.
+// ranks, stored compactly (non-zero words and their indices, in increasing
+// word order) at the edge's T_e offset; one workgroup per edge, once per
+// launch.
 __global__ __launch_bounds__(kGlobalNT) void k_global_tbits(const SlotDesc *__restrict__ slots,
                                                             const int32_t *__restrict__ bslot, int64_t nedges,
                                                             const int64_t *__restrict__ tbase,
@@ -1150,14 +1137,16 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_tbits(const SlotDesc *__re
                                                             unsigned long long *__restrict__ tbw,
                                                             int16_t *__restrict__ tbi) {
   __shared__ unsigned long long bits[kBitsWords];
-  __shared__ int cnt;
+  __shared__ int wcnt[kGlobalNT / kWave];
+  const int lane = threadIdx.x & 63;
+  const int wv_id = threadIdx.x >> 6;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (int64_t e = blockIdx.x; e < nedges; e += gridDim.x) {
     const SlotDesc &S = slots[bslot[e]];
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;
     const int t = (int)gacc[e].t;
     if (hcw == 0 || t == 0) continue;  // uniform per block; nzw stays 0
     for (int i = threadIdx.x; i < hcw; i += kGlobalNT) bits[i] = 0ull;
-    if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     const int32_t *T = tlist + 3 * tbase[e];
     for (int i = threadIdx.x; i < t; i += kGlobalNT) {
@@ -1165,17 +1154,27 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_tbits(const SlotDesc *__re
       if (r >= 0) atomicOr(&bits[r >> 6], 1ull << (r & 63));
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < hcw; i += kGlobalNT) {
-      const unsigned long long wv = bits[i];
+    int cnt = 0;  // non-zero words so far (uniform)
+    for (int i0 = 0; i0 < hcw; i0 += kGlobalNT) {
+      const int i = i0 + (int)threadIdx.x;
+      const unsigned long long wv = i < hcw ? bits[i] : 0ull;
+      const uint64_t m = __ballot(wv != 0ull);
+      if (lane == 0) wcnt[wv_id] = __popcll(m);
+      __syncthreads();
+      int off = cnt, tot = 0;
+      for (int q = 0; q < kGlobalNT / kWave; ++q) {
+        if (q < wv_id) off += wcnt[q];
+        tot += wcnt[q];
+      }
       if (wv) {
-        const int k = atomicAdd(&cnt, 1);
+        const int k = off + __popcll(m & lt_mask);
         tbw[tbase[e] + k] = wv;
         tbi[tbase[e] + k] = (int16_t)i;
       }
+      cnt += tot;
+      __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x == 0) gacc[e].nzw = (unsigned long long)cnt;
-    __syncthreads();
   }
 }
 
@@ -1504,31 +1503,58 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       }
     }
     words += steps + (tid == 0 ? 2ull * (unsigned long long)L : 0ull);
-    // bit-row phase: for every ranked member x of T_e in this chunk, the
-    // ranked partners |Gamma(x) n T_e n ranked| = popcount of x's bit row AND
-    // the ranked-member set, over its non-zero words.  The (member, word)
-    // pairs are spread over the whole workgroup, two loads in flight per
-    // thread; consecutive pairs are consecutive words of one row.
+    // bit-row phase: the edges between ranked members of T_e, each counted
+    // once, from its lower-rank end x in this chunk, with weight 2: the
+    // popcount of x's bit row AND the ranked-member set over the non-zero
+    // words from x's own word on (bits above x's rank only).  Ranks grow
+    // with degree, so the common high-degree members read few words.  The
+    // (member, word) pairs are spread over the whole workgroup.
+    __syncthreads();  // wl_pref and wl_beg are reused below
     {
       const int nb = sh_cnt[2];
-      const int P = nb * nzw;
-      unsigned long long bsum = 0;
-      for (int q0 = tid; q0 < P; q0 += 2 * NT) {
-        const int q1 = q0 + NT;
-        const int x0 = q0 / nzw, k0 = q0 - x0 * nzw;
-        const unsigned long long v0 = S.hbits[(int64_t)bx_rank[x0] * S.hcw + twidx[k0]];
-        unsigned long long v1 = 0;
-        int k1 = 0;
-        if (q1 < P) {
-          const int x1 = q1 / nzw;
-          k1 = q1 - x1 * nzw;
-          v1 = S.hbits[(int64_t)bx_rank[x1] * S.hcw + twidx[k1]];
-          words += 2;
+      int32_t *const bk0 = wl_beg;   // first word index of member j
+      int32_t *const bpref = wl_pref;  // pairs before member j
+      for (int j = tid; j < nb; j += NT) {
+        const int wx = bx_rank[j] >> 6;
+        int lo = 0, hi = nzw;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (twidx[mid] < wx)
+            lo = mid + 1;
+          else
+            hi = mid;
         }
-        bsum += (unsigned long long)(__popcll(v0 & tbits[k0]) + (q1 < P ? __popcll(v1 & tbits[k1]) : 0));
+        bk0[j] = lo;
+        bpref[j] = nzw - lo;
+      }
+      __syncthreads();
+      const int32_t P = block_scan_lds<NT>(bpref, nb, carry_sh);
+      if (tid == 0) bpref[nb] = P;
+      __syncthreads();
+      unsigned long long bsum = 0;
+      int jc = 0;
+      for (int q = tid; q < P; q += NT) {
+        int lo = jc;
+        if (bpref[lo + 1] <= q) {
+          int hi = nb - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (bpref[mid] <= q)
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+        }
+        jc = lo;
+        const int rx = bx_rank[jc];
+        const int k = bk0[jc] + (q - bpref[jc]);
+        const int wk = twidx[k];
+        unsigned long long v = S.hbits[(int64_t)rx * S.hcw + wk] & tbits[k];
+        if (wk == (rx >> 6)) v &= (rx & 63) == 63 ? 0ull : (~0ull << ((rx & 63) + 1));
+        bsum += (unsigned long long)__popcll(v);
         words += 2;
       }
-      kt += bsum;
+      kt += 2ull * bsum;
     }
     block_sum2_u64<NT>(kt, cs, red);
     if (icnt == 1) {  // the edge's only item: no partial sums to meet
@@ -2001,18 +2027,6 @@ hipError_t launch_hub_build(const int32_t *row_ptr, const int32_t *col, int64_t 
                             uint32_t *htab, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_hub_build, dim3(grid_for(n, 64, 8192)), dim3(256), 0, s, row_ptr, col, n, hoff, htab);
-  return hipGetLastError();
-}
-
-hipError_t launch_codeg_flags(const int32_t *row_ptr, int64_t n, int32_t tau, int64_t *flag, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_codeg_flags, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, row_ptr, n, tau, flag);
-  return hipGetLastError();
-}
-
-hipError_t launch_codeg_rank(const int64_t *flag, const int64_t *pref, int64_t n, int32_t *crank, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_codeg_rank, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, flag, pref, n, crank);
   return hipGetLastError();
 }
 
