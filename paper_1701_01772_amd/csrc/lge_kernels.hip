@@ -432,79 +432,125 @@ __global__ __launch_bounds__(256) void k_scan_add(int64_t *out, int64_t len,
 // Sampling and binning (a pass over the canonical edge ids of every range)
 // ---------------------------------------------------------------------------
 
+constexpr int kSamplePer = 4;  // edges per thread per round of the sampling kernel
+
 __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__ slots,
                                                     const RangeDesc *__restrict__ ranges, int32_t nranges,
                                                     int64_t total, Bins bins, KernelCfg cfg) {
+  constexpr int NT = 256, NW = NT / kWave;
+  __shared__ int wcnt[kNumClasses][NW];
+  __shared__ unsigned long long bbase[kNumClasses];
   const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
-    const int64_t i = base + threadIdx.x;
-    int cls = -1;
-    int32_t slot = 0, a = 0, b = 0;
-    unsigned long long alg = 0;
-    if (i < total) {
-      int lo = 0, hi = nranges - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ranges[mid].pref <= i)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      const RangeDesc R = ranges[lo];
-      slot = R.slot;
-      const SlotDesc &S = slots[slot];
-      const int64_t eid = R.e0 + (i - R.pref);
-      bool take;
-      if (S.design == kDesignBernoulli) {
-        take = edge_taken(S.seed, (uint64_t)eid, S.p_lo, S.p);
-      } else if (S.design == kDesignWeighted) {
-        const int l = S.level[eid];
-        take = edge_taken(S.seed, (uint64_t)eid, 0.0, S.plev[l]);
-        slot += l;
-      } else {
-        const uint64_t key = philox_bits(S.seed, (uint64_t)eid);
-        take = key < S.kkey || (key == S.kkey && eid <= S.keid);
-      }
-      if (take) {
-        const uint64_t e = S.edges[eid];
-        const int32_t u = (int32_t)(e >> 32), v = (int32_t)(uint32_t)e;
-        const int32_t du = S.row_ptr[u + 1] - S.row_ptr[u];
-        const int32_t dv = S.row_ptr[v + 1] - S.row_ptr[v];
-        const int64_t wu = S.vol2[u], wv = S.vol2[v];
-        // iterate the side whose neighbours have the smaller total degree
-        const bool ua = wu < wv || (wu == wv && (du < dv || (du == dv && u < v)));
-        a = ua ? u : v;
-        b = ua ? v : u;
-        const int32_t dmax = du > dv ? du : dv;
-        cls = dmax <= cfg.wave_max_deg ? kClassWave : (dmax <= kHubDeg ? kClassBlock : kClassGlobal);
-        // bytes the neighbour iteration of Alg. 2-4 reads for this edge:
-        // both row_ptr pairs, both rows, and for every w in Gamma(a) \ {b}
-        // its row_ptr pair and row
-        const int64_t da = ua ? du : dv, db = ua ? dv : du, wa = ua ? wu : wv;
-        alg = 16ull + 4ull * (unsigned long long)(du + dv) + 8ull * (unsigned long long)(da - 1) +
-              4ull * (unsigned long long)(wa - db);
+  unsigned long long algc[kNumClasses];
+#pragma unroll
+  for (int c = 0; c < kNumClasses; ++c) algc[c] = 0ull;
+  // one round: NT * kSamplePer consecutive edge positions per workgroup; the
+  // workgroup claims its positions in each class list with one atomic
+  const int64_t span = (int64_t)NT * kSamplePer;
+  for (int64_t base = (int64_t)blockIdx.x * span; base < total; base += (int64_t)gridDim.x * span) {
+    int cls[kSamplePer];
+    int32_t sl[kSamplePer], av[kSamplePer], bv[kSamplePer];
+#pragma unroll
+    for (int k = 0; k < kSamplePer; ++k) {
+      const int64_t i = base + (int64_t)k * NT + threadIdx.x;
+      cls[k] = -1;
+      sl[k] = 0;
+      av[k] = 0;
+      bv[k] = 0;
+      if (i < total) {
+        int lo = 0, hi = nranges - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (ranges[mid].pref <= i)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const RangeDesc R = ranges[lo];
+        int32_t slot = R.slot;
+        const SlotDesc &S = slots[slot];
+        const int64_t eid = R.e0 + (i - R.pref);
+        bool take;
+        if (S.design == kDesignBernoulli) {
+          take = edge_taken(S.seed, (uint64_t)eid, S.p_lo, S.p);
+        } else if (S.design == kDesignWeighted) {
+          const int l = S.level[eid];
+          take = edge_taken(S.seed, (uint64_t)eid, 0.0, S.plev[l]);
+          slot += l;
+        } else {
+          const uint64_t key = philox_bits(S.seed, (uint64_t)eid);
+          take = key < S.kkey || (key == S.kkey && eid <= S.keid);
+        }
+        if (take) {
+          const uint64_t e = S.edges[eid];
+          const int32_t u = (int32_t)(e >> 32), v = (int32_t)(uint32_t)e;
+          const int32_t du = S.row_ptr[u + 1] - S.row_ptr[u];
+          const int32_t dv = S.row_ptr[v + 1] - S.row_ptr[v];
+          const int64_t wu = S.vol2[u], wv = S.vol2[v];
+          // iterate the side whose neighbours have the smaller total degree
+          const bool ua = wu < wv || (wu == wv && (du < dv || (du == dv && u < v)));
+          av[k] = ua ? u : v;
+          bv[k] = ua ? v : u;
+          sl[k] = slot;
+          const int32_t dmax = du > dv ? du : dv;
+          const int c = dmax <= cfg.wave_max_deg ? kClassWave : (dmax <= kHubDeg ? kClassBlock : kClassGlobal);
+          cls[k] = c;
+          // bytes the neighbour iteration of Alg. 2-4 reads for this edge:
+          // both row_ptr pairs, both rows, and for every w in Gamma(a) \ {b}
+          // its row_ptr pair and row
+          const int64_t da = ua ? du : dv, db = ua ? dv : du, wa = ua ? wu : wv;
+          const unsigned long long alg = 16ull + 4ull * (unsigned long long)(du + dv) +
+                                         8ull * (unsigned long long)(da - 1) + 4ull * (unsigned long long)(wa - db);
+#pragma unroll
+          for (int q = 0; q < kNumClasses; ++q)
+            if (c == q) algc[q] += alg;
+        }
       }
     }
+    int wc[kNumClasses];
+#pragma unroll
     for (int c = 0; c < kNumClasses; ++c) {
-      const uint64_t msk = __ballot(cls == c);
-      if (msk == 0ull) continue;
-      const int leader = __ffsll((unsigned long long)msk) - 1;
-      const unsigned long long ab = wave_sum_u64(cls == c ? alg : 0ull);
-      unsigned long long pos0 = 0;
-      if (lane == leader) {
-        pos0 = atomicAdd(&bins.count[c], (unsigned long long)__popcll(msk));
-        atomicAdd(&bins.alg[c], ab);
-      }
-      pos0 = __shfl(pos0, leader);
-      if (cls == c) {
-        const int64_t pos = (int64_t)pos0 + __popcll(msk & lt_mask);
-        bins.slot[c][pos] = slot;
-        bins.a[c][pos] = a;
-        bins.b[c][pos] = b;
+      int nc = 0;
+#pragma unroll
+      for (int k = 0; k < kSamplePer; ++k) nc += __popcll(__ballot(cls[k] == c));
+      wc[c] = nc;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < kNumClasses; ++c) wcnt[c][wid] = wc[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses) {
+      int tot = 0;
+      for (int w = 0; w < NW; ++w) tot += wcnt[threadIdx.x][w];
+      bbase[threadIdx.x] = tot ? atomicAdd(&bins.count[threadIdx.x], (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kNumClasses; ++c) {
+      if (wc[c] == 0) continue;  // uniform per wavefront
+      int64_t pos = (int64_t)bbase[c];
+      for (int w = 0; w < wid; ++w) pos += wcnt[c][w];
+#pragma unroll
+      for (int k = 0; k < kSamplePer; ++k) {
+        const uint64_t msk = __ballot(cls[k] == c);
+        if (cls[k] == c) {
+          const int64_t at = pos + __popcll(msk & lt_mask);
+          bins.slot[c][at] = sl[k];
+          bins.a[c][at] = av[k];
+          bins.b[c][at] = bv[k];
+        }
+        pos += __popcll(msk);
       }
     }
+    __syncthreads();  // wcnt and bbase are rewritten next round
+  }
+#pragma unroll
+  for (int c = 0; c < kNumClasses; ++c) {
+    const unsigned long long v = wave_sum_u64(algc[c]);
+    if (lane == 0 && v) atomicAdd(&bins.alg[c], v);
   }
 }
 
@@ -2067,7 +2113,7 @@ hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s) {
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges, int64_t total,
                              Bins bins, KernelCfg cfg, hipStream_t s) {
   if (total <= 0 || nranges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sample_bin, dim3(grid_for(total, 256, cfg.grid_sample)), dim3(256), 0, s, slots, ranges,
+  hipLaunchKernelGGL(k_sample_bin, dim3(grid_for(total, 256 * kSamplePer, cfg.grid_sample)), dim3(256), 0, s, slots, ranges,
                      nranges, total, bins, cfg);
   return hipGetLastError();
 }
