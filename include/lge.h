@@ -63,9 +63,10 @@ extern "C" {
 /* lge_graph_create_* flag: skip validation of the CSR (caller guarantees it) */
 #define LGE_FLAG_TRUSTED 1u
 /* lge_graph_create_* flag: keep the per-graph co-degree rows of the hubs
- * small (at most 4 GB and a smaller build-work budget) instead of up to
- * 32 GB; for callers holding many large graphs at once.  Results do not
- * change, only the speed on graphs with many vertices of degree > 1024. */
+ * and the co-degree table small (at most 4 GB and 1 GiB, and smaller
+ * build-work budgets) instead of up to 32 GB and 16 GiB; for callers holding
+ * many large graphs at once.  Results do not change, only the speed on
+ * graphs with many vertices of high degree. */
 #define LGE_FLAG_COMPACT 2u
 
 typedef struct lge_ctx lge_ctx;
@@ -187,9 +188,11 @@ LGE_API int lge_validate_csr_host(int64_t n, const int32_t *row_ptr, const int32
  * Validates on the GPU unless LGE_FLAG_TRUSTED.  Preprocesses once: the
  * canonical edge list and per-vertex 2-hop volumes used for scheduling, hash
  * tables of the vertices of degree > 256, the co-degree table and adjacency
- * bit rows of the (at most 16384) highest-degree vertices, and 16-bit
- * co-degree rows |Gamma(y) n Gamma(w)| over all w for the hubs y of degree
- * > 1024 in decreasing degree, within a build-work budget and up to 32 GB
+ * bit rows of the vertices of degree > 96 (the highest-degree 65536 of them
+ * at most, 16 GiB of table, or fewer within an eighth of the free HBM; 16384
+ * and 1 GiB with LGE_FLAG_COMPACT), and 16-bit co-degree rows
+ * |Gamma(y) n Gamma(w)| over all w for the hubs y of degree > 1024 in
+ * decreasing degree, within a build-work budget and up to 32 GB
  * of HBM (capped at a quarter of the free HBM; 4 GB with LGE_FLAG_COMPACT).
  * LGE_ERANGE if n >= 2^29 or a per-edge numerator could leave int64 or a sum
  * of squares 128 bits (bound: 16 * max(C(n,2), 2 dmax n, 4 dmax^2, m)).

@@ -25,9 +25,13 @@ typedef unsigned __int128 u128;
 
 namespace {
 
-// Co-degree table: at most this many ranked vertices (hc^2 * 4 bytes <= 1 GiB),
-// each of degree > kCodegMinDeg.
-constexpr int64_t kCodegMaxVertices = kMaxRanked;
+// Co-degree table: ranked vertices of degree > kCodegMinDeg, at most
+// kMaxRanked of them and hc^2 * 4 bytes within kCodegBytes (an eighth of the
+// free HBM at most; kCodegBytesCompact with LGE_FLAG_COMPACT).
+constexpr double kCodegBytes = 17179869184.0;       // 16 GiB: 65536 ranked vertices
+constexpr double kCodegBytesCompact = 1073741824.0;  // 1 GiB: 16384
+// pairs of one vertex's ranked neighbours per work item of the table build
+constexpr int64_t kPairsPerItem = (int64_t)1 << 20;
 // Vertices above this degree get a co-degree row over all unranked vertices
 // (largest degrees first, while the build work, the sum of their 2-hop
 // volumes, and the memory stay within these budgets).
@@ -39,7 +43,9 @@ constexpr double kRowBudgetOps = 6e10;
 constexpr double kRowBudgetBytes = 32e9;
 constexpr double kRowBudgetOpsCompact = 4e9;
 constexpr double kRowBudgetBytesCompact = 4e9;
-constexpr int32_t kCodegMinDeg = 32;
+// Ranked vertices have degree > kCodegMinDeg: a walk of a shorter row costs
+// about as much as the table read that replaces it.
+constexpr int32_t kCodegMinDeg = 96;
 
 #define LGE_HIP(expr)                        \
   do {                                       \
@@ -382,7 +388,7 @@ static bool sizes_in_range(int64_t n, int64_t m, int64_t dmax) {
   return true;
 }
 
-static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr);
+static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags);
 static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags);
 
 static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const int32_t *host_row_ptr) {
@@ -476,29 +482,35 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   if (e != hipSuccess) return hip_err(e);
-  if ((rc = build_codeg(ctx, g, host_row_ptr)) != LGE_OK) return rc;
+  if ((rc = build_codeg(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
   LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, n, g->vinfo, s));
   return build_rows(ctx, g, host_row_ptr, flags);
 }
 
 // Co-degree table of the vertices of degree > tau, tau the smallest threshold
-// >= kCodegMinDeg that leaves at most kCodegMaxVertices of them.  Ranks go
-// by increasing degree (ties by id): the split kernel counts each edge
-// between two ranked members of T_e once, from its lower-rank end, over the
-// bit-row words above that rank, and high-degree members, the common ones,
-// then have few words above them.
-static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) {
+// >= kCodegMinDeg that leaves at most hc_max of them (hc_max from the table's
+// memory budget).  Ranks go by increasing degree (ties by id): the split
+// kernel counts each edge between two ranked members of T_e once, from its
+// lower-rank end, over the bit-row words above that rank, and high-degree
+// members, the common ones, then have few words above them.
+static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags) {
   const int64_t n = g->n;
   g->hc = 0;
   if (n <= 0) return LGE_OK;
+  double budget = (flags & LGE_FLAG_COMPACT) ? kCodegBytesCompact : kCodegBytes;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget = std::min(budget, 0.125 * (double)free_b);
+  int64_t hc_max = std::min<int64_t>(kMaxRanked, (int64_t)std::sqrt(budget / 4.0));
+  hc_max &= ~(int64_t)63;
   std::vector<int32_t> deg((size_t)n);
   for (int64_t u = 0; u < n; ++u) deg[u] = host_row_ptr[u + 1] - host_row_ptr[u];
   int32_t tau = kCodegMinDeg;
-  if (n > kCodegMaxVertices) {
+  if (hc_max < 2) return LGE_OK;
+  if (n > hc_max) {
     std::vector<int32_t> tmpd(deg);
-    std::nth_element(tmpd.begin(), tmpd.begin() + kCodegMaxVertices, tmpd.end(), std::greater<int32_t>());
-    tau = std::max(tau, tmpd[kCodegMaxVertices]);
+    std::nth_element(tmpd.begin(), tmpd.begin() + hc_max, tmpd.end(), std::greater<int32_t>());
+    tau = std::max(tau, tmpd[hc_max]);
   }
   std::vector<int32_t> ranked;
   for (int64_t u = 0; u < n; ++u)
@@ -546,13 +558,36 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr) 
     cleanup();
     return rc;
   }
-  e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, list, s);
+  // pair-enumeration work items: (vertex, part, parts), about kPairsPerItem
+  // pairs each
+  std::vector<int64_t> hcnt((size_t)n);
+  e = hipMemcpyAsync(hcnt.data(), cnt, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_err(e);
+  }
+  std::vector<int3> items;
+  for (int64_t u = 0; u < n; ++u) {
+    const int64_t k = hcnt[u];
+    if (k < 2) continue;
+    const int64_t parts = std::min<int64_t>(k - 1, std::max<int64_t>(1, (k * (k - 1) / 2) / kPairsPerItem));
+    for (int64_t q = 0; q < parts; ++q) items.push_back(make_int3((int)u, (int)q, (int)parts));
+  }
+  int3 *ditems = nullptr;
+  if ((rc = dev_alloc(&ditems, std::max<int64_t>((int64_t)items.size(), 1))) != LGE_OK) {
+    cleanup();
+    return rc;
+  }
+  e = hipMemcpyAsync(ditems, items.data(), items.size() * sizeof(int3), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, list, s);
   if (e == hipSuccess) e = hipMemsetAsync(g->codeg, 0, (size_t)hc * (size_t)hc * sizeof(uint32_t), s);
-  if (e == hipSuccess) e = launch_codeg_pairs(off, cnt, list, n, hc, g->codeg, s);
+  if (e == hipSuccess) e = launch_codeg_pairs(off, cnt, list, ditems, (int64_t)items.size(), hc, g->codeg, s);
   if (e == hipSuccess) e = launch_codeg_mirror(hc, g->codeg, s);
   if (e == hipSuccess) e = launch_zero_u64(g->hbits, hc * hcw, s);
   if (e == hipSuccess) e = launch_codeg_bits(g->row_ptr, g->col, g->crank, n, hcw, g->hbits, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(ditems);
   cleanup();
   if (e != hipSuccess) return hip_err(e);
   g->hc = hc;

@@ -26,7 +26,7 @@ constexpr int kHubDeg = 1024;
 constexpr int kTableDeg = 256;
 // Ranked (co-degree table) vertices at most, and the 64-bit words of one
 // adjacency bit row over them.
-constexpr int kMaxRanked = 16384;
+constexpr int kMaxRanked = 65536;
 constexpr int kBitsWords = kMaxRanked / 64;
 // Largest number of Gamma(a) positions handled by one global-class work item.
 constexpr int kGlobalChunkMax = 256;
@@ -153,8 +153,8 @@ hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const i
                              unsigned long long *bits, hipStream_t s);
 // copy the upper triangle of the hc x hc co-degree table into the lower one
 hipError_t launch_codeg_mirror(int64_t hc, uint32_t *tab, hipStream_t s);
-hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, int64_t n, int64_t hc,
-                              uint32_t *tab, hipStream_t s);
+hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, const int3 *items,
+                              int64_t nitems, int64_t hc, uint32_t *tab, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
                              int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);

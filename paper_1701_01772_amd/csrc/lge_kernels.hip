@@ -598,15 +598,18 @@ __global__ __launch_bounds__(256) void k_codeg_fill(const int32_t *__restrict__ 
   }
 }
 
+// Work items (u, part, parts): item (u, p, P) enumerates the pairs (i, j),
+// i < j, of u's ranked-neighbour list for the rows i = p, p + P, ...; a
+// vertex with many ranked neighbours is split over several workgroups.
 __global__ __launch_bounds__(256) void k_codeg_pairs(const int64_t *__restrict__ off,
                                                      const int64_t *__restrict__ cnt,
-                                                     const int32_t *__restrict__ list, int64_t n, int64_t hc,
-                                                     uint32_t *tab) {
-  for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
-    const int64_t k = cnt[u];
-    if (k < 2) continue;  // uniform per block
-    const int32_t *l = list + off[u];
-    for (int64_t i = 0; i + 1 < k; ++i) {
+                                                     const int32_t *__restrict__ list, const int3 *__restrict__ items,
+                                                     int64_t nitems, int64_t hc, uint32_t *tab) {
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int3 w = items[it];
+    const int64_t k = cnt[w.x];
+    const int32_t *l = list + off[w.x];
+    for (int64_t i = w.y; i + 1 < k; i += w.z) {
       const int32_t ri = l[i];
       for (int64_t j = i + 1 + threadIdx.x; j < k; j += blockDim.x) {
         const int32_t rj = l[j];
@@ -1257,6 +1260,7 @@ constexpr uint8_t kFCodeg = 4;   // co-degree from the table
 constexpr uint8_t kFLookB = 8;   // w in S_a: cbx by look-ups of Gamma(b)
 constexpr uint8_t kFBits = 16;   // ranked w in T_e: degT over ranked members from bit rows
 constexpr uint32_t kRTag = 0x40000000u;  // T_e hash key tag: member is ranked
+constexpr int kBitsLds = 512;            // words of an edge's ranked-member set held in LDS
 
 __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_global(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
@@ -1283,8 +1287,8 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   __shared__ unsigned long long red[2 * NT / kWave];
   __shared__ long long sh_item;
   __shared__ int sh_last;
-  __shared__ unsigned long long tbits[kBitsWords];  // non-zero words of the ranked members of T_e
-  __shared__ int16_t twidx[kBitsWords];            // and their indices
+  __shared__ unsigned long long tbits[kBitsLds];  // non-zero words of the ranked members of T_e
+  __shared__ int16_t twidx[kBitsLds];            // and their indices
   __shared__ int32_t bx_rank[CH];  // ranked members of T_e in this chunk
 
   const int tid = threadIdx.x;
@@ -1343,7 +1347,10 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     const bool tl = t <= kTHashCap;
     const int tlg = table_log(t);
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;  // 0: no ranked vertices, no bit rows
-    const int nzw = hcw ? (int)G.nzw : 0;
+    // the bit rows serve edges whose ranked-member set fits its LDS copy; on
+    // the others every member of T_e is treated as unranked in the T_e terms
+    const bool ubits = hcw > 0 && G.nzw <= (unsigned long long)kBitsLds;
+    const int nzw = ubits ? (int)G.nzw : 0;
     if (tid < 4) sh_cnt[tid] = 0;
     if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
@@ -1369,7 +1376,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         }
         if (xb >= 0 && xb != a) lds_insert(hB, blg, (uint32_t)xb);
         if (xa >= 0 && xa != b) lds_insert(hA, alg, (uint32_t)xa);
-        if (ty >= 0) lds_insert(hT, tlg, (uint32_t)ty | (tr >= 0 ? kRTag : 0u));
+        if (ty >= 0) lds_insert(hT, tlg, (uint32_t)ty | (ubits && tr >= 0 ? kRTag : 0u));
       }
       if (tid == 0) words += (unsigned long long)(nB + nA + 2 * nT + 3 * nzw + 32);  // per-item terms once
     }
@@ -1388,7 +1395,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         return sl < 0 ? 0 : ((hT[sl] & kRTag) ? 2 : 1);
       }
       if (table_find(atab, alg, r) < 0 || table_find(btab, blg, r) < 0) return 0;
-      return (hcw && S.crank[r] >= 0) ? 2 : 1;
+      return (ubits && S.crank[r] >= 0) ? 2 : 1;
     };
     const int64_t mB = hb ? 16 : 4, mA = ha ? 16 : 4, mT = tl ? 4 : 32;
     // this chunk's vertices w of Gamma(a) \ {b}, each with its mode: the loads
@@ -1443,7 +1450,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
             units = dw;
           }
         } else {
-          const bool bits = rw >= 0;
+          const bool bits = ubits && rw >= 0;
           const bool lt = !bits && t_looks(dw, t, mT, probe_ratio);
           if (lt) fl |= kFLookT;
           if (bits) {  // degT over ranked partners in the bit-row phase below
@@ -1531,7 +1538,8 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
               const int dy = T[3 * off + 1];
               // ranked members count only ranked partners; pairs of unranked
               // look-up members are tested by the smaller id only
-              const int wgt = T[3 * off + 2] >= 0 ? 2 : (t_looks(dy, t, mT, probe_ratio) ? (y > w ? 2 : 0) : 1);
+              const int wgt =
+                  (ubits && T[3 * off + 2] >= 0) ? 2 : (t_looks(dy, t, mT, probe_ratio) ? (y > w ? 2 : 0) : 1);
               if (wgt && w_has(S, w, wl_beg[l2], dw, y, &steps)) kt += (unsigned long long)wgt;
             } else {
               kt += (unsigned long long)tmemb((uint32_t)col[wl_beg[l2] + off]);
@@ -2097,10 +2105,11 @@ hipError_t launch_codeg_mirror(int64_t hc, uint32_t *tab, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, int64_t n, int64_t hc,
-                              uint32_t *tab, hipStream_t s) {
-  if (n <= 0 || hc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_codeg_pairs, dim3(grid_for(n, 1, 16384)), dim3(256), 0, s, off, cnt, list, n, hc, tab);
+hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, const int3 *items,
+                              int64_t nitems, int64_t hc, uint32_t *tab, hipStream_t s) {
+  if (nitems <= 0 || hc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_pairs, dim3(grid_for(nitems, 1, 16384)), dim3(256), 0, s, off, cnt, list, items, nitems,
+                     hc, tab);
   return hipGetLastError();
 }
 

@@ -337,3 +337,29 @@ def test_compact_graph_same_results(ctx, rmat22):
             lge.lge_graph_destroy(h)
     for k in ("sampled", "csum", "zsum", "qsum", "estimate", "variance"):
         assert outs[0][k] == outs[1][k], k
+
+
+def wide_t_graph(k):
+    """Hubs 0 and 1, adjacent, with k common neighbours joined in a ring
+    lattice (48 on each side), so every common neighbour has degree 98 and is
+    in the co-degree table: T_e of the hub edge holds k ranked members."""
+    e = [(0, 1)] + [(0, 2 + i) for i in range(k)] + [(1, 2 + i) for i in range(k)]
+    e += [(2 + i, 2 + (i + s) % k) for i in range(k) for s in range(1, 49)]
+    return inputs.from_edges(k + 2, np.array(e, dtype=np.int32))
+
+
+@pytest.mark.parametrize("k", [20000, 40000])
+def test_wide_ranked_t(ctx, k):
+    # k = 20000: the ranked members of T_e fill 313 bit-set words (held in
+    # LDS); k = 40000: 626 words, beyond the LDS copy, so the split kernel
+    # treats them as unranked for that edge
+    g = wide_t_graph(k)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        for a, b in ((0, 1), (1, 9), (k + 1, k + 9), (2 * k + 1, 2 * k + 40), (g.m - 5, g.m)):
+            _say("wide T_e k=%d range [%d, %d)" % (k, a, b))
+            got = lge.lge_estimate_range(ctx, h, 1.0, 5, a, b)
+            mask = oracle.sample_mask(5, 1.0, g.m, a, b)
+            assert_parity(got, oracle.estimate(g.row_ptr, g.col, 1.0, 5, mask=mask), "wide-t k=%d [%d,%d)" % (k, a, b))
+    finally:
+        lge.lge_graph_destroy(h)
