@@ -73,7 +73,19 @@ def cpu_baseline(g, p, seed, target_s=15.0):
         stride = max(1, int(stride * dt / target_s))
     return {"value": r["sampled"] / dt, "unit": "sampled edges/s", "cores": 1, "kind": "oracle",
             "sample": "every %d-th of the %d Philox-sampled edges (%d edges, %.1f s)" % (
-                stride, sampled_ids.size, r["sampled"], dt)}
+                stride, sampled_ids.size, r["sampled"], dt),
+            "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def roofline_of(tim, workload):

@@ -483,9 +483,11 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   cleanup();
   if (e != hipSuccess) return hip_err(e);
   if ((rc = build_codeg(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
+  if ((rc = build_rows(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
-  LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, n, g->vinfo, s));
-  return build_rows(ctx, g, host_row_ptr, flags);
+  LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, g->nrows > 0 ? g->hrow : nullptr, n, g->vinfo, s));
+  LGE_HIP(hipStreamSynchronize(s));
+  return LGE_OK;
 }
 
 // Co-degree table of the vertices of degree > tau, tau the smallest threshold

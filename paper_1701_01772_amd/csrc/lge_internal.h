@@ -46,7 +46,7 @@ struct SlotDesc {
   int64_t hc;               // ranked vertices (0: no table)
   const unsigned long long *hbits;  // hc x hcw bit rows: bit ry of row rx = (x, y) adjacent
   int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
-  const int4 *vinfo;        // n: (row start, degree, rank or -1, 0)
+  const int4 *vinfo;        // n: (row start, degree, rank or -1, co-degree row or -1)
   const int32_t *hrow;      // n: co-degree row of the vertex, -1 if none (null: no rows)
   const uint16_t *rows;     // rows x rows_stride: |Gamma(y) n Gamma(w)| at [hrow[y]][w], unranked w only
   int64_t rows_stride;
@@ -143,7 +143,8 @@ hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const 
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
                              const int64_t *off, int32_t *list, hipStream_t s);
 // per-vertex (row start, degree, rank or -1, 0) records (crank may be null)
-hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, int64_t n, int4 *vinfo, hipStream_t s);
+hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, int64_t n, int4 *vinfo,
+                        hipStream_t s);
 // co-degree rows of the vertices `hubs` over the unranked vertices (rows
 // zeroed by the caller; stride even, in uint16)
 hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,

@@ -669,9 +669,10 @@ __global__ __launch_bounds__(256) void k_rows_build(const int32_t *__restrict__ 
 
 // (row start, degree, rank or -1, 0) of every vertex
 __global__ __launch_bounds__(256) void k_vinfo(const int32_t *__restrict__ rp, const int32_t *__restrict__ crank,
-                                               int64_t n, int4 *__restrict__ vinfo) {
+                                               const int32_t *__restrict__ hrow, int64_t n,
+                                               int4 *__restrict__ vinfo) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    vinfo[v] = make_int4(rp[v], rp[v + 1] - rp[v], crank ? crank[v] : -1, 0);
+    vinfo[v] = make_int4(rp[v], rp[v + 1] - rp[v], crank ? crank[v] : -1, hrow ? hrow[v] : -1);
 }
 
 __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -691,12 +692,25 @@ __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ 
   }
 }
 
-__device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t y, uint32_t *val) {
+// |Gamma(x) n Gamma(y)| when tabulated: both ranked (the symmetric table,
+// y's row), or one end unranked and the other with a co-degree row.  vy is
+// y's vertex record.
+__device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t y, int4 vy, uint32_t *val) {
   if (S.hc <= 0) return false;
-  const int32_t rx = S.crank[x], ry = S.crank[y];
-  if (rx < 0 || ry < 0) return false;
-  *val = S.codeg[(int64_t)ry * S.hc + rx];  // the table is symmetric: y's row
-  return true;
+  const int4 vx = S.vinfo[x];
+  if (vx.z >= 0 && vy.z >= 0) {
+    *val = S.codeg[(int64_t)vy.z * S.hc + vx.z];
+    return true;
+  }
+  if (vx.z < 0 && vy.w >= 0) {
+    *val = S.rows[(int64_t)vy.w * S.rows_stride + x];
+    return true;
+  }
+  if (vy.z < 0 && vx.w >= 0) {
+    *val = S.rows[(int64_t)vx.w * S.rows_stride + y];
+    return true;
+  }
+  return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -979,12 +993,13 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       const int sbn = sh_cnt[2];
       // per-w modes
       long long cyc_base = 0;
+      const int4 vb = S.hc > 0 ? S.vinfo[b] : make_int4(0, 0, -1, -1);
       for (int i = tid; i < L; i += NT) {
         const uint32_t v = wl_v[i];
         const bool isT = (v & kTag) != 0;
         const int32_t w = (int32_t)(v & kIdMask);
         uint32_t cdeg = 0;
-        const bool cok = !isT && codeg_pair(S, w, b, &cdeg);
+        const bool cok = !isT && codeg_pair(S, w, b, vb, &cdeg);
         const WMode md = choose_mode(isT, wl_deg[i], t, sbn, cok, cdeg, probe_ratio);
         wl_v[i] = v | md.flags;
         wl_pref[i] = md.units;
@@ -1410,13 +1425,14 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       bool valid = i < p1;
       const int32_t x = valid ? col[abeg + i] : -1;
       valid = valid && x != b;
-      int32_t wb = 0, we = 0, rw = -1;
+      int32_t wb = 0, we = 0, rw = -1, hw = -1;
       bool isT = false;
       if (valid) {
-        const int4 vi = S.vinfo[x];  // row start, degree, rank in one 16-byte read
+        const int4 vi = S.vinfo[x];  // row start, degree, rank, co-degree row in one 16-byte read
         wb = vi.x;
         we = vi.x + vi.y;
         rw = hcw ? vi.z : -1;
+        hw = vi.w;
         // x in Gamma(a) is in T_e iff in Gamma(b): the classify pass's bit
         isT = ((tmask[item * kMaskWords + ((i - p0) >> 6)] >> ((i - p0) & 63)) & 1ull) != 0;
       }
@@ -1431,7 +1447,10 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
           cdeg = S.codeg[(int64_t)ry * S.hc + rw];  // symmetric table: the row of the item's fixed end
           cok = true;
         } else if (rw < 0 && hr >= 0) {
-          cdeg = S.rows[(int64_t)hr * S.rows_stride + x];
+          cdeg = S.rows[(int64_t)hr * S.rows_stride + x];  // the fixed end's row at unranked x
+          cok = true;
+        } else if (ry < 0 && hw >= 0) {
+          cdeg = S.rows[(int64_t)hw * S.rows_stride + (isT ? a : b)];  // x's own row at the unranked end
           cok = true;
         }
       }
@@ -2215,9 +2234,10 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 
 size_t gedge_bytes() { return sizeof(GEdge); }
 
-hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, int64_t n, int4 *vinfo, hipStream_t s) {
+hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, int64_t n, int4 *vinfo,
+                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, n, vinfo);
+  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, hrow, n, vinfo);
   return hipGetLastError();
 }
 
