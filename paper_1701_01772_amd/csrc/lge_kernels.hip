@@ -823,64 +823,32 @@ struct SlotAcc {
 };
 
 // ---------------------------------------------------------------------------
-// Per-neighbour work modes.  For every w in Gamma(a) \ {b} the kernels pick
-// the cheapest of
-//   scan   : walk Gamma(w), test each r against the tables of b / T_e
-//            (neighbour iteration, Alg. 3/4)                  units = d_w
-//   lookT  : w in T_e: look each member of T_e up in Gamma(w)  units = t
-//            (restricted search, Alg. 5)
-//   lookS  : w in S_a: look each member of S_b up in Gamma(w)  units = |S_b source|
-//            (restricted search, Alg. 6)
-//   codeg  : w in S_a with w, b in the co-degree table:
-//            |Gamma(w) n S_b| = codeg(w,b) - 1 - |Gamma(w) n T_e|, the last term
-//            by looking T_e up in Gamma(w)                  units = t
-// "Look up x in Gamma(w)" uses w's hub table when d_w > kTableDeg, else a binary
-// search of the sorted list.  Costs are in quarter units: a scanned entry
-// costs 8 (a coalesced load and a table probe), a look-up 4*(2 + probe cost)
-// scaled by probe_ratio / 4.
+// Per-neighbour work of the workgroup classes.  With probe_ratio > 0 they
+// count in the aggregate form the split class uses,
+//   cyc = sum_{w in S_a} cbx(w) - sum_{x in T_e} cax(x) + sum_{x in T_e} degT(x),
+// cbx(w) = |Gamma(w) n Gamma(b)\{a}|, cax(x) = |Gamma(x) n Gamma(a)\{b}|,
+// degT(x) = |Gamma(x) n T_e|, k4 = sum degT / 2, and pick per w the cheapest
+// way to each term:
+//   w in S_a : cbx = codeg(w,b) - 1 when tabulated (no units); else scan
+//              Gamma(w) against the table of Gamma(b)\{a}        units = d_w
+//              or look each of Gamma(b)\{a} up in Gamma(w)       units = d_b - 1
+//   x in T_e : degT by scan (T-tagged hits)                      units = d_x
+//              or by looking T_e up in Gamma(x) (Alg. 5)         units = t
+//              cax = codeg(x,a) - 1 when tabulated, else look each of
+//              Gamma(a)\{b} up in Gamma(x)                       units = d_a - 1
+// With probe_ratio <= 0 every w scans Gamma(w) (neighbour iteration,
+// Alg. 3/4): S_a members count their neighbours in S_b, T_e members theirs
+// in T_e.  "Look up x in Gamma(w)" uses w's hub table when d_w > kTableDeg,
+// else a binary search of the sorted list.  Costs are in quarter units: a
+// scanned entry costs 8 (a coalesced load and a table probe), a look-up
+// 4*(2 + probe cost) scaled by probe_ratio / 4.
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kModeLook = 0x40000000u;
-constexpr uint32_t kModeCodeg = 0x20000000u;
+constexpr uint32_t kModeLook = 0x40000000u;  // S_a: look Gamma(b)\{a} up; T_e: degT by looking T_e up
+constexpr uint32_t kModeAux = 0x20000000u;   // S_a: cbx tabulated (no units); T_e: cax by look-ups
 
-struct WMode {
-  uint32_t flags;
-  int32_t units;
-  int64_t base;  // added to the cycle count once (codeg mode)
-};
-
-__device__ __forceinline__ WMode choose_mode(bool isT, int dw, int t, int sb_src, bool codeg_ok, uint32_t cdeg,
-                                             int probe_ratio) {
-  WMode m;
-  m.flags = 0;
-  m.units = dw;
-  m.base = 0;
-  if (probe_ratio <= 0) return m;
-  const int64_t look = (int64_t)((has_table(dw) ? 1 : ceil_log2((uint32_t)dw + 1u)) + 2) * probe_ratio;
-  int64_t best = 8ll * dw;
-  if (isT) {
-    const int64_t c = (int64_t)t * look;
-    if (c < best) {
-      m.flags = kModeLook;
-      m.units = t;
-    }
-    return m;
-  }
-  const int64_t cs = (int64_t)sb_src * look;
-  if (cs < best) {
-    best = cs;
-    m.flags = kModeLook;
-    m.units = sb_src;
-  }
-  if (codeg_ok) {
-    const int64_t cc = (int64_t)t * look;
-    if (cc < best) {
-      m.flags = kModeLook | kModeCodeg;
-      m.units = t;
-      m.base = (int64_t)cdeg - 1;
-    }
-  }
-  return m;
+__device__ __forceinline__ int64_t look_cost(int dw, int probe_ratio) {
+  return (int64_t)((has_table(dw) ? 1 : ceil_log2((uint32_t)dw + 1u)) + 2) * probe_ratio;
 }
 
 // is x in Gamma(w)?  (w's hub table, or binary search of its sorted list)
@@ -991,26 +959,92 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       const int L = sh_cnt[0];
       const int t = sh_cnt[1];
       const int sbn = sh_cnt[2];
-      // per-w modes
+      // per-w modes under both schemes; the edge takes the cheaper one
+      const bool may_look = probe_ratio > 0;
+      int4 va = make_int4(0, 0, -1, -1), vb = va;
+      if (may_look && S.hc > 0) {
+        va = S.vinfo[a];
+        vb = S.vinfo[b];
+      }
       long long cyc_base = 0;
-      const int4 vb = S.hc > 0 ? S.vinfo[b] : make_int4(0, 0, -1, -1);
+      unsigned long long c_plain = 0, c_agg = 0;
       for (int i = tid; i < L; i += NT) {
         const uint32_t v = wl_v[i];
         const bool isT = (v & kTag) != 0;
         const int32_t w = (int32_t)(v & kIdMask);
+        const int dw = wl_deg[i];
+        const int64_t scan = 8ll * dw;
+        if (!may_look) {
+          c_plain += (unsigned long long)scan;
+          continue;
+        }
+        const int64_t lk = look_cost(dw, probe_ratio);
+        const int64_t lt = (int64_t)t * lk;
+        c_plain += (unsigned long long)(isT ? (lt < scan ? lt : scan)
+                                             : ((int64_t)sbn * lk < scan ? (int64_t)sbn * lk : scan));
         uint32_t cdeg = 0;
-        const bool cok = !isT && codeg_pair(S, w, b, vb, &cdeg);
-        const WMode md = choose_mode(isT, wl_deg[i], t, sbn, cok, cdeg, probe_ratio);
-        wl_v[i] = v | md.flags;
-        wl_pref[i] = md.units;
-        cyc_base += md.base;
+        const bool cok = codeg_pair(S, w, isT ? a : b, isT ? va : vb, &cdeg);
+        uint32_t fl = 0;
+        int32_t units = dw;
+        int64_t cost = scan;
+        if (!isT) {
+          if (cok) {
+            fl = kModeAux;
+            units = 0;
+            cost = 0;
+            cyc_base += (long long)cdeg - 1;
+          } else if ((int64_t)(db - 1) * lk < scan) {
+            fl = kModeLook;
+            units = db - 1;
+            cost = (int64_t)(db - 1) * lk;
+          }
+        } else {
+          if (lt < scan) {
+            fl = kModeLook;
+            units = t;
+            cost = lt;
+          }
+          if (cok) {
+            cyc_base -= (long long)cdeg - 1;
+          } else {
+            fl |= kModeAux;
+            units += L;  // Gamma(a) \ {b} is the w-list (x itself is never found)
+            cost += (int64_t)L * lk;
+          }
+        }
+        c_agg += (unsigned long long)cost;
+        wl_v[i] = v | fl;
+        wl_pref[i] = units;
+      }
+      c_plain = block_sum_u64<NT>(c_plain, red);
+      c_agg = block_sum_u64<NT>(c_agg, red);
+      const bool agg = may_look && c_agg < c_plain;
+      if (!agg) {  // plain scheme: S_a members count |Gamma(w) n S_b|, T_e members degT
+        cyc_base = 0;
+        for (int i = tid; i < L; i += NT) {
+          const uint32_t v = wl_v[i] & ~(kModeLook | kModeAux);
+          const bool isT = (v & kTag) != 0;
+          const int dw = wl_deg[i];
+          uint32_t fl = 0;
+          int32_t units = dw;
+          if (may_look) {
+            const int64_t lk = look_cost(dw, probe_ratio);
+            const int32_t src = isT ? t : sbn;
+            if ((int64_t)src * lk < 8ll * dw) {
+              fl = kModeLook;
+              units = src;
+            }
+          }
+          wl_v[i] = v | fl;
+          wl_pref[i] = units;
+        }
       }
       __syncthreads();
       const int32_t total = block_scan_lds<NT>(wl_pref, L, carry_sh);
       if (tid == 0) wl_pref[L] = total;
       __syncthreads();
       // flattened (w, unit) loop
-      unsigned long long k4 = 0, cyc = (unsigned long long)cyc_base;
+      unsigned long long kt = 0, cs = (unsigned long long)cyc_base;
       int cur = 0;
       uint32_t steps = 0;
       for (int base = 0; base < total; base += NT) {
@@ -1028,34 +1062,42 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           const uint32_t v = wl_v[lo];
           const int off = idx - wl_pref[lo];
           const bool isT = (v & kTag) != 0;
-          if (v & kModeLook) {
-            const bool fromT = isT || (v & kModeCodeg);
-            const int32_t x = fromT ? tgt[off] : tgt[CAP - sbn + off];
-            if (w_has(S, (int32_t)(v & kIdMask), wl_beg[lo], wl_deg[lo], x, &steps)) {
-              if (isT)
-                ++k4;
-              else if (v & kModeCodeg)
-                --cyc;
-              else
-                ++cyc;
+          const int32_t w = (int32_t)(v & kIdMask);
+          if (!isT) {
+            if (v & kModeLook) {  // look up Gamma(b) \ {a} (T_e, then S_b) for cbx, else S_b
+              const int32_t x = agg ? (off < t ? tgt[off] : tgt[CAP - sbn + (off - t)]) : tgt[CAP - sbn + off];
+              if (w_has(S, w, wl_beg[lo], wl_deg[lo], x, &steps)) ++cs;
+            } else {  // scan: cbx (any hit), or |Gamma(w) n S_b| without the aggregate form
+              const int32_t r = col[wl_beg[lo] + off];
+              ++steps;
+              const int sl = table_find(htab, lg, (uint32_t)r);
+              if (sl >= 0 && (agg || !(htab[sl] & kTag))) ++cs;
             }
           } else {
-            const int32_t r = col[wl_beg[lo] + off];
-            ++steps;
-            const int sl = table_find(htab, lg, (uint32_t)r);
-            if (sl >= 0) {
-              const bool rT = (htab[sl] & kTag) != 0;
-              if (isT && rT) ++k4;
-              if (!isT && !rT) ++cyc;
+            const bool lt = (v & kModeLook) != 0;
+            const int part1 = lt ? t : wl_deg[lo];
+            if (off < part1) {  // degT
+              if (lt) {
+                if (w_has(S, w, wl_beg[lo], wl_deg[lo], tgt[off], &steps)) ++kt;
+              } else {
+                const int32_t r = col[wl_beg[lo] + off];
+                ++steps;
+                const int sl = table_find(htab, lg, (uint32_t)r);
+                if (sl >= 0 && (htab[sl] & kTag)) ++kt;
+              }
+            } else {  // cax: look Gamma(a) \ {b} up in Gamma(x)
+              const int32_t y = (int32_t)(wl_v[off - part1] & kIdMask);
+              if (w_has(S, w, wl_beg[lo], wl_deg[lo], y, &steps)) --cs;
             }
           }
         }
       }
       words += steps + (tid == 0 ? 2ull * (unsigned long long)L : 0ull);
-      k4 = block_sum_u64<NT>(k4, red);
-      cyc = block_sum_u64<NT>(cyc, red);
-      if (tid < kWave) acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(k4 / 2), (int64_t)cyc);
-      if (tid == 0) micro_put(S, a, b, t, (int64_t)(k4 / 2), (int64_t)cyc);
+      kt = block_sum_u64<NT>(kt, red);
+      cs = block_sum_u64<NT>(cs, red);
+      const unsigned long long cyc = agg ? cs + kt : cs;
+      if (tid < kWave) acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(kt / 2), (int64_t)cyc);
+      if (tid == 0) micro_put(S, a, b, t, (int64_t)(kt / 2), (int64_t)cyc);
       __syncthreads();
     }
   }
