@@ -116,7 +116,7 @@ struct KernelCfg {
 
 // split-class edge ordering: key = rank of the table-side endpoint in the
 // co-degree table, kSortKeys - 1 for unranked endpoints
-constexpr int kSortKeys = 16385;
+constexpr int kSortKeys = kMaxRanked + 1;
 constexpr int kXcds = 8;
 constexpr uint32_t kOptSortHub = 1u;
 constexpr uint32_t kOptXcdLocal = 2u;

@@ -1223,10 +1223,11 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
       if (lane == 0 && tm) pos0 = atomicAdd(&gacc[e].t, (unsigned long long)__popcll(tm));
       pos0 = __shfl(pos0, 0);
       if (isT) {  // (id, degree, rank) triples; rank -1 when not ranked
+        const int4 vi = S.vinfo[x];
         const int64_t pos = tbase[e] + (int64_t)pos0 + __popcll(tm & lt_mask);
         tlist[3 * pos] = x;
-        tlist[3 * pos + 1] = rp[x + 1] - rp[x];
-        tlist[3 * pos + 2] = S.hc > 0 ? S.crank[x] : -1;
+        tlist[3 * pos + 1] = vi.y;
+        tlist[3 * pos + 2] = vi.z;
       }
     }
   }
@@ -2031,8 +2032,8 @@ __global__ __launch_bounds__(256) void k_select_hist(uint64_t seed, int64_t m, i
 
 __device__ __forceinline__ int sort_key(const SlotDesc &S, int32_t b) {
   if (S.hc <= 0) return kSortKeys - 1;
-  const int32_t r = S.crank[b];
-  return (r >= 0 && r < kSortKeys - 1) ? r : kSortKeys - 1;
+  const int32_t r = S.crank[b];  // < kMaxRanked
+  return r >= 0 ? r : kSortKeys - 1;
 }
 
 __global__ __launch_bounds__(256) void k_sort_hist(const SlotDesc *__restrict__ slots,
