@@ -39,7 +39,7 @@ constexpr int32_t kRowDeg = 1024;
 // co-degree rows: build work (sum of 2-hop volumes) and HBM per graph; the
 // byte budget is also capped at a quarter of the free HBM at creation.
 // LGE_FLAG_COMPACT keeps the small budget for callers holding many graphs.
-constexpr double kRowBudgetOps = 6e10;
+constexpr double kRowBudgetOps = 1.2e11;
 constexpr double kRowBudgetBytes = 32e9;
 constexpr double kRowBudgetOpsCompact = 4e9;
 constexpr double kRowBudgetBytesCompact = 4e9;
@@ -598,12 +598,14 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
 }
 
 // Co-degree rows: for the chosen vertices y, |Gamma(y) n Gamma(w)| for every
-// unranked w (ranked pairs use the co-degree table).  Counts of unranked w
-// are at most the ranking threshold, so 16 bits hold them.
+// unranked w (ranked pairs use the co-degree table).  An unranked degree is
+// at most the ranking threshold, so one byte holds the count when that is
+// <= kRowMaxDeg, two bytes otherwise.
 static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags) {
   g->nrows = 0;
   const int64_t n = g->n;
-  if (n <= 0 || g->hc <= 0 || g->codeg_tau >= 65535) return LGE_OK;
+  if (n <= 0 || g->hc <= 0 || g->codeg_tau > 65535) return LGE_OK;
+  const int width = g->codeg_tau <= kRowMaxDeg ? 1 : 2;
   std::vector<std::pair<int32_t, int32_t>> cand;
   for (int64_t v = 0; v < n; ++v) {
     const int32_t d = host_row_ptr[v + 1] - host_row_ptr[v];
@@ -617,7 +619,7 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   hipStream_t s = ctx->stream;
   LGE_HIP(hipMemcpyAsync(vol2.data(), g->vol2, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   LGE_HIP(hipStreamSynchronize(s));
-  const int64_t stride = (n + 1) & ~(int64_t)1;
+  const int64_t stride = (n + 7) & ~(int64_t)7;  // entries; rows of whole 64-bit words for the zero fill
   const bool compact = (flags & LGE_FLAG_COMPACT) != 0;
   const double budget_ops = compact ? kRowBudgetOpsCompact : kRowBudgetOps;
   double budget_bytes = compact ? kRowBudgetBytesCompact : kRowBudgetBytes;
@@ -626,7 +628,7 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   std::vector<int32_t> hubs;
   double ops = 0.0;
   for (const auto &c : cand) {
-    const double bytes = (double)(hubs.size() + 1) * (double)stride * 2.0;
+    const double bytes = (double)(hubs.size() + 1) * (double)stride * width;
     if (ops + (double)vol2[c.second] > budget_ops || bytes > budget_bytes) break;
     ops += (double)vol2[c.second];
     hubs.push_back(c.second);
@@ -638,7 +640,7 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   int32_t *dhubs = nullptr;
   int rc;
   if ((rc = dev_alloc(&dhubs, nh)) != LGE_OK) return rc;
-  const int64_t nent = (nh * stride + 3) & ~(int64_t)3;  // whole 64-bit words for the zero fill
+  const int64_t nent = nh * stride * width;  // bytes
   if ((rc = dev_alloc(&g->hrow, n)) != LGE_OK || (rc = dev_alloc(&g->rows, nent)) != LGE_OK) {
     dev_free(dhubs);
     dev_free(g->hrow);
@@ -647,8 +649,8 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   }
   hipError_t e = hipMemcpyAsync(dhubs, hubs.data(), (size_t)nh * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->hrow, hrow.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_zero_u64((unsigned long long *)g->rows, nent / 4, s);
-  if (e == hipSuccess) e = launch_rows_build(g->row_ptr, g->col, g->crank, dhubs, nh, stride, g->rows, s);
+  if (e == hipSuccess) e = launch_zero_u64((unsigned long long *)g->rows, nent / 8, s);
+  if (e == hipSuccess) e = launch_rows_build(g->row_ptr, g->col, g->crank, dhubs, nh, stride, width, g->rows, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dev_free(dhubs);
   if (e != hipSuccess) {
@@ -658,6 +660,7 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   }
   g->nrows = nh;
   g->rows_stride = stride;
+  g->rows_w = width;
   return LGE_OK;
 }
 
@@ -980,6 +983,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.hrow = g->nrows > 0 ? g->hrow : nullptr;
     sd.rows = g->rows;
     sd.rows_stride = g->rows_stride;
+    sd.rows_w = g->rows_w;
     sd.n = jobs[j].n_override >= 0 ? jobs[j].n_override : g->n;
     sd.m = jobs[j].m_override >= 0 ? jobs[j].m_override : g->m;
     sd.p = jobs[j].p;
@@ -990,7 +994,6 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.micro_base = jobs[j].e0 - jobs[j].eid_base;
     sd.micro_len = jobs[j].e1 - jobs[j].e0;
     sd.design = jobs[j].design;
-    sd.pad = 0;
     sd.level = jobs[j].level;
     sd.kkey = jobs[j].kkey;
     sd.keid = jobs[j].keid;

@@ -27,6 +27,10 @@ constexpr int kTableDeg = 256;
 // Ranked (co-degree table) vertices at most, and the 64-bit words of one
 // adjacency bit row over them.
 constexpr int kMaxRanked = 65536;
+// Co-degree rows hold one byte per vertex when no unranked vertex has degree
+// above kRowMaxDeg (no co-degree with an unranked vertex can exceed it), else
+// two.
+constexpr int kRowMaxDeg = 254;
 constexpr int kBitsWords = kMaxRanked / 64;
 // Largest number of Gamma(a) positions handled by one global-class work item.
 constexpr int kGlobalChunkMax = 256;
@@ -48,7 +52,8 @@ struct SlotDesc {
   int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
   const int4 *vinfo;        // n: (row start, degree, rank or -1, co-degree row or -1)
   const int32_t *hrow;      // n: co-degree row of the vertex, -1 if none (null: no rows)
-  const uint16_t *rows;     // rows x rows_stride: |Gamma(y) n Gamma(w)| at [hrow[y]][w], unranked w only
+  const uint8_t *rows;      // rows x rows_stride entries of rows_w bytes: |Gamma(y) n Gamma(w)| at
+                            // [hrow[y]][w], unranked w only
   int64_t rows_stride;
   int64_t n, m;
   double p;
@@ -62,7 +67,8 @@ struct SlotDesc {
   int64_t micro_base, micro_len;
   // sampling design (kDesignBernoulli: p_lo <= uniform < p)
   int32_t design;
-  int32_t pad;
+  int32_t rows_w;           // bytes per co-degree row entry: 1 when every unranked degree is
+                            // <= kRowMaxDeg, else 2
   const uint8_t *level;     // kDesignWeighted: class of every edge id; class l is
                             //   kept iff uniform < plev[l] and binned to slot + l
   uint64_t kkey;            // kDesignFixedK: kept iff (Philox key, id) <= (kkey, keid)
@@ -145,10 +151,10 @@ hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const i
 // per-vertex (row start, degree, rank or -1, 0) records (crank may be null)
 hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, int64_t n, int4 *vinfo,
                         hipStream_t s);
-// co-degree rows of the vertices `hubs` over the unranked vertices (rows
-// zeroed by the caller; stride even, in uint16)
+// co-degree rows of the vertices `hubs` over the unranked vertices, width
+// bytes per entry (rows zeroed by the caller; stride * width a multiple of 4)
 hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,
-                             int64_t nh, int64_t stride, uint16_t *rows, hipStream_t s);
+                             int64_t nh, int64_t stride, int width, uint8_t *rows, hipStream_t s);
 // adjacency bit rows among the ranked vertices (bits zeroed by the caller)
 hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,
                              unsigned long long *bits, hipStream_t s);

@@ -645,26 +645,36 @@ __global__ __launch_bounds__(256) void k_codeg_mirror(int64_t hc, uint32_t *tab)
 }
 
 // One workgroup per row: for x in Gamma(b), for unranked w in Gamma(x), count
-// w once more.  A row belongs to one workgroup, so workgroup-scope atomics
-// on its packed 16-bit counters suffice.
+// w once more (at most w's degree in all, which fits the entry width).  A row
+// belongs to one workgroup, so workgroup-scope atomics on its packed
+// counters suffice.
 __global__ __launch_bounds__(256) void k_rows_build(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ crank,
                                                     const int32_t *__restrict__ hubs, int64_t nh, int64_t stride,
-                                                    uint16_t *rows) {
+                                                    int width, uint8_t *rows) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
     const int32_t b = hubs[h];
-    uint32_t *row = reinterpret_cast<uint32_t *>(rows + h * stride);
+    uint32_t *row = reinterpret_cast<uint32_t *>(rows + h * stride * width);
     for (int32_t j = rp[b] + wv; j < rp[b + 1]; j += (int32_t)(blockDim.x >> 6)) {
       const int32_t x = col[j];
       for (int32_t k = rp[x] + lane; k < rp[x + 1]; k += 64) {
         const int32_t w = col[k];
         if (crank[w] >= 0) continue;
-        __hip_atomic_fetch_add(row + (w >> 1), 1u << ((w & 1) * 16), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (width == 1)
+          __hip_atomic_fetch_add(row + (w >> 2), 1u << ((w & 3) * 8), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          __hip_atomic_fetch_add(row + (w >> 1), 1u << ((w & 1) * 16), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
   }
+}
+
+// entry x of co-degree row r
+__device__ __forceinline__ uint32_t row_at(const SlotDesc &S, int64_t r, int64_t x) {
+  const int64_t i = r * S.rows_stride + x;
+  return S.rows_w == 1 ? (uint32_t)S.rows[i] : (uint32_t)reinterpret_cast<const uint16_t *>(S.rows)[i];
 }
 
 // (row start, degree, rank or -1, 0) of every vertex
@@ -703,11 +713,11 @@ __device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t
     return true;
   }
   if (vx.z < 0 && vy.w >= 0) {
-    *val = S.rows[(int64_t)vy.w * S.rows_stride + x];
+    *val = row_at(S, vy.w, x);
     return true;
   }
   if (vy.z < 0 && vx.w >= 0) {
-    *val = S.rows[(int64_t)vx.w * S.rows_stride + y];
+    *val = row_at(S, vx.w, y);
     return true;
   }
   return false;
@@ -1490,10 +1500,10 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
           cdeg = S.codeg[(int64_t)ry * S.hc + rw];  // symmetric table: the row of the item's fixed end
           cok = true;
         } else if (rw < 0 && hr >= 0) {
-          cdeg = S.rows[(int64_t)hr * S.rows_stride + x];  // the fixed end's row at unranked x
+          cdeg = row_at(S, hr, x);  // the fixed end's row at unranked x
           cok = true;
         } else if (ry < 0 && hw >= 0) {
-          cdeg = S.rows[(int64_t)hw * S.rows_stride + (isT ? a : b)];  // x's own row at the unranked end
+          cdeg = row_at(S, hw, isT ? a : b);  // x's own row at the unranked end
           cok = true;
         }
       }
@@ -2285,10 +2295,10 @@ hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int3
 }
 
 hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,
-                             int64_t nh, int64_t stride, uint16_t *rows, hipStream_t s) {
+                             int64_t nh, int64_t stride, int width, uint8_t *rows, hipStream_t s) {
   if (nh <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rows_build, dim3(grid_for(nh, 1, 65536)), dim3(256), 0, s, row_ptr, col, crank, hubs, nh,
-                     stride, rows);
+                     stride, width, rows);
   return hipGetLastError();
 }
 
