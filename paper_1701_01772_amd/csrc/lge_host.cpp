@@ -485,7 +485,9 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   if ((rc = build_codeg(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
   if ((rc = build_rows(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
-  LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, g->nrows > 0 ? g->hrow : nullptr, n, g->vinfo, s));
+  if ((rc = dev_alloc(&g->vrh, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
+  LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, g->nrows > 0 ? g->hrow : nullptr, n, g->vinfo,
+                       g->vrh, s));
   LGE_HIP(hipStreamSynchronize(s));
   return LGE_OK;
 }
@@ -629,7 +631,7 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   double ops = 0.0;
   for (const auto &c : cand) {
     const double bytes = (double)(hubs.size() + 1) * (double)stride * width;
-    if (ops + (double)vol2[c.second] > budget_ops || bytes > budget_bytes) break;
+    if (ops + (double)vol2[c.second] > budget_ops || bytes > budget_bytes || (int64_t)hubs.size() >= kMaxRows) break;
     ops += (double)vol2[c.second];
     hubs.push_back(c.second);
   }
@@ -677,6 +679,7 @@ static void graph_free(lge_graph *g) {
   dev_free(g->hrow);
   dev_free(g->rows);
   dev_free(g->vinfo);
+  dev_free(g->vrh);
   dev_free(g->t_arc);
   dev_free(g->tri);
   dev_free(g->mred);
@@ -980,6 +983,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.hbits = g->hbits;
     sd.hcw = g->hcw;
     sd.vinfo = g->vinfo;
+    sd.vrh = g->vrh;
     sd.hrow = g->nrows > 0 ? g->hrow : nullptr;
     sd.rows = g->rows;
     sd.rows_stride = g->rows_stride;

@@ -677,12 +677,16 @@ __device__ __forceinline__ uint32_t row_at(const SlotDesc &S, int64_t r, int64_t
   return S.rows_w == 1 ? (uint32_t)S.rows[i] : (uint32_t)reinterpret_cast<const uint16_t *>(S.rows)[i];
 }
 
-// (row start, degree, rank or -1, 0) of every vertex
+// (row start, degree, rank or -1, co-degree row or -1) of every vertex, and
+// the rank and row packed into one word
 __global__ __launch_bounds__(256) void k_vinfo(const int32_t *__restrict__ rp, const int32_t *__restrict__ crank,
                                                const int32_t *__restrict__ hrow, int64_t n,
-                                               int4 *__restrict__ vinfo) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    vinfo[v] = make_int4(rp[v], rp[v + 1] - rp[v], crank ? crank[v] : -1, hrow ? hrow[v] : -1);
+                                               int4 *__restrict__ vinfo, uint32_t *__restrict__ vrh) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = crank ? crank[v] : -1, h = hrow ? hrow[v] : -1;
+    vinfo[v] = make_int4(rp[v], rp[v + 1] - rp[v], r, h);
+    vrh[v] = (uint32_t)(r + 1) | ((uint32_t)(h + 1) << 17);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -1478,35 +1482,35 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       bool valid = i < p1;
       const int32_t x = valid ? col[abeg + i] : -1;
       valid = valid && x != b;
-      int32_t wb = 0, we = 0, rw = -1, hw = -1;
+      int32_t wb = 0, dw = 0, rw = -1, hw = -1;
       bool isT = false;
       if (valid) {
-        const int4 vi = S.vinfo[x];  // row start, degree, rank, co-degree row in one 16-byte read
-        wb = vi.x;
-        we = vi.x + vi.y;
-        rw = hcw ? vi.z : -1;
-        hw = vi.w;
+        const uint32_t rh = S.vrh[x];  // rank and co-degree row in one 4-byte read
+        rw = (int32_t)(rh & 0x1FFFFu) - 1;
+        hw = (int32_t)(rh >> 17) - 1;
         // x in Gamma(a) is in T_e iff in Gamma(b): the classify pass's bit
         isT = ((tmask[item * kMaskWords + ((i - p0) >> 6)] >> ((i - p0) & 63)) & 1ull) != 0;
       }
-      const int dw = we - wb;
       // |Gamma(x) n Gamma(y)|, y = a for T_e members, b otherwise: the table
-      // for ranked pairs, y's co-degree row for unranked x
-      uint32_t cdeg = 0;
-      bool cok = false;
+      // for ranked pairs, y's co-degree row for unranked x, x's own row for
+      // unranked y
+      int tab = 0;
       if (valid && may_look) {
         const int32_t ry = isT ? ra : rb, hr = isT ? hra : hrb;
-        if (rw >= 0 && ry >= 0) {
-          cdeg = S.codeg[(int64_t)ry * S.hc + rw];  // symmetric table: the row of the item's fixed end
-          cok = true;
-        } else if (rw < 0 && hr >= 0) {
-          cdeg = row_at(S, hr, x);  // the fixed end's row at unranked x
-          cok = true;
-        } else if (ry < 0 && hw >= 0) {
-          cdeg = row_at(S, hw, isT ? a : b);  // x's own row at the unranked end
-          cok = true;
-        }
+        tab = (rw >= 0 && ry >= 0) ? 1 : (rw < 0 && hr >= 0) ? 2 : (ry < 0 && hw >= 0) ? 3 : 0;
       }
+      // row start and degree unless x is a tabulated S_a member (no units);
+      // issued together with the co-degree read
+      if (valid && (isT || tab == 0)) {
+        const int4 vi = S.vinfo[x];
+        wb = vi.x;
+        dw = vi.y;
+      }
+      uint32_t cdeg = 0;
+      if (tab == 1) cdeg = S.codeg[(int64_t)(isT ? ra : rb) * S.hc + rw];  // symmetric: the fixed end's row
+      else if (tab == 2) cdeg = row_at(S, isT ? hra : hrb, x);
+      else if (tab == 3) cdeg = row_at(S, hw, isT ? a : b);
+      const bool cok = tab != 0;
       uint8_t fl = 0;
       int32_t units = 0;
       if (valid) {
@@ -2288,9 +2292,9 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 size_t gedge_bytes() { return sizeof(GEdge); }
 
 hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, int64_t n, int4 *vinfo,
-                        hipStream_t s) {
+                        uint32_t *vrh, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, hrow, n, vinfo);
+  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, hrow, n, vinfo, vrh);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ struct lge_graph {
   unsigned long long *hbits = nullptr;  // hc x hcw adjacency bit rows of the ranked vertices
   int64_t hcw = 0;
   int4 *vinfo = nullptr;     // n: (row start, degree, rank or -1, co-degree row or -1)
+  uint32_t *vrh = nullptr;   // n: (rank + 1) | (co-degree row + 1) << 17
   int32_t *hrow = nullptr;   // n: co-degree row index, -1 if none
   uint8_t *rows = nullptr;   // nrows x rows_stride co-degree rows over the unranked vertices
   int64_t nrows = 0, rows_stride = 0;  // rows, entries per row
