@@ -115,7 +115,7 @@ extern "C" int lge_opts_default(lge_opts *o) {
   o->block_max_deg = kHubDeg;
   o->probe_ratio = 4;
   o->grid_per_cu = 0;
-  o->global_chunk = 256;
+  o->global_chunk = kGlobalChunkMax;
   o->flags = LGE_OPT_SORT_HUB | LGE_OPT_XCD_LOCAL;
   return LGE_OK;
 }
@@ -133,7 +133,7 @@ static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
   const int cu = ctx->num_cu > 0 ? ctx->num_cu : 256;
   c.grid_wave = cu * (per_cu ? per_cu : 20);
   c.grid_block = cu * (per_cu ? per_cu : 8);
-  c.grid_global = cu * (per_cu ? per_cu : 8);
+  c.grid_global = cu * (per_cu ? per_cu : 4);  // 512-thread workgroups
   c.grid_sample = cu * 16;
   c.global_chunk = o->global_chunk > 0 ? std::min<int32_t>(o->global_chunk, kGlobalChunkMax) : d.global_chunk;
   c.flags = o->flags;

@@ -1133,7 +1133,8 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
 // t <= kTHashCap (otherwise a's hub table serves).
 // ---------------------------------------------------------------------------
 
-constexpr int kGlobalNT = 256;
+constexpr int kGlobalNT = 512;  // counting kernel: one pass over a work item's positions
+constexpr int kPrepNT = 256;    // classify and bit-set kernels
 constexpr int kTHashCap = 512;
 constexpr int kMaskWords = kGlobalChunkMax / 64;  // T_e membership words per work item
 static_assert(kGlobalChunkMax <= kGlobalNT, "one pass over an item's positions");
@@ -1198,7 +1199,7 @@ __global__ __launch_bounds__(256) void k_item_fill(const int64_t *__restrict__ i
   }
 }
 
-__global__ __launch_bounds__(kGlobalNT) void k_global_classify(
+__global__ __launch_bounds__(kPrepNT) void k_global_classify(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
     const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
@@ -1218,7 +1219,7 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
     const bool hb = has_table(db);
     const int p0 = (int)(c * chunk);
     const int p1 = p0 + chunk < da ? p0 + chunk : da;
-    for (int base = p0; base < p1; base += kGlobalNT) {
+    for (int base = p0; base < p1; base += kPrepNT) {
       const int i = base + (int)threadIdx.x;
       bool isT = false;
       int32_t x = -1;
@@ -1251,14 +1252,14 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_classify(
 // ranks, stored compactly (non-zero words and their indices, in increasing
 // word order) at the edge's T_e offset; one workgroup per edge, once per
 // launch.
-__global__ __launch_bounds__(kGlobalNT) void k_global_tbits(const SlotDesc *__restrict__ slots,
+__global__ __launch_bounds__(kPrepNT) void k_global_tbits(const SlotDesc *__restrict__ slots,
                                                             const int32_t *__restrict__ bslot, int64_t nedges,
                                                             const int64_t *__restrict__ tbase,
                                                             const int32_t *__restrict__ tlist, GEdge *gacc,
                                                             unsigned long long *__restrict__ tbw,
                                                             int16_t *__restrict__ tbi) {
   __shared__ unsigned long long bits[kBitsWords];
-  __shared__ int wcnt[kGlobalNT / kWave];
+  __shared__ int wcnt[kPrepNT / kWave];
   const int lane = threadIdx.x & 63;
   const int wv_id = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -1267,23 +1268,23 @@ __global__ __launch_bounds__(kGlobalNT) void k_global_tbits(const SlotDesc *__re
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;
     const int t = (int)gacc[e].t;
     if (hcw == 0 || t == 0) continue;  // uniform per block; nzw stays 0
-    for (int i = threadIdx.x; i < hcw; i += kGlobalNT) bits[i] = 0ull;
+    for (int i = threadIdx.x; i < hcw; i += kPrepNT) bits[i] = 0ull;
     __syncthreads();
     const int32_t *T = tlist + 3 * tbase[e];
-    for (int i = threadIdx.x; i < t; i += kGlobalNT) {
+    for (int i = threadIdx.x; i < t; i += kPrepNT) {
       const int32_t r = T[3 * i + 2];
       if (r >= 0) atomicOr(&bits[r >> 6], 1ull << (r & 63));
     }
     __syncthreads();
     int cnt = 0;  // non-zero words so far (uniform)
-    for (int i0 = 0; i0 < hcw; i0 += kGlobalNT) {
+    for (int i0 = 0; i0 < hcw; i0 += kPrepNT) {
       const int i = i0 + (int)threadIdx.x;
       const unsigned long long wv = i < hcw ? bits[i] : 0ull;
       const uint64_t m = __ballot(wv != 0ull);
       if (lane == 0) wcnt[wv_id] = __popcll(m);
       __syncthreads();
       int off = cnt, tot = 0;
-      for (int q = 0; q < kGlobalNT / kWave; ++q) {
+      for (int q = 0; q < kPrepNT / kWave; ++q) {
         if (q < wv_id) off += wcnt[q];
         tot += wcnt[q];
       }
@@ -2249,7 +2250,8 @@ hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedg
                                   int32_t *tlist, unsigned long long *tmask, void *gacc, KernelCfg cfg,
                                   hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
+  hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global * (kGlobalNT / kPrepNT)), dim3(kPrepNT), 0, s, slots,
+                     bins.slot[kClassGlobal],
                      bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
                      tlist, tmask, (GEdge *)gacc, cfg.global_chunk);
   return hipGetLastError();
@@ -2272,7 +2274,7 @@ hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, 
 hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *tbase,
                                const int32_t *tlist, unsigned long long *tbw, int16_t *tbi, void *gacc, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_global_tbits, dim3(grid_for(nedges, 1, 8192)), dim3(kGlobalNT), 0, s, slots,
+  hipLaunchKernelGGL(k_global_tbits, dim3(grid_for(nedges, 1, 8192)), dim3(kPrepNT), 0, s, slots,
                      bins.slot[kClassGlobal], nedges, tbase, tlist, (GEdge *)gacc, tbw, tbi);
   return hipGetLastError();
 }
