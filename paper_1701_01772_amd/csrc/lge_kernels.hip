@@ -1641,7 +1641,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     // with degree, so the common high-degree members read few words.  The
     // (member, word) pairs are spread over the whole workgroup.
     __syncthreads();  // wl_pref and wl_beg are reused below
-    {
+    if (sh_cnt[2] > 0 && nzw > 0) {  // uniform: skipped without ranked members in this chunk
       const int nb = sh_cnt[2];
       int32_t *const bk0 = wl_beg;   // first word index of member j
       int32_t *const bpref = wl_pref;  // pairs before member j
