@@ -118,7 +118,7 @@ typedef struct {
  * order-independent); only the speed does.  Zero-initialise and call
  * lge_opts_default(), or pass NULL for defaults.
  *  wave_max_deg   edges whose endpoints both have degree <= this are counted
- *                 by one wavefront with LDS tables (1..512, default 128)
+ *                 by one wavefront with LDS tables (1..512, default 256)
  *  block_max_deg  read-only: edges whose endpoints both have degree <= 1024
  *                 are counted by one 256-thread workgroup with LDS tables;
  *                 others are split across workgroups and use the per-vertex

@@ -111,7 +111,7 @@ extern "C" const char *lge_strerror(int code) {
 extern "C" int lge_opts_default(lge_opts *o) {
   if (!o) return LGE_EINVAL;
   memset(o, 0, sizeof(*o));
-  o->wave_max_deg = 128;
+  o->wave_max_deg = 256;
   o->block_max_deg = kHubDeg;
   o->probe_ratio = 4;
   o->grid_per_cu = 0;

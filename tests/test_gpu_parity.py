@@ -113,6 +113,8 @@ def test_er_config_exact(ctx):
 ])
 def test_all_classes_exact(ctx, maker, name):
     run_pair(ctx, maker(), 1.0, 0, what=name)
+    if name != "two-hub":  # the power-law graphs fill all three classes under the default options
+        assert all(c > 0 for c in lge.lge_last_timing(ctx)["class_edges"]), name
 
 
 @pytest.mark.parametrize("p,seed", [(0.5, 1), (0.1, 2), (0.01, 3), (1e-4, 4)])
