@@ -433,6 +433,9 @@ __global__ __launch_bounds__(256) void k_scan_add(int64_t *out, int64_t len,
 // ---------------------------------------------------------------------------
 
 constexpr int kSamplePer = 4;  // edges per thread per round of the sampling kernel
+// hub edges whose scan side has at most this degree are counted by one
+// wavefront (the wavefront class) instead of a split-class work item
+constexpr int kSmallScan = 64;
 
 __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__ slots,
                                                     const RangeDesc *__restrict__ ranges, int32_t nranges,
@@ -495,12 +498,17 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
           bv[k] = ua ? v : u;
           sl[k] = slot;
           const int32_t dmax = du > dv ? du : dv;
-          const int c = dmax <= cfg.wave_max_deg ? kClassWave : (dmax <= kHubDeg ? kClassBlock : kClassGlobal);
+          const int64_t da = ua ? du : dv, db = ua ? dv : du, wa = ua ? wu : wv;
+          // hub edges go to the split class unless the scan side is small
+          // enough for one wavefront (which then uses b's hub table)
+          const bool small_scan = cfg.probe_ratio > 0 && da <= kSmallScan;
+          const int c = dmax <= cfg.wave_max_deg ? kClassWave
+                        : dmax <= kHubDeg        ? kClassBlock
+                                                 : (small_scan ? kClassWave : kClassGlobal);
           cls[k] = c;
           // bytes the neighbour iteration of Alg. 2-4 reads for this edge:
           // both row_ptr pairs, both rows, and for every w in Gamma(a) \ {b}
           // its row_ptr pair and row
-          const int64_t da = ua ? du : dv, db = ua ? dv : du, wa = ua ? wu : wv;
           const unsigned long long alg = 16ull + 4ull * (unsigned long long)(du + dv) +
                                          8ull * (unsigned long long)(da - 1) + 4ull * (unsigned long long)(wa - db);
 #pragma unroll
@@ -921,16 +929,23 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       const int32_t *__restrict__ col = S.col;
       const int32_t abeg = rp[a], aend = rp[a + 1], bbeg = rp[b], bend = rp[b + 1];
       const int da = aend - abeg, db = bend - bbeg;
-      const int lg = table_log(db);
+      // a hub edge with a small scan side (binned here by the sampling
+      // kernel): Gamma(b) stays in b's hub table and the LDS table holds T_e
+      const bool bhub = db > CAP;
+      const uint32_t *__restrict__ btab = bhub ? S.htab + S.hoff[b] : nullptr;
+      const int blg = bhub ? table_log(db) : 0;
+      const int lg = table_log(bhub ? da : db);
       const int hs = 1 << lg;
       for (int i = tid; i < hs; i += NT) htab[i] = kEmpty;
       if (tid < 4) sh_cnt[tid] = 0;
       __syncthreads();
-      for (int i = tid; i < db; i += NT) {
-        const int32_t x = col[bbeg + i];
-        if (x != a) lds_insert(htab, lg, (uint32_t)x);
+      if (!bhub) {
+        for (int i = tid; i < db; i += NT) {
+          const int32_t x = col[bbeg + i];
+          if (x != a) lds_insert(htab, lg, (uint32_t)x);
+        }
       }
-      if (tid == 0) words += (unsigned long long)(db + 4);  // per-edge terms counted once
+      if (tid == 0) words += (unsigned long long)((bhub ? 0 : db) + 4);  // per-edge terms counted once
       __syncthreads();
       // classify Gamma(a) \ {b}: in the hash -> T_e (tag it), else S_a
       for (int base = 0; base < da; base += NT) {
@@ -939,7 +954,10 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
         const int32_t x = valid ? col[abeg + i] : -1;
         valid = valid && x != b;
         bool isT = false;
-        if (valid) {
+        if (valid && bhub) {
+          isT = table_find(btab, blg, (uint32_t)x) >= 0;
+          if (isT) lds_insert(htab, lg, (uint32_t)x | kTag);
+        } else if (valid) {
           const int sl = table_find(htab, lg, (uint32_t)x);
           if (sl >= 0) {
             isT = true;
@@ -1007,10 +1025,10 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
             units = 0;
             cost = 0;
             cyc_base += (long long)cdeg - 1;
-          } else if ((int64_t)(db - 1) * lk < scan) {
+          } else if ((int64_t)(bhub ? db : db - 1) * lk < scan) {
             fl = kModeLook;
-            units = db - 1;
-            cost = (int64_t)(db - 1) * lk;
+            units = bhub ? db : db - 1;  // a hub's list is read from its row (a skipped)
+            cost = (int64_t)units * lk;
           }
         } else {
           if (lt < scan) {
@@ -1032,7 +1050,8 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       }
       c_plain = block_sum_u64<NT>(c_plain, red);
       c_agg = block_sum_u64<NT>(c_agg, red);
-      const bool agg = may_look && c_agg < c_plain;
+      // a hub edge has no S_b list for the plain scheme
+      const bool agg = may_look && (bhub || c_agg < c_plain);
       if (!agg) {  // plain scheme: S_a members count |Gamma(w) n S_b|, T_e members degT
         cyc_base = 0;
         for (int i = tid; i < L; i += NT) {
@@ -1079,13 +1098,19 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
           const int32_t w = (int32_t)(v & kIdMask);
           if (!isT) {
             if (v & kModeLook) {  // look up Gamma(b) \ {a} (T_e, then S_b) for cbx, else S_b
-              const int32_t x = agg ? (off < t ? tgt[off] : tgt[CAP - sbn + (off - t)]) : tgt[CAP - sbn + off];
-              if (w_has(S, w, wl_beg[lo], wl_deg[lo], x, &steps)) ++cs;
+              const int32_t x = bhub  ? col[bbeg + off]
+                                : agg ? (off < t ? tgt[off] : tgt[CAP - sbn + (off - t)])
+                                      : tgt[CAP - sbn + off];
+              if (x != a && w_has(S, w, wl_beg[lo], wl_deg[lo], x, &steps)) ++cs;
             } else {  // scan: cbx (any hit), or |Gamma(w) n S_b| without the aggregate form
               const int32_t r = col[wl_beg[lo] + off];
               ++steps;
-              const int sl = table_find(htab, lg, (uint32_t)r);
-              if (sl >= 0 && (agg || !(htab[sl] & kTag))) ++cs;
+              if (bhub) {
+                if (r != a && table_find(btab, blg, (uint32_t)r) >= 0) ++cs;
+              } else {
+                const int sl = table_find(htab, lg, (uint32_t)r);
+                if (sl >= 0 && (agg || !(htab[sl] & kTag))) ++cs;
+              }
             }
           } else {
             const bool lt = (v & kModeLook) != 0;
