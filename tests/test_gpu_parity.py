@@ -365,3 +365,22 @@ def test_wide_ranked_t(ctx, k):
             assert_parity(got, oracle.estimate(g.row_ptr, g.col, 1.0, 5, mask=mask), "wide-t k=%d [%d,%d)" % (k, a, b))
     finally:
         lge.lge_graph_destroy(h)
+
+
+def test_bounds_coverage_matches_oracle(ctx):
+    # the statistical pin of the oracle (95 % bounds cover the exact counts
+    # near the nominal rate) holds for the GPU path's bounds, run for run
+    from test_oracle_estimator import COVERAGE_BAND, COVERAGE_SEEDS, coverage_of
+    g = inputs.er_2000()
+    exact = oracle.estimate(g.row_ptr, g.col, 1.0, 0)["exact"]
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        _say("coverage over %d seeds on er(2000, 0.005) at p=0.1" % COVERAGE_SEEDS)
+        runs = [lge.lge_estimate(ctx, h, 0.1, 1000 + s) for s in range(COVERAGE_SEEDS)]
+    finally:
+        lge.lge_graph_destroy(h)
+    for s in (0, COVERAGE_SEEDS // 2, COVERAGE_SEEDS - 1):
+        assert_parity(runs[s], oracle.estimate(g.row_ptr, g.col, 0.1, 1000 + s), "coverage seed %d" % s)
+    cov = coverage_of(runs, exact)
+    for i, c in cov.items():
+        assert COVERAGE_BAND[0] <= c <= COVERAGE_BAND[1], (i, c)

@@ -7,6 +7,11 @@
 * p = 1: estimate == exact, zero variance, collapsed bounds.
 * Philox4x32-10 known-answer vectors (Salmon et al., SC'11) and a
   cross-check against rocRAND's independent Philox4x32-10.
+* Coverage of the 95 % bounds (Sec. 6, the bounds are expected to contain
+  the actual value): over 200 seeds on the Erdos-Renyi n = 2000 workload at
+  p = 0.1 every graphlet with a non-zero count is covered in a share of runs
+  near the nominal 95 % (a soft band: the normal approximation is loose for
+  counts of a few dozen).
 * Planted mistakes (the paper's printed variants and off-by-ones) compiled
   into a copy of the oracle must fail the brute-force pin.
 """
@@ -59,6 +64,29 @@ def test_exact_unbiasedness_by_enumeration(case):
         scale = max(1, abs(exact[i]))
         assert abs(float(mean) - exact[i]) <= 1e-9 * scale, (i, float(mean), exact[i])
         assert abs(float(mean_vhat) - float(var)) <= 1e-9 * max(1.0, float(var)), (i, float(mean_vhat), float(var))
+
+
+COVERAGE_SEEDS = 200
+COVERAGE_BAND = (0.88, 0.99)
+
+
+def coverage_of(estimates, exact):
+    hits = [0] * 18
+    for r in estimates:
+        for i in range(3, 18):
+            if r["lower95"][i] <= exact[i] <= r["upper95"][i]:
+                hits[i] += 1
+    return {i: hits[i] / len(estimates) for i in range(3, 18) if exact[i] > 0}
+
+
+def test_bounds_cover_near_nominal():
+    g = inputs.er_2000()
+    exact = oracle.estimate(g.row_ptr, g.col, 1.0, 0)["exact"]
+    runs = [oracle.estimate(g.row_ptr, g.col, 0.1, 1000 + s) for s in range(COVERAGE_SEEDS)]
+    cov = coverage_of(runs, exact)
+    assert len(cov) >= 12
+    for i, c in cov.items():
+        assert COVERAGE_BAND[0] <= c <= COVERAGE_BAND[1], (i, c)
 
 
 def test_p_one_is_exact():
