@@ -1146,8 +1146,9 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// Global class: edges with an endpoint of degree > kHubDeg.  Work item =
-// (edge, chunk of Gamma(a) positions).  Three kernels:
+// Global class: edges with an endpoint of degree > kHubDeg whose scan side has
+// degree > kSmallScan (the others go to the wavefront kernel).  Work item =
+// (edge, chunk of up to kGlobalChunkMax Gamma(a) positions).  Kernels:
 //   prep     : items and T_e capacity per edge, partial sums cleared
 //   classify : T_e of every edge into a global list (membership in Gamma(b)
 //              by b's hub table or binary search)
@@ -1333,16 +1334,19 @@ __global__ __launch_bounds__(kPrepNT) void k_global_tbits(const SlotDesc *__rest
 //   cyc = sum_{w in S_a} cbx(w) - sum_{x in T_e} cax(x) + sum_{x in T_e} degT(x)
 // (each w in S_a is adjacent to a, and a's other neighbours split into T_e and
 // S_a), and the edges inside T_e number k4 = sum degT / 2.  cbx and cax are
-// pair co-degrees: one table read when both vertices are ranked.  Per vertex
-// the kernel picks the cheapest way to get its terms:
+// pair co-degrees: one read when tabulated (both ranked: the co-degree table;
+// one unranked: the other's co-degree row).  Per vertex the kernel picks the
+// cheapest way to get its terms:
 //   w in S_a : codeg(w,b) - 1 | walk Gamma(w) testing Gamma(b) | look Gamma(b) up in Gamma(w)
-//   x in T_e : degT by walking Gamma(x) against T_e or by looking T_e up in
-//              Gamma(x); cax from the table, or by walking Gamma(x) against
-//              Gamma(a), or by looking Gamma(a) up in Gamma(x)
-// A pair of T_e members that both look up is tested once, by the one of
-// smaller id, with weight 2 (the look-up choice depends only on (d_x, t) so
-// every workgroup agrees on it).  Costs are in quarter units of one
-// coalesced load.
+//   x in T_e : degT from the bit rows (ranked x: its ranked partners above
+//              its rank, weight 2), by walking Gamma(x) against T_e or by
+//              looking T_e up in Gamma(x); cax from the tables, or by walking
+//              Gamma(x) against Gamma(a), or by looking Gamma(a) up in Gamma(x)
+// A pair of unranked T_e members that both look up is tested once, by the one
+// of smaller id, with weight 2, and an unranked member counts a ranked
+// partner with weight 2 (the choices depend only on (d_x, t) and the edge's
+// bit-set size, so every workgroup of the edge agrees on them).  Costs are in
+// quarter units of one coalesced load.
 __device__ __forceinline__ int64_t lookup_cost(int dw) {
   return has_table(dw) ? 16 : 8ll * (ceil_log2((uint32_t)dw + 1u) + 1);
 }
