@@ -191,8 +191,8 @@ LGE_API int lge_validate_csr_host(int64_t n, const int32_t *row_ptr, const int32
  * bit rows of the vertices of degree > 96 (the highest-degree 65536 of them
  * at most, 16 GiB of table, or fewer within an eighth of the free HBM; 16384
  * and 1 GiB with LGE_FLAG_COMPACT), and co-degree rows (one byte per
- * entry, two when an unranked degree exceeds 254)
- * |Gamma(y) n Gamma(w)| over all w for the hubs y of degree > 1024 in
+ * entry, two when an unranked degree exceeds 254) |Gamma(y) n Gamma(w)| over
+ * the unranked w above a small degree floor for the hubs y of degree > 1024 in
  * decreasing degree, within a build-work budget and up to 32 GB
  * of HBM (capped at a quarter of the free HBM; 4 GB with LGE_FLAG_COMPACT).
  * LGE_ERANGE if n >= 2^29 or a per-edge numerator could leave int64 or a sum

@@ -486,9 +486,15 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   if ((rc = build_rows(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->vrh, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
-  LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, g->nrows > 0 ? g->hrow : nullptr, n, g->vinfo,
-                       g->vrh, s));
+  const bool rows = g->nrows > 0;
+  LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, rows ? g->hrow : nullptr,
+                       rows ? g->rcol : nullptr, n, g->vinfo, g->vrh, s));
   LGE_HIP(hipStreamSynchronize(s));
+  // rows and columns now live in the vertex records
+  dev_free(g->hrow);
+  dev_free(g->rcol);
+  g->hrow = nullptr;
+  g->rcol = nullptr;
   return LGE_OK;
 }
 
@@ -599,10 +605,15 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
   return LGE_OK;
 }
 
-// Co-degree rows: for the chosen vertices y, |Gamma(y) n Gamma(w)| for every
-// unranked w (ranked pairs use the co-degree table).  An unranked degree is
-// at most the ranking threshold, so one byte holds the count when that is
-// <= kRowMaxDeg, two bytes otherwise.
+// Co-degree rows: for the chosen ranked hubs y, |Gamma(y) n Gamma(w)| for the
+// unranked w of degree above a floor, each at w's column (its position among
+// those vertices); ranked pairs use the co-degree table.  The floor is the
+// smallest of 0, 1, 2, 4, ..., 64 at which the rows of every hub within the
+// build-work budget fit the byte budget (isolated vertices never need a
+// column; an S_a member of degree at or below it is walked instead).  An
+// unranked degree is at most the ranking threshold, so one byte holds a count
+// when that is <= kRowMaxDeg, two bytes otherwise.  Leaves g->hrow (row of
+// every vertex) and g->rcol (column of every vertex) for the vertex records.
 static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags) {
   g->nrows = 0;
   const int64_t n = g->n;
@@ -618,51 +629,69 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
     return x.first != y.first ? x.first > y.first : x.second < y.second;
   });
   std::vector<int64_t> vol2((size_t)n);
+  std::vector<int32_t> rank((size_t)n);
   hipStream_t s = ctx->stream;
   LGE_HIP(hipMemcpyAsync(vol2.data(), g->vol2, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipMemcpyAsync(rank.data(), g->crank, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   LGE_HIP(hipStreamSynchronize(s));
-  const int64_t stride = (n + 7) & ~(int64_t)7;  // entries; rows of whole 64-bit words for the zero fill
   const bool compact = (flags & LGE_FLAG_COMPACT) != 0;
   const double budget_ops = compact ? kRowBudgetOpsCompact : kRowBudgetOps;
   double budget_bytes = compact ? kRowBudgetBytesCompact : kRowBudgetBytes;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget_bytes = std::min(budget_bytes, 0.25 * (double)free_b);
-  std::vector<int32_t> hubs;
+  std::vector<int32_t> hubs;  // ranked hubs within the build-work budget, largest degree first
   double ops = 0.0;
   for (const auto &c : cand) {
-    const double bytes = (double)(hubs.size() + 1) * (double)stride * width;
-    if (ops + (double)vol2[c.second] > budget_ops || bytes > budget_bytes || (int64_t)hubs.size() >= kMaxRows) break;
+    if (rank[c.second] < 0) continue;
+    if (ops + (double)vol2[c.second] > budget_ops || (int64_t)hubs.size() >= kMaxRows) break;
     ops += (double)vol2[c.second];
     hubs.push_back(c.second);
   }
   if (hubs.empty()) return LGE_OK;
-  const int64_t nh = (int64_t)hubs.size();
-  std::vector<int32_t> hrow((size_t)n, -1);
+  // the column floor, and the columns
+  static const int32_t kFloors[] = {0, 1, 2, 4, 8, 16, 32, 64};
+  int32_t floor_deg = kFloors[7];
+  int64_t ncol = 0;
+  for (int32_t f : kFloors) {
+    int64_t c = 0;
+    for (int64_t v = 0; v < n; ++v) c += (rank[v] < 0 && host_row_ptr[v + 1] - host_row_ptr[v] > f) ? 1 : 0;
+    floor_deg = f;
+    ncol = c;
+    const double bytes = (double)hubs.size() * (double)((c + 7) & ~(int64_t)7) * width;
+    if (bytes <= budget_bytes) break;
+  }
+  const int64_t stride = (ncol + 7) & ~(int64_t)7;  // entries; rows of whole 64-bit words for the zero fill
+  if (stride == 0) return LGE_OK;
+  const int64_t nh = std::min<int64_t>((int64_t)hubs.size(), (int64_t)(budget_bytes / ((double)stride * width)));
+  if (nh <= 0) return LGE_OK;
+  std::vector<int32_t> rcol((size_t)n, -1), hrow((size_t)n, -1);
+  {
+    int32_t c = 0;
+    for (int64_t v = 0; v < n; ++v)
+      if (rank[v] < 0 && host_row_ptr[v + 1] - host_row_ptr[v] > floor_deg) rcol[v] = c++;
+  }
   for (int64_t h = 0; h < nh; ++h) hrow[hubs[h]] = (int32_t)h;
   int32_t *dhubs = nullptr;
   int rc;
   if ((rc = dev_alloc(&dhubs, nh)) != LGE_OK) return rc;
   const int64_t nent = nh * stride * width;  // bytes
-  if ((rc = dev_alloc(&g->hrow, n)) != LGE_OK || (rc = dev_alloc(&g->rows, nent)) != LGE_OK) {
+  if ((rc = dev_alloc(&g->hrow, n)) != LGE_OK || (rc = dev_alloc(&g->rcol, n)) != LGE_OK ||
+      (rc = dev_alloc(&g->rows, nent)) != LGE_OK) {
     dev_free(dhubs);
-    dev_free(g->hrow);
-    dev_free(g->rows);
-    return rc;
+    return rc;  // graph_free releases the partial allocations
   }
   hipError_t e = hipMemcpyAsync(dhubs, hubs.data(), (size_t)nh * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->hrow, hrow.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->rcol, rcol.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_zero_u64((unsigned long long *)g->rows, nent / 8, s);
-  if (e == hipSuccess) e = launch_rows_build(g->row_ptr, g->col, g->crank, dhubs, nh, stride, width, g->rows, s);
+  if (e == hipSuccess) e = launch_rows_build(g->row_ptr, g->col, g->rcol, dhubs, nh, stride, width, g->rows, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dev_free(dhubs);
-  if (e != hipSuccess) {
-    dev_free(g->hrow);
-    dev_free(g->rows);
-    return hip_err(e);
-  }
+  if (e != hipSuccess) return hip_err(e);
   g->nrows = nh;
   g->rows_stride = stride;
   g->rows_w = width;
+  g->rows_floor = floor_deg;
   return LGE_OK;
 }
 
@@ -677,6 +706,7 @@ static void graph_free(lge_graph *g) {
   dev_free(g->codeg);
   dev_free(g->hbits);
   dev_free(g->hrow);
+  dev_free(g->rcol);
   dev_free(g->rows);
   dev_free(g->vinfo);
   dev_free(g->vrh);
@@ -984,7 +1014,6 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.hcw = g->hcw;
     sd.vinfo = g->vinfo;
     sd.vrh = g->vrh;
-    sd.hrow = g->nrows > 0 ? g->hrow : nullptr;
     sd.rows = g->rows;
     sd.rows_stride = g->rows_stride;
     sd.rows_w = g->rows_w;

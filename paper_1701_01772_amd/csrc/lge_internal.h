@@ -31,9 +31,9 @@ constexpr int kMaxRanked = 65536;
 // above kRowMaxDeg (no co-degree with an unranked vertex can exceed it), else
 // two.
 constexpr int kRowMaxDeg = 254;
-// At most this many co-degree rows (a row index fits 15 bits of a vertex's
+// At most this many co-degree rows (a row index fits 14 bits of a vertex's
 // packed rank / row word).
-constexpr int kMaxRows = 32767;
+constexpr int kMaxRows = 16383;
 constexpr int kBitsWords = kMaxRanked / 64;
 // Largest number of Gamma(a) positions handled by one global-class work item.
 constexpr int kGlobalChunkMax = 512;
@@ -53,11 +53,12 @@ struct SlotDesc {
   int64_t hc;               // ranked vertices (0: no table)
   const unsigned long long *hbits;  // hc x hcw bit rows: bit ry of row rx = (x, y) adjacent
   int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
-  const int4 *vinfo;        // n: (row start, degree, rank or -1, co-degree row or -1)
-  const uint32_t *vrh;      // n: (rank + 1) | (co-degree row + 1) << 17 (0: none), the same in 4 bytes
-  const int32_t *hrow;      // n: co-degree row of the vertex, -1 if none (null: no rows)
+  const int4 *vinfo;        // n: (row start, degree, rank or -1, co-degree row (ranked) or row column
+                            //     (unranked), -1 if none)
+  const uint32_t *vrh;      // n: the same in 4 bytes: ranked (rank + 1) | (row + 1) << 17,
+                            //     unranked 1 << 31 | (column + 1)
   const uint8_t *rows;      // rows x rows_stride entries of rows_w bytes: |Gamma(y) n Gamma(w)| at
-                            // [hrow[y]][w], unranked w only
+                            // [row of ranked y][column of unranked w] (both from vinfo)
   int64_t rows_stride;
   int64_t n, m;
   double p;
@@ -152,12 +153,14 @@ hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const 
                               int64_t *cnt, hipStream_t s);
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
                              const int64_t *off, int32_t *list, hipStream_t s);
-// per-vertex (row start, degree, rank or -1, 0) records (crank may be null)
-hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, int64_t n, int4 *vinfo,
-                        uint32_t *vrh, hipStream_t s);
-// co-degree rows of the vertices `hubs` over the unranked vertices, width
-// bytes per entry (rows zeroed by the caller; stride * width a multiple of 4)
-hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,
+// per-vertex records (row start, degree, rank, row or column) and packed rank
+// words (crank, hrow, rcol may be null)
+hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, const int32_t *rcol,
+                        int64_t n, int4 *vinfo, uint32_t *vrh, hipStream_t s);
+// co-degree rows of the vertices `hubs` at the columns rcol of the unranked
+// vertices, width bytes per entry (rows zeroed by the caller; stride * width
+// a multiple of 4)
+hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *rcol, const int32_t *hubs,
                              int64_t nh, int64_t stride, int width, uint8_t *rows, hipStream_t s);
 // adjacency bit rows among the ranked vertices (bits zeroed by the caller)
 hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,

@@ -652,12 +652,13 @@ __global__ __launch_bounds__(256) void k_codeg_mirror(int64_t hc, uint32_t *tab)
   }
 }
 
-// One workgroup per row: for x in Gamma(b), for unranked w in Gamma(x), count
-// w once more (at most w's degree in all, which fits the entry width).  A row
-// belongs to one workgroup, so workgroup-scope atomics on its packed
+// One workgroup per row: for x in Gamma(b), for every w in Gamma(x) with a row
+// column (unranked, degree above the graph's column floor), count w once more
+// at its column (at most w's degree in all, which fits the entry width).  A
+// row belongs to one workgroup, so workgroup-scope atomics on its packed
 // counters suffice.
 __global__ __launch_bounds__(256) void k_rows_build(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                    const int32_t *__restrict__ crank,
+                                                    const int32_t *__restrict__ rcol,
                                                     const int32_t *__restrict__ hubs, int64_t nh, int64_t stride,
                                                     int width, uint8_t *rows) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -667,33 +668,36 @@ __global__ __launch_bounds__(256) void k_rows_build(const int32_t *__restrict__ 
     for (int32_t j = rp[b] + wv; j < rp[b + 1]; j += (int32_t)(blockDim.x >> 6)) {
       const int32_t x = col[j];
       for (int32_t k = rp[x] + lane; k < rp[x + 1]; k += 64) {
-        const int32_t w = col[k];
-        if (crank[w] >= 0) continue;
+        const int32_t c = rcol[col[k]];  // the vertex's row column, -1: ranked or not tabulated
+        if (c < 0) continue;
         if (width == 1)
-          __hip_atomic_fetch_add(row + (w >> 2), 1u << ((w & 3) * 8), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_fetch_add(row + (c >> 2), 1u << ((c & 3) * 8), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
-          __hip_atomic_fetch_add(row + (w >> 1), 1u << ((w & 1) * 16), __ATOMIC_RELAXED,
+          __hip_atomic_fetch_add(row + (c >> 1), 1u << ((c & 1) * 16), __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
   }
 }
 
-// entry x of co-degree row r
+// column c of co-degree row r
 __device__ __forceinline__ uint32_t row_at(const SlotDesc &S, int64_t r, int64_t x) {
   const int64_t i = r * S.rows_stride + x;
   return S.rows_w == 1 ? (uint32_t)S.rows[i] : (uint32_t)reinterpret_cast<const uint16_t *>(S.rows)[i];
 }
 
-// (row start, degree, rank or -1, co-degree row or -1) of every vertex, and
-// the rank and row packed into one word
+// (row start, degree, rank or -1, co-degree row of a ranked vertex or row
+// column of an unranked one, -1 if none) of every vertex, and the rank and
+// row / column packed into one word: ranked (rank + 1) | (row + 1) << 17,
+// unranked 1 << 31 | (column + 1)
 __global__ __launch_bounds__(256) void k_vinfo(const int32_t *__restrict__ rp, const int32_t *__restrict__ crank,
-                                               const int32_t *__restrict__ hrow, int64_t n,
-                                               int4 *__restrict__ vinfo, uint32_t *__restrict__ vrh) {
+                                               const int32_t *__restrict__ hrow, const int32_t *__restrict__ rcol,
+                                               int64_t n, int4 *__restrict__ vinfo, uint32_t *__restrict__ vrh) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = crank ? crank[v] : -1, h = hrow ? hrow[v] : -1;
+    const int32_t r = crank ? crank[v] : -1;
+    const int32_t h = r >= 0 ? (hrow ? hrow[v] : -1) : (rcol ? rcol[v] : -1);
     vinfo[v] = make_int4(rp[v], rp[v + 1] - rp[v], r, h);
-    vrh[v] = (uint32_t)(r + 1) | ((uint32_t)(h + 1) << 17);
+    vrh[v] = r >= 0 ? (uint32_t)(r + 1) | ((uint32_t)(h + 1) << 17) : (0x80000000u | (uint32_t)(h + 1));
   }
 }
 
@@ -715,8 +719,8 @@ __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ 
 }
 
 // |Gamma(x) n Gamma(y)| when tabulated: both ranked (the symmetric table,
-// y's row), or one end unranked and the other with a co-degree row.  vy is
-// y's vertex record.
+// y's row), or one end unranked with a row column and the other ranked with
+// a co-degree row.  vy is y's vertex record.
 __device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t y, int4 vy, uint32_t *val) {
   if (S.hc <= 0) return false;
   const int4 vx = S.vinfo[x];
@@ -724,12 +728,12 @@ __device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t
     *val = S.codeg[(int64_t)vy.z * S.hc + vx.z];
     return true;
   }
-  if (vx.z < 0 && vy.w >= 0) {
-    *val = row_at(S, vy.w, x);
+  if (vx.z < 0 && vx.w >= 0 && vy.z >= 0 && vy.w >= 0) {  // x's column of y's row
+    *val = row_at(S, vy.w, vx.w);
     return true;
   }
-  if (vy.z < 0 && vx.w >= 0) {
-    *val = row_at(S, vx.w, y);
+  if (vy.z < 0 && vy.w >= 0 && vx.z >= 0 && vx.w >= 0) {  // y's column of x's row
+    *val = row_at(S, vx.w, vy.w);
     return true;
   }
   return false;
@@ -1171,7 +1175,7 @@ static_assert(kGlobalChunkMax <= kGlobalNT, "one pass over an item's positions")
 struct GEdge {
   unsigned long long t, k4, cyc, done, nzw;
   int32_t a, b, slot, da, db, abeg, bbeg, ra;  // ra / rb: ranks (-1 when unranked)
-  int32_t rb, hra, hrb, pad;                   // hra / hrb: co-degree rows (-1 when none)
+  int32_t rb, hra, hrb, pad;                   // hra / hrb: co-degree row (ranked) or row column (unranked), -1 none
   int64_t hoffa, hoffb;                        // hub-table offsets (-1 when no table)
   int64_t tbase, ipref, icnt;                  // T_e offset, first work item, work items
 };
@@ -1200,10 +1204,11 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
     G.db = db;
     G.abeg = abeg;
     G.bbeg = bbeg;
-    G.ra = S.hc > 0 ? S.crank[a] : -1;
-    G.rb = S.hc > 0 ? S.crank[b] : -1;
-    G.hra = S.hrow ? S.hrow[a] : -1;
-    G.hrb = S.hrow ? S.hrow[b] : -1;
+    const int4 va = S.vinfo[a], vb = S.vinfo[b];
+    G.ra = va.z;
+    G.rb = vb.z;
+    G.hra = va.w;
+    G.hrb = vb.w;
     G.pad = 0;
     G.hoffa = has_table(da) ? S.hoff[a] : -1;
     G.hoffb = has_table(db) ? S.hoff[b] : -1;
@@ -1515,19 +1520,27 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       int32_t wb = 0, dw = 0, rw = -1, hw = -1;
       bool isT = false;
       if (valid) {
-        const uint32_t rh = S.vrh[x];  // rank and co-degree row in one 4-byte read
-        rw = (int32_t)(rh & 0x1FFFFu) - 1;
-        hw = (int32_t)(rh >> 17) - 1;
+        // rank and co-degree row (ranked) or row column (unranked) in one 4-byte read
+        const uint32_t rh = S.vrh[x];
+        if (rh >> 31) {
+          hw = (int32_t)(rh & 0x7FFFFFFFu) - 1;
+        } else {
+          rw = (int32_t)(rh & 0x1FFFFu) - 1;
+          hw = (int32_t)(rh >> 17) - 1;
+        }
         // x in Gamma(a) is in T_e iff in Gamma(b): the classify pass's bit
         isT = ((tmask[item * kMaskWords + ((i - p0) >> 6)] >> ((i - p0) & 63)) & 1ull) != 0;
       }
       // |Gamma(x) n Gamma(y)|, y = a for T_e members, b otherwise: the table
-      // for ranked pairs, y's co-degree row for unranked x, x's own row for
-      // unranked y
+      // for ranked pairs; a ranked end's co-degree row at the unranked end's
+      // column
       int tab = 0;
-      if (valid && may_look) {
-        const int32_t ry = isT ? ra : rb, hr = isT ? hra : hrb;
-        tab = (rw >= 0 && ry >= 0) ? 1 : (rw < 0 && hr >= 0) ? 2 : (ry < 0 && hw >= 0) ? 3 : 0;
+      const int32_t ry = isT ? ra : rb, hy = isT ? hra : hrb;
+      if (valid && may_look && hcw) {
+        tab = (rw >= 0 && ry >= 0)                         ? 1
+              : (rw < 0 && hw >= 0 && ry >= 0 && hy >= 0) ? 2
+              : (ry < 0 && hy >= 0 && rw >= 0 && hw >= 0) ? 3
+                                                          : 0;
       }
       // row start and degree unless x is a tabulated S_a member (no units);
       // issued together with the co-degree read
@@ -1537,9 +1550,9 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         dw = vi.y;
       }
       uint32_t cdeg = 0;
-      if (tab == 1) cdeg = S.codeg[(int64_t)(isT ? ra : rb) * S.hc + rw];  // symmetric: the fixed end's row
-      else if (tab == 2) cdeg = row_at(S, isT ? hra : hrb, x);
-      else if (tab == 3) cdeg = row_at(S, hw, isT ? a : b);
+      if (tab == 1) cdeg = S.codeg[(int64_t)ry * S.hc + rw];  // symmetric: the fixed end's row
+      else if (tab == 2) cdeg = row_at(S, hy, hw);
+      else if (tab == 3) cdeg = row_at(S, hw, hy);
       const bool cok = tab != 0;
       uint8_t fl = 0;
       int32_t units = 0;
@@ -2322,17 +2335,18 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 
 size_t gedge_bytes() { return sizeof(GEdge); }
 
-hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, int64_t n, int4 *vinfo,
-                        uint32_t *vrh, hipStream_t s) {
+hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, const int32_t *rcol,
+                        int64_t n, int4 *vinfo, uint32_t *vrh, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, hrow, n, vinfo, vrh);
+  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, hrow, rcol, n, vinfo,
+                     vrh);
   return hipGetLastError();
 }
 
-hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, const int32_t *hubs,
+hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *rcol, const int32_t *hubs,
                              int64_t nh, int64_t stride, int width, uint8_t *rows, hipStream_t s) {
   if (nh <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_build, dim3(grid_for(nh, 1, 65536)), dim3(256), 0, s, row_ptr, col, crank, hubs, nh,
+  hipLaunchKernelGGL(k_rows_build, dim3(grid_for(nh, 1, 65536)), dim3(256), 0, s, row_ptr, col, rcol, hubs, nh,
                      stride, width, rows);
   return hipGetLastError();
 }

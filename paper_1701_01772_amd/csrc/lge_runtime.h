@@ -33,10 +33,12 @@ struct lge_graph {
   int64_t hcw = 0;
   int4 *vinfo = nullptr;     // n: (row start, degree, rank or -1, co-degree row or -1)
   uint32_t *vrh = nullptr;   // n: (rank + 1) | (co-degree row + 1) << 17
-  int32_t *hrow = nullptr;   // n: co-degree row index, -1 if none
+  int32_t *hrow = nullptr;   // n: co-degree row index, -1 if none (graph creation only)
+  int32_t *rcol = nullptr;   // n: column in the co-degree rows, -1 if none (graph creation only)
   uint8_t *rows = nullptr;   // nrows x rows_stride co-degree rows over the unranked vertices
-  int64_t nrows = 0, rows_stride = 0;  // rows, entries per row
+  int64_t nrows = 0, rows_stride = 0;  // rows, columns per row
   int32_t rows_w = 0;                 // bytes per entry (1 or 2)
+  int32_t rows_floor = 0;             // unranked vertices above this degree have a column
   int32_t codeg_tau = 0;
   double work_per_id = 0.0;  // scheduling weight per canonical edge id
   // micro statistics, built on first use: t of every arc, triangles per
