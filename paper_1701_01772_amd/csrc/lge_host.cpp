@@ -39,7 +39,7 @@ constexpr int32_t kRowDeg = 1024;
 // co-degree rows: build work (sum of 2-hop volumes) and HBM per graph; the
 // byte budget is also capped at a quarter of the free HBM at creation.
 // LGE_FLAG_COMPACT keeps the small budget for callers holding many graphs.
-constexpr double kRowBudgetOps = 1.2e11;
+constexpr double kRowBudgetOps = 1.5e11;
 constexpr double kRowBudgetBytes = 32e9;
 constexpr double kRowBudgetOpsCompact = 4e9;
 constexpr double kRowBudgetBytesCompact = 4e9;
