@@ -433,8 +433,9 @@ __global__ __launch_bounds__(256) void k_scan_add(int64_t *out, int64_t len,
 // ---------------------------------------------------------------------------
 
 constexpr int kSamplePer = 4;  // edges per thread per round of the sampling kernel
-// hub edges whose scan side has at most this degree are counted by one
-// wavefront (the wavefront class) instead of a split-class work item
+// edges whose scan side has at most this degree (and whose other end owns a
+// hub table) are counted by one wavefront (the wavefront class) instead of a
+// workgroup or a split-class work item
 constexpr int kSmallScan = 64;
 
 __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__ slots,
@@ -499,12 +500,12 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
           sl[k] = slot;
           const int32_t dmax = du > dv ? du : dv;
           const int64_t da = ua ? du : dv, db = ua ? dv : du, wa = ua ? wu : wv;
-          // hub edges go to the split class unless the scan side is small
-          // enough for one wavefront (which then uses b's hub table)
-          const bool small_scan = cfg.probe_ratio > 0 && da <= kSmallScan;
-          const int c = dmax <= cfg.wave_max_deg ? kClassWave
-                        : dmax <= kHubDeg        ? kClassBlock
-                                                 : (small_scan ? kClassWave : kClassGlobal);
+          // an edge with a small scan side and b owning a hub table is
+          // counted by one wavefront (using b's hub table) whatever b's degree
+          const bool small_scan = cfg.probe_ratio > 0 && da <= kSmallScan && db > kTableDeg;
+          const int c = (dmax <= cfg.wave_max_deg || small_scan) ? kClassWave
+                        : dmax <= kHubDeg                         ? kClassBlock
+                                                                  : kClassGlobal;
           cls[k] = c;
           // bytes the neighbour iteration of Alg. 2-4 reads for this edge:
           // both row_ptr pairs, both rows, and for every w in Gamma(a) \ {b}
@@ -933,8 +934,8 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
       const int32_t *__restrict__ col = S.col;
       const int32_t abeg = rp[a], aend = rp[a + 1], bbeg = rp[b], bend = rp[b + 1];
       const int da = aend - abeg, db = bend - bbeg;
-      // a hub edge with a small scan side (binned here by the sampling
-      // kernel): Gamma(b) stays in b's hub table and the LDS table holds T_e
+      // an edge with a small scan side and a large b (binned here by the
+      // sampling kernel): Gamma(b) stays in b's hub table, the LDS table holds T_e
       const bool bhub = db > CAP;
       const uint32_t *__restrict__ btab = bhub ? S.htab + S.hoff[b] : nullptr;
       const int blg = bhub ? table_log(db) : 0;
