@@ -122,7 +122,7 @@ typedef struct {
  *  block_max_deg  read-only: edges whose endpoints both have degree <= 1024
  *                 are counted by one 256-thread workgroup with LDS tables;
  *                 others are split across workgroups and use the per-vertex
- *                 global hash tables kept for every vertex of degree > 256
+ *                 global hash tables kept for every vertex of degree > 32
  *  probe_ratio    per neighbour w, look the target set up inside Gamma(w)
  *                 (binary search or w's table) instead of scanning Gamma(w)
  *                 when |target| * lookup_cost(d_w) * probe_ratio < d_w
@@ -187,7 +187,7 @@ LGE_API int lge_validate_csr_host(int64_t n, const int32_t *row_ptr, const int32
  * Graph from host arrays (copied into HBM; the caller keeps its arrays).
  * Validates on the GPU unless LGE_FLAG_TRUSTED.  Preprocesses once: the
  * canonical edge list and per-vertex 2-hop volumes used for scheduling, hash
- * tables of the vertices of degree > 256, the co-degree table and adjacency
+ * tables of the vertices of degree > 32, the co-degree table and adjacency
  * bit rows of the vertices of degree > 96 (the highest-degree 65536 of them
  * at most, 16 GiB of table, or fewer within an eighth of the free HBM; 16384
  * and 1 GiB with LGE_FLAG_COMPACT), and co-degree rows (one byte per

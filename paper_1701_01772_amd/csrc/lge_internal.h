@@ -21,8 +21,11 @@ constexpr int kAccSlots = 32;  // padded; one slot = 32 x (lo, hi) u64 = 512 B
 // Edges whose endpoints both have degree <= kHubDeg are counted from LDS
 // tables by one workgroup; the others are split across workgroups.
 constexpr int kHubDeg = 1024;
-// Vertices of degree > kTableDeg get a global hash table of their neighbours
+// Vertices of degree > kHashDeg get a global hash table of their neighbours
 // ("hub table"): O(1) membership tests instead of binary searches.
+constexpr int kHashDeg = 32;
+// The split kernel copies an endpoint's neighbours into an LDS table when its
+// degree is <= kTableDeg and probes the endpoint's hub table otherwise.
 constexpr int kTableDeg = 256;
 // Ranked (co-degree table) vertices at most, and the 64-bit words of one
 // adjacency bit row over them.

@@ -47,7 +47,7 @@ __device__ __forceinline__ int table_log(int len) {
 
 // whether a vertex of degree d owns a global hub table (the single rule used
 // by the table sizing, the table build and every lookup)
-__device__ __forceinline__ bool has_table(int d) { return d > kTableDeg; }
+__device__ __forceinline__ bool has_table(int d) { return d > kHashDeg; }
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t x, int logsz) {
   return (x * 2654435761u) >> (32 - logsz);
@@ -1211,8 +1211,9 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
     G.hra = va.w;
     G.hrb = vb.w;
     G.pad = 0;
-    G.hoffa = has_table(da) ? S.hoff[a] : -1;
-    G.hoffb = has_table(db) ? S.hoff[b] : -1;
+    // hub-table offsets of the sides too large for the LDS tables
+    G.hoffa = da > kTableDeg ? S.hoff[a] : -1;
+    G.hoffb = db > kTableDeg ? S.hoff[b] : -1;
   }
 }
 
