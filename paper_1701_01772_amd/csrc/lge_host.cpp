@@ -485,10 +485,11 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   if ((rc = build_codeg(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
   if ((rc = build_rows(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
-  if ((rc = dev_alloc(&g->vrh, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&g->arh, std::max<int64_t>(2 * g->m, 1))) != LGE_OK) return rc;
   const bool rows = g->nrows > 0;
   LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, rows ? g->hrow : nullptr,
-                       rows ? g->rcol : nullptr, n, g->vinfo, g->vrh, s));
+                       rows ? g->rcol : nullptr, n, g->vinfo, s));
+  LGE_HIP(launch_arc_rank(g->col, g->vinfo, 2 * g->m, g->arh, s));
   LGE_HIP(hipStreamSynchronize(s));
   // rows and columns now live in the vertex records
   dev_free(g->hrow);
@@ -709,7 +710,7 @@ static void graph_free(lge_graph *g) {
   dev_free(g->rcol);
   dev_free(g->rows);
   dev_free(g->vinfo);
-  dev_free(g->vrh);
+  dev_free(g->arh);
   dev_free(g->t_arc);
   dev_free(g->tri);
   dev_free(g->mred);
@@ -1013,7 +1014,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.hbits = g->hbits;
     sd.hcw = g->hcw;
     sd.vinfo = g->vinfo;
-    sd.vrh = g->vrh;
+    sd.arh = g->arh;
     sd.rows = g->rows;
     sd.rows_stride = g->rows_stride;
     sd.rows_w = g->rows_w;

@@ -58,8 +58,8 @@ struct SlotDesc {
   int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
   const int4 *vinfo;        // n: (row start, degree, rank or -1, co-degree row (ranked) or row column
                             //     (unranked), -1 if none)
-  const uint32_t *vrh;      // n: the same in 4 bytes: ranked (rank + 1) | (row + 1) << 17,
-                            //     unranked 1 << 31 | (column + 1)
+  const uint32_t *arh;      // 2m, beside col: rank and row / column of the arc's head in 4 bytes,
+                            //     ranked (rank + 1) | (row + 1) << 17, unranked 1 << 31 | (column + 1)
   const uint8_t *rows;      // rows x rows_stride entries of rows_w bytes: |Gamma(y) n Gamma(w)| at
                             // [row of ranked y][column of unranked w] (both from vinfo)
   int64_t rows_stride;
@@ -156,10 +156,12 @@ hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const 
                               int64_t *cnt, hipStream_t s);
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
                              const int64_t *off, int32_t *list, hipStream_t s);
-// per-vertex records (row start, degree, rank, row or column) and packed rank
-// words (crank, hrow, rcol may be null)
+// per-vertex records (row start, degree, rank, row or column); crank, hrow,
+// rcol may be null
 hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, const int32_t *rcol,
-                        int64_t n, int4 *vinfo, uint32_t *vrh, hipStream_t s);
+                        int64_t n, int4 *vinfo, hipStream_t s);
+// packed rank words of every arc's head (after the vertex records)
+hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, uint32_t *arh, hipStream_t s);
 // co-degree rows of the vertices `hubs` at the columns rcol of the unranked
 // vertices, width bytes per entry (rows zeroed by the caller; stride * width
 // a multiple of 4)

@@ -688,17 +688,25 @@ __device__ __forceinline__ uint32_t row_at(const SlotDesc &S, int64_t r, int64_t
 }
 
 // (row start, degree, rank or -1, co-degree row of a ranked vertex or row
-// column of an unranked one, -1 if none) of every vertex, and the rank and
-// row / column packed into one word: ranked (rank + 1) | (row + 1) << 17,
-// unranked 1 << 31 | (column + 1)
+// column of an unranked one, -1 if none) of every vertex
 __global__ __launch_bounds__(256) void k_vinfo(const int32_t *__restrict__ rp, const int32_t *__restrict__ crank,
                                                const int32_t *__restrict__ hrow, const int32_t *__restrict__ rcol,
-                                               int64_t n, int4 *__restrict__ vinfo, uint32_t *__restrict__ vrh) {
+                                               int64_t n, int4 *__restrict__ vinfo) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = crank ? crank[v] : -1;
     const int32_t h = r >= 0 ? (hrow ? hrow[v] : -1) : (rcol ? rcol[v] : -1);
     vinfo[v] = make_int4(rp[v], rp[v + 1] - rp[v], r, h);
-    vrh[v] = r >= 0 ? (uint32_t)(r + 1) | ((uint32_t)(h + 1) << 17) : (0x80000000u | (uint32_t)(h + 1));
+  }
+}
+
+// the rank and row / column of every arc's head, packed into one word and
+// stored beside the adjacency lists (read with them, coalesced): ranked
+// (rank + 1) | (row + 1) << 17, unranked 1 << 31 | (column + 1)
+__global__ __launch_bounds__(256) void k_arc_rank(const int32_t *__restrict__ col, const int4 *__restrict__ vinfo,
+                                                  int64_t nnz, uint32_t *__restrict__ arh) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * blockDim.x) {
+    const int4 v = vinfo[col[j]];
+    arh[j] = v.z >= 0 ? (uint32_t)(v.z + 1) | ((uint32_t)(v.w + 1) << 17) : (0x80000000u | (uint32_t)(v.w + 1));
   }
 }
 
@@ -1522,8 +1530,9 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       int32_t wb = 0, dw = 0, rw = -1, hw = -1;
       bool isT = false;
       if (valid) {
-        // rank and co-degree row (ranked) or row column (unranked) in one 4-byte read
-        const uint32_t rh = S.vrh[x];
+        // rank and co-degree row (ranked) or row column (unranked): the arc's
+        // packed word, read coalesced beside Gamma(a)
+        const uint32_t rh = S.arh[abeg + i];
         if (rh >> 31) {
           hw = (int32_t)(rh & 0x7FFFFFFFu) - 1;
         } else {
@@ -2338,10 +2347,15 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges,
 size_t gedge_bytes() { return sizeof(GEdge); }
 
 hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, const int32_t *rcol,
-                        int64_t n, int4 *vinfo, uint32_t *vrh, hipStream_t s) {
+                        int64_t n, int4 *vinfo, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, hrow, rcol, n, vinfo,
-                     vrh);
+  hipLaunchKernelGGL(k_vinfo, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, row_ptr, crank, hrow, rcol, n, vinfo);
+  return hipGetLastError();
+}
+
+hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, uint32_t *arh, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_arc_rank, dim3(grid_for(nnz, 256, 16384)), dim3(256), 0, s, col, vinfo, nnz, arh);
   return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ struct lge_graph {
   unsigned long long *hbits = nullptr;  // hc x hcw adjacency bit rows of the ranked vertices
   int64_t hcw = 0;
   int4 *vinfo = nullptr;     // n: (row start, degree, rank or -1, co-degree row or -1)
-  uint32_t *vrh = nullptr;   // n: (rank + 1) | (co-degree row + 1) << 17
+  uint32_t *arh = nullptr;   // 2m: packed rank word of every arc's head
   int32_t *hrow = nullptr;   // n: co-degree row index, -1 if none (graph creation only)
   int32_t *rcol = nullptr;   // n: column in the co-degree rows, -1 if none (graph creation only)
   uint8_t *rows = nullptr;   // nrows x rows_stride co-degree rows over the unranked vertices
