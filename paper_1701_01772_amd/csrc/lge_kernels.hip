@@ -1553,9 +1553,10 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
               : (ry < 0 && hy >= 0 && rw >= 0 && hw >= 0) ? 3
                                                           : 0;
       }
-      // row start and degree unless x is a tabulated S_a member (no units);
-      // issued together with the co-degree read
-      if (valid && (isT || tab == 0)) {
+      // row start and degree unless x has no units: a tabulated S_a member,
+      // or a tabulated T_e member whose degT comes from the bit rows; issued
+      // together with the co-degree read
+      if (valid && (tab == 0 || (isT && !(ubits && rw >= 0)))) {
         const int4 vi = S.vinfo[x];
         wb = vi.x;
         dw = vi.y;
