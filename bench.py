@@ -444,8 +444,8 @@ def main():
                     help="also run a plain 1 GiB device copy (known bytes) to scale memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: every box here has one MI355X; the path shards by "
-              "canonical edge-id ranges (lge_estimate_range) but no multi-GPU run is part of this build",
+        print("bench.py runs on one GPU only (--gpus 1): the estimate shards by canonical edge-id "
+              "ranges (lge_estimate_range), but no multi-GPU launcher is implemented",
               file=sys.stderr)
         sys.exit(2)
 
