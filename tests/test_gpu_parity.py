@@ -384,3 +384,16 @@ def test_bounds_coverage_matches_oracle(ctx):
     cov = coverage_of(runs, exact)
     for i, c in cov.items():
         assert COVERAGE_BAND[0] <= c <= COVERAGE_BAND[1], (i, c)
+
+
+def test_single_hub_without_co_degree_table(ctx):
+    # one vertex above degree 96 (so no co-degree table, no ranks, no rows):
+    # a hub of degree 3001, its leaves on a ring, and a vertex of degree 80
+    # adjacent to the hub and 79 leaves, whose edge to the hub is a split-class
+    # work item; the hub's other edges go to the wavefront kernel via its table
+    k = 3000
+    e = [(0, i) for i in range(1, k + 1)] + [(i, i % k + 1) for i in range(1, k + 1)]
+    e += [(0, k + 1)] + [(k + 1, i) for i in range(1, 80)]
+    g = inputs.from_edges(k + 2, np.array(e, dtype=np.int32))
+    for p, seed in ((1.0, 0), (0.3, 12)):
+        run_pair(ctx, g, p, seed, what="single hub p=%g" % p)
