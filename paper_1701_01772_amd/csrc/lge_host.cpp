@@ -1088,8 +1088,8 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
                                    w.gacc, cfg, s));
     LGE_HIP(launch_global_tbits(w.slots, bins, ng, w.tbase, w.tlist, w.tbw, w.tbi, w.gacc, s));
     LGE_HIP(hipEventRecord(ev[6], s));
-    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.tbw,
-                                w.tbi, w.tmask, w.gacc, cfg, s));
+    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tlist, w.tbw, w.tbi,
+                                w.tmask, w.gacc, cfg, s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
   LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)nslots * kAccSlots * 2 * sizeof(unsigned long long),

@@ -730,7 +730,7 @@ __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ 
 // |Gamma(x) n Gamma(y)| when tabulated: both ranked (the symmetric table,
 // y's row), or one end unranked with a row column and the other ranked with
 // a co-degree row.  vy is y's vertex record.
-__device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int32_t y, int4 vy, uint32_t *val) {
+__device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int4 vy, uint32_t *val) {
   if (S.hc <= 0) return false;
   const int4 vx = S.vinfo[x];
   if (vx.z >= 0 && vy.z >= 0) {
@@ -873,7 +873,7 @@ struct SlotAcc {
 //              Gamma(a)\{b} up in Gamma(x)                       units = d_a - 1
 // With probe_ratio <= 0 every w scans Gamma(w) (neighbour iteration,
 // Alg. 3/4): S_a members count their neighbours in S_b, T_e members theirs
-// in T_e.  "Look up x in Gamma(w)" uses w's hub table when d_w > kTableDeg,
+// in T_e.  "Look up x in Gamma(w)" uses w's hub table when d_w > kHashDeg,
 // else a binary search of the sorted list.  Costs are in quarter units: a
 // scanned entry costs 8 (a coalesced load and a table probe), a look-up
 // 4*(2 + probe cost) scaled by probe_ratio / 4.
@@ -1028,7 +1028,7 @@ __global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ s
         c_plain += (unsigned long long)(isT ? (lt < scan ? lt : scan)
                                              : ((int64_t)sbn * lk < scan ? (int64_t)sbn * lk : scan));
         uint32_t cdeg = 0;
-        const bool cok = codeg_pair(S, w, isT ? a : b, isT ? va : vb, &cdeg);
+        const bool cok = codeg_pair(S, w, isT ? va : vb, &cdeg);
         uint32_t fl = 0;
         int32_t units = dw;
         int64_t cost = scan;
@@ -1380,10 +1380,8 @@ constexpr uint32_t kRTag = 0x40000000u;  // T_e hash key tag: member is ranked
 constexpr int kBitsLds = 512;            // words of an edge's ranked-member set held in LDS
 
 __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_global(
-    const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
-    const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
-    const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
-    const int32_t *__restrict__ tlist, const unsigned long long *__restrict__ tbw, const int16_t *__restrict__ tbi,
+    const SlotDesc *__restrict__ slots, int64_t nedges, const int64_t *__restrict__ item_pref,
+    const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int32_t *__restrict__ tlist, const unsigned long long *__restrict__ tbw, const int16_t *__restrict__ tbi,
     const unsigned long long *__restrict__ tmask, GEdge *gacc,
     unsigned long long *cursor, unsigned long long *xcd_cursor, unsigned long long *words_out, int32_t probe_ratio,
     int32_t chunk, uint32_t flags) {
@@ -1453,7 +1451,6 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     const int64_t c = item - G.ipref;
     const int t = (int)G.t;
     const SlotDesc &S = slots[slot];
-    const int32_t *__restrict__ rp = S.row_ptr;
     const int32_t *__restrict__ col = S.col;
     const bool ha = hoffa >= 0, hb = hoffb >= 0;
     static_assert(2 * kTableDeg <= (1 << 9), "LDS tables of the split kernel hold degree <= kTableDeg");
@@ -2334,14 +2331,12 @@ hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges,
 }
 
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
-                               const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
-                               const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi,
+                               const int64_t *item_cnt, const int32_t *item_edge, const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi,
                                const unsigned long long *tmask, void *gacc, KernelCfg cfg, hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins.slot[kClassGlobal],
-                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
-                     tlist, tbw, tbi, tmask, (GEdge *)gacc, bins.cursor + kClassGlobal, bins.xcd_cursor, bins.words + kClassGlobal,
-                     cfg.probe_ratio, cfg.global_chunk, cfg.flags);
+  hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, nedges, item_pref,
+                     item_cnt, item_edge, tlist, tbw, tbi, tmask, (GEdge *)gacc, bins.cursor + kClassGlobal,
+                     bins.xcd_cursor, bins.words + kClassGlobal, cfg.probe_ratio, cfg.global_chunk, cfg.flags);
   return hipGetLastError();
 }
 
