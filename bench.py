@@ -71,10 +71,41 @@ def cpu_baseline(g, p, seed, target_s=15.0):
         if dt >= target_s * 0.5 or stride == 1:
             break
         stride = max(1, int(stride * dt / target_s))
-    return {"value": r["sampled"] / dt, "unit": "sampled edges/s", "cores": 1, "kind": "oracle",
-            "sample": "every %d-th of the %d Philox-sampled edges (%d edges, %.1f s)" % (
-                stride, sampled_ids.size, r["sampled"], dt),
-            "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
+    out = {"value": r["sampled"] / dt, "unit": "sampled edges/s", "cores": 1, "kind": "oracle",
+           "sample": "every %d-th of the %d Philox-sampled edges (%d edges, %.1f s)" % (
+               stride, sampled_ids.size, r["sampled"], dt),
+           "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
+    out["all_cores"] = cpu_baseline_threads(g, p, seed, sub, r)
+    return out
+
+
+def cpu_baseline_threads(g, p, seed, sub, whole):
+    """The same oracle call on the same sample, split round-robin over one
+    thread per usable host core (the C oracle is reentrant and ctypes drops
+    the GIL during the call).  The per-thread integer sums must add up to the
+    single-thread ones exactly, since the sums are order-independent."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    threads = max(1, min(threads, 16, sub.size))
+    masks = []
+    for i in range(threads):
+        mk = np.zeros(g.m, dtype=np.uint8)
+        mk[sub[i::threads]] = 1
+        masks.append(mk)
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        t0 = time.perf_counter()
+        parts = list(pool.map(lambda mk: oracle.estimate(g.row_ptr, g.col, p, seed, mask=mk), masks))
+        dt = time.perf_counter() - t0
+    sampled = sum(x["sampled"] for x in parts)
+    same = sampled == whole["sampled"] and all(
+        sum(x[k][i] for x in parts) == whole[k][i] for k in ("csum", "qsum") for i in range(18))
+    return {"value": sampled / dt, "unit": "sampled edges/s", "cores": threads,
+            "seconds": round(dt, 3), "sums_match_single_thread": bool(same)}
 
 
 def host_cpu_model():
