@@ -131,7 +131,7 @@ static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
   c.probe_ratio = o->probe_ratio >= 0 ? o->probe_ratio : d.probe_ratio;
   const int per_cu = o->grid_per_cu > 0 ? o->grid_per_cu : 0;
   const int cu = ctx->num_cu > 0 ? ctx->num_cu : 256;
-  c.grid_wave = cu * (per_cu ? per_cu : 20);
+  c.grid_wave = cu * (per_cu ? per_cu : 24);
   c.grid_block = cu * (per_cu ? per_cu : 8);
   c.grid_global = cu * (per_cu ? per_cu : 4);  // 512-thread workgroups
   c.grid_sample = cu * 16;

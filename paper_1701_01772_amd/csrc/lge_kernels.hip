@@ -904,7 +904,7 @@ __device__ __forceinline__ bool w_has(const SlotDesc &S, int32_t w, int32_t wbeg
 // ---------------------------------------------------------------------------
 
 template <int NT, int CAP>
-__global__ __launch_bounds__(NT) void k_count_lds(const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_count_lds(const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot,
                                                   const int32_t *__restrict__ ba, const int32_t *__restrict__ bb,
                                                   int64_t nedges, unsigned long long *cursor,
                                                   unsigned long long *words_out, int32_t probe_ratio, int32_t chunk) {
@@ -1244,11 +1244,21 @@ __global__ __launch_bounds__(kPrepNT) void k_global_classify(
     const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
     const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
     const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
-    int32_t *tlist, unsigned long long *__restrict__ tmask, GEdge *gacc, int32_t chunk) {
+    int32_t *tlist, unsigned long long *__restrict__ tmask, GEdge *gacc, int32_t chunk, int32_t xcd_local) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
-  for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
+  // XCD-local mapping: the workgroups of XCD x = blockIdx % kXcds take
+  // segment x of the items, so the items of one table-side endpoint b
+  // (adjacent after the hub ordering) probe b's hub table through one L2
+  int64_t first = blockIdx.x, hi = total_items, stride = gridDim.x;
+  if (xcd_local && gridDim.x % kXcds == 0) {
+    const int64_t sg = blockIdx.x % kXcds;
+    first = total_items * sg / kXcds + blockIdx.x / kXcds;
+    hi = total_items * (sg + 1) / kXcds;
+    stride = gridDim.x / kXcds;
+  }
+  for (int64_t item = first; item < hi; item += stride) {
     const int64_t e = item_edge[item];
     const int64_t c = item - item_pref[e];
     const SlotDesc &S = slots[bslot[e]];
@@ -2304,7 +2314,7 @@ hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedg
   hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global * (kGlobalNT / kPrepNT)), dim3(kPrepNT), 0, s, slots,
                      bins.slot[kClassGlobal],
                      bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
-                     tlist, tmask, (GEdge *)gacc, cfg.global_chunk);
+                     tlist, tmask, (GEdge *)gacc, cfg.global_chunk, (cfg.flags & kOptXcdLocal) ? 1 : 0);
   return hipGetLastError();
 }
 
