@@ -1387,7 +1387,7 @@ constexpr uint8_t kFCodeg = 4;   // co-degree from the table
 constexpr uint8_t kFLookB = 8;   // w in S_a: cbx by look-ups of Gamma(b)
 constexpr uint8_t kFBits = 16;   // ranked w in T_e: degT over ranked members from bit rows
 constexpr uint32_t kRTag = 0x40000000u;  // T_e hash key tag: member is ranked
-constexpr int kBitsLds = 512;            // words of an edge's ranked-member set held in LDS
+constexpr int kBitsLds = kBitsWords;  // words of an edge's ranked-member set held in LDS (all of them)
 
 __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_global(
     const SlotDesc *__restrict__ slots, int64_t nedges, const int64_t *__restrict__ item_pref,
@@ -1471,8 +1471,10 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     const bool tl = t <= kTHashCap;
     const int tlg = table_log(t);
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;  // 0: no ranked vertices, no bit rows
-    // the bit rows serve edges whose ranked-member set fits its LDS copy; on
-    // the others every member of T_e is treated as unranked in the T_e terms
+    // the LDS copy holds the largest possible ranked-member set (nzw <= hcw
+    // <= kBitsWords), so every edge of a graph with ranked vertices uses the
+    // bit rows; the size test only guards the LDS array
+    static_assert(kBitsLds >= kBitsWords, "the LDS bit set holds every possible ranked-member set");
     const bool ubits = hcw > 0 && G.nzw <= (unsigned long long)kBitsLds;
     const int nzw = ubits ? (int)G.nzw : 0;
     if (tid < 4) sh_cnt[tid] = 0;

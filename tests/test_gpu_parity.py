@@ -352,9 +352,8 @@ def wide_t_graph(k):
 
 @pytest.mark.parametrize("k", [20000, 40000])
 def test_wide_ranked_t(ctx, k):
-    # k = 20000: the ranked members of T_e fill 313 bit-set words (held in
-    # LDS); k = 40000: 626 words, beyond the LDS copy, so the split kernel
-    # treats them as unranked for that edge
+    # the ranked members of T_e fill 313 (k = 20000) and 626 (k = 40000)
+    # bit-set words, all held in the split kernel's LDS copy
     g = wide_t_graph(k)
     h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
     try:
