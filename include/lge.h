@@ -119,8 +119,9 @@ typedef struct {
  * lge_opts_default(), or pass NULL for defaults.
  *  wave_max_deg   edges whose endpoints both have degree <= this are counted
  *                 by one wavefront with LDS tables (1..512, default 256)
- *  block_max_deg  read-only: edges whose endpoints both have degree <= 1024
- *                 are counted by one 256-thread workgroup with LDS tables;
+ *  block_max_deg  edges outside the wavefront class whose endpoints both
+ *                 have degree <= this (1..1024, default 1024) are counted by
+ *                 one 256-thread workgroup with LDS tables;
  *                 others are split across workgroups and use the per-vertex
  *                 global hash tables kept for every vertex of degree > 32
  *  probe_ratio    per neighbour w, look the target set up inside Gamma(w)

@@ -127,7 +127,7 @@ static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
   KernelCfg c;
   int wmd = o->wave_max_deg > 0 ? o->wave_max_deg : d.wave_max_deg;
   c.wave_max_deg = std::min(std::max(wmd, 1), 512);
-  c.block_max_deg = kHubDeg;
+  c.block_max_deg = o->block_max_deg > 0 ? std::min(o->block_max_deg, kHubDeg) : kHubDeg;
   c.probe_ratio = o->probe_ratio >= 0 ? o->probe_ratio : d.probe_ratio;
   const int per_cu = o->grid_per_cu > 0 ? o->grid_per_cu : 0;
   const int cu = ctx->num_cu > 0 ? ctx->num_cu : 256;

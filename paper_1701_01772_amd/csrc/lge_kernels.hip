@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
           // counted by one wavefront (using b's hub table) whatever b's degree
           const bool small_scan = cfg.probe_ratio > 0 && da <= kSmallScan && db > kTableDeg;
           const int c = (dmax <= cfg.wave_max_deg || small_scan) ? kClassWave
-                        : dmax <= kHubDeg                         ? kClassBlock
+                        : dmax <= cfg.block_max_deg               ? kClassBlock
                                                                   : kClassGlobal;
           cls[k] = c;
           // bytes the neighbour iteration of Alg. 2-4 reads for this edge:
@@ -1268,6 +1268,10 @@ __global__ __launch_bounds__(kPrepNT) void k_global_classify(
     const int32_t abeg = rp[a], bbeg = rp[b];
     const int da = rp[a + 1] - abeg, db = rp[b + 1] - bbeg;
     const bool hb = has_table(db);
+    // a ranked b tests ranked x in its adjacency bit row (hcw words, shared
+    // by the adjacent items of the same b), other x in b's table or list
+    const int32_t rb = S.hc > 0 ? S.crank[b] : -1;
+    const unsigned long long *__restrict__ brow = rb >= 0 ? S.hbits + (int64_t)rb * S.hcw : nullptr;
     const int p0 = (int)(c * chunk);
     const int p1 = p0 + chunk < da ? p0 + chunk : da;
     for (int base = p0; base < p1; base += kPrepNT) {
@@ -1276,7 +1280,11 @@ __global__ __launch_bounds__(kPrepNT) void k_global_classify(
       int32_t x = -1;
       if (i < p1) {
         x = col[abeg + i];
-        if (x != b) {
+        const uint32_t rh = brow ? S.arh[abeg + i] : 0u;
+        if (brow && !(rh >> 31)) {  // x ranked: its rank + 1 in the low bits
+          const int32_t rx = (int32_t)(rh & 0x1FFFFu) - 1;
+          isT = ((brow[rx >> 6] >> (rx & 63)) & 1ull) != 0;
+        } else if (x != b) {
           uint32_t st = 0;
           isT = hb ? table_find(S.htab + S.hoff[b], table_log(db), (uint32_t)x) >= 0
                    : sorted_has(col + bbeg, db, x, &st);

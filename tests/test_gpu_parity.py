@@ -146,6 +146,10 @@ def test_tuning_invariance(ctx):
                 got = lge.lge_estimate(ctx, h, 0.7, 3, o)
                 for k in ("sampled", "csum", "zsum", "qsum"):
                     assert got[k] == base[k], (chunk, flags, k)
+        for bmd in (1, 100, 300, 700):  # block class narrowed or empty
+            got = lge.lge_estimate(ctx, h, 0.7, 3, lge.make_opts(block_max_deg=bmd))
+            for k in ("sampled", "csum", "zsum", "qsum"):
+                assert got[k] == base[k], (bmd, k)
     finally:
         lge.lge_graph_destroy(h)
     assert_parity(base, oracle.estimate(g.row_ptr, g.col, 0.7, 3), "rmat-11 tuned")
