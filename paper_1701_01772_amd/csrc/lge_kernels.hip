@@ -729,20 +729,24 @@ __global__ __launch_bounds__(256) void k_codeg_bits(const int32_t *__restrict__ 
 
 // |Gamma(x) n Gamma(y)| when tabulated: both ranked (the symmetric table,
 // y's row), or one end unranked with a row column and the other ranked with
-// a co-degree row.  vy is y's vertex record.
-__device__ __forceinline__ bool codeg_pair(const SlotDesc &S, int32_t x, int4 vy, uint32_t *val) {
+// a co-degree row.  rhx is the packed rank word of an arc ending at x (rank
+// + 1 and co-degree row + 1 when ranked, else bit 31 and column + 1); vy is
+// y's vertex record.
+__device__ __forceinline__ bool codeg_pair(const SlotDesc &S, uint32_t rhx, int4 vy, uint32_t *val) {
   if (S.hc <= 0) return false;
-  const int4 vx = S.vinfo[x];
-  if (vx.z >= 0 && vy.z >= 0) {
-    *val = S.codeg[(int64_t)vy.z * S.hc + vx.z];
+  const bool xr = (rhx >> 31) == 0u;
+  const int32_t xrank = xr ? (int32_t)(rhx & 0x1FFFFu) - 1 : -1;
+  const int32_t xw = xr ? (int32_t)(rhx >> 17) - 1 : (int32_t)(rhx & 0x7FFFFFFFu) - 1;
+  if (xrank >= 0 && vy.z >= 0) {
+    *val = S.codeg[(int64_t)vy.z * S.hc + xrank];
     return true;
   }
-  if (vx.z < 0 && vx.w >= 0 && vy.z >= 0 && vy.w >= 0) {  // x's column of y's row
-    *val = row_at(S, vy.w, vx.w);
+  if (xrank < 0 && xw >= 0 && vy.z >= 0 && vy.w >= 0) {  // x's column of y's row
+    *val = row_at(S, vy.w, xw);
     return true;
   }
-  if (vy.z < 0 && vy.w >= 0 && vx.z >= 0 && vx.w >= 0) {  // y's column of x's row
-    *val = row_at(S, vx.w, vy.w);
+  if (vy.z < 0 && vy.w >= 0 && xrank >= 0 && xw >= 0) {  // y's column of x's row
+    *val = row_at(S, xw, vy.w);
     return true;
   }
   return false;
@@ -945,6 +949,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
       // an edge with a small scan side and a large b (binned here by the
       // sampling kernel): Gamma(b) stays in b's hub table, the LDS table holds T_e
       const bool bhub = db > CAP;
+      // endpoint records for the co-degree reads, loaded early
+      const bool has_ranks = probe_ratio > 0 && S.hc > 0;
+      int4 va = make_int4(0, 0, -1, -1), vb = va;
+      if (has_ranks) {
+        va = S.vinfo[a];
+        vb = S.vinfo[b];
+      }
       const uint32_t *__restrict__ btab = bhub ? S.htab + S.hoff[b] : nullptr;
       const int blg = bhub ? table_log(db) : 0;
       const int lg = table_log(bhub ? da : db);
@@ -965,6 +976,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
         const int i = base + tid;
         bool valid = i < da;
         const int32_t x = valid ? col[abeg + i] : -1;
+        // the arc's packed rank word, read coalesced beside Gamma(a)
+        const uint32_t rh = valid && has_ranks ? S.arh[abeg + i] : 0x80000000u;
         valid = valid && x != b;
         bool isT = false;
         if (valid && bhub) {
@@ -987,6 +1000,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
           wl_v[pos] = (uint32_t)x | (isT ? kTag : 0u);
           wl_beg[pos] = wb;
           wl_deg[pos] = we - wb;
+          wl_pref[pos] = (int32_t)rh;  // until the mode pass turns it into the unit count
         }
       }
       if (tid == 0) words += (unsigned long long)(3 * da);
@@ -1006,17 +1020,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
       const int sbn = sh_cnt[2];
       // per-w modes under both schemes; the edge takes the cheaper one
       const bool may_look = probe_ratio > 0;
-      int4 va = make_int4(0, 0, -1, -1), vb = va;
-      if (may_look && S.hc > 0) {
-        va = S.vinfo[a];
-        vb = S.vinfo[b];
-      }
       long long cyc_base = 0;
       unsigned long long c_plain = 0, c_agg = 0;
       for (int i = tid; i < L; i += NT) {
         const uint32_t v = wl_v[i];
         const bool isT = (v & kTag) != 0;
-        const int32_t w = (int32_t)(v & kIdMask);
+        const uint32_t rh = (uint32_t)wl_pref[i];
         const int dw = wl_deg[i];
         const int64_t scan = 8ll * dw;
         if (!may_look) {
@@ -1028,7 +1037,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
         c_plain += (unsigned long long)(isT ? (lt < scan ? lt : scan)
                                              : ((int64_t)sbn * lk < scan ? (int64_t)sbn * lk : scan));
         uint32_t cdeg = 0;
-        const bool cok = codeg_pair(S, w, isT ? va : vb, &cdeg);
+        const bool cok = codeg_pair(S, rh, isT ? va : vb, &cdeg);
         uint32_t fl = 0;
         int32_t units = dw;
         int64_t cost = scan;
