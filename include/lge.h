@@ -156,7 +156,9 @@ typedef struct {
   float total_ms;          /* first kernel start to last kernel end (includes one host round trip) */
   float sample_ms;         /* sampling + binning kernel */
   float count_ms[3];       /* counting kernels: wavefront, workgroup and split global classes
-                              (count_ms[2] is k_count_global alone) */
+                              (count_ms[2] is k_count_global alone; the fold of
+                              edges counted by several work items that follows
+                              it is in total_ms only) */
   float global_prep_ms;    /* global class set-up: work items, T_e lists */
   uint64_t class_edges[3]; /* sampled edges per class */
   uint64_t words_read[3];  /* 4-byte words each class's counting kernels read (algorithmic) */

@@ -1063,7 +1063,10 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   LGE_HIP(hipEventRecord(ev[3], s));
   LGE_HIP(launch_count_block(w.slots, bins, nb, cfg, s));
   LGE_HIP(hipEventRecord(ev[4], s));
-  if (ng == 0) LGE_HIP(hipEventRecord(ev[6], s));
+  if (ng == 0) {
+    LGE_HIP(hipEventRecord(ev[6], s));
+    LGE_HIP(hipEventRecord(ev[7], s));
+  }
   if (ng > 0) {
     if (cfg.flags & kOptSortHub) {
       LGE_HIP(launch_sort_global(w.slots, bins, ng, w.sort_slot, w.sort_a, w.sort_b, w.sort_hist, w.sort_off,
@@ -1090,6 +1093,8 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     LGE_HIP(hipEventRecord(ev[6], s));
     LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tlist, w.tbw, w.tbi,
                                 w.tmask, w.gacc, cfg, s));
+    LGE_HIP(hipEventRecord(ev[7], s));  // the counting kernel alone, for its roofline
+    LGE_HIP(launch_global_finish(w.slots, ng, w.items, w.gacc, s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
   LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)nslots * kAccSlots * 2 * sizeof(unsigned long long),
@@ -1102,12 +1107,12 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) t.sample_ms = ms;
   if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) t.count_ms[0] = ms;
   if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) t.count_ms[1] = ms;
-  if (hipEventElapsedTime(&ms, ev[6], ev[5]) == hipSuccess) t.count_ms[2] = ms;
+  if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) t.count_ms[2] = ms;
   if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
   for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[c];
   for (int c = 0; c < kNumClasses; ++c) t.words_read[c] = w.h_counters[6 + c];
   for (int c = 0; c < kNumClasses; ++c) t.alg_bytes[c] = w.h_counters[12 + c];
-  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 6 : 0);
+  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 7 : 0);
   return LGE_OK;
 }
 

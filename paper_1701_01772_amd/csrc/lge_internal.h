@@ -202,6 +202,9 @@ hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges,
 hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
                                const int64_t *item_cnt, const int32_t *item_edge, const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi,
                                const unsigned long long *tmask, void *gacc, KernelCfg cfg, hipStream_t s);
+// folds the edges counted by several work items into their slots
+hipError_t launch_global_finish(const SlotDesc *slots, int64_t nedges, const int64_t *item_cnt, const void *gacc,
+                                hipStream_t s);
 size_t gedge_bytes();
 // micro statistics: t of every arc (position j of col holds |Gamma(x) n
 // Gamma(col[j])| for the row x owning j), vertex triangle counts, the

@@ -1188,10 +1188,11 @@ constexpr int kMaskWords = kGlobalChunkMax / 64;  // T_e membership words per wo
 static_assert(kGlobalChunkMax <= kGlobalNT, "one pass over an item's positions");
 
 // Per split-class edge: counters (t by classify, nzw by the bit-set kernel,
-// k4 / cyc / done by the counting items) and the edge's descriptor, written
-// once per launch so a work item finds everything in one 128-byte record.
+// k4 / cyc summed by the counting items of edges with several) and the
+// edge's descriptor, written once per launch so a work item finds
+// everything in one 128-byte record.
 struct GEdge {
-  unsigned long long t, k4, cyc, done, nzw;
+  unsigned long long t, k4, cyc, spare, nzw;
   int32_t a, b, slot, da, db, abeg, bbeg, ra;  // ra / rb: ranks (-1 when unranked)
   int32_t rb, hra, hrb, pad;                   // hra / hrb: co-degree row (ranked) or row column (unranked), -1 none
   int64_t hoffa, hoffb;                        // hub-table offsets (-1 when no table)
@@ -1214,7 +1215,7 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
     items[e] = (da + chunk - 1) / chunk;
     tcap[e] = da < db ? da : db;
     GEdge &G = gacc[e];
-    G.t = G.k4 = G.cyc = G.done = G.nzw = 0ull;
+    G.t = G.k4 = G.cyc = G.spare = G.nzw = 0ull;
     G.a = a;
     G.b = b;
     G.slot = slot;
@@ -1428,7 +1429,6 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   __shared__ int32_t carry_sh[NT / kWave + 1];
   __shared__ unsigned long long red[2 * NT / kWave];
   __shared__ long long sh_item;
-  __shared__ int sh_last;
   __shared__ unsigned long long tbits[kBitsLds];  // non-zero words of the ranked members of T_e
   __shared__ int16_t twidx[kBitsLds];            // and their indices
   __shared__ int32_t bx_rank[CH];  // ranked members of T_e in this chunk
@@ -1774,24 +1774,10 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(kt / 2), (int64_t)(cs + kt));
         if (lane == 0) micro_put(S, a, b, t, (int64_t)(kt / 2), (int64_t)(cs + kt));
       }
-    } else {
-      if (tid == 0) {
-        GEdge *g = gacc + e;
-        if (kt) atomicAdd(&g->k4, kt);
-        if (cs) atomicAdd(&g->cyc, cs);
-        __threadfence();
-        const unsigned long long d = atomicAdd(&g->done, 1ull);
-        sh_last = (d + 1ull == (unsigned long long)icnt) ? 1 : 0;
-      }
-      __syncthreads();
-      if (sh_last && tid < kWave) {
-        GEdge *g = gacc + e;
-        __threadfence();
-        const unsigned long long kk = atomicAdd(&g->k4, 0ull);
-        const unsigned long long cc = atomicAdd(&g->cyc, 0ull) + kk;
-        acc.add(slots, slot, S.n, S.m, da, db, t, (int64_t)(kk / 2), (int64_t)cc);
-        if (lane == 0) micro_put(S, a, b, t, (int64_t)(kk / 2), (int64_t)cc);
-      }
+    } else if (tid == 0) {  // partial sums; k_global_finish folds the edge
+      GEdge *g = gacc + e;
+      if (kt) atomicAdd(&g->k4, kt);
+      if (cs) atomicAdd(&g->cyc, cs);
     }
     if (tid == 0) sh_item = upcoming;
     __syncthreads();
@@ -1799,6 +1785,36 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   if (tid < kWave) acc.flush(slots);
   const unsigned long long wsum = block_sum_u64<NT>(words, red);
   if (tid == 0 && wsum) atomicAdd(words_out, wsum);
+}
+
+// Edges counted by several work items: their items left k4 (twice the
+// edges inside T_e) and the rest of cyc in the edge's counters; one
+// wavefront per edge turns them into the edge's terms (Alg. 2) and folds
+// them into its slot.
+__global__ __launch_bounds__(256) void k_global_finish(const SlotDesc *__restrict__ slots,
+                                                       const GEdge *__restrict__ gacc,
+                                                       const int64_t *__restrict__ item_cnt, int64_t nedges) {
+  SlotAcc acc;
+  acc.init();
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  // 64 edges per wavefront and round: their item counts in one coalesced
+  // read, then the multi-item ones one after another
+  for (int64_t base = w0 * kWave; base < nedges; base += nw * kWave) {
+    const int64_t e = base + lane;
+    uint64_t m = __ballot(e < nedges && item_cnt[e] > 1);
+    while (m) {  // uniform per wavefront
+      const int k = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const GEdge &G = gacc[base + k];
+      const SlotDesc &S = slots[G.slot];
+      const unsigned long long kk = G.k4, cc = G.cyc + kk;
+      acc.add(slots, G.slot, S.n, S.m, G.da, G.db, (int64_t)G.t, (int64_t)(kk / 2), (int64_t)cc);
+      if (lane == 0) micro_put(S, G.a, G.b, (int64_t)G.t, (int64_t)(kk / 2), (int64_t)cc);
+    }
+  }
+  acc.flush(slots);
 }
 
 // ---------------------------------------------------------------------------
@@ -2322,6 +2338,14 @@ hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, cons
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_item_fill, dim3(grid_for(nedges, 256, 8192)), dim3(256), 0, s, item_pref, items, tbase,
                      nedges, item_edge, (GEdge *)gacc);
+  return hipGetLastError();
+}
+
+hipError_t launch_global_finish(const SlotDesc *slots, int64_t nedges, const int64_t *item_cnt, const void *gacc,
+                                hipStream_t s) {
+  if (nedges <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_global_finish, dim3(grid_for(nedges, 4 * kWave, 1024)), dim3(256), 0, s, slots,
+                     (const GEdge *)gacc, item_cnt, nedges);
   return hipGetLastError();
 }
 
