@@ -131,7 +131,7 @@ typedef struct {
  *  grid_per_cu    persistent workgroups per compute unit for each counting
  *                 kernel (0 = library default)
  *  global_chunk   Gamma(a) positions per work item of the split class
- *                 (1..512, default 512)
+ *                 (1..1024, default 1024)
  *  flags          LGE_OPT_SORT_HUB: order split-class edges by their
  *                 table-side endpoint so consecutive work items share its
  *                 hub table; LGE_OPT_XCD_LOCAL: each XCD (workgroups

@@ -1753,7 +1753,7 @@ extern "C" int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts
   const int waves[] = {64, 128, 256, 512};
   const int ratios[] = {2, 4, 8};
   const int grids[] = {4, 8, 12};
-  const int chunks[] = {128, 256};
+  const int chunks[] = {256, 512};
   for (int pass = 0; pass < 2; ++pass) {
     for (int v : waves) {
       lge_opts o = best;

@@ -39,7 +39,7 @@ constexpr int kRowMaxDeg = 254;
 constexpr int kMaxRows = 16383;
 constexpr int kBitsWords = kMaxRanked / 64;
 // Largest number of Gamma(a) positions handled by one global-class work item.
-constexpr int kGlobalChunkMax = 512;
+constexpr int kGlobalChunkMax = 1024;
 // Vertex ids must stay below 2^29: the kernels keep three tag bits above them.
 constexpr int64_t kMaxVertices = (int64_t)1 << 29;
 

@@ -1185,7 +1185,7 @@ constexpr int kGlobalNT = 512;  // counting kernel: one pass over a work item's 
 constexpr int kPrepNT = 256;    // classify and bit-set kernels
 constexpr int kTHashCap = 512;
 constexpr int kMaskWords = kGlobalChunkMax / 64;  // T_e membership words per work item
-static_assert(kGlobalChunkMax <= kGlobalNT, "one pass over an item's positions");
+static_assert(kGlobalChunkMax % kGlobalNT == 0, "an item's positions take whole passes of the workgroup");
 
 // Per split-class edge: counters (t by classify, nzw by the bit-set kernel,
 // k4 / cyc summed by the counting items of edges with several) and the
