@@ -32,10 +32,12 @@ constexpr double kCodegBytes = 17179869184.0;       // 16 GiB: 65536 ranked vert
 constexpr double kCodegBytesCompact = 1073741824.0;  // 1 GiB: 16384
 // pairs of one vertex's ranked neighbours per work item of the table build
 constexpr int64_t kPairsPerItem = (int64_t)1 << 20;
-// Vertices above this degree get a co-degree row over all unranked vertices
-// (largest degrees first, while the build work, the sum of their 2-hop
-// volumes, and the memory stay within these budgets).
-constexpr int32_t kRowDeg = 1024;
+// Ranked vertices above this degree get a co-degree row over the unranked
+// vertices (largest degrees first, while the build work, the sum of their
+// 2-hop volumes, and the memory stay within these budgets).  Every ranked
+// vertex qualifies: the rows of mid-degree vertices serve the wavefront and
+// workgroup classes, whose b rarely exceeds degree 1024.
+constexpr int32_t kRowDeg = 96;
 // co-degree rows: build work (sum of 2-hop volumes) and HBM per graph; the
 // byte budget is also capped at a quarter of the free HBM at creation.
 // LGE_FLAG_COMPACT keeps the small budget for callers holding many graphs.
