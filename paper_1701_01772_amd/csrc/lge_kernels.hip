@@ -1185,7 +1185,8 @@ constexpr int kGlobalNT = 512;  // counting kernel: one pass over a work item's 
 constexpr int kPrepNT = 256;    // classify and bit-set kernels
 constexpr int kTHashCap = 512;
 constexpr int kMaskWords = kGlobalChunkMax / 64;  // T_e membership words per work item
-static_assert(kGlobalChunkMax % kGlobalNT == 0, "an item's positions take whole passes of the workgroup");
+static_assert(kGlobalChunkMax % kGlobalNT == 0 && kGlobalChunkMax % kPrepNT == 0,
+              "an item's positions take whole passes of the workgroups");
 
 // Per split-class edge: counters (t by classify, nzw by the bit-set kernel,
 // k4 / cyc summed by the counting items of edges with several) and the
@@ -1251,10 +1252,9 @@ __global__ __launch_bounds__(256) void k_item_fill(const int64_t *__restrict__ i
 }
 
 __global__ __launch_bounds__(kPrepNT) void k_global_classify(
-    const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
-    const int32_t *__restrict__ bb, int64_t nedges, const int64_t *__restrict__ item_pref,
-    const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int64_t *__restrict__ tbase,
-    int32_t *tlist, unsigned long long *__restrict__ tmask, GEdge *gacc, int32_t chunk, int32_t xcd_local) {
+    const SlotDesc *__restrict__ slots, int64_t nedges, const int64_t *__restrict__ item_pref,
+    const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, int32_t *tlist,
+    unsigned long long *__restrict__ tmask, GEdge *gacc, int32_t chunk, int32_t xcd_local) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
@@ -1268,52 +1268,82 @@ __global__ __launch_bounds__(kPrepNT) void k_global_classify(
     hi = total_items * (sg + 1) / kXcds;
     stride = gridDim.x / kXcds;
   }
+  constexpr int kPass = kGlobalChunkMax / kPrepNT;  // passes over an item's positions
+  constexpr int kNW = kPrepNT / kWave;
+  __shared__ int wcnt[kNW];
+  __shared__ unsigned long long sbase;
+  const int wv = threadIdx.x >> 6;
   for (int64_t item = first; item < hi; item += stride) {
+    // the edge's record (written by the preparation kernels)
     const int64_t e = item_edge[item];
-    const int64_t c = item - item_pref[e];
-    const SlotDesc &S = slots[bslot[e]];
-    const int32_t *__restrict__ rp = S.row_ptr;
+    const GEdge &G = gacc[e];
+    const SlotDesc &S = slots[G.slot];
     const int32_t *__restrict__ col = S.col;
-    const int32_t a = ba[e], b = bb[e];
-    const int32_t abeg = rp[a], bbeg = rp[b];
-    const int da = rp[a + 1] - abeg, db = rp[b + 1] - bbeg;
+    const int32_t b = G.b, abeg = G.abeg, bbeg = G.bbeg, da = G.da, db = G.db;
+    const int64_t c = item - G.ipref, tb0 = G.tbase;
     const bool hb = has_table(db);
+    const uint32_t *__restrict__ btab = hb ? S.htab + S.hoff[b] : nullptr;
     // a ranked b tests ranked x in its adjacency bit row (hcw words, shared
     // by the adjacent items of the same b), other x in b's table or list
-    const int32_t rb = S.hc > 0 ? S.crank[b] : -1;
-    const unsigned long long *__restrict__ brow = rb >= 0 ? S.hbits + (int64_t)rb * S.hcw : nullptr;
+    const unsigned long long *__restrict__ brow = G.rb >= 0 ? S.hbits + (int64_t)G.rb * S.hcw : nullptr;
     const int p0 = (int)(c * chunk);
     const int p1 = p0 + chunk < da ? p0 + chunk : da;
-    for (int base = p0; base < p1; base += kPrepNT) {
-      const int i = base + (int)threadIdx.x;
-      bool isT = false;
-      int32_t x = -1;
-      if (i < p1) {
-        x = col[abeg + i];
-        const uint32_t rh = brow ? S.arh[abeg + i] : 0u;
-        if (brow && !(rh >> 31)) {  // x ranked: its rank + 1 in the low bits
-          const int32_t rx = (int32_t)(rh & 0x1FFFFu) - 1;
-          isT = ((brow[rx >> 6] >> (rx & 63)) & 1ull) != 0;
+    // every read of the item's positions goes out before any is used
+    int32_t xs[kPass];
+    uint32_t rhs[kPass];
+#pragma unroll
+    for (int q = 0; q < kPass; ++q) {
+      const int i = p0 + q * kPrepNT + (int)threadIdx.x;
+      xs[q] = i < p1 ? col[abeg + i] : -1;
+      rhs[q] = (i < p1 && brow) ? S.arh[abeg + i] : 0x80000000u;
+    }
+    bool ts[kPass];
+#pragma unroll
+    for (int q = 0; q < kPass; ++q) {
+      const int32_t x = xs[q];
+      ts[q] = false;
+      if (x >= 0) {
+        if (brow && !(rhs[q] >> 31)) {  // x ranked: its rank + 1 in the low bits
+          const int32_t rx = (int32_t)(rhs[q] & 0x1FFFFu) - 1;
+          ts[q] = ((brow[rx >> 6] >> (rx & 63)) & 1ull) != 0;
         } else if (x != b) {
           uint32_t st = 0;
-          isT = hb ? table_find(S.htab + S.hoff[b], table_log(db), (uint32_t)x) >= 0
-                   : sorted_has(col + bbeg, db, x, &st);
+          ts[q] = hb ? table_find(btab, table_log(db), (uint32_t)x) >= 0 : sorted_has(col + bbeg, db, x, &st);
         }
       }
-      const uint64_t tm = __ballot(isT);
-      // membership of this wavefront's 64 positions, for the counting items
-      if (lane == 0) tmask[item * kMaskWords + ((base - p0) >> 6) + (threadIdx.x >> 6)] = tm;
-      unsigned long long pos0 = 0;
-      if (lane == 0 && tm) pos0 = atomicAdd(&gacc[e].t, (unsigned long long)__popcll(tm));
-      pos0 = __shfl(pos0, 0);
-      if (isT) {  // (id, degree, rank) triples; rank -1 when not ranked
-        const int4 vi = S.vinfo[x];
-        const int64_t pos = tbase[e] + (int64_t)pos0 + __popcll(tm & lt_mask);
-        tlist[3 * pos] = x;
-        tlist[3 * pos + 1] = vi.y;
-        tlist[3 * pos + 2] = vi.z;
-      }
     }
+    // membership words for the counting items, and one claim of T_e slots
+    // per item
+    uint64_t tms[kPass];
+    int wc = 0;
+#pragma unroll
+    for (int q = 0; q < kPass; ++q) {
+      tms[q] = __ballot(ts[q]);
+      wc += __popcll(tms[q]);
+      if (lane == 0 && p0 + q * kPrepNT < p1) tmask[item * kMaskWords + q * kNW + wv] = tms[q];
+    }
+    if (lane == 0) wcnt[wv] = wc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < kNW; ++w) tot += wcnt[w];
+      sbase = tot ? atomicAdd(&gacc[e].t, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    int64_t pos = tb0 + (int64_t)sbase;
+    for (int w = 0; w < wv; ++w) pos += wcnt[w];
+#pragma unroll
+    for (int q = 0; q < kPass; ++q) {
+      if (ts[q]) {  // (id, degree, rank) triples; rank -1 when not ranked
+        const int4 vi = S.vinfo[xs[q]];
+        const int64_t at = pos + __popcll(tms[q] & lt_mask);
+        tlist[3 * at] = xs[q];
+        tlist[3 * at + 1] = vi.y;
+        tlist[3 * at + 2] = vi.z;
+      }
+      pos += __popcll(tms[q]);
+    }
+    __syncthreads();  // wcnt and sbase are rewritten by the next item
   }
 }
 
@@ -2355,9 +2385,8 @@ hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedg
                                   hipStream_t s) {
   if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global * (kGlobalNT / kPrepNT)), dim3(kPrepNT), 0, s, slots,
-                     bins.slot[kClassGlobal],
-                     bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, item_pref, item_cnt, item_edge, tbase,
-                     tlist, tmask, (GEdge *)gacc, cfg.global_chunk, (cfg.flags & kOptXcdLocal) ? 1 : 0);
+                     nedges, item_pref, item_cnt, item_edge, tlist, tmask, (GEdge *)gacc, cfg.global_chunk,
+                     (cfg.flags & kOptXcdLocal) ? 1 : 0);
   return hipGetLastError();
 }
 
