@@ -29,3 +29,36 @@ def test_cpu_baseline_threads_reproduce_single_thread_sums():
     mt = out["all_cores"]
     assert mt["cores"] >= 1 and mt["value"] > 0
     assert mt["sums_match_single_thread"] is True
+
+
+def _timing(count_ms, words, alg):
+    return {"count_ms": count_ms, "words_read": words, "alg_bytes": alg, "sample_ms": 0.5,
+            "global_prep_ms": 1.0}
+
+
+def test_roofline_takes_the_dominant_kernel_and_its_bytes():
+    import bench
+    tim = [_timing([2.0, 1.0, 4.0], [10, 20, 1000], [1e9, 2e9, 8e9]),
+           _timing([2.0, 1.0, 6.0], [10, 20, 3000], [1e9, 2e9, 8e9])]
+    dev, roof = bench.roofline_of(tim, "no_such_workload")
+    assert dev["count_global"] == 5.0 and dev["count_wave"] == 2.0 and dev["global_prep"] == 1.0
+    assert roof["kernel"].startswith("k_count_global")
+    assert roof["launch_ms"] == 5.0
+    assert roof["achieved"] == 8e9 / 5e-3 / 1e9  # GB/s
+    assert roof["frac"] == roof["achieved"] / 8000.0
+    assert roof["issued_bytes_per_launch"] == 4.0 * 2000
+    assert roof["traffic"] is None  # no counter profile for this workload
+
+
+def test_roofline_traffic_only_from_a_profile_of_the_same_source():
+    import json
+    import bench
+    for wl in ("chung_lu", "rmat"):
+        with open(os.path.join(ROOT, "profiles", "pmc_%s_global.json" % wl)) as fh:
+            pmc = json.load(fh)
+        tim = [_timing([1.0, 1.0, 3.0], [0, 0, 0], [0, 0, 1e9])]
+        _, roof = bench.roofline_of(tim, wl)
+        if pmc["kernel_hash"] == bench.kernel_source_hash():
+            assert roof["traffic"] == pmc["traffic_bytes_per_launch"]
+        else:
+            assert roof["traffic"] is None
