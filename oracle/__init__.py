@@ -94,6 +94,11 @@ def _load():
         lib.oracle_philox_keys.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.POINTER(ctypes.c_uint64)]
         lib.oracle_philox_keys.restype = None
+        lib.oracle_finalize_sums.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                             ctypes.c_uint64, _U128 * 17, _U128 * 18, ctypes.POINTER(_Result)]
+        lib.oracle_finalize_sums.restype = ctypes.c_int
+        lib.oracle_i128_to_double.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.oracle_i128_to_double.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -144,6 +149,14 @@ def philox_keys(seed: int, m: int) -> np.ndarray:
     return out[:m]
 
 
+def i128_to_double(x: int) -> float:
+    """The oracle's int128 -> double conversion (round to nearest, ties to even)."""
+    if not -(1 << 127) <= x < (1 << 127):
+        raise ValueError("not a signed 128-bit value")
+    v = x & ((1 << 128) - 1)
+    return float(_load().oracle_i128_to_double(v & ((1 << 64) - 1), v >> 64))
+
+
 def _csr(row_ptr, col):
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     cl = np.ascontiguousarray(col, dtype=np.int32)
@@ -171,6 +184,10 @@ def estimate(row_ptr, col, p: float, seed: int = 0, mask=None) -> dict:
                              mptr, ctypes.byref(res))
     if rc != 0:
         raise RuntimeError("oracle_estimate failed: %d" % rc)
+    return _result_dict(res)
+
+
+def _result_dict(res) -> dict:
     return {
         "n": res.n, "m": res.m, "p": res.p, "seed": res.seed, "sampled": res.sampled,
         "csum": [_u(res.csum[i]) for i in range(18)],
@@ -180,6 +197,48 @@ def estimate(row_ptr, col, p: float, seed: int = 0, mask=None) -> dict:
         "estimate": list(res.estimate), "variance": list(res.variance),
         "lower95": list(res.lower95), "upper95": list(res.upper95),
     }
+
+
+def _limbs(x: int) -> _U128:
+    v = x & ((1 << 128) - 1)
+    return _U128(v & ((1 << 64) - 1), v >> 64)
+
+
+def estimate_threads(row_ptr, col, p: float, seed: int = 0, threads: int = 8, mask=None) -> dict:
+    """``estimate`` over the same sample, split round-robin by sampled edge
+    over ``threads`` host threads (the C oracle is reentrant and ctypes drops
+    the GIL during a call).  Each thread's integer sums come from the plain
+    oracle on its share; their exact totals are finalised once, as one call
+    would.  The result equals ``estimate`` bit for bit (the sums do not
+    depend on the order of the edges).  Also returns the per-thread results
+    under ``"parts"``."""
+    from concurrent.futures import ThreadPoolExecutor
+    rp, cl = _csr(row_ptr, col)
+    n = rp.shape[0] - 1
+    m = int(rp[-1]) // 2
+    if mask is None:
+        mask = sample_mask(seed, p, m)
+    ids = np.nonzero(np.asarray(mask, dtype=np.uint8)[:m])[0]
+    threads = max(1, min(int(threads), max(1, ids.size)))
+    masks = []
+    for i in range(threads):
+        mk = np.zeros(max(m, 1), dtype=np.uint8)
+        mk[ids[i::threads]] = 1
+        masks.append(mk)
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        parts = list(pool.map(lambda mk: estimate(rp, cl, p, seed, mask=mk), masks))
+    sampled = sum(x["sampled"] for x in parts)
+    csum = [sum(x["csum"][i] for x in parts) for i in range(17)]
+    qsum = [sum(x["qsum"][i] for x in parts) for i in range(18)]
+    cs = (_U128 * 17)(*[_limbs(v) for v in csum])
+    qs = (_U128 * 18)(*[_limbs(v) for v in qsum])
+    res = _Result()
+    rc = _load().oracle_finalize_sums(n, m, float(p), int(seed), sampled, cs, qs, ctypes.byref(res))
+    if rc != 0:
+        raise RuntimeError("oracle_finalize_sums failed: %d" % rc)
+    out = _result_dict(res)
+    out["parts"] = parts
+    return out
 
 
 def edge_local(row_ptr, col, u: int, v: int) -> dict:

@@ -261,8 +261,9 @@ static double i128_to_double(i128 x) {
   if ((a >> 53) == 0) {
     d = (double)(uint64_t)a;
   } else {
-    int shift = 0;
-    while ((a >> (53 + shift)) != 0) ++shift;
+    int bits = 0; /* significant bits of a, 54..128 here */
+    for (u128 t = a; t != 0; t >>= 1) ++bits;
+    int shift = bits - 53;
     u128 mant = a >> shift;
     u128 rem = a & (((u128)1 << shift) - 1);
     u128 half = (u128)1 << (shift - 1);
@@ -391,6 +392,31 @@ int oracle_estimate(int64_t n, const int32_t *row_ptr, const int32_t *col, doubl
   res->sampled = sampled;
   if (rc != 0) return rc;
   return finalize(n, m, p, csum, q, res);
+}
+
+/* The finalisation above applied to sums the caller already holds: csum[0..16]
+ * (C_i by graphlet number, two's complement limbs) and q[0..17] (Q_i), e.g.
+ * the exact totals of several oracle_estimate calls over disjoint masks.
+ * Returns 0 or -2 on an inexact division. */
+int oracle_finalize_sums(int64_t n, int64_t m, double p, uint64_t seed, uint64_t sampled,
+                         const oracle_u128 csum_in[17], const oracle_u128 q_in[18], oracle_result *res) {
+  memset(res, 0, sizeof(*res));
+  res->n = n;
+  res->m = m;
+  res->p = p;
+  res->seed = seed;
+  res->sampled = sampled;
+  i128 csum[17];
+  u128 q[18];
+  for (int i = 0; i < 17; ++i) csum[i] = (i128)(((u128)csum_in[i].hi << 64) | (u128)csum_in[i].lo);
+  for (int i = 0; i < 18; ++i) q[i] = ((u128)q_in[i].hi << 64) | (u128)q_in[i].lo;
+  return finalize(n, m, p, csum, q, res);
+}
+
+/* The int128 -> double conversion used by the finalisation, exposed so that
+ * its rounding (to nearest, ties to even, above 2^53) can be pinned. */
+double oracle_i128_to_double(uint64_t lo, uint64_t hi) {
+  return i128_to_double((i128)(((u128)hi << 64) | (u128)lo));
 }
 
 /* Per-edge local quantities for edge (u, v) (micro view, Alg. 2-4);

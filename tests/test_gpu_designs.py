@@ -1,8 +1,10 @@
 """GPU parity of the other sampling designs: k-core numbers, weighted
 (degree / k-core) Horvitz-Thompson sampling and fixed-size samples with the
-ratio estimator, against the oracle.  Integers bit-equal; FP64 within a
-relative 1e-12 of the larger magnitude (or of the sum of the class terms
-for the weighted estimate)."""
+ratio estimator, against the oracle.  Integers bit-equal; class
+probabilities equal; FP64 within a relative 1e-12 of the larger magnitude.
+Both sides combine the exact per-class sums in class order with the same
+IEEE operations, so the weighted estimate is held to the same bar even when
+its class terms cancel."""
 import math
 import sys
 
@@ -29,11 +31,10 @@ def ctx():
     lge.lge_close(c)
 
 
-def _close(a, b, scale=None):
+def _close(a, b):
     if a == b or (math.isnan(a) and math.isnan(b)):
         return True
-    s = max(abs(a), abs(b)) if scale is None else max(scale, abs(a), abs(b))
-    return abs(a - b) <= REL * s
+    return abs(a - b) <= REL * max(abs(a), abs(b))
 
 
 GRAPHS = [
@@ -68,7 +69,7 @@ def _weighted_check(ctx, g, mode, p_mean, seed, what):
         lge.lge_graph_destroy(h)
     want = D.estimate_weighted(g.row_ptr, g.col, mode, p_mean, seed)
     for l in range(16):
-        assert _close(info["p_level"][l], want["p_level"][l]), (l, info["p_level"][l], want["p_level"][l])
+        assert info["p_level"][l] == want["p_level"][l], (l, info["p_level"][l], want["p_level"][l])
     assert info["edges"] == want["hist"]
     assert info["sampled"] == want["sampled_level"]
     assert got["sampled"] == want["sampled"]
@@ -76,9 +77,7 @@ def _weighted_check(ctx, g, mode, p_mean, seed, what):
         for i in range(3, 18):
             assert got[key][i] == want[key][i], (key, i)
     for i in range(1, 18):
-        # the class terms may cancel: compare against their total magnitude
-        scale = sum(abs(z[i]) / 12.0 / p for z, p in zip(want["zsum_level"], want["p_level"]))
-        assert _close(got["estimate"][i], want["estimate"][i], scale), (i, got["estimate"][i], want["estimate"][i])
+        assert _close(got["estimate"][i], want["estimate"][i]), (i, got["estimate"][i], want["estimate"][i])
         assert _close(got["variance"][i], want["variance"][i]), (i, got["variance"][i], want["variance"][i])
     return got, info
 

@@ -67,7 +67,7 @@ def test_exact_unbiasedness_by_enumeration(case):
 
 
 COVERAGE_SEEDS = 200
-COVERAGE_BAND = (0.88, 0.99)
+COVERAGE_BAND = (0.90, 0.99)
 
 
 def coverage_of(estimates, exact):
