@@ -171,11 +171,13 @@ def bench_batch(args):
     for h in hs[:64]:
         lge.lge_estimate(ctx, h, p, 1)
     torch.cuda.synchronize()
-    # plain path: one estimate (one launch sequence) per graph
+    # plain path: one estimate (one launch sequence) per graph; both legs
+    # keep the library's result structs (no conversion to Python numbers)
+    res = lge.Result()
     t0 = time.perf_counter()
     plain_sampled = 0
     for h, sd in zip(hs, seeds):
-        plain_sampled += lge.lge_estimate(ctx, h, p, sd)["sampled"]
+        plain_sampled += lge.lge_estimate(ctx, h, p, sd, raw=True, out=res).sampled_edges
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     log("plain: %.3f s" % t_plain)
@@ -184,8 +186,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        outs = lge.lge_estimate_many(ctx, hs, p, seeds)
-        sampled += sum(o["sampled"] for o in outs)
+        outs = lge.lge_estimate_many(ctx, hs, p, seeds, raw=True)
+        sampled += sum(outs[k].sampled_edges for k in range(len(hs)))
         tim.append(lge.lge_last_timing(ctx))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0

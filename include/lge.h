@@ -153,7 +153,7 @@ typedef struct {
 
 /* Device-time breakdown of the last estimate/batch call on a ctx. */
 typedef struct {
-  float total_ms;          /* first kernel start to last kernel end (includes one host round trip) */
+  float total_ms;          /* first kernel start to last kernel end */
   float sample_ms;         /* sampling + binning kernel */
   float count_ms[3];       /* counting kernels: wavefront, workgroup and split global classes
                               (count_ms[2] is k_count_global alone; the fold of
@@ -164,7 +164,8 @@ typedef struct {
   uint64_t words_read[3];  /* 4-byte words each class's counting kernels read (algorithmic) */
   uint64_t launches;       /* kernel launches issued */
   float micro_ms;          /* lge_micro only: the row kernel (after the counting pass) */
-  float pad;
+  uint32_t host_waits;     /* host waits on the device: 1, or 2 when the split-class work lists outgrew
+                              the context's buffers (which then grow for later calls) */
   uint64_t alg_bytes[3];   /* per class: bytes the neighbour iteration of Alg. 2-4 would read for the
                               sampled edges, 16 + 4(d_u + d_v) + sum over w in Gamma(a)\{b} of (8 + 4 d_w) */
 } lge_timing;

@@ -152,10 +152,8 @@ static void ws_free(Workspace &w) {
     dev_free(w.bin_a[c]);
     dev_free(w.bin_b[c]);
   }
-  dev_free(w.counters);
-  dev_free(w.slots);
-  dev_free(w.ranges);
-  dev_free(w.acc);
+  dev_free(w.ctl);
+  if (w.desc) (void)hipFree(w.desc);
   dev_free(w.items);
   dev_free(w.item_pref);
   dev_free(w.tcap);
@@ -174,12 +172,12 @@ static void ws_free(Workspace &w) {
   dev_free(w.sort_hist);
   dev_free(w.sort_off);
   dev_free(w.sort_tmp);
-  if (w.h_slots) (void)hipHostFree(w.h_slots);
-  if (w.h_ranges) (void)hipHostFree(w.h_ranges);
-  if (w.h_acc) (void)hipHostFree(w.h_acc);
-  if (w.h_counters) (void)hipHostFree(w.h_counters);
+  if (w.h_desc) (void)hipHostFree(w.h_desc);
+  if (w.h_ctl) (void)hipHostFree(w.h_ctl);
   w = Workspace();
 }
+
+static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges);
 
 extern "C" int lge_open(int device, lge_ctx **out) {
   if (!out) return LGE_EINVAL;
@@ -209,9 +207,8 @@ extern "C" int lge_open(int device, lge_ctx **out) {
     }
   }
   Workspace &w = ctx->ws;
-  if (dev_alloc(&w.counters, 32) != LGE_OK ||
-      hipHostMalloc((void **)&w.h_counters, 32 * sizeof(unsigned long long), 0) != hipSuccess ||
-      dev_alloc(&w.sort_hist, kSortKeys) != LGE_OK || dev_alloc(&w.sort_off, kSortKeys) != LGE_OK ||
+  if (ws_reserve(ctx, 0, 16, 16) != LGE_OK || dev_alloc(&w.sort_hist, kSortKeys) != LGE_OK ||
+      dev_alloc(&w.sort_off, kSortKeys) != LGE_OK ||
       dev_alloc(&w.sort_tmp, scan_tmp_size(kSortKeys)) != LGE_OK) {
     lge_close(ctx);
     return LGE_ENOMEM;
@@ -275,34 +272,42 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     if ((rc = dev_alloc(&w.sort_b, cap)) != LGE_OK) return rc;
     w.cap_edges = cap;
   }
-  if (slots > w.cap_slots) {
-    int32_t cap = std::max<int32_t>(slots, 16);
-    dev_free(w.slots);
-    dev_free(w.acc);
-    if (w.h_slots) (void)hipHostFree(w.h_slots);
-    if (w.h_acc) (void)hipHostFree(w.h_acc);
-    w.h_slots = nullptr;
-    w.h_acc = nullptr;
-    w.cap_slots = 0;
+  if (slots > w.cap_slots || ranges > w.cap_ranges) {
+    const int32_t cs = std::max(std::max<int32_t>(slots, w.cap_slots), 16);
+    const int32_t cr = std::max(std::max<int32_t>(ranges, w.cap_ranges), 16);
+    dev_free(w.ctl);
+    if (w.desc) (void)hipFree(w.desc);
+    if (w.h_desc) (void)hipHostFree(w.h_desc);
+    if (w.h_ctl) (void)hipHostFree(w.h_ctl);
+    w.desc = w.h_desc = nullptr;
+    w.h_ctl = nullptr;
+    w.cap_slots = w.cap_ranges = 0;
+    const int64_t nctl = kNumCtrs + (int64_t)cs * kAccSlots * 2;
+    const size_t ndesc = (size_t)cr * sizeof(RangeDesc) + (size_t)cs * sizeof(SlotDesc);
     int rc;
-    if ((rc = dev_alloc(&w.slots, cap)) != LGE_OK) return rc;
-    if ((rc = dev_alloc(&w.acc, (int64_t)cap * kAccSlots * 2)) != LGE_OK) return rc;
-    if (hipHostMalloc((void **)&w.h_slots, (size_t)cap * sizeof(SlotDesc), 0) != hipSuccess) return LGE_ENOMEM;
-    if (hipHostMalloc((void **)&w.h_acc, (size_t)cap * kAccSlots * 2 * sizeof(unsigned long long), 0) !=
-        hipSuccess)
+    if ((rc = dev_alloc(&w.ctl, nctl)) != LGE_OK) return rc;
+    if (hipMalloc(&w.desc, ndesc) != hipSuccess) {
+      w.desc = nullptr;
       return LGE_ENOMEM;
-    w.cap_slots = cap;
-  }
-  if (ranges > w.cap_ranges) {
-    int32_t cap = std::max<int32_t>(ranges, 16);
-    dev_free(w.ranges);
-    if (w.h_ranges) (void)hipHostFree(w.h_ranges);
-    w.h_ranges = nullptr;
-    w.cap_ranges = 0;
-    int rc;
-    if ((rc = dev_alloc(&w.ranges, cap)) != LGE_OK) return rc;
-    if (hipHostMalloc((void **)&w.h_ranges, (size_t)cap * sizeof(RangeDesc), 0) != hipSuccess) return LGE_ENOMEM;
-    w.cap_ranges = cap;
+    }
+    if (hipHostMalloc((void **)&w.h_ctl, (size_t)nctl * sizeof(unsigned long long), 0) != hipSuccess) {
+      w.h_ctl = nullptr;
+      return LGE_ENOMEM;
+    }
+    if (hipHostMalloc(&w.h_desc, ndesc, 0) != hipSuccess) {
+      w.h_desc = nullptr;
+      return LGE_ENOMEM;
+    }
+    w.counters = w.ctl;
+    w.acc = w.ctl + kNumCtrs;
+    w.h_counters = w.h_ctl;
+    w.h_acc = w.h_ctl + kNumCtrs;
+    w.ranges = (RangeDesc *)w.desc;
+    w.slots = (SlotDesc *)((char *)w.desc + (size_t)cr * sizeof(RangeDesc));
+    w.h_ranges = (RangeDesc *)w.h_desc;
+    w.h_slots = (SlotDesc *)((char *)w.h_desc + (size_t)cr * sizeof(RangeDesc));
+    w.cap_slots = cs;
+    w.cap_ranges = cr;
   }
   return LGE_OK;
 }
@@ -973,12 +978,16 @@ static Bins make_bins(Workspace &w) {
     b.a[c] = w.bin_a[c];
     b.b[c] = w.bin_b[c];
   }
-  b.count = w.counters;
-  b.cursor = w.counters + 3;
-  b.words = w.counters + 6;
-  b.alg = w.counters + 12;
-  b.xcd_cursor = w.counters + 16;
+  b.count = w.counters + kCtrCount;
+  b.cursor = w.counters + kCtrCursor;
+  b.words = w.counters + kCtrWords;
+  b.alg = w.counters + kCtrAlg;
+  b.xcd_cursor = w.counters + kCtrXcd;
+  b.lds_xcd = w.counters + kCtrLdsXcd;
+  b.gtot = w.counters + kCtrItems;
   b.cap = w.cap_edges;
+  b.cap_items = w.cap_items;
+  b.cap_tlist = w.cap_tlist;
   return b;
 }
 
@@ -994,11 +1003,15 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     total += jobs[j].e1 - jobs[j].e0;
     nslots += lge_job_slots(jobs[j]);
   }
-  int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), nslots, njobs);
+  // accumulator replicas per slot: few slots are shared by many workgroups,
+  // whose final atomics would otherwise queue on the same few cache lines
+  const int reps = std::min(kAccReplicas, std::max(1, kAccReplicaBudget / std::max(nslots, 1)));
+  int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), nslots * reps, njobs);
   if (rc != LGE_OK) return rc;
   Workspace &w = ctx->ws;
   hipStream_t s = ctx->stream;
   const KernelCfg cfg = make_cfg(ctx, opts);
+  const int64_t rep_words = (int64_t)reps * kAccSlots * 2;
   int64_t pref = 0;
   int slot0 = 0;
   for (int j = 0; j < njobs; ++j) {
@@ -1025,7 +1038,9 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     sd.p = jobs[j].p;
     sd.p_lo = jobs[j].p_lo;
     sd.seed = jobs[j].seed;
-    sd.acc = w.acc + (int64_t)slot0 * kAccSlots * 2;
+    sd.acc = w.acc + (int64_t)slot0 * rep_words;
+    sd.acc_reps = reps;
+    sd.acc_pad = 0;
     sd.micro = jobs[j].micro;
     sd.micro_base = jobs[j].e0 - jobs[j].eid_base;
     sd.micro_len = jobs[j].e1 - jobs[j].e0;
@@ -1036,7 +1051,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
     for (int l = 0; l < kWeightLevels; ++l) sd.plev[l] = jobs[j].plev ? jobs[j].plev[l] : 0.0;
     for (int l = 1; l < lge_job_slots(jobs[j]); ++l) {  // one accumulator slot per class
       w.h_slots[slot0 + l] = sd;
-      w.h_slots[slot0 + l].acc = w.acc + (int64_t)(slot0 + l) * kAccSlots * 2;
+      w.h_slots[slot0 + l].acc = w.acc + (int64_t)(slot0 + l) * rep_words;
     }
     RangeDesc &rd = w.h_ranges[j];
     rd.slot = slot0;
@@ -1049,60 +1064,101 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   }
   ctx->timing = lge_timing();
   hipEvent_t *ev = ctx->ev;
-  LGE_HIP(hipMemcpyAsync(w.slots, w.h_slots, (size_t)nslots * sizeof(SlotDesc), hipMemcpyHostToDevice, s));
-  LGE_HIP(hipMemcpyAsync(w.ranges, w.h_ranges, (size_t)njobs * sizeof(RangeDesc), hipMemcpyHostToDevice, s));
-  LGE_HIP(launch_zero_u64(w.counters, 32, s));
-  LGE_HIP(launch_zero_u64(w.acc, (int64_t)nslots * kAccSlots * 2, s));
+  // Could any job have split-class edges?  (An endpoint above the workgroup
+  // bound; otherwise the class stays empty and its kernels are not enqueued.)
+  bool split = false;
+  for (int j = 0; j < njobs; ++j) split = split || jobs[j].g->max_deg > cfg.block_max_deg;
+  if (split && (w.cap_items == 0 || w.cap_tlist == 0)) {  // first use: a modest start, grown on demand
+    if ((rc = ws_reserve_items(ctx, 1 << 14)) != LGE_OK) return rc;
+    if ((rc = ws_reserve_tlist(ctx, 1 << 20)) != LGE_OK) return rc;
+  }
+  // Everything is enqueued at once: each kernel reads the sizes it needs
+  // (class counts, split-class totals) from the device counters, and grids
+  // are sized by `total`, which bounds every class count.
+  // one copy of the descriptors (all range entries, then the used slots),
+  // one kernel zeroing the counters and the used accumulators
+  const size_t desc_bytes = (size_t)w.cap_ranges * sizeof(RangeDesc) + (size_t)nslots * sizeof(SlotDesc);
+  const int64_t ctl_words = kNumCtrs + (int64_t)nslots * rep_words;
+  LGE_HIP(hipMemcpyAsync(w.desc, w.h_desc, desc_bytes, hipMemcpyHostToDevice, s));
+  LGE_HIP(launch_zero_u64(w.ctl, ctl_words, s));
   Bins bins = make_bins(w);
   LGE_HIP(hipEventRecord(ev[0], s));
   LGE_HIP(launch_sample_bin(w.slots, w.ranges, njobs, total, bins, cfg, s));
   LGE_HIP(hipEventRecord(ev[1], s));
-  LGE_HIP(hipMemcpyAsync(w.h_counters, w.counters, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  LGE_HIP(hipStreamSynchronize(s));
-  const int64_t nw = (int64_t)w.h_counters[0], nb = (int64_t)w.h_counters[1], ng = (int64_t)w.h_counters[2];
   LGE_HIP(hipEventRecord(ev[2], s));
-  LGE_HIP(launch_count_wave(w.slots, bins, nw, cfg, s));
+  LGE_HIP(launch_count_wave(w.slots, bins, total, cfg, s));
   LGE_HIP(hipEventRecord(ev[3], s));
-  LGE_HIP(launch_count_block(w.slots, bins, nb, cfg, s));
+  LGE_HIP(launch_count_block(w.slots, bins, total, cfg, s));
   LGE_HIP(hipEventRecord(ev[4], s));
-  if (ng == 0) {
+  // split class: ordering, per-edge work items and T_e capacities, their
+  // scans (totals into the device counters), then the tail: item map,
+  // classify, bit sets, counting, fold.  The tail kernels do nothing when the
+  // totals exceed the item or T_e buffers; the host then grows them and runs
+  // the tail again (the class's lists, items and offsets stay valid).
+  auto split_tail = [&](Bins &bb) -> int {
+    LGE_HIP(launch_item_fill(bb, w.item_pref, w.items, w.tbase, total, w.item_edge, w.gacc, s));
+    LGE_HIP(launch_global_classify(w.slots, bb, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.tmask,
+                                   w.gacc, cfg, s));
+    LGE_HIP(launch_global_tbits(w.slots, bb, total, w.tbase, w.tlist, w.tbw, w.tbi, w.gacc, s));
     LGE_HIP(hipEventRecord(ev[6], s));
-    LGE_HIP(hipEventRecord(ev[7], s));
-  }
-  if (ng > 0) {
+    LGE_HIP(launch_count_global(w.slots, bb, w.item_pref, w.items, w.item_edge, w.tlist, w.tbw, w.tbi, w.tmask,
+                                w.gacc, cfg, s));
+    LGE_HIP(hipEventRecord(ev[7], s));  // the counting kernel alone, for its roofline
+    LGE_HIP(launch_global_finish(w.slots, bb, total, w.items, w.gacc, s));
+    return LGE_OK;
+  };
+  if (split) {
     if (cfg.flags & kOptSortHub) {
-      LGE_HIP(launch_sort_global(w.slots, bins, ng, w.sort_slot, w.sort_a, w.sort_b, w.sort_hist, w.sort_off,
+      LGE_HIP(launch_sort_global(w.slots, bins, total, w.sort_slot, w.sort_a, w.sort_b, w.sort_hist, w.sort_off,
                                  w.sort_tmp, s));
       bins.slot[kClassGlobal] = w.sort_slot;
       bins.a[kClassGlobal] = w.sort_a;
       bins.b[kClassGlobal] = w.sort_b;
     }
-    LGE_HIP(launch_global_prep(w.slots, bins, ng, cfg.global_chunk, w.items, w.tcap, w.gacc, s));
-    LGE_HIP(launch_scan_i64(w.items, w.item_pref, ng, w.scan_tmp, s));
-    LGE_HIP(launch_scan_i64(w.tcap, w.tbase, ng, w.scan_tmp, s));
-    int64_t *hl = (int64_t *)w.h_counters + 16;
-    LGE_HIP(hipMemcpyAsync(hl, w.tbase + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LGE_HIP(hipMemcpyAsync(hl + 1, w.tcap + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LGE_HIP(hipMemcpyAsync(hl + 2, w.item_pref + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LGE_HIP(hipMemcpyAsync(hl + 3, w.items + ng - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    LGE_HIP(hipStreamSynchronize(s));
-    if ((rc = ws_reserve_tlist(ctx, hl[0] + hl[1])) != LGE_OK) return rc;
-    if ((rc = ws_reserve_items(ctx, hl[2] + hl[3])) != LGE_OK) return rc;
-    LGE_HIP(launch_item_fill(w.item_pref, w.items, w.tbase, ng, w.item_edge, w.gacc, s));
-    LGE_HIP(launch_global_classify(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tbase, w.tlist, w.tmask,
-                                   w.gacc, cfg, s));
-    LGE_HIP(launch_global_tbits(w.slots, bins, ng, w.tbase, w.tlist, w.tbw, w.tbi, w.gacc, s));
+    LGE_HIP(launch_global_prep(w.slots, bins, total, cfg.global_chunk, w.items, w.tcap, w.gacc, s));
+    LGE_HIP(launch_global_scans(bins, w.items, w.item_pref, w.tcap, w.tbase, w.scan_tmp, s));
+    if ((rc = split_tail(bins)) != LGE_OK) return rc;
+  } else {
     LGE_HIP(hipEventRecord(ev[6], s));
-    LGE_HIP(launch_count_global(w.slots, bins, ng, w.item_pref, w.items, w.item_edge, w.tlist, w.tbw, w.tbi,
-                                w.tmask, w.gacc, cfg, s));
-    LGE_HIP(hipEventRecord(ev[7], s));  // the counting kernel alone, for its roofline
-    LGE_HIP(launch_global_finish(w.slots, ng, w.items, w.gacc, s));
+    LGE_HIP(hipEventRecord(ev[7], s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
-  LGE_HIP(hipMemcpyAsync(w.h_acc, w.acc, (size_t)nslots * kAccSlots * 2 * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, s));
-  LGE_HIP(hipMemcpyAsync(w.h_counters, w.counters, 15 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  LGE_HIP(hipStreamSynchronize(s));
+  LGE_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, (size_t)ctl_words * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  LGE_HIP(hipStreamSynchronize(s));  // the sequence's only wait, unless the split lists outgrew their buffers
+  int64_t reruns = 0;
+  if (split && !split_fits(bins, w.h_counters[kCtrItems], w.h_counters[kCtrTList])) {
+    // grow to the totals the scans found and run the tail again; the
+    // accumulators hold the other classes' sums, the tail adds the split class
+    if ((rc = ws_reserve_items(ctx, (int64_t)w.h_counters[kCtrItems])) != LGE_OK) return rc;
+    if ((rc = ws_reserve_tlist(ctx, (int64_t)w.h_counters[kCtrTList])) != LGE_OK) return rc;
+    bins.cap_items = w.cap_items;
+    bins.cap_tlist = w.cap_tlist;
+    if (!split_fits(bins, w.h_counters[kCtrItems], w.h_counters[kCtrTList])) return LGE_EINTERNAL;
+    if ((rc = split_tail(bins)) != LGE_OK) return rc;
+    LGE_HIP(hipEventRecord(ev[5], s));
+    LGE_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, (size_t)ctl_words * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           s));
+    LGE_HIP(hipStreamSynchronize(s));
+    reruns = 1;
+  }
+  // add up each slot's replicas (exact 128-bit sums) and pack the slots:
+  // slot k's sums end at h_acc + k * kAccSlots * 2, as the callers read them
+  if (reps > 1) {
+    for (int k = 0; k < nslots; ++k) {
+      unsigned long long sum[kAccSlots * 2];
+      const unsigned long long *src = w.h_acc + (int64_t)k * rep_words;
+      for (int q = 0; q < kAccSlots; ++q) {
+        u128 v = 0;
+        for (int r = 0; r < reps; ++r) {
+          const unsigned long long *x = src + (int64_t)r * kAccSlots * 2 + 2 * q;
+          v += ((u128)x[1] << 64) | (u128)x[0];
+        }
+        sum[2 * q] = (unsigned long long)v;
+        sum[2 * q + 1] = (unsigned long long)(v >> 64);
+      }
+      memcpy(w.h_acc + (int64_t)k * kAccSlots * 2, sum, sizeof(sum));
+    }
+  }
   lge_timing &t = ctx->timing;
   float ms = 0;
   if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) t.total_ms = ms;
@@ -1111,10 +1167,16 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) t.count_ms[1] = ms;
   if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) t.count_ms[2] = ms;
   if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
-  for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[c];
-  for (int c = 0; c < kNumClasses; ++c) t.words_read[c] = w.h_counters[6 + c];
-  for (int c = 0; c < kNumClasses; ++c) t.alg_bytes[c] = w.h_counters[12 + c];
-  t.launches = 3 + (nw > 0) + (nb > 0) + (ng > 0 ? 7 : 0);
+  for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[kCtrCount + c];
+  for (int c = 0; c < kNumClasses; ++c) {
+    t.words_read[c] = t.alg_bytes[c] = 0;
+    for (int x = 0; x < kXcds; ++x) {
+      t.words_read[c] += w.h_counters[kCtrWords + (kXcds * c + x) * kLine];
+      t.alg_bytes[c] += w.h_counters[kCtrAlg + (kXcds * c + x) * kLine];
+    }
+  }
+  t.launches = 5 + (split ? 16 + 6 * reruns : 0);
+  t.host_waits = 1 + reruns;
   return LGE_OK;
 }
 
@@ -1421,7 +1483,7 @@ static int ensure_core(lge_ctx *ctx, lge_graph *g) {
     return rc;
   }
   hipStream_t s = ctx->stream;
-  unsigned long long *h = ctx->ws.h_counters + 24;  // pinned staging (4 words)
+  unsigned long long *h = ctx->ws.h_counters + kCtrHost;  // pinned staging (4 words)
   auto fail = [&](hipError_t e) {
     cleanup();
     return hip_err(e);

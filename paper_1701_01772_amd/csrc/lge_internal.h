@@ -17,6 +17,11 @@ constexpr int kNumQ = 15;
 constexpr int kAccIdxCount = 28;
 constexpr int kAccIdxWords = 29;
 constexpr int kAccSlots = 32;  // padded; one slot = 32 x (lo, hi) u64 = 512 B
+// Accumulator replicas per slot: kAccReplicas for a launch sequence of few
+// slots, fewer as the slot count grows (kAccReplicaBudget replicas in all,
+// at least one per slot).
+constexpr int kAccReplicas = 32;
+constexpr int kAccReplicaBudget = 2048;
 
 // Edges whose endpoints both have degree <= kHubDeg are counted from LDS
 // tables by one workgroup; the others are split across workgroups.
@@ -66,7 +71,11 @@ struct SlotDesc {
   int64_t n, m;
   double p;
   uint64_t seed;
-  unsigned long long *acc;  // kAccSlots x {lo, hi}
+  unsigned long long *acc;  // acc_reps replicas of kAccSlots x {lo, hi}; workgroup w adds into replica
+                            // w % acc_reps (the host adds the replicas up), which spreads the atomics
+                            // of many workgroups on one slot over several cache lines
+  int32_t acc_reps;
+  int32_t acc_pad;
   double p_lo;              // sample edges with p_lo <= uniform < p (nested samples)
   // per-edge write-out (micro statistics; null otherwise): the counting
   // kernels store t, k4, cyc of edge id e in row e - micro_base of a
@@ -105,6 +114,27 @@ struct RangeDesc {
 // Edge classes (who counts the edge).
 enum EdgeClass { kClassWave = 0, kClassBlock = 1, kClassGlobal = 2, kNumClasses = 3 };
 
+// Device counters of one launch sequence (unsigned long long each, zeroed
+// at its start).  The kernels read every size they need from here, so the
+// host enqueues the whole sequence without waiting for any of them.
+// A device-scope atomic is carried out away from the XCD's L2, and the
+// atomics of all XCDs on one 128-byte line queue behind each other.  So the
+// counters and cursors that many workgroups touch come kXcds at a time
+// (workgroup w uses copy w % kXcds), each copy on a line of its own (kLine
+// words apart), and the host adds the copies up.
+constexpr int kXcds = 8;
+constexpr int kLine = 16;         // unsigned long long per 128-byte line
+constexpr int kCtrCount = 0;      // sampled edges per class (kNumClasses)
+constexpr int kCtrCursor = 3;     // work-queue cursors per class (split class without XCD-local order)
+constexpr int kCtrItems = 6;      // split class: work items in all
+constexpr int kCtrTList = 7;      // split class: T_e entries reserved in all
+constexpr int kCtrHost = 8;       // 4 words of host-side staging (not written by the sequence)
+constexpr int kCtrXcd = 16;       // XCD-local cursors of the split-class queue (kXcds lines)
+constexpr int kCtrLdsXcd = kCtrXcd + kXcds * kLine;       // cursors of the wavefront and workgroup classes
+constexpr int kCtrWords = kCtrLdsXcd + 2 * kXcds * kLine;  // 4-byte words read, per class and XCD
+constexpr int kCtrAlg = kCtrWords + 3 * kXcds * kLine;     // neighbour-iteration bytes, per class and XCD
+constexpr int kNumCtrs = kCtrAlg + 3 * kXcds * kLine;
+
 // Binned work lists: structure of arrays, one per class, capacity `cap` each.
 struct Bins {
   int32_t *slot[kNumClasses];
@@ -112,11 +142,21 @@ struct Bins {
   int32_t *b[kNumClasses];  // side held in the membership table
   unsigned long long *count;   // kNumClasses counters
   unsigned long long *cursor;  // kNumClasses work-queue cursors
-  unsigned long long *words;   // kNumClasses counters of 4-byte words read
-  unsigned long long *alg;     // kNumClasses counters of neighbour-iteration bytes of the sampled edges
+  unsigned long long *words;   // kNumClasses x kXcds counters of 4-byte words read
+  unsigned long long *alg;     // kNumClasses x kXcds counters of neighbour-iteration bytes of the sampled edges
   unsigned long long *xcd_cursor;  // kXcds cursors of the XCD-local split-class queue
-  int64_t cap;
+  unsigned long long *lds_xcd;     // kXcds cursors per LDS class (wavefront, workgroup)
+  unsigned long long *gtot;    // split class: [0] work items, [1] T_e entries (totals of the scans)
+  int64_t cap;                 // entries of each class list
+  int64_t cap_items;           // split class: work-item buffers (item -> edge map, T_e masks)
+  int64_t cap_tlist;           // split class: T_e entry buffers
 };
+
+// The split class's work lists fit their buffers (the tail kernels of the
+// class do nothing otherwise; the host grows the buffers and runs them again).
+__host__ __device__ inline bool split_fits(const Bins &b, unsigned long long items, unsigned long long tl) {
+  return (int64_t)items <= b.cap_items && (int64_t)tl <= b.cap_tlist;
+}
 
 struct KernelCfg {
   int32_t wave_max_deg;
@@ -131,7 +171,6 @@ struct KernelCfg {
 // split-class edge ordering: key = rank of the table-side endpoint in the
 // co-degree table, kSortKeys - 1 for unranked endpoints
 constexpr int kSortKeys = kMaxRanked + 1;
-constexpr int kXcds = 8;
 constexpr uint32_t kOptSortHub = 1u;
 constexpr uint32_t kOptXcdLocal = 2u;
 
@@ -143,6 +182,10 @@ hipError_t launch_graph_upper(const int32_t *row_ptr, const int32_t *col, int64_
 // exclusive scan; tmp must hold scan_tmp_size(len) entries
 hipError_t launch_scan_i64(const int64_t *in, int64_t *out_excl, int64_t len, int64_t *tmp, hipStream_t s);
 int64_t scan_tmp_size(int64_t len);
+// exclusive scan of in[0, *len) with the length read on the device
+// (*len <= cap); *total receives the sum; tmp holds ceil(cap / 1024) entries
+hipError_t launch_scan_dev(const int64_t *in, int64_t *out_excl, const unsigned long long *len, int64_t cap,
+                           int64_t *tmp, unsigned long long *total, hipStream_t s);
 hipError_t launch_graph_edges(const int32_t *row_ptr, const int32_t *col, const int32_t *up_start,
                               const int64_t *eid_base, int64_t n, uint64_t *edges, hipStream_t s);
 hipError_t launch_graph_vol2(const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t *vol2,
@@ -177,34 +220,41 @@ hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int3
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
                              int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);
-hipError_t launch_count_wave(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s);
-hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s);
+// The counting launchers read each class's edge count from bins.count on the
+// device; `bound` (>= that count, e.g. the length of the sampled ranges)
+// only sizes the grids.
+hipError_t launch_count_wave(const SlotDesc *slots, Bins bins, int64_t bound, KernelCfg cfg, hipStream_t s);
+hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t bound, KernelCfg cfg, hipStream_t s);
 // global class: per-edge work items and T_e capacities, T_e lists, counting
-hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t chunk, int64_t *items,
+hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t bound, int32_t chunk, int64_t *items,
                               int64_t *tcap, void *gacc, hipStream_t s);
-// work item -> edge map (item_edge holds the total number of items)
-hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, const int64_t *tbase, int64_t nedges,
-                            int32_t *item_edge, void *gacc, hipStream_t s);
+// the per-edge first work items and T_e offsets (exclusive scans of items
+// and tcap; totals into bins.gtot); tmp: scan scratch for bins.cap entries
+hipError_t launch_global_scans(Bins bins, const int64_t *items, int64_t *item_pref, const int64_t *tcap,
+                               int64_t *tbase, int64_t *tmp, hipStream_t s);
+// work item -> edge map
+hipError_t launch_item_fill(Bins bins, const int64_t *item_pref, const int64_t *items, const int64_t *tbase,
+                            int64_t bound, int32_t *item_edge, void *gacc, hipStream_t s);
 // T_e lists, and per work item the T_e membership of its positions of
 // Gamma(a) (kGlobalChunkMax / 64 words per item)
-hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
+hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, const int64_t *item_pref,
                                   const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
                                   int32_t *tlist, unsigned long long *tmask, void *gacc, KernelCfg cfg,
                                   hipStream_t s);
 // counting sort of the split-class edges by key (see kSortKeys) into
 // (slot2, a2, b2); hist, off: kSortKeys int64 each; tmp: scan scratch
-hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t *slot2, int32_t *a2,
+hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t bound, int32_t *slot2, int32_t *a2,
                               int32_t *b2, int64_t *hist, int64_t *off, int64_t *tmp, hipStream_t s);
 // the compact ranked-member bit sets of every edge's T_e (non-zero words and
 // their indices at the T_e offsets), then the counting
-hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *tbase,
+hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t bound, const int64_t *tbase,
                                const int32_t *tlist, unsigned long long *tbw, int16_t *tbi, void *gacc, hipStream_t s);
-hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
+hipError_t launch_count_global(const SlotDesc *slots, Bins bins, const int64_t *item_pref,
                                const int64_t *item_cnt, const int32_t *item_edge, const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi,
                                const unsigned long long *tmask, void *gacc, KernelCfg cfg, hipStream_t s);
 // folds the edges counted by several work items into their slots
-hipError_t launch_global_finish(const SlotDesc *slots, int64_t nedges, const int64_t *item_cnt, const void *gacc,
-                                hipStream_t s);
+hipError_t launch_global_finish(const SlotDesc *slots, Bins bins, int64_t bound, const int64_t *item_cnt,
+                                const void *gacc, hipStream_t s);
 size_t gedge_bytes();
 // micro statistics: t of every arc (position j of col holds |Gamma(x) n
 // Gamma(col[j])| for the row x owning j), vertex triangle counts, the

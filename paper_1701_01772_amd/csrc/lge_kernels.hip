@@ -428,6 +428,57 @@ __global__ __launch_bounds__(256) void k_scan_add(int64_t *out, int64_t len,
     if (base + i < len) out[base + i] += off;
 }
 
+// The same scan with the length read on the device (the work lists of a
+// launch sequence are sized by earlier kernels of the sequence): grid-stride
+// blocks of kScanBlock elements, one workgroup turning the block sums into
+// block offsets (and writing the total), then the add.
+__global__ __launch_bounds__(256) void k_scan_dev_blocks(const int64_t *__restrict__ in, int64_t *out,
+                                                         const unsigned long long *__restrict__ len_p,
+                                                         int64_t *block_sums) {
+  __shared__ int64_t sh[256];
+  const int64_t len = (int64_t)*len_p;
+  const int64_t nb = (len + kScanBlock - 1) / kScanBlock;
+  for (int64_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {  // uniform per block
+    const int64_t base = bi * kScanBlock + threadIdx.x * 4;
+    int64_t v[4];
+    for (int i = 0; i < 4; ++i) v[i] = base + i < len ? in[base + i] : 0;
+    const int64_t total = block_exclusive_scan_256x4(v, sh);
+    for (int i = 0; i < 4; ++i)
+      if (base + i < len) out[base + i] = v[i];
+    if (threadIdx.x == 0) block_sums[bi] = total;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_dev_sums(int64_t *block_sums, const unsigned long long *__restrict__ len_p,
+                                                       unsigned long long *total) {
+  __shared__ int64_t sh[256];
+  const int64_t len = (int64_t)*len_p;
+  const int64_t nb = (len + kScanBlock - 1) / kScanBlock;
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanBlock) {  // uniform
+    const int64_t base = b0 + threadIdx.x * 4;
+    int64_t v[4];
+    for (int i = 0; i < 4; ++i) v[i] = base + i < nb ? block_sums[base + i] : 0;
+    const int64_t t = block_exclusive_scan_256x4(v, sh);
+    for (int i = 0; i < 4; ++i)
+      if (base + i < nb) block_sums[base + i] = carry + v[i];
+    carry += t;
+  }
+  if (threadIdx.x == 0 && total) *total = (unsigned long long)carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_dev_add(int64_t *out, const unsigned long long *__restrict__ len_p,
+                                                      const int64_t *__restrict__ offsets) {
+  const int64_t len = (int64_t)*len_p;
+  const int64_t nb = (len + kScanBlock - 1) / kScanBlock;
+  for (int64_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+    const int64_t off = offsets[bi];
+    const int64_t base = bi * kScanBlock + threadIdx.x * 4;
+    for (int i = 0; i < 4; ++i)
+      if (base + i < len) out[base + i] += off;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sampling and binning (a pass over the canonical edge ids of every range)
 // ---------------------------------------------------------------------------
@@ -559,7 +610,7 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
 #pragma unroll
   for (int c = 0; c < kNumClasses; ++c) {
     const unsigned long long v = wave_sum_u64(algc[c]);
-    if (lane == 0 && v) atomicAdd(&bins.alg[c], v);
+    if (lane == 0 && v) atomicAdd(&bins.alg[(c * kXcds + blockIdx.x % kXcds) * kLine], v);
   }
 }
 
@@ -847,7 +898,11 @@ struct SlotAcc {
   }
   __device__ void flush(const SlotDesc *__restrict__ slots) {
     const int lane = threadIdx.x & 63;
-    if (slot >= 0 && lane < kAccSlots && acc != 0) atomic_add_u128(slots[slot].acc + 2 * lane, acc);
+    if (slot >= 0 && lane < kAccSlots && acc != 0) {
+      const SlotDesc &S = slots[slot];
+      const int64_t r = (int64_t)(blockIdx.x % (unsigned)S.acc_reps);
+      atomic_add_u128(S.acc + r * (kAccSlots * 2) + 2 * lane, acc);
+    }
     acc = 0;
   }
   __device__ void add(const SlotDesc *__restrict__ slots, int32_t s, int64_t n, int64_t m, int64_t da, int64_t db,
@@ -883,6 +938,9 @@ struct SlotAcc {
 // 4*(2 + probe cost) scaled by probe_ratio / 4.
 // ---------------------------------------------------------------------------
 
+// workgroups per XCD that take blocks from the other XCDs' queues
+constexpr int kLdsStealers = 16;
+
 constexpr uint32_t kModeLook = 0x40000000u;  // S_a: look Gamma(b)\{a} up; T_e: degT by looking T_e up
 constexpr uint32_t kModeAux = 0x20000000u;   // S_a: cbx tabulated (no units); T_e: cax by look-ups
 
@@ -910,8 +968,9 @@ __device__ __forceinline__ bool w_has(const SlotDesc &S, int32_t w, int32_t wbeg
 template <int NT, int CAP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_count_lds(const SlotDesc *__restrict__ slots, const int32_t *__restrict__ bslot,
                                                   const int32_t *__restrict__ ba, const int32_t *__restrict__ bb,
-                                                  int64_t nedges, unsigned long long *cursor,
-                                                  unsigned long long *words_out, int32_t probe_ratio, int32_t chunk) {
+                                                  const unsigned long long *__restrict__ ncount,
+                                                  unsigned long long *xcd_cursor,
+                                                  unsigned long long *words_out, int32_t probe_ratio, int32_t max_chunk) {
   constexpr int HS = 2 * CAP;
   __shared__ uint32_t htab[HS];
   __shared__ uint32_t wl_v[CAP];
@@ -922,40 +981,69 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
   __shared__ int32_t sh_cnt[4];
   __shared__ int32_t carry_sh[NT / kWave + 1];
   __shared__ unsigned long long red[NT / kWave];
-  __shared__ unsigned long long sh_e;
+  __shared__ long long sh_e0, sh_e1;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t nedges = (int64_t)*ncount;  // the class's edges, binned by the sampling kernel
+  if (nedges == 0) return;  // uniform
   SlotAcc acc;
   acc.init();
   unsigned long long words = 0;
+  // XCD-local queues: the class list is cut into blocks of `run` consecutive
+  // edges, block j in queue j % kXcds (one queue when the grid is not a
+  // multiple of kXcds), so every queue sees the same mix of light and heavy
+  // edges (heavy ones cluster: the rows of hubs).  The workgroups of XCD x
+  // (blockIdx % kXcds) take blocks from queue x, each claim one atomic on
+  // that queue's own cache line; once it is empty only kLdsStealers of them
+  // per XCD go on to the other queues, which keeps the failed claims at the
+  // end few.  A block mostly keeps one slot (the register sums are flushed
+  // when it changes); about four blocks per workgroup keep the tail short.
+  const int nseg = gridDim.x % kXcds == 0 ? kXcds : 1;
+  const int my_seg = (int)(blockIdx.x % (unsigned)nseg);
+  int64_t run = nedges / (4 * (int64_t)gridDim.x);
+  run = run < 1 ? 1 : (run > max_chunk ? max_chunk : run);
+  const int64_t nblk = (nedges + run - 1) / run;
+  const bool stealer = (int64_t)(blockIdx.x / (unsigned)nseg) < kLdsStealers;
+  int seg_off = 0;  // thread 0's position in the segment order
 
   for (;;) {
-    if (tid == 0) sh_e = atomicAdd(cursor, (unsigned long long)chunk);
+    if (tid == 0) {
+      long long e0 = -1, e1 = -1;
+      while (seg_off < nseg && (seg_off == 0 || stealer)) {
+        const int sg = (my_seg + seg_off) % nseg;
+        const int64_t j = (int64_t)atomicAdd(&xcd_cursor[sg * kLine], 1ull) * nseg + sg;
+        if (j < nblk) {
+          e0 = j * run;
+          e1 = e0 + run < nedges ? e0 + run : nedges;
+          break;
+        }
+        ++seg_off;
+      }
+      sh_e0 = e0;
+      sh_e1 = e1;
+    }
     __syncthreads();
-    const int64_t e0 = (int64_t)sh_e;
+    const int64_t e0 = sh_e0, e1 = sh_e1;
     __syncthreads();
-    if (e0 >= nedges) break;
-    const int64_t e1 = e0 + chunk < nedges ? e0 + chunk : nedges;
+    if (e0 < 0) break;
     for (int64_t e = e0; e < e1; ++e) {
       const int32_t slot = bslot[e];
       const int32_t a = ba[e], b = bb[e];
       const SlotDesc &S = slots[slot];
-      const int32_t *__restrict__ rp = S.row_ptr;
       const int32_t *__restrict__ col = S.col;
-      const int32_t abeg = rp[a], aend = rp[a + 1], bbeg = rp[b], bend = rp[b + 1];
-      const int da = aend - abeg, db = bend - bbeg;
+      // endpoint records (row start, degree, rank, co-degree row / column)
+      const int4 ra4 = S.vinfo[a], rb4 = S.vinfo[b];
+      const int32_t abeg = ra4.x, bbeg = rb4.x;
+      const int da = ra4.y, db = rb4.y;
       // an edge with a small scan side and a large b (binned here by the
       // sampling kernel): Gamma(b) stays in b's hub table, the LDS table holds T_e
       const bool bhub = db > CAP;
-      // endpoint records for the co-degree reads, loaded early
+      // ranks and rows for the co-degree reads
       const bool has_ranks = probe_ratio > 0 && S.hc > 0;
-      int4 va = make_int4(0, 0, -1, -1), vb = va;
-      if (has_ranks) {
-        va = S.vinfo[a];
-        vb = S.vinfo[b];
-      }
+      const int4 va = has_ranks ? ra4 : make_int4(0, 0, -1, -1);
+      const int4 vb = has_ranks ? rb4 : make_int4(0, 0, -1, -1);
       const uint32_t *__restrict__ btab = bhub ? S.htab + S.hoff[b] : nullptr;
       const int blg = bhub ? table_log(db) : 0;
       const int lg = table_log(bhub ? da : db);
@@ -996,10 +1084,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
         pos0 = __shfl(pos0, 0);
         if (valid) {
           const int pos = pos0 + __popcll(vm & lt_mask);
-          const int32_t wb = rp[x], we = rp[x + 1];
+          const int4 vx = S.vinfo[x];
           wl_v[pos] = (uint32_t)x | (isT ? kTag : 0u);
-          wl_beg[pos] = wb;
-          wl_deg[pos] = we - wb;
+          wl_beg[pos] = vx.x;
+          wl_deg[pos] = vx.y;
           wl_pref[pos] = (int32_t)rh;  // until the mode pass turns it into the unit count
         }
       }
@@ -1164,7 +1252,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
   }
   if (tid < kWave) acc.flush(slots);
   const unsigned long long wsum = block_sum_u64<NT>(words, red);
-  if (tid == 0 && wsum) atomicAdd(words_out, wsum);
+  if (tid == 0 && wsum) atomicAdd(words_out + (blockIdx.x % kXcds) * kLine, wsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -1203,8 +1291,10 @@ static_assert(sizeof(GEdge) == 128, "one GEdge per 128 bytes");
 
 __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict__ slots,
                                                      const int32_t *__restrict__ bslot, const int32_t *__restrict__ ba,
-                                                     const int32_t *__restrict__ bb, int64_t nedges, int32_t chunk,
+                                                     const int32_t *__restrict__ bb,
+                                                     const unsigned long long *__restrict__ ncount, int32_t chunk,
                                                      int64_t *items, int64_t *tcap, GEdge *gacc) {
+  const int64_t nedges = (int64_t)*ncount;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t slot = bslot[e];
@@ -1237,10 +1327,12 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
 }
 
 // the work item -> edge map: item_pref[e] .. item_pref[e] + items[e] - 1 -> e
-__global__ __launch_bounds__(256) void k_item_fill(const int64_t *__restrict__ item_pref,
+__global__ __launch_bounds__(256) void k_item_fill(Bins bins, const int64_t *__restrict__ item_pref,
                                                    const int64_t *__restrict__ items,
-                                                   const int64_t *__restrict__ tbase, int64_t nedges,
+                                                   const int64_t *__restrict__ tbase,
                                                    int32_t *__restrict__ item_edge, GEdge *gacc) {
+  if (!split_fits(bins, bins.gtot[0], bins.gtot[1])) return;  // the host grows the buffers and runs again
+  const int64_t nedges = (int64_t)bins.count[kClassGlobal];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nedges;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = item_pref[e], k = items[e];
@@ -1252,12 +1344,13 @@ __global__ __launch_bounds__(256) void k_item_fill(const int64_t *__restrict__ i
 }
 
 __global__ __launch_bounds__(kPrepNT) void k_global_classify(
-    const SlotDesc *__restrict__ slots, int64_t nedges, const int64_t *__restrict__ item_pref,
+    const SlotDesc *__restrict__ slots, Bins bins, const int64_t *__restrict__ item_pref,
     const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, int32_t *tlist,
     unsigned long long *__restrict__ tmask, GEdge *gacc, int32_t chunk, int32_t xcd_local) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
+  const int64_t total_items = (int64_t)bins.gtot[0];
+  if (!split_fits(bins, bins.gtot[0], bins.gtot[1])) return;
   // XCD-local mapping: the workgroups of XCD x = blockIdx % kXcds take
   // segment x of the items, so the items of one table-side endpoint b
   // (adjacent after the hub ordering) probe b's hub table through one L2
@@ -1352,11 +1445,13 @@ __global__ __launch_bounds__(kPrepNT) void k_global_classify(
 // word order) at the edge's T_e offset; one workgroup per edge, once per
 // launch.
 __global__ __launch_bounds__(kPrepNT) void k_global_tbits(const SlotDesc *__restrict__ slots,
-                                                            const int32_t *__restrict__ bslot, int64_t nedges,
+                                                            const int32_t *__restrict__ bslot, Bins bins,
                                                             const int64_t *__restrict__ tbase,
                                                             const int32_t *__restrict__ tlist, GEdge *gacc,
                                                             unsigned long long *__restrict__ tbw,
                                                             int16_t *__restrict__ tbi) {
+  if (!split_fits(bins, bins.gtot[0], bins.gtot[1])) return;
+  const int64_t nedges = (int64_t)bins.count[kClassGlobal];
   __shared__ unsigned long long bits[kBitsWords];
   __shared__ int wcnt[kPrepNT / kWave];
   const int lane = threadIdx.x & 63;
@@ -1438,7 +1533,7 @@ constexpr uint32_t kRTag = 0x40000000u;  // T_e hash key tag: member is ranked
 constexpr int kBitsLds = kBitsWords;  // words of an edge's ranked-member set held in LDS (all of them)
 
 __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_global(
-    const SlotDesc *__restrict__ slots, int64_t nedges, const int64_t *__restrict__ item_pref,
+    const SlotDesc *__restrict__ slots, Bins bins, const int64_t *__restrict__ item_pref,
     const int64_t *__restrict__ item_cnt, const int32_t *__restrict__ item_edge, const int32_t *__restrict__ tlist, const unsigned long long *__restrict__ tbw, const int16_t *__restrict__ tbi,
     const unsigned long long *__restrict__ tmask, GEdge *gacc,
     unsigned long long *cursor, unsigned long long *xcd_cursor, unsigned long long *words_out, int32_t probe_ratio,
@@ -1466,10 +1561,11 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (!split_fits(bins, bins.gtot[0], bins.gtot[1])) return;  // uniform
   unsigned long long words = 0;
   SlotAcc acc;
   acc.init();
-  const int64_t total_items = nedges > 0 ? item_pref[nedges - 1] + item_cnt[nedges - 1] : 0;
+  const int64_t total_items = (int64_t)bins.gtot[0];
   // XCD-local queue: workgroups of XCD x = blockIdx % kXcds drain segment x
   // of the item range first, then the following segments
   const bool xcd_local = (flags & kOptXcdLocal) != 0;
@@ -1485,7 +1581,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     while (seg_off < kXcds) {
       const int sg = (my_seg + seg_off) % kXcds;
       const int64_t lo = total_items * sg / kXcds, hi = total_items * (sg + 1) / kXcds;
-      const long long k = (long long)atomicAdd(&xcd_cursor[sg], 1ull);
+      const long long k = (long long)atomicAdd(&xcd_cursor[sg * kLine], 1ull);
       if (lo + k < hi) return lo + k;
       ++seg_off;
     }
@@ -1814,16 +1910,18 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
   }
   if (tid < kWave) acc.flush(slots);
   const unsigned long long wsum = block_sum_u64<NT>(words, red);
-  if (tid == 0 && wsum) atomicAdd(words_out, wsum);
+  if (tid == 0 && wsum) atomicAdd(words_out + (blockIdx.x % kXcds) * kLine, wsum);
 }
 
 // Edges counted by several work items: their items left k4 (twice the
 // edges inside T_e) and the rest of cyc in the edge's counters; one
 // wavefront per edge turns them into the edge's terms (Alg. 2) and folds
 // them into its slot.
-__global__ __launch_bounds__(256) void k_global_finish(const SlotDesc *__restrict__ slots,
+__global__ __launch_bounds__(256) void k_global_finish(const SlotDesc *__restrict__ slots, Bins bins,
                                                        const GEdge *__restrict__ gacc,
-                                                       const int64_t *__restrict__ item_cnt, int64_t nedges) {
+                                                       const int64_t *__restrict__ item_cnt) {
+  if (!split_fits(bins, bins.gtot[0], bins.gtot[1])) return;
+  const int64_t nedges = (int64_t)bins.count[kClassGlobal];
   SlotAcc acc;
   acc.init();
   const int lane = threadIdx.x & 63;
@@ -2179,7 +2277,8 @@ __device__ __forceinline__ int sort_key(const SlotDesc &S, int32_t b) {
 
 __global__ __launch_bounds__(256) void k_sort_hist(const SlotDesc *__restrict__ slots,
                                                    const int32_t *__restrict__ bslot, const int32_t *__restrict__ bb,
-                                                   int64_t n, int64_t *hist) {
+                                                   const unsigned long long *__restrict__ ncount, int64_t *hist) {
+  const int64_t n = (int64_t)*ncount;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     atomicAdd((unsigned long long *)&hist[sort_key(slots[bslot[e]], bb[e])], 1ull);
 }
@@ -2187,8 +2286,9 @@ __global__ __launch_bounds__(256) void k_sort_hist(const SlotDesc *__restrict__ 
 __global__ __launch_bounds__(256) void k_sort_scatter(const SlotDesc *__restrict__ slots,
                                                       const int32_t *__restrict__ bslot,
                                                       const int32_t *__restrict__ ba, const int32_t *__restrict__ bb,
-                                                      int64_t n, int64_t *off, int32_t *slot2, int32_t *a2,
-                                                      int32_t *b2) {
+                                                      const unsigned long long *__restrict__ ncount, int64_t *off,
+                                                      int32_t *slot2, int32_t *a2, int32_t *b2) {
+  const int64_t n = (int64_t)*ncount;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t sl = bslot[e], b = bb[e];
     const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&off[sort_key(slots[sl], b)], 1ull);
@@ -2239,6 +2339,19 @@ hipError_t launch_scan_i64(const int64_t *in, int64_t *out, int64_t len, int64_t
   err = launch_scan_i64(sums, sums_scanned, nb, tmp + 2 * nb, s);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(256), 0, s, out, len, sums_scanned);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_dev(const int64_t *in, int64_t *out, const unsigned long long *len, int64_t cap, int64_t *tmp,
+                           unsigned long long *total, hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  const int grid = grid_for(cap, kScanBlock, 2048);
+  hipLaunchKernelGGL(k_scan_dev_blocks, dim3(grid), dim3(256), 0, s, in, out, len, tmp);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scan_dev_sums, dim3(1), dim3(256), 0, s, tmp, len, total);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scan_dev_add, dim3(grid), dim3(256), 0, s, out, len, (const int64_t *)tmp);
   return hipGetLastError();
 }
 
@@ -2331,94 +2444,102 @@ hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int
 }
 
 template <int NT, int CAP>
-static hipError_t launch_lds(const SlotDesc *slots, Bins bins, int cls, int64_t nedges, int grid_cap,
+static hipError_t launch_lds(const SlotDesc *slots, Bins bins, int cls, int64_t bound, int grid_cap,
                              int32_t probe_ratio, hipStream_t s) {
-  const int chunk = NT == kWave ? 4 : 1;
-  const int grid = grid_for(nedges, chunk, grid_cap);
+  const int max_chunk = NT == kWave ? 64 : 1;
+  int grid = grid_for(bound, 1, grid_cap);
+  if (grid >= kXcds) grid -= grid % kXcds;  // whole XCD segments
   hipLaunchKernelGGL((k_count_lds<NT, CAP>), dim3(grid), dim3(NT), 0, s, slots, bins.slot[cls], bins.a[cls],
-                     bins.b[cls], nedges, bins.cursor + cls, bins.words + cls, probe_ratio, chunk);
+                     bins.b[cls], bins.count + cls, bins.lds_xcd + kXcds * kLine * cls, bins.words + kXcds * kLine * cls,
+                     probe_ratio, max_chunk);
   return hipGetLastError();
 }
 
-hipError_t launch_count_wave(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
+hipError_t launch_count_wave(const SlotDesc *slots, Bins bins, int64_t bound, KernelCfg cfg, hipStream_t s) {
+  if (bound <= 0) return hipSuccess;
   const int d = cfg.wave_max_deg;
-  if (d <= 64) return launch_lds<kWave, 64>(slots, bins, kClassWave, nedges, cfg.grid_wave, cfg.probe_ratio, s);
-  if (d <= 128) return launch_lds<kWave, 128>(slots, bins, kClassWave, nedges, cfg.grid_wave, cfg.probe_ratio, s);
-  if (d <= 256) return launch_lds<kWave, 256>(slots, bins, kClassWave, nedges, cfg.grid_wave, cfg.probe_ratio, s);
-  return launch_lds<kWave, 512>(slots, bins, kClassWave, nedges, cfg.grid_wave, cfg.probe_ratio, s);
+  if (d <= 64) return launch_lds<kWave, 64>(slots, bins, kClassWave, bound, cfg.grid_wave, cfg.probe_ratio, s);
+  if (d <= 128) return launch_lds<kWave, 128>(slots, bins, kClassWave, bound, cfg.grid_wave, cfg.probe_ratio, s);
+  if (d <= 256) return launch_lds<kWave, 256>(slots, bins, kClassWave, bound, cfg.grid_wave, cfg.probe_ratio, s);
+  return launch_lds<kWave, 512>(slots, bins, kClassWave, bound, cfg.grid_wave, cfg.probe_ratio, s);
 }
 
-hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t nedges, KernelCfg cfg, hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
-  return launch_lds<256, kHubDeg>(slots, bins, kClassBlock, nedges, cfg.grid_block, cfg.probe_ratio, s);
+hipError_t launch_count_block(const SlotDesc *slots, Bins bins, int64_t bound, KernelCfg cfg, hipStream_t s) {
+  if (bound <= 0) return hipSuccess;
+  return launch_lds<256, kHubDeg>(slots, bins, kClassBlock, bound, cfg.grid_block, cfg.probe_ratio, s);
 }
 
-hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t chunk, int64_t *items,
+hipError_t launch_global_prep(const SlotDesc *slots, Bins bins, int64_t bound, int32_t chunk, int64_t *items,
                               int64_t *tcap, void *gacc, hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_global_prep, dim3(grid_for(nedges, 256, 8192)), dim3(256), 0, s, slots,
-                     bins.slot[kClassGlobal], bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, chunk, items, tcap,
-                     (GEdge *)gacc);
+  if (bound <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_global_prep, dim3(grid_for(bound, 256, 8192)), dim3(256), 0, s, slots,
+                     bins.slot[kClassGlobal], bins.a[kClassGlobal], bins.b[kClassGlobal], bins.count + kClassGlobal,
+                     chunk, items, tcap, (GEdge *)gacc);
   return hipGetLastError();
 }
 
-hipError_t launch_item_fill(const int64_t *item_pref, const int64_t *items, const int64_t *tbase, int64_t nedges,
-                            int32_t *item_edge, void *gacc, hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_item_fill, dim3(grid_for(nedges, 256, 8192)), dim3(256), 0, s, item_pref, items, tbase,
-                     nedges, item_edge, (GEdge *)gacc);
+hipError_t launch_global_scans(Bins bins, const int64_t *items, int64_t *item_pref, const int64_t *tcap,
+                               int64_t *tbase, int64_t *tmp, hipStream_t s) {
+  hipError_t e = launch_scan_dev(items, item_pref, bins.count + kClassGlobal, bins.cap, tmp, bins.gtot, s);
+  if (e != hipSuccess) return e;
+  return launch_scan_dev(tcap, tbase, bins.count + kClassGlobal, bins.cap, tmp, bins.gtot + 1, s);
+}
+
+hipError_t launch_item_fill(Bins bins, const int64_t *item_pref, const int64_t *items, const int64_t *tbase,
+                            int64_t bound, int32_t *item_edge, void *gacc, hipStream_t s) {
+  if (bound <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_fill, dim3(grid_for(bound, 256, 8192)), dim3(256), 0, s, bins, item_pref, items, tbase,
+                     item_edge, (GEdge *)gacc);
   return hipGetLastError();
 }
 
-hipError_t launch_global_finish(const SlotDesc *slots, int64_t nedges, const int64_t *item_cnt, const void *gacc,
-                                hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_global_finish, dim3(grid_for(nedges, 4 * kWave, 1024)), dim3(256), 0, s, slots,
-                     (const GEdge *)gacc, item_cnt, nedges);
+hipError_t launch_global_finish(const SlotDesc *slots, Bins bins, int64_t bound, const int64_t *item_cnt,
+                                const void *gacc, hipStream_t s) {
+  if (bound <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_global_finish, dim3(grid_for(bound, 4 * kWave, 1024)), dim3(256), 0, s, slots, bins,
+                     (const GEdge *)gacc, item_cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
+hipError_t launch_global_classify(const SlotDesc *slots, Bins bins, const int64_t *item_pref,
                                   const int64_t *item_cnt, const int32_t *item_edge, const int64_t *tbase,
                                   int32_t *tlist, unsigned long long *tmask, void *gacc, KernelCfg cfg,
                                   hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_global_classify, dim3(cfg.grid_global * (kGlobalNT / kPrepNT)), dim3(kPrepNT), 0, s, slots,
-                     nedges, item_pref, item_cnt, item_edge, tlist, tmask, (GEdge *)gacc, cfg.global_chunk,
+                     bins, item_pref, item_cnt, item_edge, tlist, tmask, (GEdge *)gacc, cfg.global_chunk,
                      (cfg.flags & kOptXcdLocal) ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t nedges, int32_t *slot2, int32_t *a2,
+hipError_t launch_sort_global(const SlotDesc *slots, Bins bins, int64_t bound, int32_t *slot2, int32_t *a2,
                               int32_t *b2, int64_t *hist, int64_t *off, int64_t *tmp, hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
+  if (bound <= 0) return hipSuccess;
   hipError_t e = launch_zero_u64((unsigned long long *)hist, kSortKeys, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(nedges, 256, 4096)), dim3(256), 0, s, slots, bins.slot[kClassGlobal],
-                     bins.b[kClassGlobal], nedges, hist);
+  hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(bound, 256, 4096)), dim3(256), 0, s, slots, bins.slot[kClassGlobal],
+                     bins.b[kClassGlobal], bins.count + kClassGlobal, hist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_scan_i64(hist, off, kSortKeys, tmp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_scatter, dim3(grid_for(nedges, 256, 4096)), dim3(256), 0, s, slots,
-                     bins.slot[kClassGlobal], bins.a[kClassGlobal], bins.b[kClassGlobal], nedges, off, slot2, a2, b2);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(grid_for(bound, 256, 4096)), dim3(256), 0, s, slots,
+                     bins.slot[kClassGlobal], bins.a[kClassGlobal], bins.b[kClassGlobal], bins.count + kClassGlobal,
+                     off, slot2, a2, b2);
   return hipGetLastError();
 }
 
-hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *tbase,
+hipError_t launch_global_tbits(const SlotDesc *slots, Bins bins, int64_t bound, const int64_t *tbase,
                                const int32_t *tlist, unsigned long long *tbw, int16_t *tbi, void *gacc, hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_global_tbits, dim3(grid_for(nedges, 1, 8192)), dim3(kPrepNT), 0, s, slots,
-                     bins.slot[kClassGlobal], nedges, tbase, tlist, (GEdge *)gacc, tbw, tbi);
+  if (bound <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_global_tbits, dim3(grid_for(bound, 1, 8192)), dim3(kPrepNT), 0, s, slots,
+                     bins.slot[kClassGlobal], bins, tbase, tlist, (GEdge *)gacc, tbw, tbi);
   return hipGetLastError();
 }
 
-hipError_t launch_count_global(const SlotDesc *slots, Bins bins, int64_t nedges, const int64_t *item_pref,
+hipError_t launch_count_global(const SlotDesc *slots, Bins bins, const int64_t *item_pref,
                                const int64_t *item_cnt, const int32_t *item_edge, const int32_t *tlist, const unsigned long long *tbw, const int16_t *tbi,
                                const unsigned long long *tmask, void *gacc, KernelCfg cfg, hipStream_t s) {
-  if (nedges <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, nedges, item_pref,
+  hipLaunchKernelGGL(k_count_global, dim3(cfg.grid_global), dim3(kGlobalNT), 0, s, slots, bins, item_pref,
                      item_cnt, item_edge, tlist, tbw, tbi, tmask, (GEdge *)gacc, bins.cursor + kClassGlobal,
-                     bins.xcd_cursor, bins.words + kClassGlobal, cfg.probe_ratio, cfg.global_chunk, cfg.flags);
+                     bins.xcd_cursor, bins.words + kXcds * kLine * kClassGlobal, cfg.probe_ratio, cfg.global_chunk, cfg.flags);
   return hipGetLastError();
 }
 

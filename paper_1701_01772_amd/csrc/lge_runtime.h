@@ -61,10 +61,17 @@ struct Workspace {
   int32_t *bin_slot[kNumClasses] = {};
   int32_t *bin_a[kNumClasses] = {};
   int32_t *bin_b[kNumClasses] = {};
-  unsigned long long *counters = nullptr;  // count[3], cursor[3], words[3], pad
-  SlotDesc *slots = nullptr;
+  // device control block: kNumCtrs counters followed by the per-slot
+  // accumulators (cap_slots * kAccSlots * 2), zeroed by one kernel and read
+  // back by one copy per launch sequence; pinned host mirror h_ctl
+  unsigned long long *ctl = nullptr;
+  unsigned long long *counters = nullptr;  // ctl
+  unsigned long long *acc = nullptr;       // ctl + kNumCtrs
+  // job descriptors: cap_ranges RangeDesc followed by cap_slots SlotDesc,
+  // written by one copy; pinned host mirror h_desc
+  void *desc = nullptr;
   RangeDesc *ranges = nullptr;
-  unsigned long long *acc = nullptr;  // cap_slots * kAccSlots * 2
+  SlotDesc *slots = nullptr;
   int64_t *items = nullptr;           // cap_edges
   int64_t *item_pref = nullptr;       // cap_edges
   int64_t *tcap = nullptr;            // cap_edges
@@ -87,10 +94,12 @@ struct Workspace {
   int64_t *sort_off = nullptr;   // kSortKeys
   int64_t *sort_tmp = nullptr;   // scan scratch for kSortKeys
   // pinned host staging
-  SlotDesc *h_slots = nullptr;
+  void *h_desc = nullptr;
   RangeDesc *h_ranges = nullptr;
-  unsigned long long *h_acc = nullptr;
-  unsigned long long *h_counters = nullptr;
+  SlotDesc *h_slots = nullptr;
+  unsigned long long *h_ctl = nullptr;
+  unsigned long long *h_counters = nullptr;  // h_ctl
+  unsigned long long *h_acc = nullptr;       // h_ctl + kNumCtrs
 };
 
 struct lge_ctx {

@@ -73,7 +73,7 @@ class Timing(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_float), ("sample_ms", ctypes.c_float), ("count_ms", ctypes.c_float * 3),
                 ("global_prep_ms", ctypes.c_float),
                 ("class_edges", ctypes.c_uint64 * 3), ("words_read", ctypes.c_uint64 * 3),
-                ("launches", ctypes.c_uint64), ("micro_ms", ctypes.c_float), ("pad", ctypes.c_float),
+                ("launches", ctypes.c_uint64), ("micro_ms", ctypes.c_float), ("host_waits", ctypes.c_uint32),
                 ("alg_bytes", ctypes.c_uint64 * 3)]
 
 
@@ -281,11 +281,14 @@ def result_dict(r: Result) -> dict:
     }
 
 
-def lge_estimate(ctx, g, p: float, seed: int, opts: Opts | None = None) -> dict:
-    r = Result()
+def lge_estimate(ctx, g, p: float, seed: int, opts: Opts | None = None, raw: bool = False,
+                 out: Result | None = None):
+    """Result as a dict of Python numbers, or (raw=True) the lge_result
+    struct itself (``out`` when given), skipping the conversion."""
+    r = out if out is not None else Result()
     _check(load().lge_estimate(ctx, g, float(p), int(seed), ctypes.byref(opts) if opts is not None else None,
                                ctypes.byref(r)), "lge_estimate")
-    return result_dict(r)
+    return r if raw else result_dict(r)
 
 
 def lge_estimate_range(ctx, g, p: float, seed: int, e0: int, e1: int, opts: Opts | None = None) -> dict:
@@ -344,8 +347,9 @@ def lge_count_batch(ctx, graphs, p, seed, flags: int = 0, opts: Opts | None = No
     return [result_dict(outs[i]) for i in range(G)]
 
 
-def lge_estimate_many(ctx, graphs, p, seed, opts: Opts | None = None):
-    """graphs: list of graph handles on ctx; p, seed: scalars or per-graph lists."""
+def lge_estimate_many(ctx, graphs, p, seed, opts: Opts | None = None, raw: bool = False):
+    """graphs: list of graph handles on ctx; p, seed: scalars or per-graph
+    lists.  Dicts, or (raw=True) the array of lge_result structs."""
     G = len(graphs)
     arr = (_VP * max(G, 1))(*graphs)
     ps = np.ascontiguousarray(p if np.ndim(p) else [p] * G, dtype=np.float64)
@@ -354,7 +358,7 @@ def lge_estimate_many(ctx, graphs, p, seed, opts: Opts | None = None):
     _check(load().lge_estimate_many(ctx, arr, ps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     ss.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), G,
                                     ctypes.byref(opts) if opts is not None else None, outs), "lge_estimate_many")
-    return [result_dict(outs[i]) for i in range(G)]
+    return outs if raw else [result_dict(outs[i]) for i in range(G)]
 
 
 def lge_last_timing(ctx) -> dict:
@@ -363,7 +367,7 @@ def lge_last_timing(ctx) -> dict:
     return {"total_ms": t.total_ms, "sample_ms": t.sample_ms, "count_ms": list(t.count_ms),
             "global_prep_ms": t.global_prep_ms,
             "class_edges": [int(x) for x in t.class_edges], "words_read": [int(x) for x in t.words_read],
-            "launches": int(t.launches), "micro_ms": t.micro_ms,
+            "launches": int(t.launches), "micro_ms": t.micro_ms, "host_waits": int(t.host_waits),
             "alg_bytes": [int(x) for x in t.alg_bytes]}
 
 
