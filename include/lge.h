@@ -225,6 +225,25 @@ LGE_API int lge_estimate(lge_ctx *ctx, const lge_graph *g, double p, uint64_t se
                  lge_result *out);
 
 /*
+ * lge_estimate without any allocation, for callers that cannot allocate
+ * device or pinned memory during the call: code under HIP graph capture,
+ * tight serving loops, hosts that forbid hipMalloc.  Same arguments and
+ * result as lge_estimate with default options (bit-identical integers and
+ * FP64 values); the call itself makes no hipMalloc, hipHostMalloc or hipFree.
+ * Its workspace is a fixed array of 128 MiB in device memory that every GPU
+ * the library runs on holds from lge_open until the process ends, laid out
+ * for graphs of at most 262,144 edges (2^18), 16,384 split-class work items
+ * and 2,097,152 split-class T_e entries; calls on one GPU share it and are
+ * serialised inside the process (each keeps the array until it returns; the
+ * array keeps the last call's contents, and the call clears what it needs).
+ * Errors: LGE_EINVAL as lge_estimate; LGE_ERANGE when m exceeds 2^18, or when
+ * the sampled split-class work (edges with an endpoint of degree > 1024)
+ * needs more work items or T_e entries than the layout holds (lge_estimate
+ * then serves); LGE_EDEVICE.
+ */
+LGE_API int lge_estimate_noalloc(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, lge_result *out);
+
+/*
  * Estimate restricted to the canonical edge ids [e0, e1): edges outside the
  * range are never sampled; scaling still uses 1/p.  Sums over a partition of
  * [0, m) into ranges add up to the full estimate's integers, which is how

@@ -206,8 +206,21 @@ extern "C" int lge_open(int device, lge_ctx **out) {
       return LGE_EDEVICE;
     }
   }
+  // the device's scratch array for the allocation-free estimate, and its
+  // pinned staging (one range, one slot, kAccReplicas accumulator replicas)
+  if (scratch_address(device, &ctx->scratch) != hipSuccess) {
+    lge_close(ctx);
+    return LGE_EDEVICE;
+  }
+  if (hipHostMalloc(&ctx->na_h_desc, sizeof(RangeDesc) + sizeof(SlotDesc), 0) != hipSuccess ||
+      hipHostMalloc((void **)&ctx->na_h_ctl,
+                    (size_t)(kNumCtrs + (int64_t)kAccReplicas * kAccSlots * 2) * sizeof(unsigned long long),
+                    0) != hipSuccess) {
+    lge_close(ctx);
+    return LGE_ENOMEM;
+  }
   Workspace &w = ctx->ws;
-  if (ws_reserve(ctx, 0, 16, 16) != LGE_OK || dev_alloc(&w.sort_hist, kSortKeys) != LGE_OK ||
+  if (ws_reserve(ctx, 0, kAccReplicas, 16) != LGE_OK || dev_alloc(&w.sort_hist, kSortKeys) != LGE_OK ||
       dev_alloc(&w.sort_off, kSortKeys) != LGE_OK ||
       dev_alloc(&w.sort_tmp, scan_tmp_size(kSortKeys)) != LGE_OK) {
     lge_close(ctx);
@@ -222,6 +235,8 @@ extern "C" int lge_close(lge_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ws_free(ctx->ws);
+  if (ctx->na_h_desc) (void)hipHostFree(ctx->na_h_desc);
+  if (ctx->na_h_ctl) (void)hipHostFree(ctx->na_h_ctl);
   for (auto &e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -995,22 +1010,31 @@ static Bins make_bins(Workspace &w) {
 // ws.h_acc (host) on success.
 int lge_job_slots(const Job &j) { return j.design == kDesignWeighted ? kWeightLevels : 1; }
 
-int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts) {
-  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+// Accumulator replicas per slot for a sequence of nslots slots: few slots
+// are shared by many workgroups, whose final atomics would otherwise queue on
+// the same few cache lines.
+static int acc_replicas(int nslots) {
+  return std::min(kAccReplicas, std::max(1, kAccReplicaBudget / std::max(nslots, 1)));
+}
+
+// The launch sequence of `jobs` on workspace w, whose buffers hold the
+// range length, the slots times acc_replicas(slots) accumulators, the
+// ranges, and (when split-class edges are possible) some items and T_e
+// entries.  Allocates nothing unless can_grow (then w is ctx->ws): when the
+// split-class lists outgrow w's buffers it grows them and runs the class's
+// tail again, otherwise it returns LGE_ERANGE.  On success the per-slot sums
+// are packed at w.h_acc + k * kAccSlots * 2.
+static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, const KernelCfg &cfg, bool can_grow) {
   int64_t total = 0;
   int nslots = 0;
   for (int j = 0; j < njobs; ++j) {
     total += jobs[j].e1 - jobs[j].e0;
     nslots += lge_job_slots(jobs[j]);
   }
-  // accumulator replicas per slot: few slots are shared by many workgroups,
-  // whose final atomics would otherwise queue on the same few cache lines
-  const int reps = std::min(kAccReplicas, std::max(1, kAccReplicaBudget / std::max(nslots, 1)));
-  int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), nslots * reps, njobs);
-  if (rc != LGE_OK) return rc;
-  Workspace &w = ctx->ws;
+  const int reps = acc_replicas(nslots);
+  if (total > w.cap_edges || nslots * reps > w.cap_slots || njobs > w.cap_ranges) return LGE_EINTERNAL;
+  int rc;
   hipStream_t s = ctx->stream;
-  const KernelCfg cfg = make_cfg(ctx, opts);
   const int64_t rep_words = (int64_t)reps * kAccSlots * 2;
   int64_t pref = 0;
   int slot0 = 0;
@@ -1068,10 +1092,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   // bound; otherwise the class stays empty and its kernels are not enqueued.)
   bool split = false;
   for (int j = 0; j < njobs; ++j) split = split || jobs[j].g->max_deg > cfg.block_max_deg;
-  if (split && (w.cap_items == 0 || w.cap_tlist == 0)) {  // first use: a modest start, grown on demand
-    if ((rc = ws_reserve_items(ctx, 1 << 14)) != LGE_OK) return rc;
-    if ((rc = ws_reserve_tlist(ctx, 1 << 20)) != LGE_OK) return rc;
-  }
+  if (split && (w.cap_items == 0 || w.cap_tlist == 0)) return LGE_EINTERNAL;
   // Everything is enqueued at once: each kernel reads the sizes it needs
   // (class counts, split-class totals) from the device counters, and grids
   // are sized by `total`, which bounds every class count.
@@ -1127,6 +1148,7 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   LGE_HIP(hipStreamSynchronize(s));  // the sequence's only wait, unless the split lists outgrew their buffers
   int64_t reruns = 0;
   if (split && !split_fits(bins, w.h_counters[kCtrItems], w.h_counters[kCtrTList])) {
+    if (!can_grow) return LGE_ERANGE;
     // grow to the totals the scans found and run the tail again; the
     // accumulators hold the other classes' sums, the tail adds the split class
     if ((rc = ws_reserve_items(ctx, (int64_t)w.h_counters[kCtrItems])) != LGE_OK) return rc;
@@ -1180,6 +1202,27 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   return LGE_OK;
 }
 
+int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  int64_t total = 0;
+  int nslots = 0;
+  for (int j = 0; j < njobs; ++j) {
+    total += jobs[j].e1 - jobs[j].e0;
+    nslots += lge_job_slots(jobs[j]);
+  }
+  int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), nslots * acc_replicas(nslots), njobs);
+  if (rc != LGE_OK) return rc;
+  const KernelCfg cfg = make_cfg(ctx, opts);
+  Workspace &w = ctx->ws;
+  bool split = false;
+  for (int j = 0; j < njobs; ++j) split = split || jobs[j].g->max_deg > cfg.block_max_deg;
+  if (split && (w.cap_items == 0 || w.cap_tlist == 0)) {  // first use: a modest start, grown on demand
+    if ((rc = ws_reserve_items(ctx, 1 << 14)) != LGE_OK) return rc;
+    if ((rc = ws_reserve_tlist(ctx, 1 << 20)) != LGE_OK) return rc;
+  }
+  return run_sequence(ctx, w, jobs, njobs, cfg, true);
+}
+
 static bool p_ok(double p) { return p > 0.0 && p <= 1.0; }
 
 extern "C" int lge_estimate(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, const lge_opts *opts,
@@ -1191,6 +1234,84 @@ extern "C" int lge_estimate(lge_ctx *ctx, const lge_graph *g, double p, uint64_t
   int rc = lge_run_jobs(ctx, &job, 1, opts);
   if (rc != LGE_OK) return rc;
   lge_finalize(g->n, g->m, p, seed, ctx->ws.h_acc, out);
+  return LGE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free estimate: the launch sequence of lge_estimate on a
+// workspace carved out of the device's scratch array (fixed layout for at
+// most kNoAllocEdges edge ids) with the context's pinned staging.
+// ---------------------------------------------------------------------------
+
+static bool scratch_view(lge_ctx *ctx, Workspace *v) {
+  char *base = (char *)ctx->scratch;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) -> void * {
+    cur = (cur + 255) & ~(size_t)255;
+    void *p = base + cur;
+    cur += bytes;
+    return p;
+  };
+  const int64_t cap = kNoAllocEdges;
+  *v = Workspace();
+  v->cap_edges = cap;
+  for (int c = 0; c < kNumClasses; ++c) {
+    v->bin_slot[c] = (int32_t *)take((size_t)cap * sizeof(int32_t));
+    v->bin_a[c] = (int32_t *)take((size_t)cap * sizeof(int32_t));
+    v->bin_b[c] = (int32_t *)take((size_t)cap * sizeof(int32_t));
+  }
+  v->items = (int64_t *)take((size_t)cap * sizeof(int64_t));
+  v->item_pref = (int64_t *)take((size_t)cap * sizeof(int64_t));
+  v->tcap = (int64_t *)take((size_t)cap * sizeof(int64_t));
+  v->tbase = (int64_t *)take((size_t)cap * sizeof(int64_t));
+  v->gacc = take((size_t)cap * gedge_bytes());
+  v->scan_tmp_len = scan_tmp_size(cap);
+  v->scan_tmp = (int64_t *)take((size_t)v->scan_tmp_len * sizeof(int64_t));
+  v->sort_slot = (int32_t *)take((size_t)cap * sizeof(int32_t));
+  v->sort_a = (int32_t *)take((size_t)cap * sizeof(int32_t));
+  v->sort_b = (int32_t *)take((size_t)cap * sizeof(int32_t));
+  v->cap_items = kNoAllocItems;
+  v->item_edge = (int32_t *)take((size_t)kNoAllocItems * sizeof(int32_t));
+  v->tmask = (unsigned long long *)take((size_t)kNoAllocItems * (kGlobalChunkMax / 64) * sizeof(unsigned long long));
+  v->cap_tlist = kNoAllocTList;
+  v->tlist = (int32_t *)take((size_t)3 * kNoAllocTList * sizeof(int32_t));
+  v->tbw = (unsigned long long *)take((size_t)kNoAllocTList * sizeof(unsigned long long));
+  v->tbi = (int16_t *)take((size_t)kNoAllocTList * sizeof(int16_t));
+  v->cap_slots = kAccReplicas;  // one slot and its replicas
+  v->cap_ranges = 1;
+  v->ctl = (unsigned long long *)take((size_t)(kNumCtrs + (int64_t)kAccReplicas * kAccSlots * 2) *
+                                      sizeof(unsigned long long));
+  v->counters = v->ctl;
+  v->acc = v->ctl + kNumCtrs;
+  v->desc = take(sizeof(RangeDesc) + sizeof(SlotDesc));
+  v->ranges = (RangeDesc *)v->desc;
+  v->slots = (SlotDesc *)((char *)v->desc + sizeof(RangeDesc));
+  // the sort histogram buffers and the pinned staging come from the context
+  v->sort_hist = ctx->ws.sort_hist;
+  v->sort_off = ctx->ws.sort_off;
+  v->sort_tmp = ctx->ws.sort_tmp;
+  v->h_desc = ctx->na_h_desc;
+  v->h_ranges = (RangeDesc *)ctx->na_h_desc;
+  v->h_slots = (SlotDesc *)((char *)ctx->na_h_desc + sizeof(RangeDesc));
+  v->h_ctl = ctx->na_h_ctl;
+  v->h_counters = ctx->na_h_ctl;
+  v->h_acc = ctx->na_h_ctl + kNumCtrs;
+  return cur <= kScratchBytes;
+}
+
+extern "C" int lge_estimate_noalloc(lge_ctx *ctx, const lge_graph *g, double p, uint64_t seed, lge_result *out) {
+  if (!p_ok(p)) return LGE_EINVAL;
+  if (!ctx || !g || !out || g->ctx != ctx) return LGE_EINVAL;
+  if (g->m > kNoAllocEdges) return LGE_ERANGE;
+  if (!ctx->scratch || !ctx->na_h_desc || !ctx->na_h_ctl || !ctx->ws.sort_tmp) return LGE_EDEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
+  Workspace v;
+  if (!scratch_view(ctx, &v)) return LGE_EINTERNAL;  // the layout outgrew the array (a library bug)
+  std::lock_guard<std::mutex> lk(scratch_lock(ctx->device));
+  Job job{g, p, seed, 0, g->m, -1, -1, 0};
+  const int rc = run_sequence(ctx, v, &job, 1, make_cfg(ctx, nullptr), false);
+  if (rc != LGE_OK) return rc;
+  lge_finalize(g->n, g->m, p, seed, v.h_acc, out);
   return LGE_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace lge {
 
 // Number of 128-bit accumulators per estimate slot:
@@ -173,6 +175,20 @@ struct KernelCfg {
 constexpr int kSortKeys = kMaxRanked + 1;
 constexpr uint32_t kOptSortHub = 1u;
 constexpr uint32_t kOptXcdLocal = 2u;
+
+// The allocation-free estimate keeps its whole workspace in one fixed device
+// array per GPU (kScratchBytes, held until the process ends), laid out for a
+// canonical edge-id range of at most kNoAllocEdges ids, at most
+// kNoAllocItems split-class work items and kNoAllocTList T_e entries.
+constexpr int64_t kNoAllocEdges = (int64_t)1 << 18;
+constexpr int64_t kNoAllocItems = (int64_t)1 << 14;
+constexpr int64_t kNoAllocTList = (int64_t)1 << 21;
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+constexpr int kMaxDevices = 64;
+// Device address of the array on `device` (which must be current), looked up
+// once per device; scratch_lock(device) serialises its users in the process.
+hipError_t scratch_address(int device, void **ptr);
+std::mutex &scratch_lock(int device);
 
 // ---- launchers (lge_kernels.hip) ----
 hipError_t launch_graph_validate(const int32_t *row_ptr, const int32_t *col, int64_t n, int *err,

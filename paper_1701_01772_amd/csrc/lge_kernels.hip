@@ -2545,6 +2545,39 @@ hipError_t launch_count_global(const SlotDesc *slots, Bins bins, const int64_t *
 
 size_t gedge_bytes() { return sizeof(GEdge); }
 
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free estimate: a fixed array in device memory
+// (each GPU that loads the library holds its own copy until the process
+// ends).  In host code its name is not a device address; the address comes
+// from hipGetSymbolAddress on each device, once, and only that address is
+// handed to kernels and copies.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_init_mu;
+void *g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_use_mu[kMaxDevices];
+}  // namespace
+
+hipError_t scratch_address(int device, void **ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_init_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+std::mutex &scratch_lock(int device) { return g_scratch_use_mu[device]; }
+
 hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, const int32_t *rcol,
                         int64_t n, int4 *vinfo, hipStream_t s) {
   if (n <= 0) return hipSuccess;

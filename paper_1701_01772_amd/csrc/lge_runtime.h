@@ -106,6 +106,11 @@ struct lge_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   Workspace ws;
+  // allocation-free estimate: the device's scratch array (looked up at open)
+  // and pinned staging for one range, one slot and its accumulator replicas
+  void *scratch = nullptr;
+  void *na_h_desc = nullptr;
+  unsigned long long *na_h_ctl = nullptr;
   lge_opts opts{};
   lge_timing timing{};
   hipEvent_t ev[8] = {};

@@ -148,6 +148,7 @@ def load():
         "lge_graph_m": ([_VP], ctypes.c_int64),
         "lge_estimate": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.POINTER(Result)],
                          ctypes.c_int),
+        "lge_estimate_noalloc": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
         "lge_estimate_range": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
                                 ctypes.POINTER(Opts), ctypes.POINTER(Result)], ctypes.c_int),
         "lge_estimate_async": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, _VP, ctypes.POINTER(Result),
@@ -288,6 +289,14 @@ def lge_estimate(ctx, g, p: float, seed: int, opts: Opts | None = None, raw: boo
     r = out if out is not None else Result()
     _check(load().lge_estimate(ctx, g, float(p), int(seed), ctypes.byref(opts) if opts is not None else None,
                                ctypes.byref(r)), "lge_estimate")
+    return r if raw else result_dict(r)
+
+
+def lge_estimate_noalloc(ctx, g, p: float, seed: int, raw: bool = False, out: Result | None = None):
+    """lge_estimate through the allocation-free entry point (graphs of at
+    most 2^18 edges; workspace in the library's fixed device array)."""
+    r = out if out is not None else Result()
+    _check(load().lge_estimate_noalloc(ctx, g, float(p), int(seed), ctypes.byref(r)), "lge_estimate_noalloc")
     return r if raw else result_dict(r)
 
 
