@@ -68,6 +68,10 @@ extern "C" {
  * many large graphs at once.  Results do not change, only the speed on
  * graphs with many vertices of high degree. */
 #define LGE_FLAG_COMPACT 2u
+/* lge_graph_create_* flag: build no co-degree table, bit rows or co-degree
+ * rows (hub tables only): the smallest state and the shortest build, every
+ * neighbour walked or looked up.  Results do not change, only the speed. */
+#define LGE_FLAG_NO_TABLES 4u
 
 typedef struct lge_ctx lge_ctx;
 typedef struct lge_graph lge_graph;
@@ -218,6 +222,27 @@ LGE_API int lge_graph_destroy(lge_graph *g);
 /* Number of vertices / undirected edges of a graph (host-side, no GPU call). */
 LGE_API int64_t lge_graph_n(const lge_graph *g);
 LGE_API int64_t lge_graph_m(const lge_graph *g);
+
+/*
+ * What a resident graph holds (host-side, no GPU call): sizes, the ranked
+ * vertices of the co-degree table, the co-degree rows, their column floor
+ * (unranked vertices above this degree have a column) and entry width, the
+ * device bytes the library holds for the graph (including state built on
+ * first use by lge_micro / lge_estimate_weighted, excluding adopted device
+ * buffers), and the preprocessing wall time at creation.
+ */
+typedef struct {
+  int64_t n, m;
+  int32_t max_deg;
+  int32_t ranked;
+  int32_t rows;
+  int32_t rows_floor;
+  int32_t rows_width;
+  int32_t pad;
+  uint64_t state_bytes;
+  double build_ms;
+} lge_graph_info;
+LGE_API int lge_graph_query(const lge_graph *g, lge_graph_info *out);
 
 /* Estimate (synchronous on the ctx stream).  p in (0,1] else LGE_EINVAL;
  * opts may be NULL; out caller-owned. */

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -26,23 +27,26 @@ typedef unsigned __int128 u128;
 namespace {
 
 // Co-degree table: ranked vertices of degree > kCodegMinDeg, at most
-// kMaxRanked of them and hc^2 * 4 bytes within kCodegBytes (an eighth of the
-// free HBM at most; kCodegBytesCompact with LGE_FLAG_COMPACT).
+// kMaxRanked of them and hc^2 * 4 bytes within kCodegBytes and
+// kCodegPerCsr times the graph's CSR bytes (kCodegBytesCompact with
+// LGE_FLAG_COMPACT, or when the first allocation fails).  The budgets depend
+// on the graph only, so a graph's build and speed do not depend on what else
+// is resident.
 constexpr double kCodegBytes = 17179869184.0;       // 16 GiB: 65536 ranked vertices
 constexpr double kCodegBytesCompact = 1073741824.0;  // 1 GiB: 16384
-// pairs of one vertex's ranked neighbours per work item of the table build
-constexpr int64_t kPairsPerItem = (int64_t)1 << 20;
+constexpr double kCodegPerCsr = 64.0;
 // Ranked vertices above this degree get a co-degree row over the unranked
 // vertices (largest degrees first, while the build work, the sum of their
 // 2-hop volumes, and the memory stay within these budgets).  Every ranked
 // vertex qualifies: the rows of mid-degree vertices serve the wavefront and
 // workgroup classes, whose b rarely exceeds degree 1024.
 constexpr int32_t kRowDeg = 96;
-// co-degree rows: build work (sum of 2-hop volumes) and HBM per graph; the
-// byte budget is also capped at a quarter of the free HBM at creation.
-// LGE_FLAG_COMPACT keeps the small budget for callers holding many graphs.
+// co-degree rows: build work (sum of 2-hop volumes) and HBM per graph, the
+// bytes also within kRowsPerCsr times the CSR bytes; LGE_FLAG_COMPACT (or a
+// failed first allocation) keeps the small budgets.
 constexpr double kRowBudgetOps = 1.5e11;
 constexpr double kRowBudgetBytes = 32e9;
+constexpr double kRowsPerCsr = 256.0;
 constexpr double kRowBudgetOpsCompact = 4e9;
 constexpr double kRowBudgetBytesCompact = 4e9;
 // Ranked vertices have degree > kCodegMinDeg: a walk of a shorter row costs
@@ -413,7 +417,25 @@ static bool sizes_in_range(int64_t n, int64_t m, int64_t dmax) {
 static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags);
 static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, uint32_t flags);
 
+// forget a partial co-degree table / co-degree rows (before a retry)
+static void drop_codeg(lge_graph *g) {
+  dev_free(g->crank);
+  dev_free(g->codeg);
+  dev_free(g->hbits);
+  g->hc = g->hcw = 0;
+}
+
+static void drop_rows(lge_graph *g) {
+  dev_free(g->hrow);
+  dev_free(g->rcol);
+  dev_free(g->row_hubs);
+  dev_free(g->tile_v0);
+  dev_free(g->rows);
+  g->nrows = g->rows_stride = g->ntiles = g->ncol = 0;
+}
+
 static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const int32_t *host_row_ptr) {
+  const auto t_build = std::chrono::steady_clock::now();
   hipStream_t s = ctx->stream;
   const int64_t n = g->n;
   int rc;
@@ -504,20 +526,37 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   cleanup();
   if (e != hipSuccess) return hip_err(e);
-  if ((rc = build_codeg(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
-  if ((rc = build_rows(ctx, g, host_row_ptr, flags)) != LGE_OK) return rc;
+  if (!(flags & LGE_FLAG_NO_TABLES)) {
+    rc = build_codeg(ctx, g, host_row_ptr, flags);
+    if (rc == LGE_ENOMEM && !(flags & LGE_FLAG_COMPACT)) {  // the small budgets, once
+      drop_codeg(g);
+      rc = build_codeg(ctx, g, host_row_ptr, flags | LGE_FLAG_COMPACT);
+    }
+    if (rc != LGE_OK) return rc;
+    rc = build_rows(ctx, g, host_row_ptr, flags);
+    if (rc == LGE_ENOMEM && !(flags & LGE_FLAG_COMPACT)) {
+      drop_rows(g);
+      rc = build_rows(ctx, g, host_row_ptr, flags | LGE_FLAG_COMPACT);
+    }
+    if (rc != LGE_OK) return rc;
+  }
   if ((rc = dev_alloc(&g->vinfo, std::max<int64_t>(n, 1))) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->arh, std::max<int64_t>(2 * g->m, 1))) != LGE_OK) return rc;
   const bool rows = g->nrows > 0;
   LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, rows ? g->hrow : nullptr,
                        rows ? g->rcol : nullptr, n, g->vinfo, s));
   LGE_HIP(launch_arc_rank(g->col, g->vinfo, 2 * g->m, g->arh, s));
+  // the co-degree rows, tile by tile (they read the columns from the arc words)
+  if (rows)
+    LGE_HIP(launch_rows_fill(g->row_ptr, g->col, g->arh, g->row_hubs, g->nrows, g->tile_v0, g->ntiles, g->ncol,
+                             g->rows_stride, g->rows_w, g->rows, s));
   LGE_HIP(hipStreamSynchronize(s));
-  // rows and columns now live in the vertex records
+  // rows and columns now live in the vertex records and arc words
   dev_free(g->hrow);
   dev_free(g->rcol);
-  g->hrow = nullptr;
-  g->rcol = nullptr;
+  dev_free(g->row_hubs);
+  dev_free(g->tile_v0);
+  g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build).count();
   return LGE_OK;
 }
 
@@ -531,9 +570,9 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
   const int64_t n = g->n;
   g->hc = 0;
   if (n <= 0) return LGE_OK;
+  const double csr_bytes = 4.0 * ((double)n + 1.0 + 2.0 * (double)g->m);
   double budget = (flags & LGE_FLAG_COMPACT) ? kCodegBytesCompact : kCodegBytes;
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget = std::min(budget, 0.125 * (double)free_b);
+  budget = std::min(budget, std::max(kCodegBytesCompact, kCodegPerCsr * csr_bytes));
   int64_t hc_max = std::min<int64_t>(kMaxRanked, (int64_t)std::sqrt(budget / 4.0));
   hc_max &= ~(int64_t)63;
   std::vector<int32_t> deg((size_t)n);
@@ -591,36 +630,20 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
     cleanup();
     return rc;
   }
-  // pair-enumeration work items: (vertex, part, parts), about kPairsPerItem
-  // pairs each
-  std::vector<int64_t> hcnt((size_t)n);
-  e = hipMemcpyAsync(hcnt.data(), cnt, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    cleanup();
-    return hip_err(e);
-  }
-  std::vector<int3> items;
-  for (int64_t u = 0; u < n; ++u) {
-    const int64_t k = hcnt[u];
-    if (k < 2) continue;
-    const int64_t parts = std::min<int64_t>(k - 1, std::max<int64_t>(1, (k * (k - 1) / 2) / kPairsPerItem));
-    for (int64_t q = 0; q < parts; ++q) items.push_back(make_int3((int)u, (int)q, (int)parts));
-  }
-  int3 *ditems = nullptr;
-  if ((rc = dev_alloc(&ditems, std::max<int64_t>((int64_t)items.size(), 1))) != LGE_OK) {
+  // the table row by row (every entry written): the ranked vertices in rank
+  // order on the device
+  int32_t *dranked = nullptr;
+  if ((rc = dev_alloc(&dranked, hc)) != LGE_OK) {
     cleanup();
     return rc;
   }
-  e = hipMemcpyAsync(ditems, items.data(), items.size() * sizeof(int3), hipMemcpyHostToDevice, s);
+  e = hipMemcpyAsync(dranked, ranked.data(), (size_t)hc * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, list, s);
-  if (e == hipSuccess) e = hipMemsetAsync(g->codeg, 0, (size_t)hc * (size_t)hc * sizeof(uint32_t), s);
-  if (e == hipSuccess) e = launch_codeg_pairs(off, cnt, list, ditems, (int64_t)items.size(), hc, g->codeg, s);
-  if (e == hipSuccess) e = launch_codeg_mirror(hc, g->codeg, s);
+  if (e == hipSuccess) e = launch_codeg_rows(g->row_ptr, g->col, dranked, off, cnt, list, hc, g->codeg, s);
   if (e == hipSuccess) e = launch_zero_u64(g->hbits, hc * hcw, s);
   if (e == hipSuccess) e = launch_codeg_bits(g->row_ptr, g->col, g->crank, n, hcw, g->hbits, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(ditems);
+  dev_free(dranked);
   cleanup();
   if (e != hipSuccess) return hip_err(e);
   g->hc = hc;
@@ -660,8 +683,8 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   const bool compact = (flags & LGE_FLAG_COMPACT) != 0;
   const double budget_ops = compact ? kRowBudgetOpsCompact : kRowBudgetOps;
   double budget_bytes = compact ? kRowBudgetBytesCompact : kRowBudgetBytes;
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) budget_bytes = std::min(budget_bytes, 0.25 * (double)free_b);
+  const double csr_bytes = 4.0 * ((double)n + 1.0 + 2.0 * (double)g->m);
+  budget_bytes = std::min(budget_bytes, std::max(kRowBudgetBytesCompact, kRowsPerCsr * csr_bytes));
   std::vector<int32_t> hubs;  // ranked hubs within the build-work budget, largest degree first
   double ops = 0.0;
   for (const auto &c : cand) {
@@ -683,34 +706,40 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
     const double bytes = (double)hubs.size() * (double)((c + 7) & ~(int64_t)7) * width;
     if (bytes <= budget_bytes) break;
   }
-  const int64_t stride = (ncol + 7) & ~(int64_t)7;  // entries; rows of whole 64-bit words for the zero fill
+  const int64_t stride = (ncol + 7) & ~(int64_t)7;  // entries, rows on 8-byte boundaries
   if (stride == 0) return LGE_OK;
   const int64_t nh = std::min<int64_t>((int64_t)hubs.size(), (int64_t)(budget_bytes / ((double)stride * width)));
   if (nh <= 0) return LGE_OK;
-  std::vector<int32_t> rcol((size_t)n, -1), hrow((size_t)n, -1);
+  // columns go to the vertices in id order, so a range of columns is a range
+  // of vertex ids; tile t of the fill covers columns [t T, (t + 1) T) and
+  // starts at the vertex of column t T
+  std::vector<int32_t> rcol((size_t)n, -1), hrow((size_t)n, -1), tile_v0;
   {
+    const int64_t per_tile = rows_tile_entries(width);
     int32_t c = 0;
     for (int64_t v = 0; v < n; ++v)
-      if (rank[v] < 0 && host_row_ptr[v + 1] - host_row_ptr[v] > floor_deg) rcol[v] = c++;
+      if (rank[v] < 0 && host_row_ptr[v + 1] - host_row_ptr[v] > floor_deg) {
+        if (c % per_tile == 0) tile_v0.push_back((int32_t)v);
+        rcol[v] = c++;
+      }
+    tile_v0.push_back((int32_t)n);
   }
   for (int64_t h = 0; h < nh; ++h) hrow[hubs[h]] = (int32_t)h;
-  int32_t *dhubs = nullptr;
   int rc;
-  if ((rc = dev_alloc(&dhubs, nh)) != LGE_OK) return rc;
   const int64_t nent = nh * stride * width;  // bytes
   if ((rc = dev_alloc(&g->hrow, n)) != LGE_OK || (rc = dev_alloc(&g->rcol, n)) != LGE_OK ||
-      (rc = dev_alloc(&g->rows, nent)) != LGE_OK) {
-    dev_free(dhubs);
+      (rc = dev_alloc(&g->row_hubs, nh)) != LGE_OK ||
+      (rc = dev_alloc(&g->tile_v0, (int64_t)tile_v0.size())) != LGE_OK || (rc = dev_alloc(&g->rows, nent)) != LGE_OK)
     return rc;  // graph_free releases the partial allocations
-  }
-  hipError_t e = hipMemcpyAsync(dhubs, hubs.data(), (size_t)nh * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(g->row_hubs, hubs.data(), (size_t)nh * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->hrow, hrow.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->rcol, rcol.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_zero_u64((unsigned long long *)g->rows, nent / 8, s);
-  if (e == hipSuccess) e = launch_rows_build(g->row_ptr, g->col, g->rcol, dhubs, nh, stride, width, g->rows, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(dhubs);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->tile_v0, tile_v0.data(), tile_v0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors go out of scope
   if (e != hipSuccess) return hip_err(e);
+  g->ntiles = (int64_t)tile_v0.size() - 1;
+  g->ncol = ncol;
   g->nrows = nh;
   g->rows_stride = stride;
   g->rows_w = width;
@@ -730,6 +759,8 @@ static void graph_free(lge_graph *g) {
   dev_free(g->hbits);
   dev_free(g->hrow);
   dev_free(g->rcol);
+  dev_free(g->row_hubs);
+  dev_free(g->tile_v0);
   dev_free(g->rows);
   dev_free(g->vinfo);
   dev_free(g->arh);
@@ -841,6 +872,34 @@ extern "C" int lge_graph_destroy(lge_graph *g) {
 }
 
 extern "C" int64_t lge_graph_n(const lge_graph *g) { return g ? g->n : -1; }
+
+extern "C" int lge_graph_query(const lge_graph *g, lge_graph_info *out) {
+  if (!g || !out) return LGE_EINVAL;
+  memset(out, 0, sizeof(*out));
+  out->n = g->n;
+  out->m = g->m;
+  out->max_deg = g->max_deg;
+  out->ranked = (int32_t)g->hc;
+  out->rows = (int32_t)g->nrows;
+  out->rows_floor = g->rows_floor;
+  out->rows_width = g->rows_w;
+  out->build_ms = g->build_ms;
+  const int64_t n = g->n, m = g->m;
+  int64_t b = 0;
+  if (g->own_row_ptr) b += 4 * (n + 1);
+  if (g->own_col) b += 8 * m;
+  b += 8 * m + 8 * n + 8 * n + 4 * g->htab_len;  // edge list, 2-hop volumes, hub-table offsets, hub tables
+  b += 16 * n + 8 * m;                           // vertex records, arc words
+  if (g->hc > 0) b += 4 * n + 4 * g->hc * g->hc + 8 * g->hc * g->hcw;  // ranks, co-degree table, bit rows
+  if (g->nrows > 0) b += g->nrows * g->rows_stride * g->rows_w;
+  if (g->t_arc) b += 8 * m;
+  if (g->tri) b += 8 * n;
+  if (g->core) b += 4 * n;
+  for (int k = 0; k < 2; ++k)
+    if (g->wlevel[k]) b += m;
+  out->state_bytes = (uint64_t)b;
+  return LGE_OK;
+}
 extern "C" int64_t lge_graph_m(const lge_graph *g) { return g ? g->m : -1; }
 
 // ---------------------------------------------------------------------------

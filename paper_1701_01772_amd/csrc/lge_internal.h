@@ -221,18 +221,23 @@ hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int3
                         int64_t n, int4 *vinfo, hipStream_t s);
 // packed rank words of every arc's head (after the vertex records)
 hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, uint32_t *arh, hipStream_t s);
-// co-degree rows of the vertices `hubs` at the columns rcol of the unranked
-// vertices, width bytes per entry (rows zeroed by the caller; stride * width
-// a multiple of 4)
-hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *rcol, const int32_t *hubs,
-                             int64_t nh, int64_t stride, int width, uint8_t *rows, hipStream_t s);
+// co-degree rows of the vertices `hubs` at the columns of the unranked
+// vertices (read from the arc words arh), width bytes per entry, in column
+// tiles of rows_tile_entries(width) columns; tile t starts at vertex
+// tile_v0[t] (columns numbered in vertex order, tile_v0[ntiles] = n).  Every
+// entry of the nh x stride rows is written (stride a multiple of 8).
+int64_t rows_tile_entries(int width);
+hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const uint32_t *arh, const int32_t *hubs,
+                            int64_t nh, const int32_t *tile_v0, int64_t ntiles, int64_t ncol, int64_t stride,
+                            int width, uint8_t *rows, hipStream_t s);
 // adjacency bit rows among the ranked vertices (bits zeroed by the caller)
 hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,
                              unsigned long long *bits, hipStream_t s);
-// copy the upper triangle of the hc x hc co-degree table into the lower one
-hipError_t launch_codeg_mirror(int64_t hc, uint32_t *tab, hipStream_t s);
-hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, const int3 *items,
-                              int64_t nitems, int64_t hc, uint32_t *tab, hipStream_t s);
+// the whole hc x hc co-degree table, one row per ranked vertex (ranked[r] is
+// the vertex of rank r; off / cnt / list: every vertex's ranked neighbours
+// as ranks), every entry written (diagonal 0)
+hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const int32_t *ranked, const int64_t *off,
+                             const int64_t *cnt, const int32_t *list, int64_t hc, uint32_t *tab, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
                              int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);

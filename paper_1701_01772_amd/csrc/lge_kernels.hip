@@ -617,9 +617,9 @@ __global__ __launch_bounds__(256) void k_sample_bin(const SlotDesc *__restrict__
 // ---------------------------------------------------------------------------
 // Co-degree table of the high-degree vertices: codeg[i][j] = |Gamma(x) n
 // Gamma(y)| for the vertices x, y of ranks i, j among those with degree > tau.
-// Built once per graph by enumerating, for every vertex, the pairs of its
-// ranked neighbours (each common neighbour of x and y is seen once) into the
-// upper triangle, then mirrored so that each vertex's co-degrees form a row.
+// Built once per graph: every vertex's ranked neighbours as a list of ranks,
+// then one LDS-counted row per ranked vertex (each common neighbour w of x
+// and y is seen once, from w's list, while walking Gamma(x)).
 // ---------------------------------------------------------------------------
 
 // number of ranked neighbours of every vertex
@@ -658,77 +658,140 @@ __global__ __launch_bounds__(256) void k_codeg_fill(const int32_t *__restrict__ 
   }
 }
 
-// Work items (u, part, parts): item (u, p, P) enumerates the pairs (i, j),
-// i < j, of u's ranked-neighbour list for the rows i = p, p + P, ...; a
-// vertex with many ranked neighbours is split over several workgroups.
-__global__ __launch_bounds__(256) void k_codeg_pairs(const int64_t *__restrict__ off,
-                                                     const int64_t *__restrict__ cnt,
-                                                     const int32_t *__restrict__ list, const int3 *__restrict__ items,
-                                                     int64_t nitems, int64_t hc, uint32_t *tab) {
-  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int3 w = items[it];
-    const int64_t k = cnt[w.x];
-    const int32_t *l = list + off[w.x];
-    for (int64_t i = w.y; i + 1 < k; i += w.z) {
-      const int32_t ri = l[i];
-      for (int64_t j = i + 1 + threadIdx.x; j < k; j += blockDim.x) {
-        const int32_t rj = l[j];
-        const int64_t lo = ri < rj ? ri : rj, hi = ri < rj ? rj : ri;
-        atomicAdd(&tab[lo * hc + hi], 1u);
+// Co-degree rows counted in LDS: one workgroup per ranked vertex x of rank
+// rx.  For every w in Gamma(x), every ranked neighbour of w (w's rank list)
+// adds 1 at its rank's column, so the row ends up holding
+// |Gamma(x) n Gamma(y)| for every ranked y; it is then written once,
+// coalesced, diagonal 0.  A co-degree never exceeds deg(x): rows of x with
+// deg(x) < 2^16 count in the 16-bit halves of the LDS words (kRowWords words
+// hold 2 * kRowWords ranks, the most a table has), the others in 32-bit
+// words over kRowWords ranks per pass.  A wave loads 64 of the w at once
+// (coalesced) and walks their lists one after another, lanes striding each.
+constexpr int kRowNT = 1024;
+constexpr int kRowWords = 32768;  // 128 KB of LDS counters
+static_assert(2 * kRowWords >= kMaxRanked, "a narrow row holds every rank");
+__global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ ranked,
+                                                        const int64_t *__restrict__ off,
+                                                        const int64_t *__restrict__ cnt,
+                                                        const int32_t *__restrict__ list, int64_t hc,
+                                                        uint32_t *__restrict__ tab) {
+  __shared__ uint32_t c[kRowWords];
+  const int64_t rx = blockIdx.x;
+  const int32_t x = ranked[rx];
+  const int32_t beg = rp[x], d = rp[x + 1] - beg;
+  const bool narrow = d < 65536;
+  const int passes = narrow ? 1 : (int)((hc + kRowWords - 1) / kRowWords);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kWaves = kRowNT / kWave;
+  uint32_t *row = tab + rx * hc;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int64_t c0 = narrow ? 0 : (int64_t)pass * kRowWords;
+    const int64_t c1 = narrow ? hc : (c0 + kRowWords < hc ? c0 + kRowWords : hc);
+    const int64_t words = narrow ? (hc + 1) / 2 : c1 - c0;
+    for (int64_t i = threadIdx.x; i < words; i += kRowNT) c[i] = 0u;
+    __syncthreads();
+    for (int32_t g0 = wid * kWave; g0 < d; g0 += kWaves * kWave) {
+      const int32_t j = g0 + lane;
+      const int32_t w = j < d ? col[beg + j] : -1;
+      const long long o = w >= 0 ? (long long)off[w] : 0ll;
+      const int k = w >= 0 ? (int)cnt[w] : 0;
+      const int ng = d - g0 < kWave ? d - g0 : kWave;
+      for (int q = 0; q < ng; ++q) {  // uniform per wave
+        const long long oq = __shfl(o, q);
+        const int kq = __shfl(k, q);
+        for (int i = lane; i < kq; i += kWave) {
+          const int32_t y = list[oq + i];
+          if (narrow)
+            atomicAdd(&c[y >> 1], 1u << ((y & 1) << 4));
+          else if (y >= c0 && y < c1)
+            atomicAdd(&c[y - c0], 1u);
+        }
       }
     }
+    __syncthreads();
+    for (int64_t y = c0 + threadIdx.x; y < c1; y += kRowNT) {
+      const uint32_t v = narrow ? (c[y >> 1] >> ((y & 1) << 4)) & 0xFFFFu : c[y - c0];
+      row[y] = y == rx ? 0u : v;
+    }
+    __syncthreads();
   }
 }
 
-// Mirror the upper triangle into the lower one, so that every vertex's
-// co-degrees are one contiguous row: 64 x 64 tiles through LDS, one
-// workgroup per tile above (or on) the diagonal.
-__global__ __launch_bounds__(256) void k_codeg_mirror(int64_t hc, uint32_t *tab) {
-  __shared__ uint32_t tile[64][65];
-  const int64_t nt = (hc + 63) / 64;
-  for (int64_t k = blockIdx.x; k < nt * nt; k += gridDim.x) {
-    const int64_t ti = k / nt, tj = k % nt;
-    if (tj < ti) continue;  // uniform per block
-    for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
-      const int r = q >> 6, c = q & 63;
-      const int64_t i = ti * 64 + r, j = tj * 64 + c;
-      tile[r][c] = (i < hc && j < hc && i < j) ? tab[i * hc + j] : 0u;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < 64 * 64; q += blockDim.x) {
-      const int r = q >> 6, c = q & 63;  // destination (j, i) = (tj*64 + r, ti*64 + c)
-      const int64_t i = ti * 64 + c, j = tj * 64 + r;
-      if (i < hc && j < hc && i < j) tab[j * hc + i] = tile[c][r];
-    }
-    __syncthreads();
+// Co-degree rows over the unranked columns, one workgroup per (row h,
+// column tile t): the row's hub y, every x in Gamma(y), and in Gamma(x) the
+// neighbours w with a column in the tile, counted in LDS (each w once per x,
+// so the entry ends as |Gamma(y) n Gamma(w)|).  Columns are numbered in
+// vertex order, so the tile's columns are a range [v0, v1) of vertex ids and
+// the w of x lie in one segment of x's sorted list (two binary searches);
+// the arc word beside each w gives its column.  One 32-bit LDS counter per
+// column (packing them 4 or 2 to a word measured slower); the tile is then
+// written out once as entries of `width` bytes.  A wave searches the segments
+// of 64 x at once, then walks them one after another, lanes striding each.
+constexpr int kTileNT = 1024;
+constexpr int kTileWords = 32768;  // 128 KB of LDS counters
+
+__device__ __forceinline__ int32_t lower_pos(const int32_t *__restrict__ a, int32_t lo, int32_t hi, int32_t v) {
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
   }
+  return lo;
 }
 
-// One workgroup per row: for x in Gamma(b), for every w in Gamma(x) with a row
-// column (unranked, degree above the graph's column floor), count w once more
-// at its column (at most w's degree in all, which fits the entry width).  A
-// row belongs to one workgroup, so workgroup-scope atomics on its packed
-// counters suffice.
-__global__ __launch_bounds__(256) void k_rows_build(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                    const int32_t *__restrict__ rcol,
-                                                    const int32_t *__restrict__ hubs, int64_t nh, int64_t stride,
-                                                    int width, uint8_t *rows) {
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
-    const int32_t b = hubs[h];
-    uint32_t *row = reinterpret_cast<uint32_t *>(rows + h * stride * width);
-    for (int32_t j = rp[b] + wv; j < rp[b + 1]; j += (int32_t)(blockDim.x >> 6)) {
-      const int32_t x = col[j];
-      for (int32_t k = rp[x] + lane; k < rp[x + 1]; k += 64) {
-        const int32_t c = rcol[col[k]];  // the vertex's row column, -1: ranked or not tabulated
-        if (c < 0) continue;
-        if (width == 1)
-          __hip_atomic_fetch_add(row + (c >> 2), 1u << ((c & 3) * 8), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-          __hip_atomic_fetch_add(row + (c >> 1), 1u << ((c & 1) * 16), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+__global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       const uint32_t *__restrict__ arh,
+                                                       const int32_t *__restrict__ hubs, int64_t nh,
+                                                       const int32_t *__restrict__ tile_v0, int64_t ntiles,
+                                                       int64_t ncol, int64_t stride, int width,
+                                                       uint8_t *__restrict__ rows) {
+  __shared__ uint32_t c[kTileWords];
+  const int64_t T = kTileWords;  // columns per tile
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kWaves = kTileNT / kWave;
+  for (int64_t wi = blockIdx.x; wi < nh * ntiles; wi += gridDim.x) {  // uniform per block
+    const int64_t h = wi / ntiles, t = wi % ntiles;
+    const int32_t y = hubs[h];
+    const int64_t c0 = t * T, c1 = c0 + T < ncol ? c0 + T : ncol;
+    const int32_t v0 = tile_v0[t], v1 = tile_v0[t + 1];
+    const int64_t words = c1 - c0;
+    for (int64_t i = threadIdx.x; i < words; i += kTileNT) c[i] = 0u;
+    __syncthreads();
+    const int32_t ybeg = rp[y], dy = rp[y + 1] - ybeg;
+    for (int32_t g0 = wid * kWave; g0 < dy; g0 += kWaves * kWave) {
+      const int32_t j = g0 + lane;
+      int32_t lo = 0, hi = 0;
+      if (j < dy) {
+        const int32_t x = col[ybeg + j];
+        const int32_t xb = rp[x], xe = rp[x + 1];
+        lo = lower_pos(col, xb, xe, v0);
+        hi = lower_pos(col, lo, xe, v1);
+      }
+      const int ng = dy - g0 < kWave ? dy - g0 : kWave;
+      for (int q = 0; q < ng; ++q) {  // uniform per wave
+        const int32_t lq = __shfl(lo, q), hq = __shfl(hi, q);
+        for (int32_t k = lq + lane; k < hq; k += kWave) {
+          const uint32_t r = arh[k];
+          if (r >> 31) {  // unranked head; its column + 1 in the low bits (0: none)
+            const int64_t cc = (int64_t)(r & 0x7FFFFFFFu) - 1;
+            if (cc >= 0) {
+              atomicAdd(&c[cc - c0], 1u);
+            }
+          }
+        }
       }
     }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < words; i += kTileNT) {
+      if (width == 1)
+        rows[h * stride + c0 + i] = (uint8_t)c[i];
+      else
+        reinterpret_cast<uint16_t *>(rows)[h * stride + c0 + i] = (uint16_t)c[i];
+    }
+    __syncthreads();
   }
 }
 
@@ -941,6 +1004,36 @@ struct SlotAcc {
 // workgroups per XCD that take blocks from the other XCDs' queues
 constexpr int kLdsStealers = 16;
 
+// One claim from the XCD-local queues of the LDS counting kernels (see
+// there): the next block [*e0, *e1) of the class list, *e0 = -1 when this
+// workgroup is done.  *qpos holds the workgroup's place in its queue order
+// (0: its own XCD's queue).  Not inlined and recomputing its parameters from
+// the launch shape each time, so it holds no registers across the edge loop.
+__device__ __noinline__ void lds_claim(unsigned long long *xcd_cursor, int64_t nedges, int max_chunk, int stealers,
+                                       int *qpos, long long *e0, long long *e1) {
+  const int nseg = gridDim.x % kXcds == 0 ? kXcds : 1;
+  const int my_seg = (int)(blockIdx.x % (unsigned)nseg);
+  int64_t run = nedges / (4 * (int64_t)gridDim.x);
+  run = run < 1 ? 1 : (run > max_chunk ? max_chunk : run);
+  const int64_t nblk = (nedges + run - 1) / run;
+  const bool stealer = (int64_t)(blockIdx.x / (unsigned)nseg) < (int64_t)stealers;
+  int seg_off = *qpos;
+  long long b0 = -1, b1 = -1;
+  while (seg_off < nseg && (seg_off == 0 || stealer)) {
+    const int sg = (my_seg + seg_off) % nseg;
+    const int64_t j = (int64_t)atomicAdd(&xcd_cursor[sg * kLine], 1ull) * nseg + sg;
+    if (j < nblk) {
+      b0 = j * run;
+      b1 = b0 + run < nedges ? b0 + run : nedges;
+      break;
+    }
+    ++seg_off;
+  }
+  *qpos = seg_off;
+  *e0 = b0;
+  *e1 = b1;
+}
+
 constexpr uint32_t kModeLook = 0x40000000u;  // S_a: look Gamma(b)\{a} up; T_e: degT by looking T_e up
 constexpr uint32_t kModeAux = 0x20000000u;   // S_a: cbx tabulated (no units); T_e: cax by look-ups
 
@@ -970,7 +1063,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
                                                   const int32_t *__restrict__ ba, const int32_t *__restrict__ bb,
                                                   const unsigned long long *__restrict__ ncount,
                                                   unsigned long long *xcd_cursor,
-                                                  unsigned long long *words_out, int32_t probe_ratio, int32_t max_chunk) {
+                                                  unsigned long long *words_out, int32_t probe_ratio, int32_t max_chunk,
+                                                  int32_t stealers) {
   constexpr int HS = 2 * CAP;
   __shared__ uint32_t htab[HS];
   __shared__ uint32_t wl_v[CAP];
@@ -982,6 +1076,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
   __shared__ int32_t carry_sh[NT / kWave + 1];
   __shared__ unsigned long long red[NT / kWave];
   __shared__ long long sh_e0, sh_e1;
+  __shared__ int sh_qpos;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -996,34 +1091,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
   // multiple of kXcds), so every queue sees the same mix of light and heavy
   // edges (heavy ones cluster: the rows of hubs).  The workgroups of XCD x
   // (blockIdx % kXcds) take blocks from queue x, each claim one atomic on
-  // that queue's own cache line; once it is empty only kLdsStealers of them
-  // per XCD go on to the other queues, which keeps the failed claims at the
-  // end few.  A block mostly keeps one slot (the register sums are flushed
-  // when it changes); about four blocks per workgroup keep the tail short.
-  const int nseg = gridDim.x % kXcds == 0 ? kXcds : 1;
-  const int my_seg = (int)(blockIdx.x % (unsigned)nseg);
-  int64_t run = nedges / (4 * (int64_t)gridDim.x);
-  run = run < 1 ? 1 : (run > max_chunk ? max_chunk : run);
-  const int64_t nblk = (nedges + run - 1) / run;
-  const bool stealer = (int64_t)(blockIdx.x / (unsigned)nseg) < kLdsStealers;
-  int seg_off = 0;  // thread 0's position in the segment order
+  // that queue's own cache line; once it is empty `stealers` of them per XCD
+  // go on to the other queues (few for light edges, which keeps the failed
+  // claims at the end few).  A block mostly keeps one slot (the register sums
+  // are flushed when it changes); about four blocks per workgroup keep the
+  // tail short.
+  if (tid == 0) sh_qpos = 0;
 
   for (;;) {
-    if (tid == 0) {
-      long long e0 = -1, e1 = -1;
-      while (seg_off < nseg && (seg_off == 0 || stealer)) {
-        const int sg = (my_seg + seg_off) % nseg;
-        const int64_t j = (int64_t)atomicAdd(&xcd_cursor[sg * kLine], 1ull) * nseg + sg;
-        if (j < nblk) {
-          e0 = j * run;
-          e1 = e0 + run < nedges ? e0 + run : nedges;
-          break;
-        }
-        ++seg_off;
-      }
-      sh_e0 = e0;
-      sh_e1 = e1;
-    }
+    if (tid == 0) lds_claim(xcd_cursor, nedges, max_chunk, stealers, &sh_qpos, &sh_e0, &sh_e1);
     __syncthreads();
     const int64_t e0 = sh_e0, e1 = sh_e1;
     __syncthreads();
@@ -1033,17 +1109,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
       const int32_t a = ba[e], b = bb[e];
       const SlotDesc &S = slots[slot];
       const int32_t *__restrict__ col = S.col;
-      // endpoint records (row start, degree, rank, co-degree row / column)
-      const int4 ra4 = S.vinfo[a], rb4 = S.vinfo[b];
-      const int32_t abeg = ra4.x, bbeg = rb4.x;
-      const int da = ra4.y, db = rb4.y;
+      // endpoint records (row start, degree, rank, co-degree row / column);
+      // the rank fields count only when co-degrees are read
+      int4 va = S.vinfo[a], vb = S.vinfo[b];
+      const int32_t abeg = va.x, bbeg = vb.x;
+      const int da = va.y, db = vb.y;
+      const bool has_ranks = probe_ratio > 0 && S.hc > 0;
+      if (!has_ranks) va.z = va.w = vb.z = vb.w = -1;
       // an edge with a small scan side and a large b (binned here by the
       // sampling kernel): Gamma(b) stays in b's hub table, the LDS table holds T_e
       const bool bhub = db > CAP;
-      // ranks and rows for the co-degree reads
-      const bool has_ranks = probe_ratio > 0 && S.hc > 0;
-      const int4 va = has_ranks ? ra4 : make_int4(0, 0, -1, -1);
-      const int4 vb = has_ranks ? rb4 : make_int4(0, 0, -1, -1);
       const uint32_t *__restrict__ btab = bhub ? S.htab + S.hoff[b] : nullptr;
       const int blg = bhub ? table_log(db) : 0;
       const int lg = table_log(bhub ? da : db);
@@ -2414,18 +2489,11 @@ hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const i
   return hipGetLastError();
 }
 
-hipError_t launch_codeg_mirror(int64_t hc, uint32_t *tab, hipStream_t s) {
-  if (hc <= 1) return hipSuccess;
-  const int64_t nt = (hc + 63) / 64;
-  hipLaunchKernelGGL(k_codeg_mirror, dim3(grid_for(nt * nt, 1, 65536)), dim3(256), 0, s, hc, tab);
-  return hipGetLastError();
-}
-
-hipError_t launch_codeg_pairs(const int64_t *off, const int64_t *cnt, const int32_t *list, const int3 *items,
-                              int64_t nitems, int64_t hc, uint32_t *tab, hipStream_t s) {
-  if (nitems <= 0 || hc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_codeg_pairs, dim3(grid_for(nitems, 1, 16384)), dim3(256), 0, s, off, cnt, list, items, nitems,
-                     hc, tab);
+hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const int32_t *ranked, const int64_t *off,
+                             const int64_t *cnt, const int32_t *list, int64_t hc, uint32_t *tab, hipStream_t s) {
+  if (hc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_codeg_rows, dim3((unsigned)hc), dim3(kRowNT), 0, s, row_ptr, col, ranked, off, cnt, list, hc,
+                     tab);
   return hipGetLastError();
 }
 
@@ -2446,12 +2514,17 @@ hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int
 template <int NT, int CAP>
 static hipError_t launch_lds(const SlotDesc *slots, Bins bins, int cls, int64_t bound, int grid_cap,
                              int32_t probe_ratio, hipStream_t s) {
+  // the wavefront class claims runs of up to 64 edges and lets 16
+  // workgroups per XCD take from the other queues; the workgroup class,
+  // whose edges are heavy and fewer, claims single edges and lets every
+  // workgroup take from every queue
   const int max_chunk = NT == kWave ? 64 : 1;
+  const int stealers = NT == kWave ? kLdsStealers : (1 << 30);
   int grid = grid_for(bound, 1, grid_cap);
   if (grid >= kXcds) grid -= grid % kXcds;  // whole XCD segments
   hipLaunchKernelGGL((k_count_lds<NT, CAP>), dim3(grid), dim3(NT), 0, s, slots, bins.slot[cls], bins.a[cls],
                      bins.b[cls], bins.count + cls, bins.lds_xcd + kXcds * kLine * cls, bins.words + kXcds * kLine * cls,
-                     probe_ratio, max_chunk);
+                     probe_ratio, max_chunk, stealers);
   return hipGetLastError();
 }
 
@@ -2591,11 +2664,14 @@ hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, u
   return hipGetLastError();
 }
 
-hipError_t launch_rows_build(const int32_t *row_ptr, const int32_t *col, const int32_t *rcol, const int32_t *hubs,
-                             int64_t nh, int64_t stride, int width, uint8_t *rows, hipStream_t s) {
-  if (nh <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_build, dim3(grid_for(nh, 1, 65536)), dim3(256), 0, s, row_ptr, col, rcol, hubs, nh,
-                     stride, width, rows);
+int64_t rows_tile_entries(int) { return kTileWords; }
+
+hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const uint32_t *arh, const int32_t *hubs,
+                            int64_t nh, const int32_t *tile_v0, int64_t ntiles, int64_t ncol, int64_t stride,
+                            int width, uint8_t *rows, hipStream_t s) {
+  if (nh <= 0 || ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_fill, dim3(grid_for(nh * ntiles, 1, 1 << 20)), dim3(kTileNT), 0, s, row_ptr, col, arh,
+                     hubs, nh, tile_v0, ntiles, ncol, stride, width, rows);
   return hipGetLastError();
 }
 

@@ -35,12 +35,16 @@ struct lge_graph {
   uint32_t *arh = nullptr;   // 2m: packed rank word of every arc's head
   int32_t *hrow = nullptr;   // n: co-degree row index, -1 if none (graph creation only)
   int32_t *rcol = nullptr;   // n: column in the co-degree rows, -1 if none (graph creation only)
+  int32_t *row_hubs = nullptr;  // nrows: vertex of every co-degree row (graph creation only)
+  int32_t *tile_v0 = nullptr;   // ntiles + 1: first vertex of every column tile of the fill (graph creation only)
+  int64_t ntiles = 0, ncol = 0;  // column tiles of the fill, columns
   uint8_t *rows = nullptr;   // nrows x rows_stride co-degree rows over the unranked vertices
   int64_t nrows = 0, rows_stride = 0;  // rows, columns per row
   int32_t rows_w = 0;                 // bytes per entry (1 or 2)
   int32_t rows_floor = 0;             // unranked vertices above this degree have a column
   int32_t codeg_tau = 0;
   double work_per_id = 0.0;  // scheduling weight per canonical edge id
+  double build_ms = 0.0;     // preprocessing wall time (after validation and the edge list)
   // micro statistics, built on first use: t of every arc, triangles per
   // vertex, and a small reduction buffer (column maxima, error flag)
   int32_t *t_arc = nullptr;

@@ -164,19 +164,35 @@ def batch_graphs(count: int = 4096, seed: int = 4096, n_lo: int = 50, n_hi: int 
     return out
 
 
-def serving_graphs(count: int = 64, seed: int = 64, m_lo: float = 1e3, m_hi: float = 5e7):
+def serving_graphs(count: int = 64, seed: int = 64, m_lo: float = 1e3, m_hi: float = 5e7, threads: int = 1):
     """Mixed resident set: target edge counts log-uniform in [m_lo, m_hi];
     even index Chung-Lu (mean degree 16, exponent 2.1, cap n/20), odd index
-    R-MAT-shaped (edge factor 16, scale chosen for the target)."""
+    R-MAT-shaped (edge factor 16, scale chosen for the target).  With
+    threads > 1 the graphs are drawn in parallel (the C generator releases
+    the interpreter lock); the result does not depend on it."""
     rng = np.random.default_rng(seed)
-    out = []
+    specs = []
     for i in range(count):
         m_t = 10 ** rng.uniform(math.log10(m_lo), math.log10(m_hi))
         gseed = int(rng.integers(0, 2**62))
+        specs.append((i, m_t, gseed))
+
+    def make(spec):
+        i, m_t, gseed = spec
         if i % 2 == 0:
             n = max(64, int(round(m_t / 8.0)))
-            out.append(chung_lu(n, 16.0, 2.1, max(16.0, n / 20.0), gseed))
-        else:
-            scale = max(6, int(round(math.log2(max(m_t / 16.0 * 1.12, 64)))))
-            out.append(rmat(scale, 16, 0.57, 0.19, 0.19, gseed))
+            return chung_lu(n, 16.0, 2.1, max(16.0, n / 20.0), gseed)
+        scale = max(6, int(round(math.log2(max(m_t / 16.0 * 1.12, 64)))))
+        return rmat(scale, 16, 0.57, 0.19, 0.19, gseed)
+
+    if threads <= 1:
+        return [make(sp) for sp in specs]
+    from concurrent.futures import ThreadPoolExecutor
+    _load()
+    # largest first, so the longest draws start early
+    order = sorted(range(count), key=lambda k: -specs[k][1])
+    out = [None] * count
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        for k, g in zip(order, pool.map(lambda k: make(specs[k]), order)):
+            out[k] = g
     return out

@@ -38,6 +38,7 @@ LGE_WEIGHT_KCORE = 2
 LGE_WEIGHT_CLASSES = 16
 LGE_FLAG_TRUSTED = 1
 LGE_FLAG_COMPACT = 2
+LGE_FLAG_NO_TABLES = 4
 LGE_OPT_SORT_HUB = 1
 LGE_OPT_XCD_LOCAL = 2
 
@@ -75,6 +76,12 @@ class Timing(ctypes.Structure):
                 ("class_edges", ctypes.c_uint64 * 3), ("words_read", ctypes.c_uint64 * 3),
                 ("launches", ctypes.c_uint64), ("micro_ms", ctypes.c_float), ("host_waits", ctypes.c_uint32),
                 ("alg_bytes", ctypes.c_uint64 * 3)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("max_deg", ctypes.c_int32), ("ranked", ctypes.c_int32),
+                ("rows", ctypes.c_int32), ("rows_floor", ctypes.c_int32), ("rows_width", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("state_bytes", ctypes.c_uint64), ("build_ms", ctypes.c_double)]
 
 
 class WeightInfo(ctypes.Structure):
@@ -149,6 +156,7 @@ def load():
         "lge_estimate": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.POINTER(Result)],
                          ctypes.c_int),
         "lge_estimate_noalloc": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(Result)], ctypes.c_int),
+        "lge_graph_query": ([_VP, ctypes.POINTER(GraphInfo)], ctypes.c_int),
         "lge_estimate_range": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
                                 ctypes.POINTER(Opts), ctypes.POINTER(Result)], ctypes.c_int),
         "lge_estimate_async": ([_VP, _VP, ctypes.c_double, ctypes.c_uint64, _VP, ctypes.POINTER(Result),
@@ -290,6 +298,12 @@ def lge_estimate(ctx, g, p: float, seed: int, opts: Opts | None = None, raw: boo
     _check(load().lge_estimate(ctx, g, float(p), int(seed), ctypes.byref(opts) if opts is not None else None,
                                ctypes.byref(r)), "lge_estimate")
     return r if raw else result_dict(r)
+
+
+def lge_graph_query(g) -> dict:
+    i = GraphInfo()
+    _check(load().lge_graph_query(g, ctypes.byref(i)), "lge_graph_query")
+    return {k: getattr(i, k) for k, _ in GraphInfo._fields_ if k != "pad"}
 
 
 def lge_estimate_noalloc(ctx, g, p: float, seed: int, raw: bool = False, out: Result | None = None):
