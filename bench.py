@@ -1,21 +1,29 @@
 """Benchmark of the sampled-edge graphlet estimator on one MI355X.
 
 A step is one full estimate (sample -> bin -> count -> reduce -> FP64
-finalise) on a graph resident in HBM.  Default workload: Chung-Lu power law,
+finalise) on a graph resident in HBM.  Headline workload: Chung-Lu power law,
 n = 1,000,000, mean expected degree 16, exponent 2.1, degree cap 50,000,
-p = 0.1.  Prints one JSON line with the throughput in sampled edges/s, the
-roofline of the dominant counting kernel (device time from HIP events the
-library records on its own stream), and the CPU oracle timed on a bounded
-subsample of the same workload on this host.
+p = 0.1.  The default run adds the large power-law workload (R-MAT scale 22
+at p = 0.1 and 0.01), the batched leg (4,096 graphs in one launch sequence
+against one launch sequence per graph), the served leg (64 resident graphs,
+edge counts log-uniform in [1e3, 5e7]), micro rows, adaptive estimation and
+the other sampling designs.  Prints one JSON line.
+
+Per workload: the roofline of the dominant counting kernel (device time from
+HIP events the library records on its own stream; bytes = the 4-byte words
+the kernel's algorithm reads, counted by the kernel), the graph build (wall
+time, state bytes, one estimate from a cold graph, estimates until the
+tables pay for their build against a hub-tables-only graph), and the CPU
+oracle timed on a bounded sample of the same workload on this host.
 
     python bench.py [--steps K] [--warmup W] [--workload chung_lu|rmat|er|batch|serve|micro|designs] [--p P]
 """
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -37,23 +45,52 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+WORKLOAD_NAMES = {"chung_lu": "chung_lu_n1e6_d16_g2.1_cap5e4", "rmat": "rmat_s22_ef16_a.57_b.19_c.19",
+                  "er": "erdos_renyi_n2000_q0.005"}
+
+
 def make_workload(name):
     from paper_1701_01772_amd import inputs
-    if name == "chung_lu":
-        return inputs.chung_lu_1m(), "chung_lu_n1e6_d16_g2.1_cap5e4"
-    if name == "rmat":
-        return inputs.rmat_22(), "rmat_s22_ef16_a.57_b.19_c.19"
-    if name == "er":
-        return inputs.er_2000(), "erdos_renyi_n2000_q0.005"
-    raise SystemExit("unknown workload %s" % name)
+    makers = {"chung_lu": inputs.chung_lu_1m, "rmat": inputs.rmat_22, "er": inputs.er_2000}
+    if name not in makers:
+        raise SystemExit("unknown workload %s" % name)
+    return makers[name](), WORKLOAD_NAMES[name]
 
 
-CLASS_KERNELS = ["k_count_lds<64,128> (wavefront per edge)", "k_count_lds<256,1024> (workgroup per edge)",
+class Background:
+    """A value computed on a host thread (input generation overlapping GPU work)."""
+
+    def __init__(self, fn, *args, **kw):
+        self._out, self._err = None, None
+
+        def run():
+            try:
+                self._out = fn(*args, **kw)
+            except BaseException as e:  # re-raised in get()
+                self._err = e
+        self._t = threading.Thread(target=run, daemon=True)
+        self._t.start()
+
+    def get(self):
+        self._t.join()
+        if self._err is not None:
+            raise self._err
+        return self._out
+
+
+CLASS_KERNELS = ["k_count_lds<64,256> (wavefront per edge)", "k_count_lds<256,1024> (workgroup per edge)",
                  "k_count_global (split hub edges)"]
+CLASS_TAGS = ["wave", "block", "global"]
 
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle, untuned
+# ---------------------------------------------------------------------------
 
 def cpu_baseline(g, p, seed, target_s=15.0):
-    """The oracle, untuned, on every K-th sampled edge of the same workload."""
+    """The oracle, untuned, on every K-th sampled edge of the same workload
+    (K chosen so the single-thread run takes about target_s), then the same
+    sample split over the host's cores."""
     import numpy as np
     import oracle
     mask_all = oracle.sample_mask(seed, p, g.m)
@@ -119,40 +156,187 @@ def host_cpu_model():
     return None
 
 
+# ---------------------------------------------------------------------------
+# roofline of the dominant counting kernel
+# ---------------------------------------------------------------------------
+
+def load_counter_profile(workload, cls_tag):
+    """Counter figures of the kernel (profiles/pmc_<workload>_<class>.json),
+    or None when absent or taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (workload, cls_tag))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        pmc = json.load(fh)
+    if pmc.get("kernel_hash") != kernel_source_hash():
+        return None
+    return pmc
+
+
 def roofline_of(tim, workload):
-    """Roofline of the dominant counting kernel.  achieved = the neighbour-
-    iteration bytes of the sampled edges it counts (per edge
-    16 + 4(d_u + d_v) + sum over w in Gamma(a)\\{b} of (8 + 4 d_w), summed by
-    the sampling kernel) / its mean launch time; the kernel's tables let it
-    read far fewer bytes, so this "effective" figure can exceed the HBM peak.
-    traffic = HBM-side bytes per launch from the committed rocprofv3 counter
-    profile of the same kernel source (null when the source has changed)."""
+    """Roofline of the counting kernel with the longest mean launch.
+
+    achieved = the bytes the kernel's algorithm reads per launch (4-byte words
+    counted by the kernel as it issues them: positions, packed rank words,
+    vertex records, co-degree and row entries, walked list entries, table
+    probes, bit-row words) / the mean launch time; frac = achieved / peak.
+    effective = the same launch priced at the neighbour iteration of
+    Alg. 2-4 (per edge 16 + 4(d_u + d_v) + sum over w in Gamma(a)\\{b} of
+    (8 + 4 d_w)), which the tables avoid reading, so it may exceed the peak.
+    traffic = HBM-side bytes per launch from the committed counter profile of
+    the same kernel source (null when there is none)."""
     k = len(tim)
     cnt_ms = [sum(t["count_ms"][c] for t in tim) / k for c in range(3)]
     words = [sum(t["words_read"][c] for t in tim) / k for c in range(3)]
     alg = [sum(t["alg_bytes"][c] for t in tim) / k for c in range(3)]
     dom = max(range(3), key=lambda c: cnt_ms[c])
     sec = cnt_ms[dom] * 1e-3
-    achieved = alg[dom] / sec / 1e9 if sec > 0 else 0.0
-    traffic = None
-    pmc_path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (workload, ["wave", "block", "global"][dom]))
-    if os.path.exists(pmc_path):
-        with open(pmc_path) as fh:
-            pmc = json.load(fh)
-        if pmc.get("kernel_hash") == kernel_source_hash():
-            traffic = pmc.get("traffic_bytes_per_launch")
+    read_bytes = 4.0 * words[dom]
+    achieved = read_bytes / sec / 1e9 if sec > 0 else 0.0
+    eff = alg[dom] / sec / 1e9 if sec > 0 else 0.0
     device_ms = {"sample_bin": sum(t["sample_ms"] for t in tim) / k, "count_wave": cnt_ms[0],
                  "count_block": cnt_ms[1], "global_prep": sum(t["global_prep_ms"] for t in tim) / k,
                  "count_global": cnt_ms[2]}
     roof = {"bound": "hbm", "kernel": CLASS_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg[dom], "issued_bytes_per_launch": 4.0 * words[dom],
-            "launch_ms": cnt_ms[dom]}
-    if traffic is not None and sec > 0:
-        roof["traffic_GBps"] = traffic / sec / 1e9
-        roof["traffic_frac"] = traffic / sec / 1e9 / HBM_PEAK_GBS
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": read_bytes, "launch_ms": cnt_ms[dom],
+            "effective": {"bytes_per_launch": alg[dom], "GBps": eff, "vs_peak": eff / HBM_PEAK_GBS,
+                          "basis": "neighbour iteration of Alg. 2-4"}}
+    pmc = load_counter_profile(workload, CLASS_TAGS[dom])
+    if pmc is not None:
+        roof["traffic"] = pmc["traffic_bytes_per_launch"]
+        if sec > 0:
+            roof["traffic_GBps"] = pmc["traffic_bytes_per_launch"] / sec / 1e9
+            roof["traffic_frac"] = roof["traffic_GBps"] / HBM_PEAK_GBS
+        roof["traffic_source"] = pmc.get("source")
     return device_ms, roof
 
+
+# ---------------------------------------------------------------------------
+# timed steps and graph build reports
+# ---------------------------------------------------------------------------
+
+def time_steps(lge, ctx, h, p, seed0, steps, opts=None):
+    """K timed estimates (device idle before and after); per-step timing."""
+    import torch
+    r = lge.Result()
+    torch.cuda.synchronize()
+    sampled, tim = 0, []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        sampled += lge.lge_estimate(ctx, h, p, seed0 + i, opts, raw=True, out=r).sampled_edges
+        tim.append(lge.lge_last_timing(ctx))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"seconds": dt, "sampled": sampled, "value": sampled / dt, "ms_per_step": 1e3 * dt / steps, "tim": tim}
+
+
+def create_timed(lge, ctx, g, flags=0):
+    t0 = time.perf_counter()
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col, flags)
+    return h, time.perf_counter() - t0
+
+
+def cold_estimate(lge, ctx, h, p, seed, create_s):
+    """The first estimate on a just-created graph (its work lists are sized
+    on the way): one estimate's throughput counting the graph build."""
+    t0 = time.perf_counter()
+    r = lge.lge_estimate(ctx, h, p, seed, raw=True)
+    first = time.perf_counter() - t0
+    return {"first_estimate_s": first, "create_plus_first_s": create_s + first,
+            "sampled_edges_per_s": r.sampled_edges / (create_s + first)}
+
+
+def build_report(lge, ctx, g, h, create_s, p, seed, step_ms, min_steps=3):
+    """Graph build against a hub-tables-only graph of the same CSR: state,
+    build time and the number of estimates after which the co-degree table,
+    bit rows and co-degree rows have paid for their build."""
+    info = lge.lge_graph_query(h)
+    hm, create_min = create_timed(lge, ctx, g, lge.LGE_FLAG_NO_TABLES)
+    try:
+        lge.lge_estimate(ctx, hm, p, seed, raw=True)
+        mst = time_steps(lge, ctx, hm, p, seed + 1, min_steps)
+        info_min = lge.lge_graph_query(hm)
+    finally:
+        lge.lge_graph_destroy(hm)
+    gain_ms = mst["ms_per_step"] - step_ms
+    extra_s = create_s - create_min
+    return {"graph_create_s": create_s, "build_ms": info["build_ms"], "state_bytes": info["state_bytes"],
+            "csr_bytes": 4 * (g.n + 1 + 2 * g.m), "ranked_vertices": info["ranked"], "codeg_rows": info["rows"],
+            "p": p, "ms_per_step": step_ms,
+            "hub_tables_only": {"graph_create_s": create_min, "state_bytes": info_min["state_bytes"],
+                                "ms_per_step": mst["ms_per_step"]},
+            "break_even_estimates": (extra_s / (gain_ms * 1e-3)) if gain_ms > 0 else None}
+
+
+# ---------------------------------------------------------------------------
+# the headline and large power-law legs
+# ---------------------------------------------------------------------------
+
+def estimate_leg(lge, ctx, g, wname, workload, p, seed, steps, warmup, h=None, create_s=None, cpu_s=0.0,
+                 want_build=True):
+    """One workload at one p: cold estimate (if the graph is new), warm-up,
+    K timed steps, roofline, build report, CPU oracle baseline."""
+    out = {"workload": wname, "n": g.n, "m": g.m, "p": p}
+    own = h is None
+    if own:
+        h, create_s = create_timed(lge, ctx, g)
+        log("%s resident in %.2f s" % (wname, create_s))
+        out["cold"] = cold_estimate(lge, ctx, h, p, seed, create_s)
+    for i in range(warmup):
+        lge.lge_estimate(ctx, h, p, seed + i, raw=True)
+    st = time_steps(lge, ctx, h, p, seed + 100, steps)
+    log("%s p=%g: %d steps in %.3f s (%.1f M sampled edges/s)" % (wname, p, steps, st["seconds"], st["value"] / 1e6))
+    k = len(st["tim"])
+    device_ms, roof = roofline_of(st["tim"], workload)
+    out.update({"value": st["value"], "unit": "sampled edges/s", "steps": steps, "warmup": warmup,
+                "ms_per_step": st["ms_per_step"], "seed0": seed + 100, "device_ms": device_ms,
+                "class_edges": [sum(t["class_edges"][c] for t in st["tim"]) // k for c in range(3)],
+                "host_waits": max(t["host_waits"] for t in st["tim"]), "roofline": roof})
+    if want_build:
+        out["build"] = build_report(lge, ctx, g, h, create_s, p, seed + 200, st["ms_per_step"])
+        log("%s build: %.2f s, %.1f GB state, break-even %s estimates" % (
+            wname, create_s, out["build"]["state_bytes"] / 1e9, out["build"]["break_even_estimates"]))
+    if cpu_s > 0:
+        log("%s p=%g: cpu baseline (oracle)" % (wname, p))
+        out["cpu_baseline"] = cpu_baseline(g, p, seed + 100, cpu_s)
+    if own:
+        lge.lge_graph_destroy(h)
+    return out
+
+
+def rmat_leg(lge, ctx, args, g):
+    """R-MAT scale 22 (the large power-law configuration) at p = 0.1 and
+    0.01: plain path, roofline, build, CPU baseline; autotuned options
+    against the defaults."""
+    wname = WORKLOAD_NAMES["rmat"]
+    h, create_s = create_timed(lge, ctx, g)
+    log("%s resident in %.2f s" % (wname, create_s))
+    out = {"workload": wname, "n": g.n, "m": g.m, "cold": cold_estimate(lge, ctx, h, 0.1, 7, create_s)}
+    try:
+        for p, steps in ((0.1, args.rmat_steps), (0.01, 3 * args.rmat_steps)):
+            leg = estimate_leg(lge, ctx, g, wname, "rmat", p, args.seed, steps, 1, h=h, create_s=create_s,
+                               cpu_s=args.rmat_cpu_seconds if not args.no_cpu_baseline else 0.0,
+                               want_build=(p == 0.01))
+            t0 = time.perf_counter()
+            opts = lge.lge_autotune(ctx, h, p)
+            tune_s = time.perf_counter() - t0
+            tuned = time_steps(lge, ctx, h, p, args.seed + 500, steps, opts)
+            base = time_steps(lge, ctx, h, p, args.seed + 500, steps)
+            leg["autotune"] = {"seconds": tune_s, "options": lge.opts_dict(opts),
+                               "tuned_ms_per_step": tuned["ms_per_step"], "default_ms_per_step": base["ms_per_step"],
+                               "tuned_vs_default": base["ms_per_step"] / tuned["ms_per_step"]}
+            log("%s p=%g autotune: %.1f vs %.1f ms per step (%.1f s of tuning)" % (
+                wname, p, tuned["ms_per_step"], base["ms_per_step"], tune_s))
+            out["p%g" % p] = leg
+    finally:
+        lge.lge_graph_destroy(h)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# batched and served legs
+# ---------------------------------------------------------------------------
 
 def bench_batch(args):
     """4096 small graphs: one lge_estimate_many launch sequence per step vs
@@ -167,20 +351,20 @@ def bench_batch(args):
     hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col) for g in graphs]
     seeds = [args.seed + i for i in range(len(hs))]
     p = args.p if args.p is not None else 1.0
-    lge.lge_estimate_many(ctx, hs, p, seeds)
+    lge.lge_estimate_many(ctx, hs, p, seeds, raw=True)
+    res = lge.Result()
     for h in hs[:64]:
-        lge.lge_estimate(ctx, h, p, 1)
+        lge.lge_estimate(ctx, h, p, 1, raw=True, out=res)
     torch.cuda.synchronize()
     # plain path: one estimate (one launch sequence) per graph; both legs
     # keep the library's result structs (no conversion to Python numbers)
-    res = lge.Result()
     t0 = time.perf_counter()
     plain_sampled = 0
     for h, sd in zip(hs, seeds):
         plain_sampled += lge.lge_estimate(ctx, h, p, sd, raw=True, out=res).sampled_edges
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    log("plain: %.3f s" % t_plain)
+    log("plain: %.3f s (%.0f us per graph)" % (t_plain, 1e6 * t_plain / len(hs)))
     sampled = 0
     tim = []
     torch.cuda.synchronize()
@@ -208,6 +392,7 @@ def bench_batch(args):
         "config": {"workload": "batch_4096_er_chunglu_n50_5000", "graphs": len(graphs), "m_total": tot_m, "p": p,
                    "path": "batched (one lge_estimate_many per step, graphs resident)"},
         "plain": {"value": plain_sampled / t_plain, "unit": "sampled edges/s", "s": t_plain,
+                  "us_per_graph": 1e6 * t_plain / len(hs),
                   "path": "4096 lge_estimate calls, one launch sequence each"},
         "batched_vs_plain": (sampled / dt) / (plain_sampled / t_plain),
         "end_to_end_count_batch_s": t_e2e,
@@ -215,21 +400,29 @@ def bench_batch(args):
     }
 
 
-def bench_serve(args):
+def serving_set(args, threads=16):
+    from paper_1701_01772_amd import inputs
+    return inputs.serving_graphs(64, 64, 1e3, args.serve_m_hi, threads=threads)
+
+
+def bench_serve(args, graphs=None):
     """Poisson request stream over resident graphs served by lge_server
     (continuous batching); rates at 50% and 80% of the plain path's measured
     saturation throughput."""
-    import threading
     from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import torch
-    from paper_1701_01772_amd import inputs, lge
-    log("generating 64 serving graphs (edge counts log-uniform in [1e3, %.0e])" % args.serve_m_hi)
-    graphs = inputs.serving_graphs(64, 64, 1e3, args.serve_m_hi)
-    log("serving set: %d edges total" % sum(g.m for g in graphs))
+    from paper_1701_01772_amd import lge
+    if graphs is None:
+        log("generating 64 serving graphs (edge counts log-uniform in [1e3, %.0e])" % args.serve_m_hi)
+        graphs = serving_set(args)
+    log("serving set: %d graphs, %d edges in all" % (len(graphs), sum(g.m for g in graphs)))
     ctx = lge.lge_open(0)
-    # 64 graphs stay resident: compact co-degree rows keep the set's HBM bounded
+    # 64 graphs stay resident: compact tables keep the set's HBM bounded
+    t0 = time.perf_counter()
     hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col, lge.LGE_FLAG_COMPACT) for g in graphs]
+    state = sum(lge.lge_graph_query(h)["state_bytes"] for h in hs)
+    log("serving set resident in %.1f s (%.1f GB of graph state)" % (time.perf_counter() - t0, state / 1e9))
     rng = np.random.default_rng(args.seed)
     n_req = args.serve_requests
 
@@ -238,17 +431,24 @@ def bench_serve(args):
 
     # plain-path saturation: requests back to back, one lge_estimate each
     cal = draw(n_req)
+    res = lge.Result()
     for gi, p, s in cal[:8]:
-        lge.lge_estimate(ctx, hs[gi], p, s)
+        lge.lge_estimate(ctx, hs[gi], p, s, raw=True, out=res)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain_edges = 0
+    plain_lat = []
     for gi, p, s in cal:
-        plain_edges += lge.lge_estimate(ctx, hs[gi], p, s)["sampled"]
+        t1 = time.perf_counter()
+        plain_edges += lge.lge_estimate(ctx, hs[gi], p, s, raw=True, out=res).sampled_edges
+        plain_lat.append(time.perf_counter() - t1)
     t_plain = time.perf_counter() - t0
     sat_qps = len(cal) / t_plain
     log("plain saturation: %.1f requests/s" % sat_qps)
-    out = {"plain": {"requests_per_s": sat_qps, "sampled_edges_per_s": plain_edges / t_plain}}
+    out = {"graphs": len(graphs), "edges_total": sum(g.m for g in graphs), "graph_state_bytes": state,
+           "plain": {"requests_per_s": sat_qps, "sampled_edges_per_s": plain_edges / t_plain,
+                     "p50_ms_alone": float(np.percentile(np.array(plain_lat) * 1e3, 50)),
+                     "p99_ms_alone": float(np.percentile(np.array(plain_lat) * 1e3, 99))}}
     scfg = lge.lge_server_cfg_default()
     if args.serve_step_us:
         scfg.target_step_us = int(args.serve_step_us)
@@ -323,7 +523,6 @@ def bench_serve(args):
 def bench_sweep(args):
     """Times option settings on one resident workload (results never depend
     on them); prints one line per setting to stderr and a JSON summary."""
-    import torch
     from paper_1701_01772_amd import lge
     p = args.p if args.p is not None else 0.1
     g, wname = make_workload(args.workload)
@@ -337,40 +536,34 @@ def bench_sweep(args):
     ref = None
     for kw in settings:
         o = lge.make_opts(**kw)
-        lge.lge_estimate(ctx, h, p, args.seed, o)
-        tim = []
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            r = lge.lge_estimate(ctx, h, p, args.seed + i, o)
-            tim.append(lge.lge_last_timing(ctx))
-            if i == 0:
-                key = (r["sampled"], tuple(r["csum"]), tuple(r["qsum"]))
-                ref = ref or key
-                assert key == ref, "results changed with options %s" % kw
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        dev, roof = roofline_of(tim, args.workload)
-        rows.append({"opts": kw, "ms_per_step": 1e3 * dt, "device_ms": dev})
+        r = lge.lge_estimate(ctx, h, p, args.seed, o)
+        key = (r["sampled"], tuple(r["csum"]), tuple(r["qsum"]))
+        ref = ref or key
+        assert key == ref, "results changed with options %s" % kw
+        st = time_steps(lge, ctx, h, p, args.seed, args.steps, o)
+        dev, roof = roofline_of(st["tim"], args.workload)
+        rows.append({"opts": kw, "ms_per_step": st["ms_per_step"], "device_ms": dev})
         log("%-60s %8.2f ms/step  global %8.2f  block %7.2f  wave %6.2f" % (
-            kw, 1e3 * dt, dev["count_global"], dev["count_block"], dev["count_wave"]))
+            kw, st["ms_per_step"], dev["count_global"], dev["count_block"], dev["count_wave"]))
     lge.lge_graph_destroy(h)
     lge.lge_close(ctx)
     return {"sweep": rows, "workload": wname, "p": p}
 
 
-def bench_micro(args):
+def bench_micro(args, g=None):
     """Micro-level rows (Sec. 3, Alg. 7 at p_e = 1) of every edge of the
     Chung-Lu 1e6 graph: one lge_micro over all m edges per step, rows in a
     resident m x 17 int64 device buffer."""
     import torch
     from paper_1701_01772_amd import lge
-    g, wname = make_workload("chung_lu")
+    if g is None:
+        g, _ = make_workload("chung_lu")
+    wname = WORKLOAD_NAMES["chung_lu"]
     ctx = lge.lge_open(0)
     h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
     rows = torch.empty((g.m, lge.LGE_MICRO_COLS), dtype=torch.int64, device="cuda:0")
     for i in range(max(1, args.warmup)):
         lge.lge_micro(ctx, h, 0, g.m, out=rows)
-        log("micro warmup %d" % (i + 1))
     torch.cuda.synchronize()
     tim = []
     t0 = time.perf_counter()
@@ -398,12 +591,13 @@ def bench_micro(args):
     return res
 
 
-def bench_adaptive(args):
+def bench_adaptive(args, g=None):
     """Adaptive estimation (Sec. 4, Alg. 8) on the Chung-Lu 1e6 graph,
     beta = 0.01, phi0 = 1/sqrt(m)."""
     import torch
     from paper_1701_01772_amd import lge
-    g, wname = make_workload("chung_lu")
+    if g is None:
+        g, _ = make_workload("chung_lu")
     ctx = lge.lge_open(0)
     h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
     lge.lge_estimate_adaptive(ctx, h, args.seed, beta=0.01)
@@ -414,21 +608,22 @@ def bench_adaptive(args):
     dt = time.perf_counter() - t0
     lge.lge_graph_destroy(h)
     lge.lge_close(ctx)
-    return {"workload": wname, "beta": 0.01, "rounds": tr["rounds"], "final_p": tr["p"][-1],
+    return {"workload": WORKLOAD_NAMES["chung_lu"], "beta": 0.01, "rounds": tr["rounds"], "final_p": tr["p"][-1],
             "sampled": tr["sampled"][-1], "seconds": dt, "sampled_edges_per_s": tr["sampled"][-1] / dt,
             "final_delta": tr["delta"][-1]}
 
 
-def bench_designs(args):
+def bench_designs(args, g=None):
     """The other sampling designs on the Chung-Lu 1e6 graph: k-core and
     degree weighted Bernoulli samples (mean probability 0.1) and a fixed-size
     sample of 0.1 m edges with the ratio estimator."""
     import torch
     from paper_1701_01772_amd import lge
-    g, wname = make_workload("chung_lu")
+    if g is None:
+        g, _ = make_workload("chung_lu")
     ctx = lge.lge_open(0)
     h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
-    out = {"workload": wname}
+    out = {"workload": WORKLOAD_NAMES["chung_lu"]}
     t0 = time.perf_counter()
     _, mc = lge.lge_core_numbers(ctx, h)
     out["core_numbers_s"] = time.perf_counter() - t0
@@ -457,6 +652,8 @@ def bench_designs(args):
     return out
 
 
+# ---------------------------------------------------------------------------
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -466,13 +663,15 @@ def main():
     ap.add_argument("--p", type=float, default=None)
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--rmat-cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--rmat-steps", type=int, default=3, help="timed steps at p = 0.1 (three times that at 0.01)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-m-hi", type=float, default=2e6)
+    ap.add_argument("--serve-m-hi", type=float, default=5e7)
     ap.add_argument("--sweep", default=None,
                     help="';'-separated option settings, e.g. 'flags=0;flags=1,global_chunk=128'")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-step-us", type=int, default=0, help="server target step time (0: library default)")
-    ap.add_argument("--quick", action="store_true", help="headline workload only (no batched / served legs)")
+    ap.add_argument("--quick", action="store_true", help="headline workload only (no other legs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale memory counters")
     args = ap.parse_args()
@@ -498,57 +697,45 @@ def main():
         print(json.dumps(bench_designs(args)))
         return
 
-    import torch
-    from paper_1701_01772_amd import lge
+    from paper_1701_01772_amd import inputs, lge
+    full = args.workload == "chung_lu" and not args.quick and not args.copy_calibration
+    # the other legs' inputs are drawn on host threads while the GPU works
+    bg_rmat = Background(inputs.rmat_22) if full else None
+    bg_serve = Background(serving_set, args) if full else None
 
     p = args.p if args.p is not None else {"chung_lu": 0.1, "rmat": 0.1, "er": 1.0}.get(args.workload, 0.1)
     log("generating %s" % args.workload)
     g, wname = make_workload(args.workload)
     log("graph n=%d m=%d" % (g.n, g.m))
     ctx = lge.lge_open(0)
-    t_create = time.perf_counter()
-    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
-    t_create = time.perf_counter() - t_create
-    log("graph resident in %.2f s (upload, validation, edge list, hub and co-degree tables)" % t_create)
-    for i in range(args.warmup):
-        lge.lge_estimate(ctx, h, p, args.seed + i)
-        log("warmup %d/%d" % (i + 1, args.warmup))
-    torch.cuda.synchronize()
-    sampled = 0
-    tim = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        r = lge.lge_estimate(ctx, h, p, args.seed + 100 + i)
-        sampled += r["sampled"]
-        tim.append(lge.lge_last_timing(ctx))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    log("timed %d steps in %.3f s" % (args.steps, dt))
-    k = len(tim)
-    device_ms, roof = roofline_of(tim, args.workload)
+    head = estimate_leg(lge, ctx, g, wname, args.workload, p, args.seed, args.steps, args.warmup,
+                        cpu_s=0.0, want_build=not args.quick)
     result = {
         "metric": "sampled edges/s (all 3/4-node graphlets)",
-        "value": sampled / dt,
+        "value": head["value"],
         "unit": "sampled edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": wname, "n": g.n, "m": g.m, "p": p, "seed0": args.seed + 100,
+        "config": {"workload": wname, "n": g.n, "m": g.m, "p": p, "seed0": head["seed0"],
                    "path": "plain (one lge_estimate per step, graph resident)"},
-        "device_ms": device_ms,
-        "class_edges": [sum(t["class_edges"][c] for t in tim) // k for c in range(3)],
-        "graph_create_s": t_create,
-        "roofline": roof,
+        "device_ms": head["device_ms"],
+        "class_edges": head["class_edges"],
+        "host_waits_per_step": head["host_waits"],
+        "graph_create_s": head["cold"]["create_plus_first_s"] - head["cold"]["first_estimate_s"],
+        "cold": head["cold"],
+        "roofline": head["roofline"],
     }
-    lge.lge_graph_destroy(h)
-    lge.lge_close(ctx)
+    if "build" in head:
+        result["build"] = head["build"]
     if args.copy_calibration:
+        import torch
         src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
@@ -559,27 +746,37 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(g, p, args.seed + 100, args.cpu_seconds)
-    if not args.quick and args.workload == "chung_lu" and not args.copy_calibration:
-        # the metric's other legs: batched vs plain, and served latency
+    if full:
+        log("R-MAT scale 22: waiting for the generator")
+        result["rmat"] = rmat_leg(lge, ctx, args, bg_rmat.get())
+        lge.lge_close(ctx)
+        ctx = None
         bargs = argparse.Namespace(**vars(args))
         bargs.steps, bargs.p = 3, None
         b = bench_batch(bargs)
         result["batched"] = {"workload": b["config"]["workload"], "value": b["value"], "unit": b["unit"],
-                             "plain_value": b["plain"]["value"], "batched_vs_plain": b["batched_vs_plain"],
-                             "ms_per_step": b["ms_per_step"]}
-        sv = bench_serve(bargs)["serving"]
+                             "plain_value": b["plain"]["value"], "plain_us_per_graph": b["plain"]["us_per_graph"],
+                             "batched_vs_plain": b["batched_vs_plain"], "ms_per_step": b["ms_per_step"],
+                             "end_to_end_count_batch_s": b["end_to_end_count_batch_s"]}
+        log("serving set: waiting for the generator")
+        sv = bench_serve(bargs, bg_serve.get())["serving"]
         result["served"] = {"workload": "serving_64_graphs_chunglu_rmat_m1e3_%.0e" % args.serve_m_hi,
+                            "edges_total": sv["edges_total"], "graph_state_bytes": sv["graph_state_bytes"],
+                            "requests": args.serve_requests,
                             "plain_requests_per_s": sv["plain"]["requests_per_s"],
                             "burst_vs_plain": sv["burst"]["vs_plain"],
+                            "p50_ms_alone": sv["plain"]["p50_ms_alone"], "p99_ms_alone": sv["plain"]["p99_ms_alone"],
                             "p50_ms_at_50pct": sv["served_50"]["p50_ms"], "p99_ms_at_50pct": sv["served_50"]["p99_ms"],
                             "p50_ms_at_80pct": sv["served_80"]["p50_ms"], "p99_ms_at_80pct": sv["served_80"]["p99_ms"],
                             "throughput_rps_at_80pct": sv["served_80"]["throughput_rps"]}
-        mi = bench_micro(bargs)
+        mi = bench_micro(bargs, g)
         result["micro"] = {"workload": mi["config"]["workload"], "value": mi["value"], "unit": mi["unit"],
                            "ms_per_step": mi["ms_per_step"], "device_ms": mi["device_ms"],
                            "micro_rows_kernel": mi["micro_rows_kernel"]}
-        result["adaptive"] = bench_adaptive(bargs)
-        result["designs"] = bench_designs(bargs)
+        result["adaptive"] = bench_adaptive(bargs, g)
+        result["designs"] = bench_designs(bargs, g)
+    if ctx is not None:
+        lge.lge_close(ctx)
     print(json.dumps(result))
 
 

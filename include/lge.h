@@ -142,6 +142,12 @@ typedef struct {
  *                 blockIdx % 8) takes work items from its own contiguous
  *                 segment first, so each L2 sees a fraction of the tables
  *                 (default: both)
+ *  max_list_mib   bound, in MiB, on the split-class work lists (work items
+ *                 and T_e entries) one launch sequence may hold (0 = a
+ *                 quarter of the device's memory).  A sequence whose lists
+ *                 would need more runs its edge-id range in consecutive
+ *                 pieces, each within the bound (a single edge may exceed
+ *                 it); the exact sums, so the results, are the same.
  */
 #define LGE_OPT_SORT_HUB 1u
 #define LGE_OPT_XCD_LOCAL 2u
@@ -152,7 +158,8 @@ typedef struct {
   int32_t grid_per_cu;
   int32_t global_chunk;
   uint32_t flags;
-  int32_t reserved[2];
+  int32_t max_list_mib;
+  int32_t reserved;
 } lge_opts;
 
 /* Device-time breakdown of the last estimate/batch call on a ctx. */
@@ -439,10 +446,19 @@ LGE_API int lge_micro(lge_ctx *ctx, const lge_graph *g, int64_t e0, int64_t e1, 
 LGE_API int lge_last_timing(const lge_ctx *ctx, lge_timing *out);
 
 /*
- * Autotuner: times candidate settings on (g, p) and writes the fastest to
- * *out.  The choice never changes results.
+ * Autotuner (the order of work by hardness, Sec. 5): times candidate
+ * settings on (g, p) by coordinate descent over wave_max_deg, block_max_deg,
+ * probe_ratio, global_chunk, flags and grid_per_cu, and writes the fastest
+ * to *out.  The choice is cached on ctx per graph class (bit lengths of m
+ * and of the maximum degree, and p rounded to a quarter octave): a later
+ * call for a graph of the same class returns the cached options without
+ * timing.  Costs tens of estimates on a cache miss.  The choice never
+ * changes results.  Errors: LGE_EINVAL, any lge_estimate error.
  */
 LGE_API int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *out);
+
+/* Empties ctx's autotuner cache.  Errors: LGE_EINVAL (null ctx). */
+LGE_API int lge_autotune_reset(lge_ctx *ctx);
 
 /*
  * Serving.  A server owns `ctx` (no other call may use that ctx while the

@@ -143,6 +143,7 @@ static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
   c.grid_sample = cu * 16;
   c.global_chunk = o->global_chunk > 0 ? std::min<int32_t>(o->global_chunk, kGlobalChunkMax) : d.global_chunk;
   c.flags = o->flags;
+  c.list_budget = o->max_list_mib > 0 ? (int64_t)o->max_list_mib << 20 : ctx->list_budget;
   return c;
 }
 
@@ -200,6 +201,9 @@ extern "C" int lge_open(int device, lge_ctx **out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->num_cu = prop.multiProcessorCount;
+  size_t mem_free = 0, mem_total = 0;
+  if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0)
+    ctx->list_budget = (int64_t)(mem_total / 4);
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return LGE_EDEVICE;
@@ -362,6 +366,16 @@ static int ws_reserve_tlist(lge_ctx *ctx, int64_t len) {
   w.cap_tlist = cap;
   return LGE_OK;
 }
+
+// device bytes of the split-class lists for `items` work items and `tl` T_e
+// entries, as the two functions above allocate them
+static int64_t list_bytes(int64_t items, int64_t tl) {
+  return (items + items / 4) * (int64_t)(sizeof(int32_t) + (kGlobalChunkMax / 64) * sizeof(unsigned long long)) +
+         (tl + tl / 4) * (int64_t)(3 * sizeof(int32_t) + sizeof(unsigned long long) + sizeof(int16_t));
+}
+
+// run_sequence's answer when the split-class lists would exceed the budget
+constexpr int kRunSplit = 1 << 20;
 
 // ---------------------------------------------------------------------------
 // graph validation and creation
@@ -1083,7 +1097,8 @@ static int acc_replicas(int nslots) {
 // split-class lists outgrow w's buffers it grows them and runs the class's
 // tail again, otherwise it returns LGE_ERANGE.  On success the per-slot sums
 // are packed at w.h_acc + k * kAccSlots * 2.
-static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, const KernelCfg &cfg, bool can_grow) {
+static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, const KernelCfg &cfg, bool can_grow,
+                        int64_t budget) {
   int64_t total = 0;
   int nslots = 0;
   for (int j = 0; j < njobs; ++j) {
@@ -1205,13 +1220,48 @@ static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, 
   LGE_HIP(hipEventRecord(ev[5], s));
   LGE_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, (size_t)ctl_words * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   LGE_HIP(hipStreamSynchronize(s));  // the sequence's only wait, unless the split lists outgrew their buffers
+  auto read_timing = [&](int64_t reruns) {
+    lge_timing &t = ctx->timing;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) t.total_ms = ms;
+    if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) t.sample_ms = ms;
+    if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) t.count_ms[0] = ms;
+    if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) t.count_ms[1] = ms;
+    if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) t.count_ms[2] = ms;
+    if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
+    for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[kCtrCount + c];
+    for (int c = 0; c < kNumClasses; ++c) {
+      t.words_read[c] = t.alg_bytes[c] = 0;
+      for (int x = 0; x < kXcds; ++x) {
+        t.words_read[c] += w.h_counters[kCtrWords + (kXcds * c + x) * kLine];
+        t.alg_bytes[c] += w.h_counters[kCtrAlg + (kXcds * c + x) * kLine];
+      }
+    }
+    t.launches = 5 + (split ? 16 + 6 * reruns : 0);
+    t.host_waits = 1 + (uint32_t)reruns;
+  };
   int64_t reruns = 0;
   if (split && !split_fits(bins, w.h_counters[kCtrItems], w.h_counters[kCtrTList])) {
     if (!can_grow) return LGE_ERANGE;
     // grow to the totals the scans found and run the tail again; the
-    // accumulators hold the other classes' sums, the tail adds the split class
-    if ((rc = ws_reserve_items(ctx, (int64_t)w.h_counters[kCtrItems])) != LGE_OK) return rc;
-    if ((rc = ws_reserve_tlist(ctx, (int64_t)w.h_counters[kCtrTList])) != LGE_OK) return rc;
+    // accumulators hold the other classes' sums, the tail adds the split
+    // class.  Lists beyond the budget (or beyond free memory) make the
+    // caller run the range in pieces instead.
+    const int64_t ni = (int64_t)w.h_counters[kCtrItems], nt = (int64_t)w.h_counters[kCtrTList];
+    const int64_t need = list_bytes(ni, nt);
+    if (need > budget) {
+      read_timing(0);
+      ctx->list_need = need;
+      return kRunSplit;
+    }
+    rc = ws_reserve_items(ctx, ni);
+    if (rc == LGE_OK) rc = ws_reserve_tlist(ctx, nt);
+    if (rc == LGE_ENOMEM && budget < INT64_MAX) {
+      read_timing(0);
+      ctx->list_need = need;
+      return kRunSplit;
+    }
+    if (rc != LGE_OK) return rc;
     bins.cap_items = w.cap_items;
     bins.cap_tlist = w.cap_tlist;
     if (!split_fits(bins, w.h_counters[kCtrItems], w.h_counters[kCtrTList])) return LGE_EINTERNAL;
@@ -1240,24 +1290,91 @@ static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, 
       memcpy(w.h_acc + (int64_t)k * kAccSlots * 2, sum, sizeof(sum));
     }
   }
-  lge_timing &t = ctx->timing;
-  float ms = 0;
-  if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) t.total_ms = ms;
-  if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) t.sample_ms = ms;
-  if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) t.count_ms[0] = ms;
-  if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) t.count_ms[1] = ms;
-  if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) t.count_ms[2] = ms;
-  if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
-  for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[kCtrCount + c];
+  read_timing(reruns);
+  return LGE_OK;
+}
+
+// Adds the device times and launch counts of one sequence to *sum, and its
+// class sizes and read counters when its sums were kept.
+static void add_timing(lge_timing *sum, const lge_timing &t, bool kept) {
+  sum->total_ms += t.total_ms;
+  sum->sample_ms += t.sample_ms;
+  sum->global_prep_ms += t.global_prep_ms;
   for (int c = 0; c < kNumClasses; ++c) {
-    t.words_read[c] = t.alg_bytes[c] = 0;
-    for (int x = 0; x < kXcds; ++x) {
-      t.words_read[c] += w.h_counters[kCtrWords + (kXcds * c + x) * kLine];
-      t.alg_bytes[c] += w.h_counters[kCtrAlg + (kXcds * c + x) * kLine];
+    sum->count_ms[c] += t.count_ms[c];
+    if (kept) {
+      sum->class_edges[c] += t.class_edges[c];
+      sum->words_read[c] += t.words_read[c];
+      sum->alg_bytes[c] += t.alg_bytes[c];
     }
   }
-  t.launches = 5 + (split ? 16 + 6 * reruns : 0);
-  t.host_waits = 1 + reruns;
+  sum->launches += t.launches;
+  sum->host_waits += t.host_waits;
+}
+
+// The jobs' per-slot sums into acc (kAccSlots * 2 words per slot, slots in
+// job order).  One launch sequence when its split-class lists fit the
+// budget; otherwise each job alone, and a lone job's edge-id range in
+// consecutive pieces sized from the lists the failed sequence asked for.
+// Sums over sampled edges are exact and additive over disjoint ranges.
+static int run_pieces(lge_ctx *ctx, const Job *jobs, int njobs, const KernelCfg &cfg, unsigned long long *acc,
+                      lge_timing *tsum, int depth) {
+  int nslots = 0;
+  bool split = false;
+  for (int j = 0; j < njobs; ++j) {
+    nslots += lge_job_slots(jobs[j]);
+    split = split || jobs[j].g->max_deg > cfg.block_max_deg;
+  }
+  Workspace &w = ctx->ws;
+  int rc;
+  if (split && list_bytes(w.cap_items, w.cap_tlist) > cfg.list_budget + cfg.list_budget / 4) {
+    // lists grown under a larger budget: give them back
+    dev_free(w.item_edge);
+    dev_free(w.tmask);
+    dev_free(w.tlist);
+    dev_free(w.tbw);
+    dev_free(w.tbi);
+    w.cap_items = w.cap_tlist = 0;
+  }
+  if (split && (w.cap_items == 0 || w.cap_tlist == 0)) {  // first use: a modest start, grown on demand
+    const bool tight = cfg.list_budget < ((int64_t)64 << 20);
+    if ((rc = ws_reserve_items(ctx, tight ? 1 : 1 << 14)) != LGE_OK) return rc;
+    if ((rc = ws_reserve_tlist(ctx, tight ? 1 : 1 << 20)) != LGE_OK) return rc;
+  }
+  const bool single_edge = njobs == 1 && jobs[0].e1 - jobs[0].e0 <= 1;
+  rc = run_sequence(ctx, w, jobs, njobs, cfg, true, single_edge ? INT64_MAX : cfg.list_budget);
+  if (rc != LGE_OK && rc != kRunSplit) return rc;
+  add_timing(tsum, ctx->timing, rc == LGE_OK);
+  if (rc == LGE_OK) {
+    memcpy(acc, w.h_acc, (size_t)nslots * kAccSlots * 2 * sizeof(unsigned long long));
+    return LGE_OK;
+  }
+  if (depth > 48) return LGE_ENOMEM;
+  if (njobs > 1) {
+    for (int j = 0, s0 = 0; j < njobs; s0 += lge_job_slots(jobs[j]), ++j)
+      if ((rc = run_pieces(ctx, jobs + j, 1, cfg, acc + (int64_t)s0 * kAccSlots * 2, tsum, depth + 1)) != LGE_OK)
+        return rc;
+    return LGE_OK;
+  }
+  const Job &J = jobs[0];
+  const int64_t len = J.e1 - J.e0;
+  const int64_t want = ctx->list_need / std::max<int64_t>(cfg.list_budget, 1) + 1;
+  const int64_t k = std::min<int64_t>(std::max<int64_t>(want + want / 4 + 1, 2), std::min<int64_t>(len, 4096));
+  std::vector<unsigned long long> part((size_t)nslots * kAccSlots * 2);
+  memset(acc, 0, part.size() * sizeof(unsigned long long));
+  for (int64_t i = 0; i < k; ++i) {
+    Job sub = J;
+    sub.e0 = J.e0 + len * i / k;
+    sub.e1 = J.e0 + len * (i + 1) / k;
+    if (sub.e1 == sub.e0) continue;
+    if (J.micro) sub.micro = J.micro + (sub.e0 - J.e0) * kMicroCols;
+    if ((rc = run_pieces(ctx, &sub, 1, cfg, part.data(), tsum, depth + 1)) != LGE_OK) return rc;
+    for (size_t q = 0; q < part.size(); q += 2) {
+      const u128 v = (((u128)acc[q + 1] << 64) | (u128)acc[q]) + (((u128)part[q + 1] << 64) | (u128)part[q]);
+      acc[q] = (unsigned long long)v;
+      acc[q + 1] = (unsigned long long)(v >> 64);
+    }
+  }
   return LGE_OK;
 }
 
@@ -1272,14 +1389,13 @@ int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts)
   int rc = ws_reserve(ctx, std::max<int64_t>(total, 1), nslots * acc_replicas(nslots), njobs);
   if (rc != LGE_OK) return rc;
   const KernelCfg cfg = make_cfg(ctx, opts);
-  Workspace &w = ctx->ws;
-  bool split = false;
-  for (int j = 0; j < njobs; ++j) split = split || jobs[j].g->max_deg > cfg.block_max_deg;
-  if (split && (w.cap_items == 0 || w.cap_tlist == 0)) {  // first use: a modest start, grown on demand
-    if ((rc = ws_reserve_items(ctx, 1 << 14)) != LGE_OK) return rc;
-    if ((rc = ws_reserve_tlist(ctx, 1 << 20)) != LGE_OK) return rc;
-  }
-  return run_sequence(ctx, w, jobs, njobs, cfg, true);
+  lge_timing tsum{};
+  std::vector<unsigned long long> acc((size_t)nslots * kAccSlots * 2);
+  rc = run_pieces(ctx, jobs, njobs, cfg, acc.data(), &tsum, 0);
+  if (rc != LGE_OK) return rc;
+  memcpy(ctx->ws.h_acc, acc.data(), acc.size() * sizeof(unsigned long long));
+  ctx->timing = tsum;
+  return LGE_OK;
 }
 
 static bool p_ok(double p) { return p > 0.0 && p <= 1.0; }
@@ -1368,7 +1484,7 @@ extern "C" int lge_estimate_noalloc(lge_ctx *ctx, const lge_graph *g, double p, 
   if (!scratch_view(ctx, &v)) return LGE_EINTERNAL;  // the layout outgrew the array (a library bug)
   std::lock_guard<std::mutex> lk(scratch_lock(ctx->device));
   Job job{g, p, seed, 0, g->m, -1, -1, 0};
-  const int rc = run_sequence(ctx, v, &job, 1, make_cfg(ctx, nullptr), false);
+  const int rc = run_sequence(ctx, v, &job, 1, make_cfg(ctx, nullptr), false, INT64_MAX);
   if (rc != LGE_OK) return rc;
   lge_finalize(g->n, g->m, p, seed, v.h_acc, out);
   return LGE_OK;
@@ -1972,17 +2088,31 @@ extern "C" int lge_estimate_fixed_k(lge_ctx *ctx, const lge_graph *g, uint64_t k
 // autotuner: results never depend on the options, only the time does
 // ---------------------------------------------------------------------------
 
+static std::array<int32_t, 3> tune_class(const lge_graph *g, double p) {
+  auto bits = [](uint64_t x) { int b = 0; for (; x; x >>= 1) ++b; return b; };
+  return {bits((uint64_t)g->m), bits((uint64_t)std::max(g->max_deg, 0)), (int32_t)std::lround(4.0 * std::log2(p))};
+}
+
 extern "C" int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *out) {
   if (!p_ok(p)) return LGE_EINVAL;
   if (!ctx || !g || !out) return LGE_EINVAL;
-  // coordinate descent over the knobs that matter, starting from the
-  // defaults; each candidate is timed on the device (sampling + counting)
+  const auto key = tune_class(g, p);
+  const auto hit = ctx->tuned.find(key);
+  if (hit != ctx->tuned.end()) {
+    *out = hit->second;
+    return LGE_OK;
+  }
+  // coordinate descent over the class thresholds, the split-class work-item
+  // size and layout flags, and the grid, starting from the defaults; each
+  // candidate is timed on the device (sampling + counting), best of two
+  // runs when one run is short
   lge_opts best;
   lge_opts_default(&best);
   lge_result r;
+  int reps = 2;
   auto time_of = [&](const lge_opts &o, float *ms) -> int {
     float t_best = 1e30f;
-    for (int rep = 0; rep < 2; ++rep) {
+    for (int rep = 0; rep < reps; ++rep) {
       const int rc = lge_estimate(ctx, g, p, 0x5eedull + (uint64_t)rep, &o, &r);
       if (rc != LGE_OK) return rc;
       const lge_timing &t = ctx->timing;
@@ -1994,40 +2124,43 @@ extern "C" int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts
   float best_ms;
   int rc = time_of(best, &best_ms);
   if (rc != LGE_OK) return rc;
-  const int waves[] = {64, 128, 256, 512};
-  const int ratios[] = {2, 4, 8};
-  const int grids[] = {4, 8, 12};
-  const int chunks[] = {256, 512};
+  if (best_ms > 50.0f) reps = 1;  // long runs vary by well under the gaps searched for
+  auto knob = [&](int32_t lge_opts::*field, std::initializer_list<int32_t> vals) -> int {
+    for (int32_t v : vals) {
+      if (best.*field == v) continue;
+      lge_opts o = best;
+      o.*field = v;
+      float ms;
+      const int rc2 = time_of(o, &ms);
+      if (rc2 != LGE_OK) return rc2;
+      if (ms < best_ms) best_ms = ms, best = o;
+    }
+    return LGE_OK;
+  };
   for (int pass = 0; pass < 2; ++pass) {
-    for (int v : waves) {
+    const lge_opts start = best;
+    if ((rc = knob(&lge_opts::wave_max_deg, {64, 128, 256, 512})) != LGE_OK) return rc;
+    if ((rc = knob(&lge_opts::block_max_deg, {256, 512, 1024})) != LGE_OK) return rc;
+    if ((rc = knob(&lge_opts::probe_ratio, {2, 4, 8})) != LGE_OK) return rc;
+    if ((rc = knob(&lge_opts::global_chunk, {256, 512, 1024})) != LGE_OK) return rc;
+    for (uint32_t f : {0u, LGE_OPT_SORT_HUB, LGE_OPT_XCD_LOCAL, LGE_OPT_SORT_HUB | LGE_OPT_XCD_LOCAL}) {
+      if (best.flags == f) continue;
       lge_opts o = best;
-      o.wave_max_deg = v;
+      o.flags = f;
       float ms;
       if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
       if (ms < best_ms) best_ms = ms, best = o;
     }
-    for (int v : ratios) {
-      lge_opts o = best;
-      o.probe_ratio = v;
-      float ms;
-      if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
-      if (ms < best_ms) best_ms = ms, best = o;
-    }
-    for (int v : grids) {
-      lge_opts o = best;
-      o.grid_per_cu = v;
-      float ms;
-      if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
-      if (ms < best_ms) best_ms = ms, best = o;
-    }
-    for (int v : chunks) {
-      lge_opts o = best;
-      o.global_chunk = v;
-      float ms;
-      if ((rc = time_of(o, &ms)) != LGE_OK) return rc;
-      if (ms < best_ms) best_ms = ms, best = o;
-    }
+    if ((rc = knob(&lge_opts::grid_per_cu, {4, 8, 12})) != LGE_OK) return rc;
+    if (memcmp(&start, &best, sizeof(best)) == 0) break;  // a pass changed nothing
   }
+  ctx->tuned[key] = best;
   *out = best;
+  return LGE_OK;
+}
+
+extern "C" int lge_autotune_reset(lge_ctx *ctx) {
+  if (!ctx) return LGE_EINVAL;
+  ctx->tuned.clear();
   return LGE_OK;
 }

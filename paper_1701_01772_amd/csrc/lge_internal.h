@@ -168,6 +168,7 @@ struct KernelCfg {
   int32_t grid_sample;
   int32_t global_chunk;  // Gamma(a) positions per global-class work item
   uint32_t flags;        // LGE_OPT_* bits
+  int64_t list_budget;   // bytes of split-class work lists one launch sequence may hold
 };
 
 // split-class edge ordering: key = rank of the table-side endpoint in the

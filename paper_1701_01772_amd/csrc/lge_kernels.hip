@@ -1378,8 +1378,14 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
     const int32_t abeg = S.row_ptr[a], bbeg = S.row_ptr[b];
     const int da = S.row_ptr[a + 1] - abeg;
     const int db = S.row_ptr[b + 1] - bbeg;
+    const int4 va = S.vinfo[a], vb = S.vinfo[b];
     items[e] = (da + chunk - 1) / chunk;
-    tcap[e] = da < db ? da : db;
+    // room for T_e = Gamma(a) n Gamma(b): its exact size when the co-degree
+    // table or rows hold the pair, else the smaller degree
+    const uint32_t rha = va.z >= 0 ? (uint32_t)(va.z + 1) | ((uint32_t)(va.w + 1) << 17)
+                                   : (0x80000000u | (uint32_t)(va.w + 1));
+    uint32_t te;
+    tcap[e] = codeg_pair(S, rha, vb, &te) ? (int64_t)te : (int64_t)(da < db ? da : db);
     GEdge &G = gacc[e];
     G.t = G.k4 = G.cyc = G.spare = G.nzw = 0ull;
     G.a = a;
@@ -1389,7 +1395,6 @@ __global__ __launch_bounds__(256) void k_global_prep(const SlotDesc *__restrict_
     G.db = db;
     G.abeg = abeg;
     G.bbeg = bbeg;
-    const int4 va = S.vinfo[a], vb = S.vinfo[b];
     G.ra = va.z;
     G.rb = vb.z;
     G.hra = va.w;

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
+#include <map>
+
 #include "../../include/lge.h"
 #include "lge_internal.h"
 
@@ -116,6 +119,13 @@ struct lge_ctx {
   void *na_h_desc = nullptr;
   unsigned long long *na_h_ctl = nullptr;
   lge_opts opts{};
+  // autotuned options per graph class (bit lengths of m and of the maximum
+  // degree, p in quarter octaves)
+  std::map<std::array<int32_t, 3>, lge_opts> tuned;
+  // split-class list bytes one launch sequence may hold (a quarter of the
+  // device's memory), and what the last sequence over it asked for
+  int64_t list_budget = (int64_t)16 << 30;
+  int64_t list_need = 0;
   lge_timing timing{};
   hipEvent_t ev[8] = {};
   int num_cu = 256;

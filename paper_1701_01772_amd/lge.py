@@ -67,7 +67,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("wave_max_deg", ctypes.c_int32), ("block_max_deg", ctypes.c_int32),
                 ("probe_ratio", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
                 ("global_chunk", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("max_list_mib", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -168,6 +168,7 @@ def load():
                                ctypes.POINTER(Result)], ctypes.c_int),
         "lge_last_timing": ([_VP, ctypes.POINTER(Timing)], ctypes.c_int),
         "lge_autotune": ([_VP, _VP, ctypes.c_double, ctypes.POINTER(Opts)], ctypes.c_int),
+        "lge_autotune_reset": ([_VP], ctypes.c_int),
         "lge_adaptive_cfg_default": ([ctypes.POINTER(AdaptiveCfg)], ctypes.c_int),
         "lge_estimate_adaptive": ([_VP, _VP, ctypes.c_uint64, ctypes.POINTER(AdaptiveCfg), ctypes.POINTER(Result),
                                    ctypes.POINTER(AdaptiveTrace)], ctypes.c_int),
@@ -221,6 +222,11 @@ def make_opts(**kw) -> Opts:
     for k, v in kw.items():
         setattr(o, k, int(v))
     return o
+
+
+def opts_dict(o: Opts) -> dict:
+    """The tuning fields of an Opts as a plain dict."""
+    return {k: getattr(o, k) for k, _ in Opts._fields_ if k != "reserved"}
 
 
 def lge_open(device: int = 0):
@@ -398,6 +404,10 @@ def lge_autotune(ctx, g, p: float) -> Opts:
     o = Opts()
     _check(load().lge_autotune(ctx, g, float(p), ctypes.byref(o)), "lge_autotune")
     return o
+
+
+def lge_autotune_reset(ctx):
+    _check(load().lge_autotune_reset(ctx), "lge_autotune_reset")
 
 
 def lge_estimate_adaptive(ctx, g, seed: int, beta: float = 0.01, t_max: int = 20, phi0: float = 0.0):

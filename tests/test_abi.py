@@ -82,6 +82,7 @@ def test_null_arguments_rejected():
     assert lib.lge_open(0, None) == lge.LGE_EINVAL
     assert lib.lge_close(None) == lge.LGE_EINVAL
     assert lib.lge_graph_destroy(None) == lge.LGE_EINVAL
+    assert lib.lge_autotune_reset(None) == lge.LGE_EINVAL
     assert lib.lge_count_batch(None, None, None, None) == lge.LGE_EINVAL
     assert lib.lge_validate_csr_host(-1, None, None) == lge.LGE_EINVAL
     assert lib.lge_graph_n(None) == -1

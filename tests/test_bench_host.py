@@ -44,9 +44,13 @@ def test_roofline_takes_the_dominant_kernel_and_its_bytes():
     assert dev["count_global"] == 5.0 and dev["count_wave"] == 2.0 and dev["global_prep"] == 1.0
     assert roof["kernel"].startswith("k_count_global")
     assert roof["launch_ms"] == 5.0
-    assert roof["achieved"] == 8e9 / 5e-3 / 1e9  # GB/s
+    # achieved: the 4-byte words the kernel read, per launch, over the launch time
+    assert roof["bytes_per_launch"] == 4.0 * 2000
+    assert roof["achieved"] == 4.0 * 2000 / 5e-3 / 1e9  # GB/s
     assert roof["frac"] == roof["achieved"] / 8000.0
-    assert roof["issued_bytes_per_launch"] == 4.0 * 2000
+    # effective: the neighbour-iteration bytes of the same launch
+    assert roof["effective"]["bytes_per_launch"] == 8e9
+    assert roof["effective"]["GBps"] == 8e9 / 5e-3 / 1e9
     assert roof["traffic"] is None  # no counter profile for this workload
 
 

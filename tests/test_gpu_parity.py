@@ -9,8 +9,10 @@ the oracle finishes in seconds, chosen to hit all three edge classes
 import math
 import os
 import sys
+import time
 
 import numpy as np
+
 import pytest
 
 import oracle
@@ -175,6 +177,46 @@ def test_range_additivity_and_parity(ctx):
         lge.lge_graph_destroy(h)
 
 
+def test_list_budget_pieces_equal_one_sequence(ctx):
+    # a 1 MiB bound on the split-class lists makes every call below run its
+    # edge-id range in pieces; the exact sums must not change
+    g = inputs.chung_lu(20000, 10.0, 2.1, 3000.0, 41)
+    g2 = inputs.rmat(12, 16, 0.57, 0.19, 0.19, 4)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    h2 = lge.lge_graph_create_host(ctx, g2.row_ptr, g2.col)
+    small = lge.make_opts(max_list_mib=1)
+    keys = ("sampled", "csum", "zsum", "qsum", "exact", "estimate", "variance")
+    try:
+        for p in (1.0, 0.5):
+            base = lge.lge_estimate(ctx, h, p, 12)
+            tb = lge.lge_last_timing(ctx)
+            got = lge.lge_estimate(ctx, h, p, 12, small)
+            t = lge.lge_last_timing(ctx)
+            _say("pieces p=%g: %d host waits (one sequence: %d)" % (p, t["host_waits"], tb["host_waits"]))
+            assert t["host_waits"] > 2, t["host_waits"]
+            assert list(t["class_edges"]) == list(tb["class_edges"])
+            for k in keys:
+                assert got[k] == base[k], (p, k)
+        assert_parity(got, oracle.estimate(g.row_ptr, g.col, 0.5, 12), "pieces")
+        many = lge.lge_estimate_many(ctx, [h, h2, h], [1.0, 0.8, 0.3], [5, 6, 7], small)
+        for hh, out, p, sd in zip([h, h2, h], many, [1.0, 0.8, 0.3], [5, 6, 7]):
+            single = lge.lge_estimate(ctx, hh, p, sd)
+            for k in keys:
+                assert out[k] == single[k], (p, k)
+        a, b = 100, g.m - 100
+        rs = lge.lge_estimate_range(ctx, h, 0.9, 3, a, b, small)
+        rb = lge.lge_estimate_range(ctx, h, 0.9, 3, a, b)
+        for k in ("sampled", "csum", "zsum", "qsum"):
+            assert rs[k] == rb[k], k
+        ws, _ = lge.lge_estimate_weighted(ctx, h2, lge.LGE_WEIGHT_DEGREE, 0.4, 9, small)
+        wb, _ = lge.lge_estimate_weighted(ctx, h2, lge.LGE_WEIGHT_DEGREE, 0.4, 9)
+        for k in ("sampled", "csum", "zsum", "qsum", "estimate", "variance"):
+            assert ws[k] == wb[k], k
+    finally:
+        lge.lge_graph_destroy(h2)
+        lge.lge_graph_destroy(h)
+
+
 def test_batch_equals_singles(ctx):
     graphs = inputs.batch_graphs(count=24, seed=77, n_lo=20, n_hi=1500)
     graphs.append(inputs.from_edges(4, []))
@@ -285,10 +327,30 @@ def test_autotune_changes_speed_not_results(ctx):
         _say("autotune on chung-lu-20k")
         o = lge.lge_autotune(ctx, h, 0.4)
         assert 1 <= o.wave_max_deg <= 512 and o.probe_ratio > 0
+        assert 1 <= o.block_max_deg <= 1024 and o.global_chunk in (256, 512, 1024)
         tuned = lge.lge_estimate(ctx, h, 0.4, 77, o)
         base = lge.lge_estimate(ctx, h, 0.4, 77)
         for k in ("sampled", "csum", "zsum", "qsum", "estimate", "variance"):
             assert tuned[k] == base[k], k
+        # a second graph of the same class (same bit lengths of m and of the
+        # maximum degree, same p) gets the cached choice at once
+        g2 = inputs.chung_lu(20000, 10.0, 2.1, 3000.0, 42)
+        h2 = lge.lge_graph_create_host(ctx, g2.row_ptr, g2.col)
+        try:
+            same_class = (g2.m.bit_length() == g.m.bit_length()
+                          and lge.lge_graph_query(h2)["max_deg"].bit_length()
+                          == lge.lge_graph_query(h)["max_deg"].bit_length())
+            t0 = time.perf_counter()
+            o2 = lge.lge_autotune(ctx, h2, 0.4)
+            dt = time.perf_counter() - t0
+            if same_class:
+                assert lge.opts_dict(o2) == lge.opts_dict(o)
+                assert dt < 0.5, dt
+            lge.lge_autotune_reset(ctx)
+            o3 = lge.lge_autotune(ctx, h2, 0.4)  # timed afresh
+            assert lge.lge_estimate(ctx, h2, 0.4, 78, o3)["csum"] == lge.lge_estimate(ctx, h2, 0.4, 78)["csum"]
+        finally:
+            lge.lge_graph_destroy(h2)
     finally:
         lge.lge_graph_destroy(h)
 
