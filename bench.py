@@ -408,7 +408,8 @@ def serving_set(args, threads=16):
 def bench_serve(args, graphs=None):
     """Poisson request stream over resident graphs served by lge_server
     (continuous batching); rates at 50% and 80% of the plain path's measured
-    saturation throughput."""
+    saturation throughput, the same requests each time, so every latency has
+    its plain latency alone beside it (the slowdown)."""
     from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import torch
@@ -418,9 +419,16 @@ def bench_serve(args, graphs=None):
         graphs = serving_set(args)
     log("serving set: %d graphs, %d edges in all" % (len(graphs), sum(g.m for g in graphs)))
     ctx = lge.lge_open(0)
-    # 64 graphs stay resident: compact tables keep the set's HBM bounded
+    # 64 graphs stay resident: their co-degree tables and rows share
+    # args.serve_table_gb of HBM in proportion to their edge counts
     t0 = time.perf_counter()
-    hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col, lge.LGE_FLAG_COMPACT) for g in graphs]
+    m_all = float(sum(g.m for g in graphs))
+    hs = []
+    for g in graphs:
+        share = args.serve_table_gb * 1e9 * g.m / m_all
+        lge.lge_set_table_budget(ctx, int(share / 2), int(share / 2))
+        hs.append(lge.lge_graph_create_host(ctx, g.row_ptr, g.col))
+    lge.lge_set_table_budget(ctx, 0, 0)
     state = sum(lge.lge_graph_query(h)["state_bytes"] for h in hs)
     log("serving set resident in %.1f s (%.1f GB of graph state)" % (time.perf_counter() - t0, state / 1e9))
     rng = np.random.default_rng(args.seed)
@@ -438,11 +446,16 @@ def bench_serve(args, graphs=None):
     t0 = time.perf_counter()
     plain_edges = 0
     plain_lat = []
-    for gi, p, s in cal:
+    for i, (gi, p, s) in enumerate(cal):
         t1 = time.perf_counter()
         plain_edges += lge.lge_estimate(ctx, hs[gi], p, s, raw=True, out=res).sampled_edges
         plain_lat.append(time.perf_counter() - t1)
+        if (i + 1) % 16 == 0:
+            log("plain: %d of %d requests, %.1f s" % (i + 1, len(cal), time.perf_counter() - t0))
     t_plain = time.perf_counter() - t0
+    alone = {}  # latency of each (graph, p, seed) alone, for slowdowns
+    for (gi, p, s), lt in zip(cal, plain_lat):
+        alone[(gi, p, s)] = lt
     sat_qps = len(cal) / t_plain
     log("plain saturation: %.1f requests/s" % sat_qps)
     out = {"graphs": len(graphs), "edges_total": sum(g.m for g in graphs), "graph_state_bytes": state,
@@ -460,7 +473,11 @@ def bench_serve(args, graphs=None):
         st0 = lge.lge_server_get_stats(srv)
         t0 = time.perf_counter()
         tk = [lge.lge_submit(srv, gids[gi], p, s) for gi, p, s in cal]
-        burst_edges = sum(lge.lge_wait(srv, t, -1)["sampled"] for t in tk)
+        burst_edges = 0
+        for i, t in enumerate(tk):
+            burst_edges += lge.lge_wait(srv, t, -1)["sampled"]
+            if (i + 1) % 16 == 0:
+                log("burst: %d of %d requests, %.1f s" % (i + 1, len(tk), time.perf_counter() - t0))
         t_burst = time.perf_counter() - t0
         st1 = lge.lge_server_get_stats(srv)
         assert burst_edges == plain_edges
@@ -469,7 +486,7 @@ def bench_serve(args, graphs=None):
                         "vs_plain": t_plain / t_burst}
         log("burst: %.1f requests/s (plain %.1f), %d steps" % (len(cal) / t_burst, sat_qps, out["burst"]["steps"]))
         for frac in (0.5, 0.8):
-            reqs = draw(n_req)
+            reqs = cal  # the measured requests again, so each has its latency alone
             qps = frac * sat_qps
             gaps = rng.exponential(1.0 / qps, len(reqs))
             lat = [None] * len(reqs)
@@ -492,17 +509,23 @@ def bench_serve(args, graphs=None):
                 t_sub = time.perf_counter()
                 ticket = lge.lge_submit(srv, gids[gi], p, s)
                 futs.append(pool.submit(waiter, i, ticket, t_sub))
-            for f in futs:
+            for i, f in enumerate(futs):
                 f.result()
+                if (i + 1) % 16 == 0:
+                    log("served at %d%%: %d of %d requests, %.1f s" % (
+                        int(frac * 100), i + 1, len(futs), time.perf_counter() - t_start))
             span = time.perf_counter() - t_start
             pool.shutdown()
             la = np.array(lat) * 1e3
+            slow = np.array([lat[i] / alone[r] for i, r in enumerate(reqs)])
             st = lge.lge_server_get_stats(srv)
             key = "served_%d" % int(frac * 100)
             out[key] = {"offered_qps": qps, "requests": len(reqs), "p50_ms": float(np.percentile(la, 50)),
                         "p99_ms": float(np.percentile(la, 99)), "throughput_rps": len(reqs) / span,
-                        "sampled_edges_per_s": sum(sampled) / span, "steps_total": st["steps"]}
-            log("%s: p50 %.2f ms p99 %.2f ms" % (key, out[key]["p50_ms"], out[key]["p99_ms"]))
+                        "sampled_edges_per_s": sum(sampled) / span, "steps_total": st["steps"],
+                        "slowdown_p50": float(np.percentile(slow, 50)), "slowdown_p99": float(np.percentile(slow, 99))}
+            log("%s: p50 %.2f ms p99 %.2f ms, slowdown vs alone p50 %.2f p99 %.2f" % (
+                key, out[key]["p50_ms"], out[key]["p99_ms"], out[key]["slowdown_p50"], out[key]["slowdown_p99"]))
     finally:
         lge.lge_server_destroy(srv)
     for h in hs:
@@ -670,6 +693,8 @@ def main():
     ap.add_argument("--sweep", default=None,
                     help="';'-separated option settings, e.g. 'flags=0;flags=1,global_chunk=128'")
     ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-table-gb", type=float, default=120.0,
+                    help="HBM the serving set's co-degree tables and rows share (in proportion to edge counts)")
     ap.add_argument("--serve-step-us", type=int, default=0, help="server target step time (0: library default)")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no other legs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -768,6 +793,8 @@ def main():
                             "p50_ms_alone": sv["plain"]["p50_ms_alone"], "p99_ms_alone": sv["plain"]["p99_ms_alone"],
                             "p50_ms_at_50pct": sv["served_50"]["p50_ms"], "p99_ms_at_50pct": sv["served_50"]["p99_ms"],
                             "p50_ms_at_80pct": sv["served_80"]["p50_ms"], "p99_ms_at_80pct": sv["served_80"]["p99_ms"],
+                            "slowdown_p50_at_80pct": sv["served_80"]["slowdown_p50"],
+                            "slowdown_p99_at_80pct": sv["served_80"]["slowdown_p99"],
                             "throughput_rps_at_80pct": sv["served_80"]["throughput_rps"]}
         mi = bench_micro(bargs, g)
         result["micro"] = {"workload": mi["config"]["workload"], "value": mi["value"], "unit": mi["unit"],

@@ -461,6 +461,15 @@ LGE_API int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts *o
 LGE_API int lge_autotune_reset(lge_ctx *ctx);
 
 /*
+ * Caps, in bytes, on the co-degree table and on the co-degree rows of the
+ * graphs created on ctx from now on (0 = the library's own budgets, which
+ * depend on the graph alone).  A resident set of many graphs shares HBM
+ * this way; smaller tables mean more neighbour walks (slower estimates),
+ * never different results.  Errors: LGE_EINVAL (null ctx).
+ */
+LGE_API int lge_set_table_budget(lge_ctx *ctx, uint64_t codeg_bytes, uint64_t rows_bytes);
+
+/*
  * Serving.  A server owns `ctx` (no other call may use that ctx while the
  * server exists) and runs `workers` step threads: the first steps on ctx,
  * the others on contexts the server opens on the same device (own stream and
@@ -469,8 +478,13 @@ LGE_API int lge_autotune_reset(lge_ctx *ctx);
  * seed) queue FIFO; up to max_inflight of them run at once.  Every step a
  * worker gives running requests the next chunks of their canonical edge-id
  * ranges: chunks share the step's work budget (measured work rate x
- * target_step_us) equally, and together fit the step's device work lists into
- * hbm_budget_bytes (the admission bound by HBM footprint); it runs all chunks
+ * target_step_us) equally, each sized by its graph's work profile along the
+ * edge ids (hub rows cost more), and together fit the step's device work
+ * lists into hbm_budget_bytes (the admission bound by HBM footprint); with
+ * three or more workers the last one is a short lane: it steps only requests
+ * whose remaining expected time is below short_us, in steps of at most
+ * short_us, and the other workers leave those to it, so short requests do
+ * not queue behind long steps.  A worker runs all chunks
  * in one launch sequence and finalises the requests whose range is done and
  * whose chunks have all returned.  Requests arriving meanwhile join at the
  * next step (continuous batching).  A request's result equals lge_estimate on
@@ -485,8 +499,9 @@ typedef struct {
   int64_t min_chunk_edges;  /* smallest edge-id chunk per request and step (default 4096) */
   int64_t target_step_us;   /* aimed duration of one step (default 100000); chunks are sized by each
                                graph's per-edge work estimate and the measured work rate */
-  int32_t workers;          /* step threads, 1..4 (default 2; 0 = default) */
-  int32_t reserved;
+  int32_t workers;          /* step threads, 1..4 (default 3; 0 = default) */
+  int32_t short_us;         /* short-lane bound on a request's remaining expected time, microseconds
+                               (default 20000; negative: no short lane) */
 } lge_server_cfg;
 
 typedef struct {

@@ -511,13 +511,22 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   }
   if (g->m > 0) e = launch_graph_edges(g->row_ptr, g->col, up, base, n, g->edges, s);
   if (e == hipSuccess) e = launch_graph_vol2(g->row_ptr, g->col, n, g->vol2, s);
-  unsigned long long work_sum = 0;
   if (e == hipSuccess && g->m > 0) {
-    e = hipMemsetAsync(tmp, 0, sizeof(int64_t), s);
-    if (e == hipSuccess) e = launch_graph_work(g->row_ptr, g->edges, g->vol2, g->m, (unsigned long long *)tmp, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&work_sum, tmp, sizeof(work_sum), hipMemcpyDeviceToHost, s);
+    // the work profile along the canonical edge ids, for chunking ranges by work
+    const int64_t nb = (g->m + kWorkBlock - 1) / kWorkBlock;
+    unsigned long long *wb = nullptr;
+    if ((rc = dev_alloc(&wb, nb)) != LGE_OK) {
+      cleanup();
+      return rc;
+    }
+    std::vector<unsigned long long> hb((size_t)nb);
+    e = launch_graph_work(g->row_ptr, g->edges, g->vol2, g->m, wb, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), wb, (size_t)nb * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    g->work_per_id = g->m > 0 ? (double)work_sum / (double)g->m : 0.0;
+    dev_free(wb);
+    g->work_pref.assign((size_t)nb + 1, 0.0);
+    for (int64_t k = 0; k < nb; ++k) g->work_pref[(size_t)k + 1] = g->work_pref[(size_t)k] + (double)hb[(size_t)k];
+    g->work_per_id = g->work_pref.back() / (double)g->m;
   }
   // hub tables
   if (e == hipSuccess) e = launch_hub_sizes(g->row_ptr, n, cnt, s);
@@ -587,6 +596,7 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
   const double csr_bytes = 4.0 * ((double)n + 1.0 + 2.0 * (double)g->m);
   double budget = (flags & LGE_FLAG_COMPACT) ? kCodegBytesCompact : kCodegBytes;
   budget = std::min(budget, std::max(kCodegBytesCompact, kCodegPerCsr * csr_bytes));
+  if (ctx->codeg_budget > 0) budget = std::min(budget, (double)ctx->codeg_budget);
   int64_t hc_max = std::min<int64_t>(kMaxRanked, (int64_t)std::sqrt(budget / 4.0));
   hc_max &= ~(int64_t)63;
   std::vector<int32_t> deg((size_t)n);
@@ -699,6 +709,7 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   double budget_bytes = compact ? kRowBudgetBytesCompact : kRowBudgetBytes;
   const double csr_bytes = 4.0 * ((double)n + 1.0 + 2.0 * (double)g->m);
   budget_bytes = std::min(budget_bytes, std::max(kRowBudgetBytesCompact, kRowsPerCsr * csr_bytes));
+  if (ctx->rows_budget > 0) budget_bytes = std::min(budget_bytes, (double)ctx->rows_budget);
   std::vector<int32_t> hubs;  // ranked hubs within the build-work budget, largest degree first
   double ops = 0.0;
   for (const auto &c : cand) {
@@ -2162,5 +2173,12 @@ extern "C" int lge_autotune(lge_ctx *ctx, const lge_graph *g, double p, lge_opts
 extern "C" int lge_autotune_reset(lge_ctx *ctx) {
   if (!ctx) return LGE_EINVAL;
   ctx->tuned.clear();
+  return LGE_OK;
+}
+
+extern "C" int lge_set_table_budget(lge_ctx *ctx, uint64_t codeg_bytes, uint64_t rows_bytes) {
+  if (!ctx) return LGE_EINVAL;
+  ctx->codeg_budget = (int64_t)std::min<uint64_t>(codeg_bytes, (uint64_t)INT64_MAX);
+  ctx->rows_budget = (int64_t)std::min<uint64_t>(rows_bytes, (uint64_t)INT64_MAX);
   return LGE_OK;
 }

@@ -207,8 +207,11 @@ hipError_t launch_graph_edges(const int32_t *row_ptr, const int32_t *col, const 
                               const int64_t *eid_base, int64_t n, uint64_t *edges, hipStream_t s);
 hipError_t launch_graph_vol2(const int32_t *row_ptr, const int32_t *col, int64_t n, int64_t *vol2,
                              hipStream_t s);
+// per-block work estimate: blocks[k] = the cost of canonical edge ids
+// [k kWorkBlock, (k + 1) kWorkBlock)
+constexpr int64_t kWorkBlock = 4096;
 hipError_t launch_graph_work(const int32_t *row_ptr, const uint64_t *edges, const int64_t *vol2, int64_t m,
-                             unsigned long long *sum, hipStream_t s);
+                             unsigned long long *blocks, hipStream_t s);
 hipError_t launch_hub_sizes(const int32_t *row_ptr, int64_t n, int64_t *size, hipStream_t s);
 hipError_t launch_hub_build(const int32_t *row_ptr, const int32_t *col, int64_t n, const int64_t *hoff,
                             uint32_t *htab, hipStream_t s);

@@ -330,21 +330,30 @@ __global__ __launch_bounds__(256) void k_graph_vol2(const int32_t *__restrict__ 
 
 // Scheduling weight of a graph: sum over canonical edges of
 // d_u + d_v + min(vol2(u), vol2(v)), the neighbour-iteration cost of the
-// cheaper orientation (an upper bound on the counting work per edge).
+// cheaper orientation (an upper bound on the counting work per edge), summed
+// over each block of kWorkBlock consecutive canonical edge ids: one
+// wavefront per block.
 __global__ __launch_bounds__(256) void k_graph_work(const int32_t *__restrict__ row_ptr,
                                                     const uint64_t *__restrict__ edges,
                                                     const int64_t *__restrict__ vol2, int64_t m,
-                                                    unsigned long long *sum) {
-  unsigned long long acc = 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t x = edges[e];
-    const int32_t u = (int32_t)(x >> 32), v = (int32_t)(uint32_t)x;
-    const int64_t du = row_ptr[u + 1] - row_ptr[u], dv = row_ptr[v + 1] - row_ptr[v];
-    const int64_t w = vol2[u] < vol2[v] ? vol2[u] : vol2[v];
-    acc += (unsigned long long)(du + dv + w);
+                                                    unsigned long long *__restrict__ blocks) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nb = (m + kWorkBlock - 1) / kWorkBlock;
+  const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t blk = w0; blk < nb; blk += nw) {
+    const int64_t e1 = (blk + 1) * kWorkBlock < m ? (blk + 1) * kWorkBlock : m;
+    unsigned long long acc = 0;
+    for (int64_t e = blk * kWorkBlock + lane; e < e1; e += kWave) {
+      const uint64_t x = edges[e];
+      const int32_t u = (int32_t)(x >> 32), v = (int32_t)(uint32_t)x;
+      const int64_t du = row_ptr[u + 1] - row_ptr[u], dv = row_ptr[v + 1] - row_ptr[v];
+      const int64_t w = vol2[u] < vol2[v] ? vol2[u] : vol2[v];
+      acc += (unsigned long long)(du + dv + w);
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0) blocks[blk] = acc;
   }
-  acc = wave_sum_u64(acc);
-  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(sum, acc);
 }
 
 // slot count (power of two) of each vertex's hub table; 0 for non-hubs
@@ -2461,9 +2470,10 @@ hipError_t launch_graph_vol2(const int32_t *row_ptr, const int32_t *col, int64_t
 }
 
 hipError_t launch_graph_work(const int32_t *row_ptr, const uint64_t *edges, const int64_t *vol2, int64_t m,
-                             unsigned long long *sum, hipStream_t s) {
+                             unsigned long long *blocks, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_graph_work, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, row_ptr, edges, vol2, m, sum);
+  hipLaunchKernelGGL(k_graph_work, dim3(grid_for((m + kWorkBlock - 1) / kWorkBlock, 4, 8192)), dim3(256), 0, s,
+                     row_ptr, edges, vol2, m, blocks);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 
 #include <array>
 #include <map>
+#include <vector>
 
 #include "../../include/lge.h"
 #include "lge_internal.h"
@@ -47,6 +48,9 @@ struct lge_graph {
   int32_t rows_floor = 0;             // unranked vertices above this degree have a column
   int32_t codeg_tau = 0;
   double work_per_id = 0.0;  // scheduling weight per canonical edge id
+  // cumulative scheduling weight at every kWorkBlock-th canonical edge id
+  // (host; the last entry is the whole graph's)
+  std::vector<double> work_pref;
   double build_ms = 0.0;     // preprocessing wall time (after validation and the edge list)
   // micro statistics, built on first use: t of every arc, triangles per
   // vertex, and a small reduction buffer (column maxima, error flag)
@@ -126,6 +130,10 @@ struct lge_ctx {
   // device's memory), and what the last sequence over it asked for
   int64_t list_budget = (int64_t)16 << 30;
   int64_t list_need = 0;
+  // caps on the co-degree table and co-degree row bytes of graphs created
+  // on this context (0: the library's own budgets)
+  int64_t codeg_budget = 0;
+  int64_t rows_budget = 0;
   lge_timing timing{};
   hipEvent_t ev[8] = {};
   int num_cu = 256;

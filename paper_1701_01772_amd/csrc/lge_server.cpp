@@ -58,6 +58,31 @@ struct Request {
   lge_result result{};
 };
 
+// scheduling weight of canonical edge ids [0, x) of g: the graph's work
+// profile, linear inside a profile block
+double work_at(const lge_graph *g, int64_t x) {
+  const std::vector<double> &P = g->work_pref;
+  if (P.size() < 2) return (double)x * g->work_per_id;
+  const int64_t k = x / kWorkBlock;
+  if (k >= (int64_t)P.size() - 1) return P.back();
+  const int64_t b0 = k * kWorkBlock, b1 = std::min(b0 + kWorkBlock, g->m);
+  return P[(size_t)k] + (P[(size_t)k + 1] - P[(size_t)k]) * (double)(x - b0) / (double)(b1 - b0);
+}
+
+// the smallest x in (c, m] with work_at(x) - work_at(c) >= units (m if none)
+int64_t ids_for_work(const lge_graph *g, int64_t c, double units) {
+  const std::vector<double> &P = g->work_pref;
+  if (P.size() < 2) return std::min(g->m, c + std::max<int64_t>(1, (int64_t)std::min(units / std::max(g->work_per_id, 1e-9), 9.0e15)));
+  const double target = work_at(g, c) + units;
+  if (target >= P.back()) return g->m;
+  const int64_t k = (int64_t)(std::lower_bound(P.begin(), P.end(), target) - P.begin());  // P[k-1] < target <= P[k]
+  const int64_t b0 = (k - 1) * kWorkBlock, b1 = std::min(k * kWorkBlock, g->m);
+  const double span = P[(size_t)k] - P[(size_t)k - 1];
+  const double f = span > 0 ? (target - P[(size_t)k - 1]) / span : 1.0;
+  const int64_t x = b0 + (int64_t)std::ceil(f * (double)(b1 - b0));
+  return std::min(g->m, std::max(x, c + 1));
+}
+
 void add_acc(unsigned long long *dst, const unsigned long long *src) {
   for (int k = 0; k < kAccSlots; ++k) {
     const unsigned long long lo = dst[2 * k] + src[2 * k];
@@ -116,35 +141,55 @@ struct lge_server {
     return r->done;
   }
 
-  bool assignable() const {
+  bool has_short_lane() const { return cfg.short_us >= 0 && nworkers >= 3; }
+
+  // expected seconds of r's remaining range on one worker
+  double remaining_s(const Request *r) const {
+    const lge_graph *g = graphs[(size_t)r->gid];
+    return r->p * (work_at(g, r->m) - work_at(g, r->cursor)) / rate;
+  }
+
+  // may a worker of this lane step r now?
+  bool eligible(const Request *r, bool short_lane) const {
+    if (r->canceled || r->error != LGE_OK || r->cursor >= r->m) return false;
+    if (!has_short_lane()) return true;
+    return short_lane == (remaining_s(r) * 1e6 < (double)cfg.short_us);
+  }
+
+  bool assignable(bool short_lane) const {
     if (!queue.empty() && (int32_t)running.size() < cfg.max_inflight) return true;
     for (const Request *r : running)
-      if (!r->canceled && r->error == LGE_OK && r->cursor < r->m) return true;
+      if (eligible(r, short_lane)) return true;
     return false;
   }
 
-  void loop(lge_ctx *wctx) {
+  void loop(lge_ctx *wctx, bool short_lane) {
     std::vector<Job> jobs;
     std::vector<Request *> in_step;
     for (;;) {
       double step_work = 0.0;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || assignable(); });
+        cv_work.wait(lk, [&] { return stop || assignable(short_lane); });
         if (stop) return;
         // admission: running slots free up as requests finish
+        bool admitted = false;
         while (!queue.empty() && (int32_t)running.size() < cfg.max_inflight) {
           running.push_back(queue.front());
           queue.pop_front();
+          admitted = true;
         }
+        if (admitted) cv_work.notify_all();  // the other lane may own some of them
         // chunks for this step, starting at a rotating request
         jobs.clear();
         in_step.clear();
         int64_t budget = std::max<int64_t>(cfg.hbm_budget_bytes / kStepBytesPerId, 1);  // edge ids
-        double wbudget = std::max(rate * (double)cfg.target_step_us * 1e-6, 1.0);       // work units
+        const double step_us = short_lane ? (double)std::min<int64_t>(cfg.short_us, cfg.target_step_us)
+                                          : (double)cfg.target_step_us;
+        double wbudget = std::max(rate * step_us * 1e-6, 1.0);  // work units
         std::vector<Request *> open;
         for (Request *r : running)
-          if (!r->canceled && r->error == LGE_OK && r->cursor < r->m) open.push_back(r);
+          if (eligible(r, short_lane)) open.push_back(r);
         const size_t nr = open.size();
         if (nr == 0) continue;
         rotate %= nr;
@@ -152,23 +197,24 @@ struct lge_server {
           Request *r = open[(rotate + k) % nr];
           const lge_graph *g = graphs[(size_t)r->gid];
           const int64_t left = r->m - r->cursor;
-          // expected work of one edge id of this request
-          const double unit = std::max(r->p * g->work_per_id, 1e-9);
+          // the ids whose expected work (the graph's profile times p) is
+          // this request's share of the step
           const double wshare = wbudget / (double)(nr - k);
-          const int64_t by_work = (int64_t)std::min(wshare / unit, 9.0e15);
+          const int64_t by_work = ids_for_work(g, r->cursor, wshare / std::max(r->p, 1e-300)) - r->cursor;
           const int64_t want = std::max<int64_t>(cfg.min_chunk_edges, by_work);
           const int64_t len = std::min(left, std::min(want, budget));
+          const double wk = r->p * (work_at(g, r->cursor + len) - work_at(g, r->cursor));
           jobs.push_back(Job{g, r->p, r->seed, r->cursor, r->cursor + len, -1, -1, 0});
           in_step.push_back(r);
           r->cursor += len;
           r->inflight += 1;
           budget -= std::max<int64_t>(len, 1);
-          wbudget -= std::min(wbudget, (double)len * unit);
-          step_work += (double)len * unit;
+          wbudget -= std::min(wbudget, wk);
+          step_work += wk;
         }
         rotate += 1;
         ++stats.steps;
-        if (assignable()) cv_work.notify_one();  // more work for an idle worker
+        if (assignable(short_lane) || assignable(!short_lane)) cv_work.notify_all();  // work for idle workers
       }
       const auto t0 = std::chrono::steady_clock::now();
       const int rc = lge_run_jobs(wctx, jobs.data(), (int)jobs.size(), nullptr);
@@ -206,7 +252,8 @@ extern "C" int lge_server_cfg_default(lge_server_cfg *c) {
   c->hbm_budget_bytes = (int64_t)2 << 30;
   c->min_chunk_edges = 4096;
   c->target_step_us = 100000;
-  c->workers = 2;
+  c->workers = 3;
+  c->short_us = 20000;
   return LGE_OK;
 }
 
@@ -225,6 +272,7 @@ extern "C" int lge_server_create(lge_ctx *ctx, const lge_server_cfg *cfg, lge_se
     if (cfg->hbm_budget_bytes) c.hbm_budget_bytes = cfg->hbm_budget_bytes;
     if (cfg->min_chunk_edges) c.min_chunk_edges = cfg->min_chunk_edges;
     if (cfg->workers) c.workers = cfg->workers;
+    if (cfg->short_us) c.short_us = cfg->short_us;
   }
   if (c.hbm_budget_bytes < kStepBytesPerId) return LGE_EINVAL;
   lge_server *s = new (std::nothrow) lge_server();
@@ -248,9 +296,10 @@ extern "C" int lge_server_create(lge_ctx *ctx, const lge_server_cfg *cfg, lge_se
   try {
     for (int k = 0; k < s->nworkers; ++k) {
       lge_ctx *wc = s->workers[k].ctx;
-      s->workers[k].th = std::thread([s, wc] {
+      const bool short_lane = s->has_short_lane() && k == s->nworkers - 1;
+      s->workers[k].th = std::thread([s, wc, short_lane] {
         (void)hipSetDevice(wc->device);
-        s->loop(wc);
+        s->loop(wc, short_lane);
       });
     }
   } catch (...) {

@@ -100,7 +100,7 @@ class Batch(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64), ("min_chunk_edges", ctypes.c_int64),
-                ("target_step_us", ctypes.c_int64), ("workers", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("target_step_us", ctypes.c_int64), ("workers", ctypes.c_int32), ("short_us", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -169,6 +169,7 @@ def load():
         "lge_last_timing": ([_VP, ctypes.POINTER(Timing)], ctypes.c_int),
         "lge_autotune": ([_VP, _VP, ctypes.c_double, ctypes.POINTER(Opts)], ctypes.c_int),
         "lge_autotune_reset": ([_VP], ctypes.c_int),
+        "lge_set_table_budget": ([_VP, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
         "lge_adaptive_cfg_default": ([ctypes.POINTER(AdaptiveCfg)], ctypes.c_int),
         "lge_estimate_adaptive": ([_VP, _VP, ctypes.c_uint64, ctypes.POINTER(AdaptiveCfg), ctypes.POINTER(Result),
                                    ctypes.POINTER(AdaptiveTrace)], ctypes.c_int),
@@ -408,6 +409,10 @@ def lge_autotune(ctx, g, p: float) -> Opts:
 
 def lge_autotune_reset(ctx):
     _check(load().lge_autotune_reset(ctx), "lge_autotune_reset")
+
+
+def lge_set_table_budget(ctx, codeg_bytes: int = 0, rows_bytes: int = 0):
+    _check(load().lge_set_table_budget(ctx, int(codeg_bytes), int(rows_bytes)), "lge_set_table_budget")
 
 
 def lge_estimate_adaptive(ctx, g, seed: int, beta: float = 0.01, t_max: int = 20, phi0: float = 0.0):

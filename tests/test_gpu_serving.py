@@ -92,6 +92,82 @@ def test_alone_equals_mix(graphs):
         lge.lge_close(alone_ctx)
 
 
+def test_alone_equals_mix_large():
+    # a graph of more than 1e7 edges among small ones, default server
+    # configuration (work-profile chunks, short lane): every result equals
+    # the same request alone
+    big = inputs.chung_lu(1_400_000, 16.0, 2.1, 70000.0, 21)
+    assert big.m >= 10_000_000
+    gs = [big, inputs.rmat(16, 16, 0.57, 0.19, 0.19, 22), inputs.erdos_renyi(500, 0.02, 23),
+          inputs.chung_lu(30000, 10.0, 2.1, 3000.0, 24)]
+    ctx = lge.lge_open(0)
+    alone_ctx = lge.lge_open(0)
+    hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col) for g in gs]
+    ha = [lge.lge_graph_create_host(alone_ctx, g.row_ptr, g.col) for g in gs]
+    srv = _server(ctx)
+    try:
+        gids = [lge.lge_server_add_graph(srv, h) for h in hs]
+        rng = np.random.default_rng(5)
+        reqs = [(0, 1.0, 900), (0, 0.1, 901), (0, 0.01, 902)]
+        reqs += [(int(rng.integers(1, len(gs))), float(rng.choice([1.0, 0.1, 0.01])), 910 + i) for i in range(24)]
+        _say("large mix: m=%d plus %d small requests" % (big.m, len(reqs) - 3))
+        tickets = [lge.lge_submit(srv, gids[gi], p, s) for gi, p, s in reqs]
+        with ThreadPoolExecutor(8) as ex:
+            results = list(ex.map(lambda t: lge.lge_wait(srv, t, -1), tickets))
+        for (gi, p, s), got in zip(reqs, results):
+            _same(got, lge.lge_estimate(alone_ctx, ha[gi], p, s))
+        st = lge.lge_server_get_stats(srv)
+        _say("stats %s" % st)
+        assert st["completed"] == len(reqs)
+    finally:
+        lge.lge_server_destroy(srv)
+        for h in hs:
+            lge.lge_graph_destroy(h)
+        for h in ha:
+            lge.lge_graph_destroy(h)
+        lge.lge_close(ctx)
+        lge.lge_close(alone_ctx)
+
+
+def test_short_request_not_behind_long_one():
+    # with the short lane a small request submitted after a long one
+    # finishes while the long one is still running
+    ctx = lge.lge_open(0)
+    big = inputs.rmat(18, 16, 0.57, 0.19, 0.19, 31)
+    small = inputs.erdos_renyi(400, 0.02, 32)
+    hb = lge.lge_graph_create_host(ctx, big.row_ptr, big.col)
+    hsm = lge.lge_graph_create_host(ctx, small.row_ptr, small.col)
+    t0 = time.perf_counter()
+    lge.lge_estimate(ctx, hb, 1.0, 40, raw=True)
+    alone_s = time.perf_counter() - t0
+    srv = _server(ctx)
+    try:
+        gb = lge.lge_server_add_graph(srv, hb)
+        gsm = lge.lge_server_add_graph(srv, hsm)
+        for i in range(3):  # let the server measure its work rate
+            lge.lge_wait(srv, lge.lge_submit(srv, gsm, 1.0, 50 + i), -1)
+        lge.lge_wait(srv, lge.lge_submit(srv, gb, 0.05, 60), -1)
+        tl = lge.lge_submit(srv, gb, 1.0, 41)
+        time.sleep(min(0.02, alone_s / 10))
+        ts = lge.lge_submit(srv, gsm, 1.0, 42)
+        t1 = time.perf_counter()
+        rs = lge.lge_wait(srv, ts, -1)
+        small_s = time.perf_counter() - t1
+        rc_long, _ = lge.lge_wait_rc(srv, tl, 0)
+        _say("long alone %.1f ms; short done after %.1f ms, long %s" % (
+            alone_s * 1e3, small_s * 1e3, "running" if rc_long == lge.LGE_ETIMEDOUT else "done"))
+        assert rs["sampled"] == small.m
+        if alone_s > 0.2:  # a long request that is long enough to tell
+            assert rc_long == lge.LGE_ETIMEDOUT
+        rc, rl = lge.lge_wait_rc(srv, tl, -1)
+        assert rc == lge.LGE_OK and rl["sampled"] == big.m
+    finally:
+        lge.lge_server_destroy(srv)
+        lge.lge_graph_destroy(hb)
+        lge.lge_graph_destroy(hsm)
+        lge.lge_close(ctx)
+
+
 def test_timeout_cancel_busy_and_shutdown():
     ctx = lge.lge_open(0)
     g = inputs.chung_lu(200000, 12.0, 2.1, 6000.0, 9)
