@@ -38,8 +38,10 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """First 16 hex digits of the SHA-256 of the device code's sources (the
+    kernels and the layouts they share with the host)."""
     h = hashlib.sha256()
-    for f in ("lge_kernels.hip", "lge_internal.h", "lge_host.cpp"):
+    for f in ("lge_kernels.hip", "lge_internal.h"):
         with open(os.path.join(ROOT, "paper_1701_01772_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -724,9 +726,6 @@ def main():
 
     from paper_1701_01772_amd import inputs, lge
     full = args.workload == "chung_lu" and not args.quick and not args.copy_calibration
-    # the other legs' inputs are drawn on host threads while the GPU works
-    bg_rmat = Background(inputs.rmat_22) if full else None
-    bg_serve = Background(serving_set, args) if full else None
 
     p = args.p if args.p is not None else {"chung_lu": 0.1, "rmat": 0.1, "er": 1.0}.get(args.workload, 0.1)
     log("generating %s" % args.workload)
@@ -735,6 +734,10 @@ def main():
     ctx = lge.lge_open(0)
     head = estimate_leg(lge, ctx, g, wname, args.workload, p, args.seed, args.steps, args.warmup,
                         cpu_s=0.0, want_build=not args.quick)
+    # the other legs' inputs are drawn on host threads (not while steps or
+    # the CPU baseline are timed: they would compete for host cores)
+    bg_rmat = Background(inputs.rmat_22) if full else None
+    bg_serve = Background(serving_set, args) if full else None
     result = {
         "metric": "sampled edges/s (all 3/4-node graphlets)",
         "value": head["value"],
@@ -768,12 +771,14 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
         del src, dst
+    if full:  # the host is quiet again before the CPU baseline is timed
+        log("waiting for the input generators")
+        g_rmat, g_serve = bg_rmat.get(), bg_serve.get()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(g, p, args.seed + 100, args.cpu_seconds)
     if full:
-        log("R-MAT scale 22: waiting for the generator")
-        result["rmat"] = rmat_leg(lge, ctx, args, bg_rmat.get())
+        result["rmat"] = rmat_leg(lge, ctx, args, g_rmat)
         lge.lge_close(ctx)
         ctx = None
         bargs = argparse.Namespace(**vars(args))
@@ -783,8 +788,7 @@ def main():
                              "plain_value": b["plain"]["value"], "plain_us_per_graph": b["plain"]["us_per_graph"],
                              "batched_vs_plain": b["batched_vs_plain"], "ms_per_step": b["ms_per_step"],
                              "end_to_end_count_batch_s": b["end_to_end_count_batch_s"]}
-        log("serving set: waiting for the generator")
-        sv = bench_serve(bargs, bg_serve.get())["serving"]
+        sv = bench_serve(bargs, g_serve)["serving"]
         result["served"] = {"workload": "serving_64_graphs_chunglu_rmat_m1e3_%.0e" % args.serve_m_hi,
                             "edges_total": sv["edges_total"], "graph_state_bytes": sv["graph_state_bytes"],
                             "requests": args.serve_requests,
