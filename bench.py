@@ -41,7 +41,7 @@ def kernel_source_hash():
     """First 16 hex digits of the SHA-256 of the device code's sources (the
     kernels and the layouts they share with the host)."""
     h = hashlib.sha256()
-    for f in ("lge_kernels.hip", "lge_internal.h"):
+    for f in ("lge_kernels.hip", "lge_internal.h", "lge_layout.h"):
         with open(os.path.join(ROOT, "paper_1701_01772_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

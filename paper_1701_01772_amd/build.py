@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblge.so")
 SOURCES = [os.path.join(CSRC, "lge_kernels.hip"), os.path.join(CSRC, "lge_host.cpp"),
-           os.path.join(CSRC, "lge_server.cpp")]
+           os.path.join(CSRC, "lge_hostmath.cpp"), os.path.join(CSRC, "lge_server.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

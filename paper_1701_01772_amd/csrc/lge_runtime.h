@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/lge.h"
+#include "lge_hostmath.h"
 #include "lge_internal.h"
 
 using lge::Bins;
@@ -169,6 +170,4 @@ int lge_job_slots(const Job &j);
 // Returns an LGE_* code.
 int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts);
 
-// Exact integers -> lge_result (C, Z, Q, exact counts, FP64 estimates,
-// variances, bounds) from one job's accumulators.
-void lge_finalize(int64_t n, int64_t m, double p, uint64_t seed, const unsigned long long *acc, lge_result *out);
+// lge_finalize (exact integers -> lge_result) is declared in lge_hostmath.h.
