@@ -495,7 +495,9 @@ LGE_API int lge_set_table_budget(lge_ctx *ctx, uint64_t codeg_bytes, uint64_t ro
 typedef struct {
   int32_t max_inflight;     /* requests running at once (default 64) */
   int32_t queue_capacity;   /* queued + running requests before LGE_EBUSY (default 4096) */
-  int64_t hbm_budget_bytes; /* device work-list budget of one step (default 2 GiB) */
+  int64_t hbm_budget_bytes; /* device workspace budget of one step and worker (default 8 GiB): half for the
+                               per-edge-id arrays of the step's ids (class lists, per-edge records), half
+                               for its split-class work lists (a step needing more runs in pieces) */
   int64_t min_chunk_edges;  /* smallest edge-id chunk per request and step (default 4096) */
   int64_t target_step_us;   /* aimed duration of one step (default 100000); chunks are sized by each
                                graph's per-edge work estimate and the measured work rate */
@@ -510,6 +512,7 @@ typedef struct {
   uint64_t queued;  /* waiting for a running slot, now */
   uint64_t running; /* admitted and not finished, now */
   double busy_s;    /* wall time spent inside steps */
+  uint64_t workspace_bytes; /* largest device workspace a worker has held after a step */
 } lge_server_stats;
 
 LGE_API int lge_server_cfg_default(lge_server_cfg *cfg);

@@ -372,6 +372,23 @@ static int64_t list_bytes(int64_t items, int64_t tl) {
          (tl + tl / 4) * (int64_t)(3 * sizeof(int32_t) + sizeof(unsigned long long) + sizeof(int16_t));
 }
 
+int64_t lge_ws_bytes_per_id() {
+  return (int64_t)(3 * kNumClasses * sizeof(int32_t)     // class lists (slot, a, b)
+                   + 4 * sizeof(int64_t)                 // items, item_pref, tcap, tbase
+                   + gedge_bytes()                       // per-edge records
+                   + 3 * sizeof(int32_t)                 // sorted split-class lists
+                   + 2 * sizeof(int64_t));               // scan scratch (bound)
+}
+
+int64_t lge_ws_bytes(const lge_ctx *ctx) {
+  const Workspace &w = ctx->ws;
+  int64_t b = w.cap_edges * lge_ws_bytes_per_id() + list_bytes(w.cap_items, w.cap_tlist) * 4 / 5;
+  b += (int64_t)(kNumCtrs + (int64_t)w.cap_slots * kAccSlots * 2) * (int64_t)sizeof(unsigned long long);
+  b += (int64_t)w.cap_ranges * (int64_t)sizeof(RangeDesc) + (int64_t)w.cap_slots * (int64_t)sizeof(SlotDesc);
+  b += 3 * (int64_t)kSortKeys * (int64_t)sizeof(int64_t);
+  return b;
+}
+
 // run_sequence's answer when the split-class lists would exceed the budget
 constexpr int kRunSplit = 1 << 20;
 
@@ -756,8 +773,11 @@ static int32_t host_max_deg(int64_t n, const int32_t *row_ptr) {
   return d;
 }
 
-extern "C" int lge_graph_create_host(lge_ctx *ctx, int64_t n, const int32_t *row_ptr, const int32_t *col,
-                                     uint32_t flags, lge_graph **out) {
+// check_sizes: the graph's own exact sums must fit (sizes_in_range); a batch
+// union skips it, since every member's sums use the member's own n and m and
+// were checked one by one
+static int create_host(lge_ctx *ctx, int64_t n, const int32_t *row_ptr, const int32_t *col, uint32_t flags,
+                       bool check_sizes, lge_graph **out) {
   if (!ctx || !out || !row_ptr || n < 0) return LGE_EINVAL;
   *out = nullptr;
   if (n >= kMaxVertices) return LGE_ERANGE;
@@ -768,7 +788,7 @@ extern "C" int lge_graph_create_host(lge_ctx *ctx, int64_t n, const int32_t *row
   if (nnz % 2) return LGE_EGRAPH;
   if (nnz > 0 && !col) return LGE_EINVAL;
   const int32_t dmax = host_max_deg(n, row_ptr);
-  if (!sizes_in_range(n, nnz / 2, dmax)) return LGE_ERANGE;
+  if (check_sizes && !sizes_in_range(n, nnz / 2, dmax)) return LGE_ERANGE;
   if (hipSetDevice(ctx->device) != hipSuccess) return LGE_EDEVICE;
   lge_graph *g = new (std::nothrow) lge_graph();
   if (!g) return LGE_ENOMEM;
@@ -800,6 +820,11 @@ extern "C" int lge_graph_create_host(lge_ctx *ctx, int64_t n, const int32_t *row
   }
   *out = g;
   return LGE_OK;
+}
+
+extern "C" int lge_graph_create_host(lge_ctx *ctx, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                                     uint32_t flags, lge_graph **out) {
+  return create_host(ctx, n, row_ptr, col, flags, true, out);
 }
 
 extern "C" int lge_graph_create_device(lge_ctx *ctx, int64_t n, const int32_t *d_row_ptr, const int32_t *d_col,
@@ -1417,7 +1442,7 @@ extern "C" int lge_count_batch(lge_ctx *ctx, const lge_batch *b, const lge_opts 
     if (!sizes_in_range(v1 - v0, (z1 - z0) / 2, host_max_deg(v1 - v0, lrp))) return LGE_ERANGE;
   }
   lge_graph *U = nullptr;
-  int rc = lge_graph_create_host(ctx, N, rp.data(), cl.data(), LGE_FLAG_TRUSTED, &U);
+  int rc = create_host(ctx, N, rp.data(), cl.data(), LGE_FLAG_TRUSTED, false, &U);
   if (rc != LGE_OK) return rc;
   std::vector<Job> jobs((size_t)G);
   for (int k = 0; k < G; ++k) {

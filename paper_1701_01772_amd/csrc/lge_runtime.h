@@ -171,3 +171,9 @@ int lge_job_slots(const Job &j);
 int lge_run_jobs(lge_ctx *ctx, const Job *jobs, int njobs, const lge_opts *opts);
 
 // lge_finalize (exact integers -> lge_result) is declared in lge_hostmath.h.
+
+// Device bytes a context's workspace holds per canonical edge id of a launch
+// sequence (class lists, split-class per-edge arrays and records, sort
+// arrays, scan scratch), and the bytes its workspace holds now in all.
+int64_t lge_ws_bytes_per_id();
+int64_t lge_ws_bytes(const lge_ctx *ctx);

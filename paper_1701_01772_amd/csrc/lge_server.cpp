@@ -36,10 +36,6 @@ using namespace lge;
 
 namespace {
 
-// device bytes a step needs per canonical edge id it covers: three class
-// lists (3 x 12 B), global-class items, prefixes, T capacities and bases
-// (4 x 8 B) and per-edge partial sums (32 B), rounded up
-constexpr int64_t kStepBytesPerId = 128;
 constexpr int32_t kMaxWorkers = 4;
 
 struct Request {
@@ -183,7 +179,10 @@ struct lge_server {
         // chunks for this step, starting at a rotating request
         jobs.clear();
         in_step.clear();
-        int64_t budget = std::max<int64_t>(cfg.hbm_budget_bytes / kStepBytesPerId, 1);  // edge ids
+        // half of the HBM budget for the per-id arrays of the step's ids, half
+        // for its split-class lists (the launch sequence runs in pieces
+        // rather than exceed that)
+        int64_t budget = std::max<int64_t>(cfg.hbm_budget_bytes / 2 / lge_ws_bytes_per_id(), 1);  // edge ids
         const double step_us = short_lane ? (double)std::min<int64_t>(cfg.short_us, cfg.target_step_us)
                                           : (double)cfg.target_step_us;
         double wbudget = std::max(rate * step_us * 1e-6, 1.0);  // work units
@@ -217,11 +216,14 @@ struct lge_server {
         if (assignable(short_lane) || assignable(!short_lane)) cv_work.notify_all();  // work for idle workers
       }
       const auto t0 = std::chrono::steady_clock::now();
-      const int rc = lge_run_jobs(wctx, jobs.data(), (int)jobs.size(), nullptr);
+      lge_opts o = wctx->opts;
+      o.max_list_mib = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cfg.hbm_budget_bytes / 2 >> 20, INT32_MAX));
+      const int rc = lge_run_jobs(wctx, jobs.data(), (int)jobs.size(), &o);
       const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       {
         std::lock_guard<std::mutex> lk(mu);
         stats.busy_s += dt;
+        stats.workspace_bytes = std::max<uint64_t>(stats.workspace_bytes, (uint64_t)lge_ws_bytes(wctx));
         // work rate of the steps that were long enough to measure it
         if (rc == LGE_OK && dt > 2e-3 && step_work > 0) rate = 0.7 * rate + 0.3 * (step_work / dt);
         for (size_t j = 0; j < in_step.size(); ++j) {
@@ -249,7 +251,7 @@ extern "C" int lge_server_cfg_default(lge_server_cfg *c) {
   memset(c, 0, sizeof(*c));
   c->max_inflight = 64;
   c->queue_capacity = 4096;
-  c->hbm_budget_bytes = (int64_t)2 << 30;
+  c->hbm_budget_bytes = (int64_t)8 << 30;
   c->min_chunk_edges = 4096;
   c->target_step_us = 100000;
   c->workers = 3;
@@ -274,7 +276,7 @@ extern "C" int lge_server_create(lge_ctx *ctx, const lge_server_cfg *cfg, lge_se
     if (cfg->workers) c.workers = cfg->workers;
     if (cfg->short_us) c.short_us = cfg->short_us;
   }
-  if (c.hbm_budget_bytes < kStepBytesPerId) return LGE_EINVAL;
+  if (c.hbm_budget_bytes < 2 * lge_ws_bytes_per_id()) return LGE_EINVAL;
   lge_server *s = new (std::nothrow) lge_server();
   if (!s) return LGE_ENOMEM;
   s->ctx = ctx;

@@ -106,7 +106,7 @@ class ServerCfg(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("queued", ctypes.c_uint64),
-                ("running", ctypes.c_uint64), ("busy_s", ctypes.c_double)]
+                ("running", ctypes.c_uint64), ("busy_s", ctypes.c_double), ("workspace_bytes", ctypes.c_uint64)]
 
 
 class AdaptiveCfg(ctypes.Structure):

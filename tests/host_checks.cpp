@@ -227,6 +227,10 @@ static void check_sizes() {
   CHECK(lge::sizes_in_range(4194304, 64156389, 163213), "R-MAT scale 22 out of range");
   CHECK(!lge::sizes_in_range(100000000, 1000000000, 100000), "10^8 vertices and 10^9 edges accepted");
   CHECK(!lge::sizes_in_range(lge::kMaxVertices, 10, 2), "kMaxVertices accepted");
+  // a batch of 16,384 members of up to 5,000 vertices: each member is in
+  // range, their disjoint union is not (the batch path checks members only)
+  CHECK(lge::sizes_in_range(5000, 50000, 4999), "batch member out of range");
+  CHECK(!lge::sizes_in_range(17000000, 100000000, 5000), "16,384-member union in range");
 }
 
 int main() {

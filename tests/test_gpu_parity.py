@@ -230,6 +230,21 @@ def test_batch_equals_singles(ctx):
         assert_parity(out, want, "batch member n=%d" % g.n)
 
 
+def test_count_batch_large_union(ctx):
+    # 16,384 members of up to 5,000 vertices: the union's own n would fail
+    # the whole-graph bound on exact sums, but every member's sums use the
+    # member's n and m, so the batch must run
+    graphs = inputs.batch_graphs(count=16384, seed=16384)
+    N = sum(g.n for g in graphs)
+    _say("batch of %d graphs, %d vertices, %d edges" % (len(graphs), N, sum(g.m for g in graphs)))
+    seeds = [5000 + i for i in range(len(graphs))]
+    outs = lge.lge_count_batch(ctx, [(g.row_ptr, g.col) for g in graphs], 1.0, seeds)
+    rng = np.random.default_rng(3)
+    for k in rng.choice(len(graphs), 12, replace=False):
+        g = graphs[int(k)]
+        assert_parity(outs[int(k)], oracle.estimate(g.row_ptr, g.col, 1.0, seeds[int(k)]), "member %d" % k)
+
+
 def test_graph_create_device_matches_host(ctx):
     torch = pytest.importorskip("torch")
     g = inputs.chung_lu(5000, 8.0, 2.3, 800.0, 12)

@@ -129,6 +129,37 @@ def test_alone_equals_mix_large():
         lge.lge_close(alone_ctx)
 
 
+def test_step_workspace_within_budget():
+    # the HBM budget bounds what a worker's workspace holds: per-id arrays
+    # for half of it, split-class lists (run in pieces) for the other half
+    budget = 64 << 20
+    gs = [inputs.rmat(16, 16, 0.57, 0.19, 0.19, 51), inputs.chung_lu(150000, 14.0, 2.1, 6000.0, 52)]
+    ctx = lge.lge_open(0)
+    alone_ctx = lge.lge_open(0)
+    hs = [lge.lge_graph_create_host(ctx, g.row_ptr, g.col) for g in gs]
+    ha = [lge.lge_graph_create_host(alone_ctx, g.row_ptr, g.col) for g in gs]
+    srv = _server(ctx, hbm_budget_bytes=budget)
+    try:
+        gids = [lge.lge_server_add_graph(srv, h) for h in hs]
+        reqs = [(0, 1.0, 61), (1, 1.0, 62), (0, 0.3, 63), (1, 0.05, 64)]
+        tickets = [lge.lge_submit(srv, gids[gi], p, sd) for gi, p, sd in reqs]
+        results = [lge.lge_wait(srv, t, -1) for t in tickets]
+        for (gi, p, sd), got in zip(reqs, results):
+            _same(got, lge.lge_estimate(alone_ctx, ha[gi], p, sd))
+        st = lge.lge_server_get_stats(srv)
+        _say("budget %d MiB: largest workspace %.1f MiB over %d steps" % (
+            budget >> 20, st["workspace_bytes"] / 2**20, st["steps"]))
+        assert 0 < st["workspace_bytes"] <= budget + (4 << 20)
+    finally:
+        lge.lge_server_destroy(srv)
+        for h in hs:
+            lge.lge_graph_destroy(h)
+        for h in ha:
+            lge.lge_graph_destroy(h)
+        lge.lge_close(ctx)
+        lge.lge_close(alone_ctx)
+
+
 def test_short_request_not_behind_long_one():
     # with the short lane a small request submitted after a long one
     # finishes while the long one is still running
