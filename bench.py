@@ -249,14 +249,16 @@ def cold_estimate(lge, ctx, h, p, seed, create_s):
             "sampled_edges_per_s": r.sampled_edges / (create_s + first)}
 
 
-def build_report(lge, ctx, g, h, create_s, p, seed, step_ms, min_steps=3):
+def build_report(lge, ctx, g, h, create_s, p, seed, step_ms, min_steps=1):
     """Graph build against a hub-tables-only graph of the same CSR: state,
     build time and the number of estimates after which the co-degree table,
     bit rows and co-degree rows have paid for their build."""
     info = lge.lge_graph_query(h)
     hm, create_min = create_timed(lge, ctx, g, lge.LGE_FLAG_NO_TABLES)
     try:
+        log("build report: hub-tables-only graph, warm-up estimate at p=%g" % p)
         lge.lge_estimate(ctx, hm, p, seed, raw=True)
+        log("build report: %d timed estimate(s)" % min_steps)
         mst = time_steps(lge, ctx, hm, p, seed + 1, min_steps)
         info_min = lge.lge_graph_query(hm)
     finally:

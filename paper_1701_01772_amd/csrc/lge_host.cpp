@@ -30,8 +30,8 @@ namespace {
 // LGE_FLAG_COMPACT, or when the first allocation fails).  The budgets depend
 // on the graph only, so a graph's build and speed do not depend on what else
 // is resident.
-constexpr double kCodegBytes = 17179869184.0;       // 16 GiB: 65536 ranked vertices
-constexpr double kCodegBytesCompact = 1073741824.0;  // 1 GiB: 16384
+constexpr double kCodegBytes = 34359738368.0;       // 32 GiB: 131008 ranked vertices (2-byte entries)
+constexpr double kCodegBytesCompact = 1073741824.0;  // 1 GiB: 23168
 constexpr double kCodegPerCsr = 64.0;
 // Ranked vertices above this degree get a co-degree row over the unranked
 // vertices (largest degrees first, while the build work, the sum of their
@@ -567,7 +567,7 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
   double budget = (flags & LGE_FLAG_COMPACT) ? kCodegBytesCompact : kCodegBytes;
   budget = std::min(budget, std::max(kCodegBytesCompact, kCodegPerCsr * csr_bytes));
   if (ctx->codeg_budget > 0) budget = std::min(budget, (double)ctx->codeg_budget);
-  int64_t hc_max = std::min<int64_t>(kMaxRanked, (int64_t)std::sqrt(budget / 4.0));
+  int64_t hc_max = std::min<int64_t>(kMaxRanked, (int64_t)std::sqrt(budget / (double)sizeof(uint16_t)));
   hc_max &= ~(int64_t)63;
   std::vector<int32_t> deg((size_t)n);
   for (int64_t u = 0; u < n; ++u) deg[u] = host_row_ptr[u + 1] - host_row_ptr[u];
@@ -587,6 +587,10 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
   std::stable_sort(ranked.begin(), ranked.end(), [&](int32_t x, int32_t y) { return deg[x] < deg[y]; });
   std::vector<int32_t> hrank((size_t)n, -1);
   for (int64_t r = 0; r < hc; ++r) hrank[ranked[r]] = (int32_t)r;
+  // ranks grow with degree: a co-degree can reach 2^16 - 1 only between two
+  // vertices of degree >= 65535, whose pairs are then never read
+  int32_t sat = (int32_t)hc;
+  while (sat > 0 && deg[ranked[sat - 1]] >= 65535) --sat;
   hipStream_t s = ctx->stream;
   int64_t *cnt = nullptr, *off = nullptr, *tmp = nullptr;
   int32_t *list = nullptr;
@@ -642,6 +646,7 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
   if (e != hipSuccess) return hip_err(e);
   g->hc = hc;
   g->hcw = hcw;
+  g->codeg_sat = sat;
   return LGE_OK;
 }
 
@@ -893,7 +898,7 @@ extern "C" int lge_graph_query(const lge_graph *g, lge_graph_info *out) {
   if (g->own_col) b += 8 * m;
   b += 8 * m + 8 * n + 8 * n + 4 * g->htab_len;  // edge list, 2-hop volumes, hub-table offsets, hub tables
   b += 16 * n + 8 * m;                           // vertex records, arc words
-  if (g->hc > 0) b += 4 * n + 4 * g->hc * g->hc + 8 * g->hc * g->hcw;  // ranks, co-degree table, bit rows
+  if (g->hc > 0) b += 4 * n + 2 * g->hc * g->hc + 8 * g->hc * g->hcw;  // ranks, co-degree table, bit rows
   if (g->nrows > 0) b += g->nrows * g->rows_stride * g->rows_w;
   if (g->t_arc) b += 8 * m;
   if (g->tri) b += 8 * n;
@@ -995,7 +1000,7 @@ static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, 
     sd.seed = jobs[j].seed;
     sd.acc = w.acc + (int64_t)slot0 * rep_words;
     sd.acc_reps = reps;
-    sd.acc_pad = 0;
+    sd.codeg_sat = g->codeg_sat;
     sd.micro = jobs[j].micro;
     sd.micro_base = jobs[j].e0 - jobs[j].eid_base;
     sd.micro_len = jobs[j].e1 - jobs[j].e0;

@@ -26,7 +26,8 @@ struct SlotDesc {
   const int64_t *hoff;      // n: offset of the vertex's hub table in htab (hubs only)
   const uint32_t *htab;     // hub tables (open addressing, 2^table_log(d) slots each)
   const int32_t *crank;     // n: rank in the co-degree table, -1 if absent
-  const uint32_t *codeg;    // hc x hc, symmetric: |Gamma(x) n Gamma(y)| at [rank x][rank y]
+  const uint16_t *codeg;    // hc x hc, symmetric: |Gamma(x) n Gamma(y)| at [rank x][rank y], 16 bits
+                            //     (pairs of two ranks >= codeg_sat are never read: they may not fit)
   int64_t hc;               // ranked vertices (0: no table)
   const unsigned long long *hbits;  // hc x hcw bit rows: bit ry of row rx = (x, y) adjacent
   int64_t hcw;              // 64-bit words per bit row, ceil(hc / 64) <= kBitsWords
@@ -44,7 +45,7 @@ struct SlotDesc {
                             // w % acc_reps (the host adds the replicas up), which spreads the atomics
                             // of many workgroups on one slot over several cache lines
   int32_t acc_reps;
-  int32_t acc_pad;
+  int32_t codeg_sat;        // first rank of degree >= 65535 (hc if none)
   double p_lo;              // sample edges with p_lo <= uniform < p (nested samples)
   // per-edge write-out (micro statistics; null otherwise): the counting
   // kernels store t, k4, cyc of edge id e in row e - micro_base of a
@@ -208,7 +209,7 @@ hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const i
 // the vertex of rank r; off / cnt / list: every vertex's ranked neighbours
 // as ranks), every entry written (diagonal 0)
 hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const int32_t *ranked, const int64_t *off,
-                             const int64_t *cnt, const int32_t *list, int64_t hc, uint32_t *tab, hipStream_t s);
+                             const int64_t *cnt, const int32_t *list, int64_t hc, uint16_t *tab, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
                              int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);

@@ -671,33 +671,33 @@ __global__ __launch_bounds__(256) void k_codeg_fill(const int32_t *__restrict__ 
 // rx.  For every w in Gamma(x), every ranked neighbour of w (w's rank list)
 // adds 1 at its rank's column, so the row ends up holding
 // |Gamma(x) n Gamma(y)| for every ranked y; it is then written once,
-// coalesced, diagonal 0.  A co-degree never exceeds deg(x): rows of x with
-// deg(x) < 2^16 count in the 16-bit halves of the LDS words (kRowWords words
-// hold 2 * kRowWords ranks, the most a table has), the others in 32-bit
-// words over kRowWords ranks per pass.  A wave loads 64 of the w at once
-// (coalesced) and walks their lists one after another, lanes striding each.
+// coalesced, diagonal 0, as 16-bit entries.  A co-degree never exceeds
+// deg(x): rows of x with deg(x) < 2^16 count in the 16-bit halves of the LDS
+// words (2 * kRowWords ranks per pass), the others in 32-bit words
+// (kRowWords ranks per pass).  A wave loads 64 of the w at once (coalesced)
+// and walks their lists one after another, lanes striding each.
 constexpr int kRowNT = 1024;
 constexpr int kRowWords = 32768;  // 128 KB of LDS counters
-static_assert(2 * kRowWords >= kMaxRanked, "a narrow row holds every rank");
 __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ ranked,
                                                         const int64_t *__restrict__ off,
                                                         const int64_t *__restrict__ cnt,
                                                         const int32_t *__restrict__ list, int64_t hc,
-                                                        uint32_t *__restrict__ tab) {
+                                                        uint16_t *__restrict__ tab) {
   __shared__ uint32_t c[kRowWords];
   const int64_t rx = blockIdx.x;
   const int32_t x = ranked[rx];
   const int32_t beg = rp[x], d = rp[x + 1] - beg;
   const bool narrow = d < 65536;
-  const int passes = narrow ? 1 : (int)((hc + kRowWords - 1) / kRowWords);
+  const int64_t span = narrow ? 2 * (int64_t)kRowWords : (int64_t)kRowWords;  // ranks per pass
+  const int passes = (int)((hc + span - 1) / span);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int kWaves = kRowNT / kWave;
-  uint32_t *row = tab + rx * hc;
+  uint16_t *row = tab + rx * hc;
   for (int pass = 0; pass < passes; ++pass) {
-    const int64_t c0 = narrow ? 0 : (int64_t)pass * kRowWords;
-    const int64_t c1 = narrow ? hc : (c0 + kRowWords < hc ? c0 + kRowWords : hc);
-    const int64_t words = narrow ? (hc + 1) / 2 : c1 - c0;
+    const int64_t c0 = (int64_t)pass * span;
+    const int64_t c1 = c0 + span < hc ? c0 + span : hc;
+    const int64_t words = narrow ? (c1 - c0 + 1) / 2 : c1 - c0;
     for (int64_t i = threadIdx.x; i < words; i += kRowNT) c[i] = 0u;
     __syncthreads();
     for (int32_t g0 = wid * kWave; g0 < d; g0 += kWaves * kWave) {
@@ -711,17 +711,22 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
         const int kq = __shfl(k, q);
         for (int i = lane; i < kq; i += kWave) {
           const int32_t y = list[oq + i];
+          if (y < c0 || y >= c1) continue;
+          const int32_t yy = y - (int32_t)c0;
           if (narrow)
-            atomicAdd(&c[y >> 1], 1u << ((y & 1) << 4));
-          else if (y >= c0 && y < c1)
-            atomicAdd(&c[y - c0], 1u);
+            atomicAdd(&c[yy >> 1], 1u << ((yy & 1) << 4));
+          else
+            atomicAdd(&c[yy], 1u);
         }
       }
     }
     __syncthreads();
+    // one 16-bit entry per rank; a count of 65535 or more (both ends of
+    // degree >= 65535, never read) is clamped
     for (int64_t y = c0 + threadIdx.x; y < c1; y += kRowNT) {
-      const uint32_t v = narrow ? (c[y >> 1] >> ((y & 1) << 4)) & 0xFFFFu : c[y - c0];
-      row[y] = y == rx ? 0u : v;
+      const int64_t yy = y - c0;
+      const uint32_t v = narrow ? (c[yy >> 1] >> ((yy & 1) << 4)) & 0xFFFFu : c[yy];
+      row[y] = y == rx ? (uint16_t)0 : (uint16_t)(v < 0xFFFFu ? v : 0xFFFFu);
     }
     __syncthreads();
   }
@@ -861,6 +866,7 @@ __device__ __forceinline__ bool codeg_pair(const SlotDesc &S, uint32_t rhx, int4
   const int32_t xrank = xr ? (int32_t)(rhx & 0x1FFFFu) - 1 : -1;
   const int32_t xw = xr ? (int32_t)(rhx >> 17) - 1 : (int32_t)(rhx & 0x7FFFFFFFu) - 1;
   if (xrank >= 0 && vy.z >= 0) {
+    if (xrank >= S.codeg_sat && vy.z >= S.codeg_sat) return false;  // may exceed 16 bits
     *val = S.codeg[(int64_t)vy.z * S.hc + xrank];
     return true;
   }
@@ -1619,7 +1625,9 @@ constexpr uint8_t kFCodeg = 4;   // co-degree from the table
 constexpr uint8_t kFLookB = 8;   // w in S_a: cbx by look-ups of Gamma(b)
 constexpr uint8_t kFBits = 16;   // ranked w in T_e: degT over ranked members from bit rows
 constexpr uint32_t kRTag = 0x40000000u;  // T_e hash key tag: member is ranked
-constexpr int kBitsLds = kBitsWords;  // words of an edge's ranked-member set held in LDS (all of them)
+// words of an edge's ranked-member set held in LDS (larger sets are read
+// from the global lists): 10 KB, which keeps four workgroups per CU
+constexpr int kBitsLds = 1024;
 
 __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_global(
     const SlotDesc *__restrict__ slots, Bins bins, const int64_t *__restrict__ item_pref,
@@ -1703,12 +1711,14 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     const bool tl = t <= kTHashCap;
     const int tlg = table_log(t);
     const int hcw = S.hc > 0 ? (int)S.hcw : 0;  // 0: no ranked vertices, no bit rows
-    // the LDS copy holds the largest possible ranked-member set (nzw <= hcw
-    // <= kBitsWords), so every edge of a graph with ranked vertices uses the
-    // bit rows; the size test only guards the LDS array
-    static_assert(kBitsLds >= kBitsWords, "the LDS bit set holds every possible ranked-member set");
-    const bool ubits = hcw > 0 && G.nzw <= (unsigned long long)kBitsLds;
+    // every edge of a graph with ranked vertices counts its ranked pairs
+    // from the bit rows; the ranked-member set is copied to LDS when it has
+    // at most kBitsLds non-zero words, larger sets are read from the global
+    // lists the bit-set kernel wrote
+    const bool ubits = hcw > 0;
     const int nzw = ubits ? (int)G.nzw : 0;
+    const bool bits_lds = nzw <= kBitsLds;
+    const int nzw_lds = bits_lds ? nzw : 0;
     if (tid < 4) sh_cnt[tid] = 0;
     if (!hb)
       for (int i = tid; i < (1 << blg); i += NT) hB[i] = kEmpty;
@@ -1720,15 +1730,15 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
     {  // the LDS tables: Gamma(b) \ {a}, Gamma(a) \ {b} (non-hub sides), T_e (small)
       const int nB = hb ? 0 : db, nA = ha ? 0 : da, nT = tl ? t : 0;
       int nmax = nB > nA ? (nB > nT ? nB : nT) : (nA > nT ? nA : nT);
-      nmax = nmax > nzw ? nmax : nzw;
+      nmax = nmax > nzw_lds ? nmax : nzw_lds;
       for (int i = tid; i < nmax; i += NT) {  // all loads first, then the LDS writes
         const int32_t xb = i < nB ? col[bbeg + i] : -1;
         const int32_t xa = i < nA ? col[abeg + i] : -1;
         const int32_t ty = i < nT ? T[3 * i] : -1;
         const int32_t tr = i < nT ? T[3 * i + 2] : -1;
-        const unsigned long long bw = i < nzw ? tbw[tb0 + i] : 0ull;
-        const int16_t bi = i < nzw ? tbi[tb0 + i] : (int16_t)0;
-        if (i < nzw) {
+        const unsigned long long bw = i < nzw_lds ? tbw[tb0 + i] : 0ull;
+        const int16_t bi = i < nzw_lds ? tbi[tb0 + i] : (int16_t)0;
+        if (i < nzw_lds) {
           tbits[i] = bw;
           twidx[i] = bi;
         }
@@ -1736,7 +1746,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         if (xa >= 0 && xa != b) lds_insert(hA, alg, (uint32_t)xa);
         if (ty >= 0) lds_insert(hT, tlg, (uint32_t)ty | (ubits && tr >= 0 ? kRTag : 0u));
       }
-      if (tid == 0) words += (unsigned long long)(nB + nA + 2 * nT + 3 * nzw + 32);  // per-item terms once
+      if (tid == 0) words += (unsigned long long)(nB + nA + 2 * nT + 3 * nzw_lds + 32);  // per-item terms once
     }
     __syncthreads();
     // r in Gamma(b) \ {a}; r in Gamma(a) \ {b}; r in T_e (the LDS tables
@@ -1789,7 +1799,7 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       int tab = 0;
       const int32_t ry = isT ? ra : rb, hy = isT ? hra : hrb;
       if (valid && may_look && hcw) {
-        tab = (rw >= 0 && ry >= 0)                         ? 1
+        tab = (rw >= 0 && ry >= 0 && (rw < S.codeg_sat || ry < S.codeg_sat)) ? 1
               : (rw < 0 && hw >= 0 && ry >= 0 && hy >= 0) ? 2
               : (ry < 0 && hy >= 0 && rw >= 0 && hw >= 0) ? 3
                                                           : 0;
@@ -1940,12 +1950,15 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
       const int nb = sh_cnt[2];
       int32_t *const bk0 = wl_beg;   // first word index of member j
       int32_t *const bpref = wl_pref;  // pairs before member j
+      // the set's word indices and words: the LDS copy, or the global lists
+      const int16_t *__restrict__ gti = tbi + tb0;
+      const unsigned long long *__restrict__ gtw = tbw + tb0;
       for (int j = tid; j < nb; j += NT) {
         const int wx = bx_rank[j] >> 6;
         int lo = 0, hi = nzw;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (twidx[mid] < wx)
+          if ((bits_lds ? twidx[mid] : gti[mid]) < wx)
             lo = mid + 1;
           else
             hi = mid;
@@ -1974,8 +1987,8 @@ __global__ __launch_bounds__(kGlobalNT) __attribute__((amdgpu_waves_per_eu(8, 8)
         jc = lo;
         const int rx = bx_rank[jc];
         const int k = bk0[jc] + (q - bpref[jc]);
-        const int wk = twidx[k];
-        unsigned long long v = S.hbits[(int64_t)rx * S.hcw + wk] & tbits[k];
+        const int wk = bits_lds ? twidx[k] : gti[k];
+        unsigned long long v = S.hbits[(int64_t)rx * S.hcw + wk] & (bits_lds ? tbits[k] : gtw[k]);
         if (wk == (rx >> 6)) v &= (rx & 63) == 63 ? 0ull : (~0ull << ((rx & 63) + 1));
         bsum += (unsigned long long)__popcll(v);
         words += 2;
@@ -2505,7 +2518,7 @@ hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const i
 }
 
 hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const int32_t *ranked, const int64_t *off,
-                             const int64_t *cnt, const int32_t *list, int64_t hc, uint32_t *tab, hipStream_t s) {
+                             const int64_t *cnt, const int32_t *list, int64_t hc, uint16_t *tab, hipStream_t s) {
   if (hc <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_codeg_rows, dim3((unsigned)hc), dim3(kRowNT), 0, s, row_ptr, col, ranked, off, cnt, list, hc,
                      tab);

@@ -27,9 +27,10 @@ constexpr int kHashDeg = 32;
 // The split kernel copies an endpoint's neighbours into an LDS table when its
 // degree is <= kTableDeg and probes the endpoint's hub table otherwise.
 constexpr int kTableDeg = 256;
-// Ranked (co-degree table) vertices at most, and the 64-bit words of one
-// adjacency bit row over them.
-constexpr int kMaxRanked = 65536;
+// Ranked (co-degree table) vertices at most (rank + 1 fills 17 bits of the
+// packed per-arc word), and the 64-bit words of one adjacency bit row over
+// them.
+constexpr int kMaxRanked = 131008;
 // Co-degree rows hold one byte per vertex when no unranked vertex has degree
 // above kRowMaxDeg (no co-degree with an unranked vertex can exceed it), else
 // two.

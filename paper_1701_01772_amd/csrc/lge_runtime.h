@@ -32,8 +32,9 @@ struct lge_graph {
   uint32_t *htab = nullptr;
   int64_t htab_len = 0;
   int32_t *crank = nullptr;
-  uint32_t *codeg = nullptr;
+  uint16_t *codeg = nullptr;  // hc x hc co-degrees, 16 bits (see codeg_sat)
   int64_t hc = 0;
+  int32_t codeg_sat = 0;      // first rank of degree >= 65535 (hc if none)
   unsigned long long *hbits = nullptr;  // hc x hcw adjacency bit rows of the ranked vertices
   int64_t hcw = 0;
   int4 *vinfo = nullptr;     // n: (row start, degree, rank or -1, co-degree row or -1)
