@@ -593,15 +593,16 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
   while (sat > 0 && deg[ranked[sat - 1]] >= 65535) --sat;
   hipStream_t s = ctx->stream;
   int64_t *cnt = nullptr, *off = nullptr, *tmp = nullptr;
-  int32_t *list = nullptr;
+  int32_t *list = nullptr, *nlo = nullptr;
   auto cleanup = [&]() {
     dev_free(cnt);
     dev_free(off);
     dev_free(tmp);
     dev_free(list);
+    dev_free(nlo);
   };
   int rc;
-  if ((rc = dev_alloc(&cnt, n)) != LGE_OK || (rc = dev_alloc(&off, n)) != LGE_OK ||
+  if ((rc = dev_alloc(&cnt, n)) != LGE_OK || (rc = dev_alloc(&off, n)) != LGE_OK || (rc = dev_alloc(&nlo, n)) != LGE_OK ||
       (rc = dev_alloc(&tmp, scan_tmp_size(n))) != LGE_OK || (rc = dev_alloc(&g->crank, n)) != LGE_OK ||
       (rc = dev_alloc(&g->codeg, hc * hc)) != LGE_OK) {
     cleanup();
@@ -636,8 +637,8 @@ static int build_codeg(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, 
     return rc;
   }
   e = hipMemcpyAsync(dranked, ranked.data(), (size_t)hc * sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, list, s);
-  if (e == hipSuccess) e = launch_codeg_rows(g->row_ptr, g->col, dranked, off, cnt, list, hc, g->codeg, s);
+  if (e == hipSuccess) e = launch_codeg_fill(g->row_ptr, g->col, g->crank, n, off, cnt, list, nlo, s);
+  if (e == hipSuccess) e = launch_codeg_rows(g->row_ptr, g->col, dranked, off, cnt, list, nlo, hc, g->codeg, s);
   if (e == hipSuccess) e = launch_zero_u64(g->hbits, hc * hcw, s);
   if (e == hipSuccess) e = launch_codeg_bits(g->row_ptr, g->col, g->crank, n, hcw, g->hbits, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

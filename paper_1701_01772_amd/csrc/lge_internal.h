@@ -186,7 +186,7 @@ hipError_t launch_hub_build(const int32_t *row_ptr, const int32_t *col, int64_t 
 hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
                               int64_t *cnt, hipStream_t s);
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
-                             const int64_t *off, int32_t *list, hipStream_t s);
+                             const int64_t *off, const int64_t *cnt, int32_t *list, int32_t *nlo, hipStream_t s);
 // per-vertex records (row start, degree, rank, row or column); crank, hrow,
 // rcol may be null
 hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int32_t *hrow, const int32_t *rcol,
@@ -209,7 +209,8 @@ hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const i
 // the vertex of rank r; off / cnt / list: every vertex's ranked neighbours
 // as ranks), every entry written (diagonal 0)
 hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const int32_t *ranked, const int64_t *off,
-                             const int64_t *cnt, const int32_t *list, int64_t hc, uint16_t *tab, hipStream_t s);
+                             const int64_t *cnt, const int32_t *list, const int32_t *nlo, int64_t hc, uint16_t *tab,
+                             hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
                              int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);

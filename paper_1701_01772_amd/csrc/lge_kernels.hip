@@ -646,24 +646,35 @@ __global__ __launch_bounds__(256) void k_codeg_count(const int32_t *__restrict__
   }
 }
 
+// every vertex's ranked neighbours as ranks, those below kRankSplit first
+// (in adjacency order) and the others after them (in reverse), with the
+// number of the first kind in nlo: a pass of the row builder over a range
+// of ranks reads only its part
+constexpr int32_t kRankSplit = 65536;
 __global__ __launch_bounds__(256) void k_codeg_fill(const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ crank, int64_t n,
-                                                    const int64_t *__restrict__ off, int32_t *list) {
+                                                    const int64_t *__restrict__ off, const int64_t *__restrict__ cnt,
+                                                    int32_t *list, int32_t *__restrict__ nlo) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t u = wave; u < n; u += nwaves) {
-    int64_t pos = off[u];
+    const int64_t o = off[u];
+    int64_t lo = o, hi = o + cnt[u];  // next low slot; one past the next high slot
     const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
     for (int32_t base = beg; base < end; base += kWave) {
       const int32_t j = base + lane;
       const int32_t r = j < end ? crank[col[j]] : -1;
-      const uint64_t m = __ballot(r >= 0);
-      if (r >= 0) list[pos + __popcll(m & lt_mask)] = r;
-      pos += __popcll(m);
+      const uint64_t ml = __ballot(r >= 0 && r < kRankSplit);
+      const uint64_t mh = __ballot(r >= kRankSplit);
+      if (r >= 0 && r < kRankSplit) list[lo + __popcll(ml & lt_mask)] = r;
+      if (r >= kRankSplit) list[hi - 1 - __popcll(mh & lt_mask)] = r;
+      lo += __popcll(ml);
+      hi -= __popcll(mh);
     }
+    if (lane == 0) nlo[u] = (int32_t)(lo - o);
   }
 }
 
@@ -682,7 +693,8 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
                                                         const int32_t *__restrict__ ranked,
                                                         const int64_t *__restrict__ off,
                                                         const int64_t *__restrict__ cnt,
-                                                        const int32_t *__restrict__ list, int64_t hc,
+                                                        const int32_t *__restrict__ list,
+                                                        const int32_t *__restrict__ nlo, int64_t hc,
                                                         uint16_t *__restrict__ tab) {
   __shared__ uint32_t c[kRowWords];
   const int64_t rx = blockIdx.x;
@@ -698,13 +710,25 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
     const int64_t c0 = (int64_t)pass * span;
     const int64_t c1 = c0 + span < hc ? c0 + span : hc;
     const int64_t words = narrow ? (c1 - c0 + 1) / 2 : c1 - c0;
+    // the part of each rank list this pass needs: ranks below kRankSplit
+    // sit first, the others after them
+    const bool low_only = c1 <= kRankSplit, high_only = c0 >= kRankSplit;
     for (int64_t i = threadIdx.x; i < words; i += kRowNT) c[i] = 0u;
     __syncthreads();
     for (int32_t g0 = wid * kWave; g0 < d; g0 += kWaves * kWave) {
       const int32_t j = g0 + lane;
       const int32_t w = j < d ? col[beg + j] : -1;
-      const long long o = w >= 0 ? (long long)off[w] : 0ll;
-      const int k = w >= 0 ? (int)cnt[w] : 0;
+      long long o = w >= 0 ? (long long)off[w] : 0ll;
+      int k = w >= 0 ? (int)cnt[w] : 0;
+      if (w >= 0 && (low_only || high_only)) {
+        const int kl = nlo[w];
+        if (low_only) {
+          k = kl;
+        } else {
+          o += kl;
+          k -= kl;
+        }
+      }
       const int ng = d - g0 < kWave ? d - g0 : kWave;
       for (int q = 0; q < ng; ++q) {  // uniform per wave
         const long long oq = __shfl(o, q);
@@ -2511,17 +2535,19 @@ hipError_t launch_codeg_count(const int32_t *row_ptr, const int32_t *col, const 
 }
 
 hipError_t launch_codeg_fill(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n,
-                             const int64_t *off, int32_t *list, hipStream_t s) {
+                             const int64_t *off, const int64_t *cnt, int32_t *list, int32_t *nlo, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_codeg_fill, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, crank, n, off, list);
+  hipLaunchKernelGGL(k_codeg_fill, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, col, crank, n, off, cnt,
+                     list, nlo);
   return hipGetLastError();
 }
 
 hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const int32_t *ranked, const int64_t *off,
-                             const int64_t *cnt, const int32_t *list, int64_t hc, uint16_t *tab, hipStream_t s) {
+                             const int64_t *cnt, const int32_t *list, const int32_t *nlo, int64_t hc, uint16_t *tab,
+                             hipStream_t s) {
   if (hc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_codeg_rows, dim3((unsigned)hc), dim3(kRowNT), 0, s, row_ptr, col, ranked, off, cnt, list, hc,
-                     tab);
+  hipLaunchKernelGGL(k_codeg_rows, dim3((unsigned)hc), dim3(kRowNT), 0, s, row_ptr, col, ranked, off, cnt, list, nlo,
+                     hc, tab);
   return hipGetLastError();
 }
 

@@ -230,6 +230,31 @@ def test_batch_equals_singles(ctx):
         assert_parity(out, want, "batch member n=%d" % g.n)
 
 
+@pytest.mark.parametrize("p", [0.25])
+def test_codeg_pair_beyond_16_bits(ctx, p):
+    # two adjacent hubs sharing 70,000 neighbours plus a few hundred mid-degree
+    # vertices (ranked, so the co-degree table is built): the hubs'
+    # co-degree, 70,000, does not fit a 16-bit entry and must come from
+    # walking; their rows count in 32-bit LDS words (degree >= 2^16)
+    k = 70000
+    rng = np.random.default_rng(9)
+    edges = [(0, 1)] + [(0, 2 + i) for i in range(k)] + [(1, 2 + i) for i in range(k)]
+    mids = np.arange(2 + k, 2 + k + 300)
+    for v in mids:  # each mid vertex: 120 random leaves and one hub
+        edges += [(int(v), int(x)) for x in rng.choice(np.arange(2, 2 + k), 120, replace=False)]
+        edges.append((0 if v % 2 else 1, int(v)))
+    g = inputs.from_edges(2 + k + len(mids), edges)
+    h = lge.lge_graph_create_host(ctx, g.row_ptr, g.col)
+    try:
+        info = lge.lge_graph_query(h)
+        _say("saturated pair: n=%d m=%d ranked %d, p=%g" % (g.n, g.m, info["ranked"], p))
+        assert info["ranked"] >= 2
+        got = lge.lge_estimate(ctx, h, p, 21)
+    finally:
+        lge.lge_graph_destroy(h)
+    assert_parity(got, oracle.estimate(g.row_ptr, g.col, p, 21), "two hubs of degree > 2^16")
+
+
 def test_count_batch_large_union(ctx):
     # 16,384 members of up to 5,000 vertices: the union's own n would fail
     # the whole-graph bound on exact sums, but every member's sums use the
