@@ -148,6 +148,9 @@ typedef struct {
  *                 would need more runs its edge-id range in consecutive
  *                 pieces, each within the bound (a single edge may exceed
  *                 it); the exact sums, so the results, are the same.
+ *  grid_share     percent (1..100, 0 = 100) of the default persistent grid
+ *                 of each counting kernel: a sequence that runs beside
+ *                 others (the serving lanes) leaves workgroup slots free.
  */
 #define LGE_OPT_SORT_HUB 1u
 #define LGE_OPT_XCD_LOCAL 2u
@@ -159,7 +162,7 @@ typedef struct {
   int32_t global_chunk;
   uint32_t flags;
   int32_t max_list_mib;
-  int32_t reserved;
+  int32_t grid_share;
 } lge_opts;
 
 /* Device-time breakdown of the last estimate/batch call on a ctx. */

@@ -138,6 +138,14 @@ static KernelCfg make_cfg(const lge_ctx *ctx, const lge_opts *o) {
   c.grid_wave = cu * (per_cu ? per_cu : 24);
   c.grid_block = cu * (per_cu ? per_cu : 8);
   c.grid_global = cu * (per_cu ? per_cu : 4);  // 512-thread workgroups
+  if (o->grid_share > 0 && o->grid_share < 100) {  // a share of each grid, whole multiples of kXcds
+    auto part = [&](int32_t g) {
+      return std::max<int32_t>(kXcds, (int32_t)((int64_t)g * o->grid_share / 100) / kXcds * kXcds);
+    };
+    c.grid_wave = part(c.grid_wave);
+    c.grid_block = part(c.grid_block);
+    c.grid_global = part(c.grid_global);
+  }
   c.grid_sample = cu * 16;
   c.global_chunk = o->global_chunk > 0 ? std::min<int32_t>(o->global_chunk, kGlobalChunkMax) : d.global_chunk;
   c.flags = o->flags;

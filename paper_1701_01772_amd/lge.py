@@ -67,7 +67,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("wave_max_deg", ctypes.c_int32), ("block_max_deg", ctypes.c_int32),
                 ("probe_ratio", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
                 ("global_chunk", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("max_list_mib", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_list_mib", ctypes.c_int32), ("grid_share", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -227,7 +227,7 @@ def make_opts(**kw) -> Opts:
 
 def opts_dict(o: Opts) -> dict:
     """The tuning fields of an Opts as a plain dict."""
-    return {k: getattr(o, k) for k, _ in Opts._fields_ if k != "reserved"}
+    return {k: getattr(o, k) for k, _ in Opts._fields_}
 
 
 def lge_open(device: int = 0):

@@ -148,6 +148,10 @@ def test_tuning_invariance(ctx):
                 got = lge.lge_estimate(ctx, h, 0.7, 3, o)
                 for k in ("sampled", "csum", "zsum", "qsum"):
                     assert got[k] == base[k], (chunk, flags, k)
+        for share in (5, 25, 75):  # smaller persistent grids
+            got = lge.lge_estimate(ctx, h, 0.7, 3, lge.make_opts(grid_share=share))
+            for k in ("sampled", "csum", "zsum", "qsum"):
+                assert got[k] == base[k], (share, k)
         for bmd in (1, 100, 300, 700):  # block class narrowed or empty
             got = lge.lge_estimate(ctx, h, 0.7, 3, lge.make_opts(block_max_deg=bmd))
             for k in ("sampled", "csum", "zsum", "qsum"):
