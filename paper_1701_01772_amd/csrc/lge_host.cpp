@@ -1045,13 +1045,16 @@ static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, 
   // one kernel zeroing the counters and the used accumulators
   const size_t desc_bytes = (size_t)w.cap_ranges * sizeof(RangeDesc) + (size_t)nslots * sizeof(SlotDesc);
   const int64_t ctl_words = kNumCtrs + (int64_t)nslots * rep_words;
-  LGE_HIP(hipMemcpyAsync(w.desc, w.h_desc, desc_bytes, hipMemcpyHostToDevice, s));
-  LGE_HIP(launch_zero_u64(w.ctl, ctl_words, s));
+  if (njobs == 1 && nslots == 1) {  // the descriptors travel as kernel arguments
+    LGE_HIP(launch_seq_init(w.ctl, ctl_words, w.ranges, w.slots, w.h_ranges[0], w.h_slots[0], s));
+  } else {
+    LGE_HIP(hipMemcpyAsync(w.desc, w.h_desc, desc_bytes, hipMemcpyHostToDevice, s));
+    LGE_HIP(launch_zero_u64(w.ctl, ctl_words, s));
+  }
   Bins bins = make_bins(w);
   LGE_HIP(hipEventRecord(ev[0], s));
   LGE_HIP(launch_sample_bin(w.slots, w.ranges, njobs, total, bins, cfg, s));
   LGE_HIP(hipEventRecord(ev[1], s));
-  LGE_HIP(hipEventRecord(ev[2], s));
   LGE_HIP(launch_count_wave(w.slots, bins, total, cfg, s));
   LGE_HIP(hipEventRecord(ev[3], s));
   LGE_HIP(launch_count_block(w.slots, bins, total, cfg, s));
@@ -1084,9 +1087,6 @@ static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, 
     LGE_HIP(launch_global_prep(w.slots, bins, total, cfg.global_chunk, w.items, w.tcap, w.gacc, s));
     LGE_HIP(launch_global_scans(bins, w.items, w.item_pref, w.tcap, w.tbase, w.scan_tmp, s));
     if ((rc = split_tail(bins)) != LGE_OK) return rc;
-  } else {
-    LGE_HIP(hipEventRecord(ev[6], s));
-    LGE_HIP(hipEventRecord(ev[7], s));
   }
   LGE_HIP(hipEventRecord(ev[5], s));
   LGE_HIP(hipMemcpyAsync(w.h_ctl, w.ctl, (size_t)ctl_words * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -1096,10 +1096,12 @@ static int run_sequence(lge_ctx *ctx, Workspace &w, const Job *jobs, int njobs, 
     float ms = 0;
     if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) t.total_ms = ms;
     if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) t.sample_ms = ms;
-    if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) t.count_ms[0] = ms;
+    if (hipEventElapsedTime(&ms, ev[1], ev[3]) == hipSuccess) t.count_ms[0] = ms;
     if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) t.count_ms[1] = ms;
-    if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) t.count_ms[2] = ms;
-    if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
+    if (split) {  // without split-class edges the class's kernels are not enqueued
+      if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) t.count_ms[2] = ms;
+      if (hipEventElapsedTime(&ms, ev[4], ev[6]) == hipSuccess) t.global_prep_ms = ms;
+    }
     for (int c = 0; c < kNumClasses; ++c) t.class_edges[c] = w.h_counters[kCtrCount + c];
     for (int c = 0; c < kNumClasses; ++c) {
       t.words_read[c] = t.alg_bytes[c] = 0;

@@ -212,6 +212,10 @@ hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const i
                              const int64_t *cnt, const int32_t *list, const int32_t *nlo, int64_t hc, uint16_t *tab,
                              hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s);
+// clears p[0, len) and stores one range and one slot descriptor (passed by
+// value) at rdst / sdst
+hipError_t launch_seq_init(unsigned long long *p, int64_t len, RangeDesc *rdst, SlotDesc *sdst, const RangeDesc &r,
+                           const SlotDesc &sd, hipStream_t s);
 hipError_t launch_sample_bin(const SlotDesc *slots, const RangeDesc *ranges, int32_t nranges,
                              int64_t total, Bins bins, KernelCfg cfg, hipStream_t s);
 // The counting launchers read each class's edge count from bins.count on the

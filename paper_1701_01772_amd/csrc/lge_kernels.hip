@@ -2430,6 +2430,20 @@ __global__ void k_zero_u64(unsigned long long *p, int64_t len) {
     p[i] = 0ull;
 }
 
+// a one-job sequence's start: the counters and accumulators cleared and the
+// job's range and slot descriptors, passed by value, stored where the
+// kernels read them (one launch in place of a copy and a clear)
+__global__ void k_seq_init(unsigned long long *p, int64_t len, RangeDesc *rdst, SlotDesc *sdst, RangeDesc r,
+                           SlotDesc sd) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *rdst = r;
+    *sdst = sd;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -2554,6 +2568,12 @@ hipError_t launch_codeg_rows(const int32_t *row_ptr, const int32_t *col, const i
 hipError_t launch_zero_u64(unsigned long long *p, int64_t len, hipStream_t s) {
   if (len <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(len, 256, 4096)), dim3(256), 0, s, p, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_seq_init(unsigned long long *p, int64_t len, RangeDesc *rdst, SlotDesc *sdst, const RangeDesc &r,
+                           const SlotDesc &sd, hipStream_t s) {
+  hipLaunchKernelGGL(k_seq_init, dim3(grid_for(len, 256, 4096)), dim3(256), 0, s, p, len, rdst, sdst, r, sd);
   return hipGetLastError();
 }
 
