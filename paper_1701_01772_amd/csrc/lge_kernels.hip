@@ -1108,7 +1108,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
   __shared__ uint32_t htab[HS];
   __shared__ uint32_t wl_v[CAP];
   __shared__ int32_t wl_beg[CAP];
-  __shared__ int32_t wl_deg[CAP];
+  __shared__ uint16_t wl_dg[CAP];  // degrees, 0xFFFF standing for 65535 or more
   __shared__ int32_t wl_pref[CAP + 1];
   __shared__ int32_t tgt[CAP];
   __shared__ int32_t sh_cnt[4];
@@ -1119,6 +1119,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  const SlotDesc *cur_slot = nullptr;  // the slot of the edge being counted
+  // degree of w-list entry i (a saturated entry is read from its record)
+  auto deg_of = [&](int i) -> int {
+    const int d = wl_dg[i];
+    return d < 0xFFFF ? d : cur_slot->vinfo[wl_v[i] & kIdMask].y;
+  };
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t nedges = (int64_t)*ncount;  // the class's edges, binned by the sampling kernel
   if (nedges == 0) return;  // uniform
@@ -1147,6 +1153,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
       const int32_t slot = bslot[e];
       const int32_t a = ba[e], b = bb[e];
       const SlotDesc &S = slots[slot];
+      cur_slot = &S;
       const int32_t *__restrict__ col = S.col;
       // endpoint records (row start, degree, rank, co-degree row / column);
       // the rank fields count only when co-degrees are read
@@ -1201,7 +1208,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
           const int4 vx = S.vinfo[x];
           wl_v[pos] = (uint32_t)x | (isT ? kTag : 0u);
           wl_beg[pos] = vx.x;
-          wl_deg[pos] = vx.y;
+          wl_dg[pos] = (uint16_t)(vx.y < 0xFFFF ? vx.y : 0xFFFF);
           wl_pref[pos] = (int32_t)rh;  // until the mode pass turns it into the unit count
         }
       }
@@ -1228,7 +1235,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
         const uint32_t v = wl_v[i];
         const bool isT = (v & kTag) != 0;
         const uint32_t rh = (uint32_t)wl_pref[i];
-        const int dw = wl_deg[i];
+        const int dw = deg_of(i);
         const int64_t scan = 8ll * dw;
         if (!may_look) {
           c_plain += (unsigned long long)scan;
@@ -1281,7 +1288,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
         for (int i = tid; i < L; i += NT) {
           const uint32_t v = wl_v[i] & ~(kModeLook | kModeAux);
           const bool isT = (v & kTag) != 0;
-          const int dw = wl_deg[i];
+          const int dw = deg_of(i);
           uint32_t fl = 0;
           int32_t units = dw;
           if (may_look) {
@@ -1325,7 +1332,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
               const int32_t x = bhub  ? col[bbeg + off]
                                 : agg ? (off < t ? tgt[off] : tgt[CAP - sbn + (off - t)])
                                       : tgt[CAP - sbn + off];
-              if (x != a && w_has(S, w, wl_beg[lo], wl_deg[lo], x, &steps)) ++cs;
+              if (x != a && w_has(S, w, wl_beg[lo], deg_of(lo), x, &steps)) ++cs;
             } else {  // scan: cbx (any hit), or |Gamma(w) n S_b| without the aggregate form
               const int32_t r = col[wl_beg[lo] + off];
               ++steps;
@@ -1338,10 +1345,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
             }
           } else {
             const bool lt = (v & kModeLook) != 0;
-            const int part1 = lt ? t : wl_deg[lo];
+            const int part1 = lt ? t : deg_of(lo);
             if (off < part1) {  // degT
               if (lt) {
-                if (w_has(S, w, wl_beg[lo], wl_deg[lo], tgt[off], &steps)) ++kt;
+                if (w_has(S, w, wl_beg[lo], deg_of(lo), tgt[off], &steps)) ++kt;
               } else {
                 const int32_t r = col[wl_beg[lo] + off];
                 ++steps;
@@ -1350,7 +1357,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 6))) void
               }
             } else {  // cax: look Gamma(a) \ {b} up in Gamma(x)
               const int32_t y = (int32_t)(wl_v[off - part1] & kIdMask);
-              if (w_has(S, w, wl_beg[lo], wl_deg[lo], y, &steps)) --cs;
+              if (w_has(S, w, wl_beg[lo], deg_of(lo), y, &steps)) --cs;
             }
           }
         }
