@@ -162,9 +162,10 @@ def host_cpu_model():
 # roofline of the dominant counting kernel
 # ---------------------------------------------------------------------------
 
-def load_counter_profile(workload, cls_tag):
+def load_counter_profile(workload, cls_tag, p=None):
     """Counter figures of the kernel (profiles/pmc_<workload>_<class>.json),
-    or None when absent or taken on another kernel source."""
+    or None when absent, taken on another kernel source or at another
+    sampling probability."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (workload, cls_tag))
     if not os.path.exists(path):
         return None
@@ -172,10 +173,12 @@ def load_counter_profile(workload, cls_tag):
         pmc = json.load(fh)
     if pmc.get("kernel_hash") != kernel_source_hash():
         return None
+    if p is not None and pmc.get("p") != p:
+        return None
     return pmc
 
 
-def roofline_of(tim, workload):
+def roofline_of(tim, workload, p=None):
     """Roofline of the counting kernel with the longest mean launch.
 
     achieved = the bytes the kernel's algorithm reads per launch (4-byte words
@@ -204,7 +207,7 @@ def roofline_of(tim, workload):
             "bytes_per_launch": read_bytes, "launch_ms": cnt_ms[dom],
             "effective": {"bytes_per_launch": alg[dom], "GBps": eff, "vs_peak": eff / HBM_PEAK_GBS,
                           "basis": "neighbour iteration of Alg. 2-4"}}
-    pmc = load_counter_profile(workload, CLASS_TAGS[dom])
+    pmc = load_counter_profile(workload, CLASS_TAGS[dom], p)
     if pmc is not None:
         roof["traffic"] = pmc["traffic_bytes_per_launch"]
         if sec > 0:
@@ -292,7 +295,7 @@ def estimate_leg(lge, ctx, g, wname, workload, p, seed, steps, warmup, h=None, c
     st = time_steps(lge, ctx, h, p, seed + 100, steps)
     log("%s p=%g: %d steps in %.3f s (%.1f M sampled edges/s)" % (wname, p, steps, st["seconds"], st["value"] / 1e6))
     k = len(st["tim"])
-    device_ms, roof = roofline_of(st["tim"], workload)
+    device_ms, roof = roofline_of(st["tim"], workload, p)
     out.update({"value": st["value"], "unit": "sampled edges/s", "steps": steps, "warmup": warmup,
                 "ms_per_step": st["ms_per_step"], "seed0": seed + 100, "device_ms": device_ms,
                 "class_edges": [sum(t["class_edges"][c] for t in st["tim"]) // k for c in range(3)],
@@ -568,7 +571,7 @@ def bench_sweep(args):
         ref = ref or key
         assert key == ref, "results changed with options %s" % kw
         st = time_steps(lge, ctx, h, p, args.seed, args.steps, o)
-        dev, roof = roofline_of(st["tim"], args.workload)
+        dev, roof = roofline_of(st["tim"], args.workload, p)
         rows.append({"opts": kw, "ms_per_step": st["ms_per_step"], "device_ms": dev})
         log("%-60s %8.2f ms/step  global %8.2f  block %7.2f  wave %6.2f" % (
             kw, st["ms_per_step"], dev["count_global"], dev["count_block"], dev["count_wave"]))

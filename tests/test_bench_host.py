@@ -61,8 +61,11 @@ def test_roofline_traffic_only_from_a_profile_of_the_same_source():
         with open(os.path.join(ROOT, "profiles", "pmc_%s_global.json" % wl)) as fh:
             pmc = json.load(fh)
         tim = [_timing([1.0, 1.0, 3.0], [0, 0, 0], [0, 0, 1e9])]
-        _, roof = bench.roofline_of(tim, wl)
+        _, roof = bench.roofline_of(tim, wl, pmc["p"])
         if pmc["kernel_hash"] == bench.kernel_source_hash():
             assert roof["traffic"] == pmc["traffic_bytes_per_launch"]
         else:
             assert roof["traffic"] is None
+        # a profile taken at another sampling probability is not used
+        _, other = bench.roofline_of(tim, wl, pmc["p"] / 10)
+        assert other["traffic"] is None
