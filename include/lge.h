@@ -64,7 +64,7 @@ extern "C" {
 #define LGE_FLAG_TRUSTED 1u
 /* lge_graph_create_* flag: keep the per-graph co-degree rows of the hubs
  * and the co-degree table small (at most 4 GB and 1 GiB, and smaller
- * build-work budgets) instead of up to 32 GB and 16 GiB; for callers holding
+ * build-work budgets) instead of up to 32 GB and 32 GiB; for callers holding
  * many large graphs at once.  Results do not change, only the speed on
  * graphs with many vertices of high degree. */
 #define LGE_FLAG_COMPACT 2u
@@ -206,13 +206,15 @@ LGE_API int lge_validate_csr_host(int64_t n, const int32_t *row_ptr, const int32
  * Validates on the GPU unless LGE_FLAG_TRUSTED.  Preprocesses once: the
  * canonical edge list and per-vertex 2-hop volumes used for scheduling, hash
  * tables of the vertices of degree > 32, the co-degree table and adjacency
- * bit rows of the vertices of degree > 96 (the highest-degree 65536 of them
- * at most, 16 GiB of table, or fewer within an eighth of the free HBM; 16384
- * and 1 GiB with LGE_FLAG_COMPACT), and co-degree rows (one byte per
- * entry, two when an unranked degree exceeds 254) |Gamma(y) n Gamma(w)| over
- * the unranked w above a small degree floor for the hubs y of degree > 1024 in
- * decreasing degree, within a build-work budget and up to 32 GB
- * of HBM (capped at a quarter of the free HBM; 4 GB with LGE_FLAG_COMPACT).
+ * bit rows of the vertices of degree > 96 (the highest-degree 131,008 of
+ * them at most, in 2-byte entries: at most 32 GiB of table and 64 times the
+ * graph's CSR bytes; 1 GiB with LGE_FLAG_COMPACT; lge_set_table_budget caps
+ * both), and co-degree rows (one byte per entry, two when an unranked
+ * degree exceeds 254) |Gamma(y) n Gamma(w)| over the unranked w above a
+ * small degree floor for the highest-degree ranked vertices y, within a
+ * build-work budget and up to 32 GB of HBM and 256 times the CSR bytes (4 GB
+ * with LGE_FLAG_COMPACT).  The budgets depend on the graph and the caller,
+ * never on what else is resident.
  * LGE_ERANGE if n >= 2^29 or a per-edge numerator could leave int64 or a sum
  * of squares 128 bits (bound: 16 * max(C(n,2), 2 dmax n, 4 dmax^2, m)).
  */
