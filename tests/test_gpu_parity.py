@@ -259,6 +259,39 @@ def test_codeg_pair_beyond_16_bits(ctx, p):
     assert_parity(got, oracle.estimate(g.row_ptr, g.col, p, 21), "two hubs of degree > 2^16")
 
 
+def test_table_budgets_change_state_not_results(ctx):
+    # the same graph with the library's tables, with capped tables, with the
+    # compact budgets and with hub tables only: identical integers and
+    # estimates, state shrinking in that order
+    g = inputs.rmat(14, 16, 0.57, 0.19, 0.19, 71)
+    made = []
+    try:
+        made.append(("default", lge.lge_graph_create_host(ctx, g.row_ptr, g.col)))
+        lge.lge_set_table_budget(ctx, 1 << 20, 1 << 20)
+        made.append(("capped", lge.lge_graph_create_host(ctx, g.row_ptr, g.col)))
+        lge.lge_set_table_budget(ctx, 0, 0)
+        made.append(("compact", lge.lge_graph_create_host(ctx, g.row_ptr, g.col, lge.LGE_FLAG_COMPACT)))
+        made.append(("no tables", lge.lge_graph_create_host(ctx, g.row_ptr, g.col, lge.LGE_FLAG_NO_TABLES)))
+        infos = [(name, lge.lge_graph_query(h)) for name, h in made]
+        _say("table budgets: " + ", ".join("%s %d ranked %.1f MB" % (n, i["ranked"], i["state_bytes"] / 1e6)
+                                           for n, i in infos))
+        assert infos[1][1]["state_bytes"] < infos[0][1]["state_bytes"]
+        assert infos[1][1]["ranked"] < infos[0][1]["ranked"]
+        assert infos[3][1]["ranked"] == 0 and infos[3][1]["rows"] == 0
+        assert infos[3][1]["state_bytes"] < infos[1][1]["state_bytes"]
+        for p, seed in ((1.0, 3), (0.3, 4)):
+            base = lge.lge_estimate(ctx, made[0][1], p, seed)
+            for name, h in made[1:]:
+                got = lge.lge_estimate(ctx, h, p, seed)
+                for k in ("sampled", "csum", "zsum", "qsum", "exact", "estimate", "variance"):
+                    assert got[k] == base[k], (name, p, k)
+        assert_parity(base, oracle.estimate(g.row_ptr, g.col, 0.3, 4), "rmat-14 with table budgets")
+    finally:
+        lge.lge_set_table_budget(ctx, 0, 0)
+        for _, h in made:
+            lge.lge_graph_destroy(h)
+
+
 def test_count_batch_large_union(ctx):
     # 16,384 members of up to 5,000 vertices: the union's own n would fail
     # the whole-graph bound on exact sums, but every member's sums use the
