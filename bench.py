@@ -163,10 +163,12 @@ def host_cpu_model():
 # ---------------------------------------------------------------------------
 
 def load_counter_profile(workload, cls_tag, p=None):
-    """Counter figures of the kernel (profiles/pmc_<workload>_<class>.json),
+    """Counter figures of the kernel (profiles/pmc_<workload>_p<p>_<class>.json),
     or None when absent, taken on another kernel source or at another
     sampling probability."""
-    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (workload, cls_tag))
+    if p is None:
+        return None
+    path = os.path.join(ROOT, "profiles", "pmc_%s_p%g_%s.json" % (workload, p, cls_tag))
     if not os.path.exists(path):
         return None
     with open(path) as fh:

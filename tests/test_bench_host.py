@@ -58,7 +58,7 @@ def test_roofline_traffic_only_from_a_profile_of_the_same_source():
     import json
     import bench
     for wl in ("chung_lu", "rmat"):
-        with open(os.path.join(ROOT, "profiles", "pmc_%s_global.json" % wl)) as fh:
+        with open(os.path.join(ROOT, "profiles", "pmc_%s_p0.1_global.json" % wl)) as fh:
             pmc = json.load(fh)
         tim = [_timing([1.0, 1.0, 3.0], [0, 0, 0], [0, 0, 1e9])]
         _, roof = bench.roofline_of(tim, wl, pmc["p"])
