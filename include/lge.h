@@ -504,7 +504,7 @@ typedef struct {
                                per-edge-id arrays of the step's ids (class lists, per-edge records), half
                                for its split-class work lists (a step needing more runs in pieces) */
   int64_t min_chunk_edges;  /* smallest edge-id chunk per request and step (default 4096) */
-  int64_t target_step_us;   /* aimed duration of one step (default 100000); chunks are sized by each
+  int64_t target_step_us;   /* aimed duration of one step (default 20000); chunks are sized by each
                                graph's per-edge work estimate and the measured work rate */
   int32_t workers;          /* step threads, 1..4 (default 3; 0 = default) */
   int32_t short_us;         /* short-lane bound on a request's remaining expected time, microseconds

@@ -253,7 +253,7 @@ extern "C" int lge_server_cfg_default(lge_server_cfg *c) {
   c->queue_capacity = 4096;
   c->hbm_budget_bytes = (int64_t)8 << 30;
   c->min_chunk_edges = 4096;
-  c->target_step_us = 100000;
+  c->target_step_us = 20000;
   c->workers = 3;
   c->short_us = 20000;
   return LGE_OK;
