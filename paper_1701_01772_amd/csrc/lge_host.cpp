@@ -47,6 +47,8 @@ constexpr double kRowBudgetBytes = 32e9;
 constexpr double kRowsPerCsr = 256.0;
 constexpr double kRowBudgetOpsCompact = 4e9;
 constexpr double kRowBudgetBytesCompact = 4e9;
+// scratch for the row fill's segment ends (freed when the graph is built)
+constexpr int64_t kRowsOffBytes = (int64_t)1 << 30;
 // Ranked vertices have degree > kCodegMinDeg: a walk of a shorter row costs
 // about as much as the table read that replaces it.
 constexpr int32_t kCodegMinDeg = 96;
@@ -547,11 +549,19 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, rows ? g->hrow : nullptr,
                        rows ? g->rcol : nullptr, n, g->vinfo, s));
   LGE_HIP(launch_arc_rank(g->col, g->vinfo, 2 * g->m, g->arh, s));
-  // the co-degree rows, tile by tile (they read the columns from the arc words)
-  if (rows)
-    LGE_HIP(launch_rows_fill(g->row_ptr, g->col, g->arh, g->row_hubs, g->nrows, g->tile_v0, g->ntiles, g->ncol,
-                             g->rows_stride, g->rows_w, g->rows, s));
-  LGE_HIP(hipStreamSynchronize(s));
+  // the co-degree rows, tile by tile (they read the columns from the arc
+  // words), with the segment ends of every list at the tile bounds in a
+  // scratch buffer of at most kRowsOffBytes (or two ends per vertex)
+  int32_t *toff = nullptr;
+  if (rows) {
+    const int64_t toff_len = std::max<int64_t>(2 * n, std::min<int64_t>(n * (g->ntiles + 1), kRowsOffBytes / 4));
+    if ((rc = dev_alloc(&toff, toff_len)) != LGE_OK) return rc;
+    e = launch_rows_fill(g->row_ptr, g->col, g->arh, g->row_hubs, g->nrows, g->tile_v0, g->ntiles, g->ncol,
+                         g->rows_stride, g->rows_w, g->rows, n, toff, toff_len, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(toff);
+  if (e != hipSuccess) return hip_err(e);
   // rows and columns now live in the vertex records and arc words
   dev_free(g->hrow);
   dev_free(g->rcol);

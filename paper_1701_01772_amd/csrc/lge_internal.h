@@ -197,11 +197,13 @@ hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, u
 // vertices (read from the arc words arh), width bytes per entry, in column
 // tiles of rows_tile_entries(width) columns; tile t starts at vertex
 // tile_v0[t] (columns numbered in vertex order, tile_v0[ntiles] = n).  Every
-// entry of the nh x stride rows is written (stride a multiple of 8).
+// entry of the nh x stride rows is written (stride a multiple of 8).  toff:
+// scratch of toff_len >= 2 n int32 for the segment ends of every vertex's
+// list at the tile bounds (the tiles go in passes of toff_len / n - 1).
 int64_t rows_tile_entries(int width);
 hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const uint32_t *arh, const int32_t *hubs,
                             int64_t nh, const int32_t *tile_v0, int64_t ntiles, int64_t ncol, int64_t stride,
-                            int width, uint8_t *rows, hipStream_t s);
+                            int width, uint8_t *rows, int64_t n, int32_t *toff, int64_t toff_len, hipStream_t s);
 // adjacency bit rows among the ranked vertices (bits zeroed by the caller)
 hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,
                              unsigned long long *bits, hipStream_t s);

@@ -686,9 +686,12 @@ __global__ __launch_bounds__(256) void k_codeg_fill(const int32_t *__restrict__ 
 // deg(x): rows of x with deg(x) < 2^16 count in the 16-bit halves of the LDS
 // words (2 * kRowWords ranks per pass), the others in 32-bit words
 // (kRowWords ranks per pass).  A wave loads 64 of the w at once (coalesced)
-// and walks their lists one after another, lanes striding each.
+// and walks the short lists each in its own lane, the long ones one after
+// another, lanes striding each.
 constexpr int kRowNT = 1024;
 constexpr int kRowWords = 32768;  // 128 KB of LDS counters
+constexpr int kOwnSeg = 16;       // longest list (segment) a lane walks by itself
+constexpr int kCoopUnroll = 8;    // reads per lane in flight when a wave walks a long list
 __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ ranked,
                                                         const int64_t *__restrict__ off,
@@ -729,18 +732,44 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
           k -= kl;
         }
       }
-      const int ng = d - g0 < kWave ? d - g0 : kWave;
-      for (int q = 0; q < ng; ++q) {  // uniform per wave
+      auto add = [&](int32_t y) {
+        if (y < c0 || y >= c1) return;
+        const int32_t yy = y - (int32_t)c0;
+        if (narrow)
+          atomicAdd(&c[yy >> 1], 1u << ((yy & 1) << 4));
+        else
+          atomicAdd(&c[yy], 1u);
+      };
+      // a short list is walked by its own lane, from a lane-dependent start
+      // (lists share their hub ranks, and lanes adding at one counter at
+      // once serialise); the wave walks the long ones one after another
+      const bool own = k <= kOwnSeg;
+      if (own && k > 0) {
+        const int st = lane % k;
+        for (int s0 = 0; s0 < k; s0 += 4) {
+          int32_t ys[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            int idx = st + s0 + u;
+            if (idx >= k) idx -= k;
+            ys[u] = s0 + u < k ? list[o + idx] : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) add(ys[u]);
+        }
+      }
+      uint64_t lm = __ballot(!own);
+      while (lm) {  // uniform per wave
+        const int q = __ffsll((long long)lm) - 1;
+        lm &= lm - 1;
         const long long oq = __shfl(o, q);
         const int kq = __shfl(k, q);
-        for (int i = lane; i < kq; i += kWave) {
-          const int32_t y = list[oq + i];
-          if (y < c0 || y >= c1) continue;
-          const int32_t yy = y - (int32_t)c0;
-          if (narrow)
-            atomicAdd(&c[yy >> 1], 1u << ((yy & 1) << 4));
-          else
-            atomicAdd(&c[yy], 1u);
+        for (int i0 = lane; i0 < kq; i0 += kCoopUnroll * kWave) {  // kCoopUnroll reads in flight
+          int32_t ys[kCoopUnroll];
+#pragma unroll
+          for (int u = 0; u < kCoopUnroll; ++u) ys[u] = i0 + u * kWave < kq ? list[oq + i0 + u * kWave] : -1;
+#pragma unroll
+          for (int u = 0; u < kCoopUnroll; ++u) add(ys[u]);
         }
       }
     }
@@ -761,11 +790,13 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
 // neighbours w with a column in the tile, counted in LDS (each w once per x,
 // so the entry ends as |Gamma(y) n Gamma(w)|).  Columns are numbered in
 // vertex order, so the tile's columns are a range [v0, v1) of vertex ids and
-// the w of x lie in one segment of x's sorted list (two binary searches);
-// the arc word beside each w gives its column.  One 32-bit LDS counter per
-// column (packing them 4 or 2 to a word measured slower); the tile is then
-// written out once as entries of `width` bytes.  A wave searches the segments
-// of 64 x at once, then walks them one after another, lanes striding each.
+// the w of x lie in one segment of x's sorted list, whose ends a separate
+// pass finds once per (x, tile) (k_rows_offsets); the arc word beside each w
+// gives its column.  One 32-bit LDS counter per column (packing them 4 or 2
+// to a word measured slower); the tile is then written out once as entries
+// of `width` bytes.  A wave reads the segment ends of 64 x at once; a lane
+// walks its own x's segment when it is short, and the wave walks the long
+// ones one after another, lanes striding each.
 constexpr int kTileNT = 1024;
 constexpr int kTileWords = 32768;  // 128 KB of LDS counters
 
@@ -780,21 +811,42 @@ __device__ __forceinline__ int32_t lower_pos(const int32_t *__restrict__ a, int3
   return lo;
 }
 
+// toff[x * (nb + 1) + i] = first position of Gamma(x) at or above vertex
+// tile_v0[t0 + i], for every vertex x and i in [0, nb]
+__global__ __launch_bounds__(256) void k_rows_offsets(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                      int64_t n, const int32_t *__restrict__ tile_v0, int64_t t0,
+                                                      int64_t nb, int32_t *__restrict__ toff) {
+  const int64_t per = nb + 1, total = n * per;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = i / per, k = i - x * per;
+    toff[i] = lower_pos(col, rp[x], rp[x + 1], tile_v0[t0 + k]);
+  }
+}
+
+__device__ __forceinline__ void rows_count(uint32_t *c, int64_t c0, uint32_t r) {
+  if (r >> 31) {  // unranked head; its column + 1 in the low bits (0: none)
+    const int64_t cc = (int64_t)(r & 0x7FFFFFFFu) - 1;
+    if (cc >= 0) atomicAdd(&c[cc - c0], 1u);
+  }
+}
+
+// tiles [t0, t0 + nb) of every row; toff from k_rows_offsets over the same
+// tiles
 __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        const uint32_t *__restrict__ arh,
                                                        const int32_t *__restrict__ hubs, int64_t nh,
-                                                       const int32_t *__restrict__ tile_v0, int64_t ntiles,
+                                                       const int32_t *__restrict__ toff, int64_t t0, int64_t nb,
                                                        int64_t ncol, int64_t stride, int width,
                                                        uint8_t *__restrict__ rows) {
   __shared__ uint32_t c[kTileWords];
   const int64_t T = kTileWords;  // columns per tile
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int kWaves = kTileNT / kWave;
-  for (int64_t wi = blockIdx.x; wi < nh * ntiles; wi += gridDim.x) {  // uniform per block
-    const int64_t h = wi / ntiles, t = wi % ntiles;
+  const int64_t per = nb + 1;
+  for (int64_t wi = blockIdx.x; wi < nh * nb; wi += gridDim.x) {  // uniform per block
+    const int64_t h = wi / nb, tt = wi % nb, t = t0 + tt;
     const int32_t y = hubs[h];
     const int64_t c0 = t * T, c1 = c0 + T < ncol ? c0 + T : ncol;
-    const int32_t v0 = tile_v0[t], v1 = tile_v0[t + 1];
     const int64_t words = c1 - c0;
     for (int64_t i = threadIdx.x; i < words; i += kTileNT) c[i] = 0u;
     __syncthreads();
@@ -803,22 +855,29 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
       const int32_t j = g0 + lane;
       int32_t lo = 0, hi = 0;
       if (j < dy) {
-        const int32_t x = col[ybeg + j];
-        const int32_t xb = rp[x], xe = rp[x + 1];
-        lo = lower_pos(col, xb, xe, v0);
-        hi = lower_pos(col, lo, xe, v1);
+        const int64_t x = col[ybeg + j];
+        lo = toff[x * per + tt];
+        hi = toff[x * per + tt + 1];
       }
-      const int ng = dy - g0 < kWave ? dy - g0 : kWave;
-      for (int q = 0; q < ng; ++q) {  // uniform per wave
+      const bool own = hi - lo <= kOwnSeg;
+      for (int32_t k = own ? lo : hi; k < hi; k += 4) {
+        uint32_t r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = k + u < hi ? arh[k + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rows_count(c, c0, r[u]);
+      }
+      uint64_t lm = __ballot(!own);
+      while (lm) {  // uniform per wave
+        const int q = __ffsll((long long)lm) - 1;
+        lm &= lm - 1;
         const int32_t lq = __shfl(lo, q), hq = __shfl(hi, q);
-        for (int32_t k = lq + lane; k < hq; k += kWave) {
-          const uint32_t r = arh[k];
-          if (r >> 31) {  // unranked head; its column + 1 in the low bits (0: none)
-            const int64_t cc = (int64_t)(r & 0x7FFFFFFFu) - 1;
-            if (cc >= 0) {
-              atomicAdd(&c[cc - c0], 1u);
-            }
-          }
+        for (int32_t k0 = lq + lane; k0 < hq; k0 += kCoopUnroll * kWave) {  // kCoopUnroll reads in flight
+          uint32_t r[kCoopUnroll];
+#pragma unroll
+          for (int u = 0; u < kCoopUnroll; ++u) r[u] = k0 + u * kWave < hq ? arh[k0 + u * kWave] : 0u;
+#pragma unroll
+          for (int u = 0; u < kCoopUnroll; ++u) rows_count(c, c0, r[u]);
         }
       }
     }
@@ -2749,11 +2808,21 @@ int64_t rows_tile_entries(int) { return kTileWords; }
 
 hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const uint32_t *arh, const int32_t *hubs,
                             int64_t nh, const int32_t *tile_v0, int64_t ntiles, int64_t ncol, int64_t stride,
-                            int width, uint8_t *rows, hipStream_t s) {
+                            int width, uint8_t *rows, int64_t n, int32_t *toff, int64_t toff_len, hipStream_t s) {
   if (nh <= 0 || ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rows_fill, dim3(grid_for(nh * ntiles, 1, 1 << 20)), dim3(kTileNT), 0, s, row_ptr, col, arh,
-                     hubs, nh, tile_v0, ntiles, ncol, stride, width, rows);
-  return hipGetLastError();
+  if (n <= 0 || toff_len < 2 * n) return hipErrorInvalidValue;
+  // tiles per pass: as many as the segment-end buffer holds
+  const int64_t nb_max = toff_len / n - 1;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += nb_max) {
+    const int64_t nb = ntiles - t0 < nb_max ? ntiles - t0 : nb_max;
+    hipLaunchKernelGGL(k_rows_offsets, dim3(grid_for(n * (nb + 1), 256, 65536)), dim3(256), 0, s, row_ptr, col, n,
+                       tile_v0, t0, nb, toff);
+    hipLaunchKernelGGL(k_rows_fill, dim3(grid_for(nh * nb, 1, 1 << 20)), dim3(kTileNT), 0, s, row_ptr, col, arh,
+                       hubs, nh, toff, t0, nb, ncol, stride, width, rows);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 
