@@ -423,9 +423,8 @@ static void drop_rows(lge_graph *g) {
   dev_free(g->hrow);
   dev_free(g->rcol);
   dev_free(g->row_hubs);
-  dev_free(g->tile_v0);
   dev_free(g->rows);
-  g->nrows = g->rows_stride = g->ntiles = g->ncol = 0;
+  g->nrows = g->rows_stride = g->ncol = 0;
 }
 
 static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const int32_t *host_row_ptr) {
@@ -549,24 +548,55 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   LGE_HIP(launch_vinfo(g->row_ptr, g->hc > 0 ? g->crank : nullptr, rows ? g->hrow : nullptr,
                        rows ? g->rcol : nullptr, n, g->vinfo, s));
   LGE_HIP(launch_arc_rank(g->col, g->vinfo, 2 * g->m, g->arh, s));
-  // the co-degree rows, tile by tile (they read the columns from the arc
-  // words), with the segment ends of every list at the tile bounds in a
-  // scratch buffer of at most kRowsOffBytes (or two ends per vertex)
-  int32_t *toff = nullptr;
+  // the co-degree rows, tile by tile, from every vertex's list of
+  // neighbour columns (taken from the arc words), with the segment ends of
+  // the lists at the tile bounds in a scratch buffer of at most
+  // kRowsOffBytes (or two ends per vertex); all of it freed here
   if (rows) {
-    const int64_t toff_len = std::max<int64_t>(2 * n, std::min<int64_t>(n * (g->ntiles + 1), kRowsOffBytes / 4));
-    if ((rc = dev_alloc(&toff, toff_len)) != LGE_OK) return rc;
-    e = launch_rows_fill(g->row_ptr, g->col, g->arh, g->row_hubs, g->nrows, g->tile_v0, g->ntiles, g->ncol,
-                         g->rows_stride, g->rows_w, g->rows, n, toff, toff_len, s);
+    int64_t *ccnt = nullptr, *coff = nullptr, *tmp = nullptr;
+    int32_t *clist = nullptr, *toff = nullptr;
+    auto release = [&]() {
+      dev_free(ccnt);
+      dev_free(coff);
+      dev_free(tmp);
+      dev_free(clist);
+      dev_free(toff);
+    };
+    if ((rc = dev_alloc(&ccnt, n)) != LGE_OK || (rc = dev_alloc(&coff, n)) != LGE_OK ||
+        (rc = dev_alloc(&tmp, scan_tmp_size(n))) != LGE_OK) {
+      release();
+      return rc;
+    }
+    e = launch_col_count(g->row_ptr, g->arh, n, ccnt, s);
+    if (e == hipSuccess) e = launch_scan_i64(ccnt, coff, n, tmp, s);
+    int64_t last[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(&last[0], coff + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&last[1], ccnt + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      release();
+      return hip_err(e);
+    }
+    const int64_t ntiles = (g->ncol + rows_tile_entries(g->rows_w) - 1) / rows_tile_entries(g->rows_w);
+    const int64_t toff_len = std::max<int64_t>(2 * n, std::min<int64_t>(n * (ntiles + 1), kRowsOffBytes / 4));
+    if ((rc = dev_alloc(&clist, std::max<int64_t>(last[0] + last[1], 1))) != LGE_OK ||
+        (rc = dev_alloc(&toff, toff_len)) != LGE_OK) {
+      release();
+      return rc;
+    }
+    e = launch_col_fill(g->row_ptr, g->arh, n, coff, clist, s);
+    if (e == hipSuccess)
+      e = launch_rows_fill(g->row_ptr, g->col, coff, ccnt, clist, g->row_hubs, g->nrows, g->ncol, g->rows_stride,
+                           g->rows_w, g->rows, n, toff, toff_len, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    release();
+    if (e != hipSuccess) return hip_err(e);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(toff);
-  if (e != hipSuccess) return hip_err(e);
+  LGE_HIP(hipStreamSynchronize(s));
   // rows and columns now live in the vertex records and arc words
   dev_free(g->hrow);
   dev_free(g->rcol);
   dev_free(g->row_hubs);
-  dev_free(g->tile_v0);
   g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build).count();
   return LGE_OK;
 }
@@ -729,35 +759,26 @@ static int build_rows(lge_ctx *ctx, lge_graph *g, const int32_t *host_row_ptr, u
   if (stride == 0) return LGE_OK;
   const int64_t nh = std::min<int64_t>((int64_t)hubs.size(), (int64_t)(budget_bytes / ((double)stride * width)));
   if (nh <= 0) return LGE_OK;
-  // columns go to the vertices in id order, so a range of columns is a range
-  // of vertex ids; tile t of the fill covers columns [t T, (t + 1) T) and
-  // starts at the vertex of column t T
-  std::vector<int32_t> rcol((size_t)n, -1), hrow((size_t)n, -1), tile_v0;
+  // columns go to the vertices in id order, so every sorted adjacency list
+  // lists its columns in increasing order
+  std::vector<int32_t> rcol((size_t)n, -1), hrow((size_t)n, -1);
   {
-    const int64_t per_tile = rows_tile_entries(width);
     int32_t c = 0;
     for (int64_t v = 0; v < n; ++v)
-      if (rank[v] < 0 && host_row_ptr[v + 1] - host_row_ptr[v] > floor_deg) {
-        if (c % per_tile == 0) tile_v0.push_back((int32_t)v);
-        rcol[v] = c++;
-      }
-    tile_v0.push_back((int32_t)n);
+      if (rank[v] < 0 && host_row_ptr[v + 1] - host_row_ptr[v] > floor_deg) rcol[v] = c++;
   }
   for (int64_t h = 0; h < nh; ++h) hrow[hubs[h]] = (int32_t)h;
   int rc;
   const int64_t nent = nh * stride * width;  // bytes
   if ((rc = dev_alloc(&g->hrow, n)) != LGE_OK || (rc = dev_alloc(&g->rcol, n)) != LGE_OK ||
       (rc = dev_alloc(&g->row_hubs, nh)) != LGE_OK ||
-      (rc = dev_alloc(&g->tile_v0, (int64_t)tile_v0.size())) != LGE_OK || (rc = dev_alloc(&g->rows, nent)) != LGE_OK)
+      (rc = dev_alloc(&g->rows, nent)) != LGE_OK)
     return rc;  // graph_free releases the partial allocations
   hipError_t e = hipMemcpyAsync(g->row_hubs, hubs.data(), (size_t)nh * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->hrow, hrow.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->rcol, rcol.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(g->tile_v0, tile_v0.data(), tile_v0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host vectors go out of scope
   if (e != hipSuccess) return hip_err(e);
-  g->ntiles = (int64_t)tile_v0.size() - 1;
   g->ncol = ncol;
   g->nrows = nh;
   g->rows_stride = stride;
@@ -779,7 +800,6 @@ static void graph_free(lge_graph *g) {
   dev_free(g->hrow);
   dev_free(g->rcol);
   dev_free(g->row_hubs);
-  dev_free(g->tile_v0);
   dev_free(g->rows);
   dev_free(g->vinfo);
   dev_free(g->arh);

@@ -193,16 +193,21 @@ hipError_t launch_vinfo(const int32_t *row_ptr, const int32_t *crank, const int3
                         int64_t n, int4 *vinfo, hipStream_t s);
 // packed rank words of every arc's head (after the vertex records)
 hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, uint32_t *arh, hipStream_t s);
-// co-degree rows of the vertices `hubs` at the columns of the unranked
-// vertices (read from the arc words arh), width bytes per entry, in column
-// tiles of rows_tile_entries(width) columns; tile t starts at vertex
-// tile_v0[t] (columns numbered in vertex order, tile_v0[ntiles] = n).  Every
-// entry of the nh x stride rows is written (stride a multiple of 8).  toff:
-// scratch of toff_len >= 2 n int32 for the segment ends of every vertex's
-// list at the tile bounds (the tiles go in passes of toff_len / n - 1).
+// the neighbours of every vertex that have a column (arc word of an unranked
+// head with a column), counted (cnt) and listed as columns at off (the
+// exclusive scan of cnt), in adjacency order
+hipError_t launch_col_count(const int32_t *row_ptr, const uint32_t *arh, int64_t n, int64_t *cnt, hipStream_t s);
+hipError_t launch_col_fill(const int32_t *row_ptr, const uint32_t *arh, int64_t n, const int64_t *off, int32_t *clist,
+                           hipStream_t s);
+// co-degree rows of the vertices `hubs` at the ncol columns of the unranked
+// vertices (coff / ccnt / clist: every vertex's column list), width bytes
+// per entry, in tiles of rows_tile_entries(width) columns.  Every entry of
+// the nh x stride rows is written (stride a multiple of 8).  toff: scratch
+// of toff_len >= 2 n int32 for the segment ends of every column list at the
+// tile bounds (the tiles go in passes of toff_len / n - 1).
 int64_t rows_tile_entries(int width);
-hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const uint32_t *arh, const int32_t *hubs,
-                            int64_t nh, const int32_t *tile_v0, int64_t ntiles, int64_t ncol, int64_t stride,
+hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const int64_t *coff, const int64_t *ccnt,
+                            const int32_t *clist, const int32_t *hubs, int64_t nh, int64_t ncol, int64_t stride,
                             int width, uint8_t *rows, int64_t n, int32_t *toff, int64_t toff_len, hipStream_t s);
 // adjacency bit rows among the ranked vertices (bits zeroed by the caller)
 hipError_t launch_codeg_bits(const int32_t *row_ptr, const int32_t *col, const int32_t *crank, int64_t n, int64_t hcw,

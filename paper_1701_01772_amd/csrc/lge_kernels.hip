@@ -692,6 +692,7 @@ constexpr int kRowNT = 1024;
 constexpr int kRowWords = 32768;  // 128 KB of LDS counters
 constexpr int kOwnSeg = 16;       // longest list (segment) a lane walks by itself
 constexpr int kCoopUnroll = 8;    // reads per lane in flight when a wave walks a long list
+constexpr int kRankUnroll = 16;   // the same for the rank lists of the co-degree table
 __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ ranked,
                                                         const int64_t *__restrict__ off,
@@ -764,12 +765,12 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
         lm &= lm - 1;
         const long long oq = __shfl(o, q);
         const int kq = __shfl(k, q);
-        for (int i0 = lane; i0 < kq; i0 += kCoopUnroll * kWave) {  // kCoopUnroll reads in flight
-          int32_t ys[kCoopUnroll];
+        for (int i0 = lane; i0 < kq; i0 += kRankUnroll * kWave) {  // kRankUnroll reads in flight
+          int32_t ys[kRankUnroll];
 #pragma unroll
-          for (int u = 0; u < kCoopUnroll; ++u) ys[u] = i0 + u * kWave < kq ? list[oq + i0 + u * kWave] : -1;
+          for (int u = 0; u < kRankUnroll; ++u) ys[u] = i0 + u * kWave < kq ? list[oq + i0 + u * kWave] : -1;
 #pragma unroll
-          for (int u = 0; u < kCoopUnroll; ++u) add(ys[u]);
+          for (int u = 0; u < kRankUnroll; ++u) add(ys[u]);
         }
       }
     }
@@ -786,13 +787,13 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
 }
 
 // Co-degree rows over the unranked columns, one workgroup per (row h,
-// column tile t): the row's hub y, every x in Gamma(y), and in Gamma(x) the
-// neighbours w with a column in the tile, counted in LDS (each w once per x,
-// so the entry ends as |Gamma(y) n Gamma(w)|).  Columns are numbered in
-// vertex order, so the tile's columns are a range [v0, v1) of vertex ids and
-// the w of x lie in one segment of x's sorted list, whose ends a separate
-// pass finds once per (x, tile) (k_rows_offsets); the arc word beside each w
-// gives its column.  One 32-bit LDS counter per column (packing them 4 or 2
+// column tile t): the row's hub y, every x in Gamma(y), and x's neighbours w
+// with a column in the tile, counted in LDS (each w once per x, so the entry
+// ends as |Gamma(y) n Gamma(w)|).  Every vertex's neighbours that have a
+// column are first listed as columns, in increasing order (columns go by
+// vertex id, and the adjacency lists are sorted); the tile's part of x's list
+// is then one segment, whose ends a separate pass finds once per (x, tile)
+// (k_rows_offsets).  One 32-bit LDS counter per column (packing them 4 or 2
 // to a word measured slower); the tile is then written out once as entries
 // of `width` bytes.  A wave reads the segment ends of 64 x at once; a lane
 // walks its own x's segment when it is short, and the wave walks the long
@@ -800,9 +801,9 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
 constexpr int kTileNT = 1024;
 constexpr int kTileWords = 32768;  // 128 KB of LDS counters
 
-__device__ __forceinline__ int32_t lower_pos(const int32_t *__restrict__ a, int32_t lo, int32_t hi, int32_t v) {
+__device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ a, int64_t lo, int64_t hi, int32_t v) {
   while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
+    const int64_t mid = (lo + hi) >> 1;
     if (a[mid] < v)
       lo = mid + 1;
     else
@@ -811,29 +812,63 @@ __device__ __forceinline__ int32_t lower_pos(const int32_t *__restrict__ a, int3
   return lo;
 }
 
-// toff[x * (nb + 1) + i] = first position of Gamma(x) at or above vertex
-// tile_v0[t0 + i], for every vertex x and i in [0, nb]
-__global__ __launch_bounds__(256) void k_rows_offsets(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                      int64_t n, const int32_t *__restrict__ tile_v0, int64_t t0,
+// column of an arc's head from its packed word (-1: ranked, or no column)
+__device__ __forceinline__ int32_t arc_column(uint32_t r) {
+  return (r >> 31) ? (int32_t)(r & 0x7FFFFFFFu) - 1 : -1;
+}
+
+// number of every vertex's neighbours that have a column
+__global__ __launch_bounds__(256) void k_col_count(const int32_t *__restrict__ rp, const uint32_t *__restrict__ arh,
+                                                   int64_t n, int64_t *__restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = wave; u < n; u += nwaves) {
+    unsigned long long c = 0;
+    for (int32_t j = rp[u] + lane; j < rp[u + 1]; j += kWave) c += arc_column(arh[j]) >= 0 ? 1ull : 0ull;
+    c = wave_sum_u64(c);
+    if (lane == 0) cnt[u] = (int64_t)c;
+  }
+}
+
+// the columns of every vertex's neighbours, in adjacency order, at off[u]
+__global__ __launch_bounds__(256) void k_col_fill(const int32_t *__restrict__ rp, const uint32_t *__restrict__ arh,
+                                                  int64_t n, const int64_t *__restrict__ off,
+                                                  int32_t *__restrict__ clist) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = wave; u < n; u += nwaves) {
+    int64_t at = off[u];
+    const int32_t end = rp[u + 1];
+    for (int32_t base = rp[u]; base < end; base += kWave) {
+      const int32_t j = base + lane;
+      const int32_t cc = j < end ? arc_column(arh[j]) : -1;
+      const uint64_t m = __ballot(cc >= 0);
+      if (cc >= 0) clist[at + __popcll(m & lt_mask)] = cc;
+      at += __popcll(m);
+    }
+  }
+}
+
+// toff[x * (nb + 1) + i] = first position of x's column list at or above
+// column (t0 + i) * kTileWords, for every vertex x and i in [0, nb]
+__global__ __launch_bounds__(256) void k_rows_offsets(const int64_t *__restrict__ off, const int64_t *__restrict__ cnt,
+                                                      const int32_t *__restrict__ clist, int64_t n, int64_t t0,
                                                       int64_t nb, int32_t *__restrict__ toff) {
   const int64_t per = nb + 1, total = n * per;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = i / per, k = i - x * per;
-    toff[i] = lower_pos(col, rp[x], rp[x + 1], tile_v0[t0 + k]);
-  }
-}
-
-__device__ __forceinline__ void rows_count(uint32_t *c, int64_t c0, uint32_t r) {
-  if (r >> 31) {  // unranked head; its column + 1 in the low bits (0: none)
-    const int64_t cc = (int64_t)(r & 0x7FFFFFFFu) - 1;
-    if (cc >= 0) atomicAdd(&c[cc - c0], 1u);
+    const int64_t lo = off[x];
+    toff[i] = (int32_t)lower_pos(clist, lo, lo + cnt[x], (int32_t)((t0 + k) * kTileWords));
   }
 }
 
 // tiles [t0, t0 + nb) of every row; toff from k_rows_offsets over the same
 // tiles
 __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                       const uint32_t *__restrict__ arh,
+                                                       const int32_t *__restrict__ clist,
                                                        const int32_t *__restrict__ hubs, int64_t nh,
                                                        const int32_t *__restrict__ toff, int64_t t0, int64_t nb,
                                                        int64_t ncol, int64_t stride, int width,
@@ -848,6 +883,7 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
     const int32_t y = hubs[h];
     const int64_t c0 = t * T, c1 = c0 + T < ncol ? c0 + T : ncol;
     const int64_t words = c1 - c0;
+    const int32_t base = (int32_t)c0;
     for (int64_t i = threadIdx.x; i < words; i += kTileNT) c[i] = 0u;
     __syncthreads();
     const int32_t ybeg = rp[y], dy = rp[y + 1] - ybeg;
@@ -861,11 +897,12 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
       }
       const bool own = hi - lo <= kOwnSeg;
       for (int32_t k = own ? lo : hi; k < hi; k += 4) {
-        uint32_t r[4];
+        int32_t cs[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = k + u < hi ? arh[k + u] : 0u;
+        for (int u = 0; u < 4; ++u) cs[u] = k + u < hi ? clist[k + u] : -1;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) rows_count(c, c0, r[u]);
+        for (int u = 0; u < 4; ++u)
+          if (cs[u] >= 0) atomicAdd(&c[cs[u] - base], 1u);
       }
       uint64_t lm = __ballot(!own);
       while (lm) {  // uniform per wave
@@ -873,11 +910,12 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
         lm &= lm - 1;
         const int32_t lq = __shfl(lo, q), hq = __shfl(hi, q);
         for (int32_t k0 = lq + lane; k0 < hq; k0 += kCoopUnroll * kWave) {  // kCoopUnroll reads in flight
-          uint32_t r[kCoopUnroll];
+          int32_t cs[kCoopUnroll];
 #pragma unroll
-          for (int u = 0; u < kCoopUnroll; ++u) r[u] = k0 + u * kWave < hq ? arh[k0 + u * kWave] : 0u;
+          for (int u = 0; u < kCoopUnroll; ++u) cs[u] = k0 + u * kWave < hq ? clist[k0 + u * kWave] : -1;
 #pragma unroll
-          for (int u = 0; u < kCoopUnroll; ++u) rows_count(c, c0, r[u]);
+          for (int u = 0; u < kCoopUnroll; ++u)
+            if (cs[u] >= 0) atomicAdd(&c[cs[u] - base], 1u);
         }
       }
     }
@@ -2806,18 +2844,32 @@ hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, u
 
 int64_t rows_tile_entries(int) { return kTileWords; }
 
-hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const uint32_t *arh, const int32_t *hubs,
-                            int64_t nh, const int32_t *tile_v0, int64_t ntiles, int64_t ncol, int64_t stride,
+hipError_t launch_col_count(const int32_t *row_ptr, const uint32_t *arh, int64_t n, int64_t *cnt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_count, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, arh, n, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_fill(const int32_t *row_ptr, const uint32_t *arh, int64_t n, const int64_t *off, int32_t *clist,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_fill, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, row_ptr, arh, n, off, clist);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const int64_t *coff, const int64_t *ccnt,
+                            const int32_t *clist, const int32_t *hubs, int64_t nh, int64_t ncol, int64_t stride,
                             int width, uint8_t *rows, int64_t n, int32_t *toff, int64_t toff_len, hipStream_t s) {
+  const int64_t ntiles = (ncol + kTileWords - 1) / kTileWords;
   if (nh <= 0 || ntiles <= 0) return hipSuccess;
   if (n <= 0 || toff_len < 2 * n) return hipErrorInvalidValue;
   // tiles per pass: as many as the segment-end buffer holds
   const int64_t nb_max = toff_len / n - 1;
   for (int64_t t0 = 0; t0 < ntiles; t0 += nb_max) {
     const int64_t nb = ntiles - t0 < nb_max ? ntiles - t0 : nb_max;
-    hipLaunchKernelGGL(k_rows_offsets, dim3(grid_for(n * (nb + 1), 256, 65536)), dim3(256), 0, s, row_ptr, col, n,
-                       tile_v0, t0, nb, toff);
-    hipLaunchKernelGGL(k_rows_fill, dim3(grid_for(nh * nb, 1, 1 << 20)), dim3(kTileNT), 0, s, row_ptr, col, arh,
+    hipLaunchKernelGGL(k_rows_offsets, dim3(grid_for(n * (nb + 1), 256, 65536)), dim3(256), 0, s, coff, ccnt, clist,
+                       n, t0, nb, toff);
+    hipLaunchKernelGGL(k_rows_fill, dim3(grid_for(nh * nb, 1, 1 << 20)), dim3(kTileNT), 0, s, row_ptr, col, clist,
                        hubs, nh, toff, t0, nb, ncol, stride, width, rows);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -42,8 +42,7 @@ struct lge_graph {
   int32_t *hrow = nullptr;   // n: co-degree row index, -1 if none (graph creation only)
   int32_t *rcol = nullptr;   // n: column in the co-degree rows, -1 if none (graph creation only)
   int32_t *row_hubs = nullptr;  // nrows: vertex of every co-degree row (graph creation only)
-  int32_t *tile_v0 = nullptr;   // ntiles + 1: first vertex of every column tile of the fill (graph creation only)
-  int64_t ntiles = 0, ncol = 0;  // column tiles of the fill, columns
+  int64_t ncol = 0;             // columns of the co-degree rows
   uint8_t *rows = nullptr;   // nrows x rows_stride co-degree rows over the unranked vertices
   int64_t nrows = 0, rows_stride = 0;  // rows, columns per row
   int32_t rows_w = 0;                 // bytes per entry (1 or 2)
