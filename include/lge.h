@@ -475,6 +475,16 @@ LGE_API int lge_autotune_reset(lge_ctx *ctx);
 LGE_API int lge_set_table_budget(lge_ctx *ctx, uint64_t codeg_bytes, uint64_t rows_bytes);
 
 /*
+ * Cap, in bytes, on the temporary device memory a graph creation on ctx
+ * takes for the ends of every vertex's neighbour segments at the co-degree
+ * row tiles (Sec. 2.6 tables; 1 GiB by default, 0 restores it; freed before
+ * the creation returns).  At least 8 bytes per vertex are taken whatever the
+ * cap: a smaller cap means more passes over the tiles, never different
+ * tables.  Errors: LGE_EINVAL (null ctx).
+ */
+LGE_API int lge_set_build_scratch(lge_ctx *ctx, uint64_t bytes);
+
+/*
  * Serving.  A server owns `ctx` (no other call may use that ctx while the
  * server exists) and runs `workers` step threads: the first steps on ctx,
  * the others on contexts the server opens on the same device (own stream and

@@ -47,7 +47,8 @@ constexpr double kRowBudgetBytes = 32e9;
 constexpr double kRowsPerCsr = 256.0;
 constexpr double kRowBudgetOpsCompact = 4e9;
 constexpr double kRowBudgetBytesCompact = 4e9;
-// scratch for the row fill's segment ends (freed when the graph is built)
+// default cap on the scratch for the row fill's segment ends (freed when
+// the graph is built)
 constexpr int64_t kRowsOffBytes = (int64_t)1 << 30;
 // Ranked vertices have degree > kCodegMinDeg: a walk of a shorter row costs
 // about as much as the table read that replaces it.
@@ -551,7 +552,8 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
   // the co-degree rows, tile by tile, from every vertex's list of
   // neighbour columns (taken from the arc words), with the segment ends of
   // the lists at the tile bounds in a scratch buffer of at most
-  // kRowsOffBytes (or two ends per vertex); all of it freed here
+  // kRowsOffBytes or the context's cap (but two ends per vertex); all of it
+  // freed here
   if (rows) {
     int64_t *ccnt = nullptr, *coff = nullptr, *tmp = nullptr;
     int32_t *clist = nullptr, *toff = nullptr;
@@ -578,7 +580,8 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
       return hip_err(e);
     }
     const int64_t ntiles = (g->ncol + rows_tile_entries(g->rows_w) - 1) / rows_tile_entries(g->rows_w);
-    const int64_t toff_len = std::max<int64_t>(2 * n, std::min<int64_t>(n * (ntiles + 1), kRowsOffBytes / 4));
+    const int64_t cap = ctx->build_scratch > 0 ? ctx->build_scratch : kRowsOffBytes;
+    const int64_t toff_len = std::max<int64_t>(2 * n, std::min<int64_t>(n * (ntiles + 1), cap / 4));
     if ((rc = dev_alloc(&clist, std::max<int64_t>(last[0] + last[1], 1))) != LGE_OK ||
         (rc = dev_alloc(&toff, toff_len)) != LGE_OK) {
       release();
@@ -2016,5 +2019,11 @@ extern "C" int lge_set_table_budget(lge_ctx *ctx, uint64_t codeg_bytes, uint64_t
   if (!ctx) return LGE_EINVAL;
   ctx->codeg_budget = (int64_t)std::min<uint64_t>(codeg_bytes, (uint64_t)INT64_MAX);
   ctx->rows_budget = (int64_t)std::min<uint64_t>(rows_bytes, (uint64_t)INT64_MAX);
+  return LGE_OK;
+}
+
+extern "C" int lge_set_build_scratch(lge_ctx *ctx, uint64_t bytes) {
+  if (!ctx) return LGE_EINVAL;
+  ctx->build_scratch = (int64_t)std::min<uint64_t>(bytes, (uint64_t)INT64_MAX);
   return LGE_OK;
 }

@@ -135,6 +135,8 @@ struct lge_ctx {
   // on this context (0: the library's own budgets)
   int64_t codeg_budget = 0;
   int64_t rows_budget = 0;
+  // cap on a graph creation's temporary row-fill scratch (0: the default)
+  int64_t build_scratch = 0;
   lge_timing timing{};
   hipEvent_t ev[8] = {};
   int num_cu = 256;

@@ -170,6 +170,7 @@ def load():
         "lge_autotune": ([_VP, _VP, ctypes.c_double, ctypes.POINTER(Opts)], ctypes.c_int),
         "lge_autotune_reset": ([_VP], ctypes.c_int),
         "lge_set_table_budget": ([_VP, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
+        "lge_set_build_scratch": ([_VP, ctypes.c_uint64], ctypes.c_int),
         "lge_adaptive_cfg_default": ([ctypes.POINTER(AdaptiveCfg)], ctypes.c_int),
         "lge_estimate_adaptive": ([_VP, _VP, ctypes.c_uint64, ctypes.POINTER(AdaptiveCfg), ctypes.POINTER(Result),
                                    ctypes.POINTER(AdaptiveTrace)], ctypes.c_int),
@@ -413,6 +414,10 @@ def lge_autotune_reset(ctx):
 
 def lge_set_table_budget(ctx, codeg_bytes: int = 0, rows_bytes: int = 0):
     _check(load().lge_set_table_budget(ctx, int(codeg_bytes), int(rows_bytes)), "lge_set_table_budget")
+
+
+def lge_set_build_scratch(ctx, nbytes: int = 0):
+    _check(load().lge_set_build_scratch(ctx, int(nbytes)), "lge_set_build_scratch")
 
 
 def lge_estimate_adaptive(ctx, g, seed: int, beta: float = 0.01, t_max: int = 20, phi0: float = 0.0):

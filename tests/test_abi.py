@@ -83,6 +83,7 @@ def test_null_arguments_rejected():
     assert lib.lge_close(None) == lge.LGE_EINVAL
     assert lib.lge_graph_destroy(None) == lge.LGE_EINVAL
     assert lib.lge_autotune_reset(None) == lge.LGE_EINVAL
+    assert lib.lge_set_build_scratch(None, 0) == lge.LGE_EINVAL
     assert lib.lge_count_batch(None, None, None, None) == lge.LGE_EINVAL
     assert lib.lge_validate_csr_host(-1, None, None) == lge.LGE_EINVAL
     assert lib.lge_graph_n(None) == -1

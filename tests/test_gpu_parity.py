@@ -292,6 +292,38 @@ def test_table_budgets_change_state_not_results(ctx):
             lge.lge_graph_destroy(h)
 
 
+def test_row_tiles_in_passes(ctx):
+    # co-degree rows over several 32,768-column tiles, built with the
+    # segment-end scratch at its minimum (one tile per pass) and in one pass:
+    # the same state, and the same integers as a graph with hub tables only
+    g = inputs.chung_lu(200000, 16.0, 2.1, 5e4, 77)
+    deg = np.diff(np.asarray(g.row_ptr, dtype=np.int64))
+    made = []
+    try:
+        made.append(lge.lge_graph_create_host(ctx, g.row_ptr, g.col))
+        lge.lge_set_build_scratch(ctx, 1)
+        made.append(lge.lge_graph_create_host(ctx, g.row_ptr, g.col))
+        lge.lge_set_build_scratch(ctx, 0)
+        made.append(lge.lge_graph_create_host(ctx, g.row_ptr, g.col, lge.LGE_FLAG_NO_TABLES))
+        i0, i1 = lge.lge_graph_query(made[0]), lge.lge_graph_query(made[1])
+        ncol = int((deg > i0["rows_floor"]).sum()) - i0["ranked"]
+        _say("row tiles: %d rows x %d columns (%d tiles), %d ranked" % (i0["rows"], ncol, -(-ncol // 32768),
+                                                                        i0["ranked"]))
+        assert i0["rows"] > 0 and ncol > 2 * 32768
+        for k in ("rows", "ranked", "rows_floor", "rows_width", "state_bytes"):
+            assert i1[k] == i0[k], k
+        for p, seed in ((1.0, 5), (0.1, 6)):
+            base = lge.lge_estimate(ctx, made[0], p, seed)
+            for h in made[1:]:
+                got = lge.lge_estimate(ctx, h, p, seed)
+                for k in ("sampled", "csum", "zsum", "qsum", "exact", "estimate", "variance"):
+                    assert got[k] == base[k], (p, k)
+    finally:
+        lge.lge_set_build_scratch(ctx, 0)
+        for h in made:
+            lge.lge_graph_destroy(h)
+
+
 def test_count_batch_large_union(ctx):
     # 16,384 members of up to 5,000 vertices: the union's own n would fail
     # the whole-graph bound on exact sums, but every member's sums use the
