@@ -72,9 +72,19 @@ int dev_alloc(T **p, int64_t count) {
   hipError_t e = hipMalloc((void **)p, (size_t)count * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
+    // a failed allocation stays the thread's last error, which the launch
+    // wrappers read back after their launches: clear it, so a caller that
+    // retries smaller (or gives up) is not handed it again
+    (void)hipGetLastError();
     return hip_err(e);
   }
   return LGE_OK;
+}
+
+// a direct hipMalloc / hipHostMalloc failed: the same clearing, and ENOMEM
+static int alloc_failed() {
+  (void)hipGetLastError();
+  return LGE_ENOMEM;
 }
 
 template <typename T>
@@ -295,7 +305,7 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     if ((rc = dev_alloc(&w.tbase, cap)) != LGE_OK) return rc;
     if (hipMalloc(&w.gacc, (size_t)cap * gedge_bytes()) != hipSuccess) {
       w.gacc = nullptr;
-      return LGE_ENOMEM;
+      return alloc_failed();
     }
     w.scan_tmp_len = scan_tmp_size(cap);
     if ((rc = dev_alloc(&w.scan_tmp, w.scan_tmp_len)) != LGE_OK) return rc;
@@ -320,15 +330,15 @@ static int ws_reserve(lge_ctx *ctx, int64_t edges, int32_t slots, int32_t ranges
     if ((rc = dev_alloc(&w.ctl, nctl)) != LGE_OK) return rc;
     if (hipMalloc(&w.desc, ndesc) != hipSuccess) {
       w.desc = nullptr;
-      return LGE_ENOMEM;
+      return alloc_failed();
     }
     if (hipHostMalloc((void **)&w.h_ctl, (size_t)nctl * sizeof(unsigned long long), 0) != hipSuccess) {
       w.h_ctl = nullptr;
-      return LGE_ENOMEM;
+      return alloc_failed();
     }
     if (hipHostMalloc(&w.h_desc, ndesc, 0) != hipSuccess) {
       w.h_desc = nullptr;
-      return LGE_ENOMEM;
+      return alloc_failed();
     }
     w.counters = w.ctl;
     w.acc = w.ctl + kNumCtrs;
@@ -581,9 +591,15 @@ static int graph_preprocess(lge_ctx *ctx, lge_graph *g, uint32_t flags, const in
     }
     const int64_t ntiles = (g->ncol + rows_tile_entries(g->rows_w) - 1) / rows_tile_entries(g->rows_w);
     const int64_t cap = ctx->build_scratch > 0 ? ctx->build_scratch : kRowsOffBytes;
-    const int64_t toff_len = std::max<int64_t>(2 * n, std::min<int64_t>(n * (ntiles + 1), cap / 4));
-    if ((rc = dev_alloc(&clist, std::max<int64_t>(last[0] + last[1], 1))) != LGE_OK ||
-        (rc = dev_alloc(&toff, toff_len)) != LGE_OK) {
+    int64_t toff_len = std::max<int64_t>(2 * n, std::min<int64_t>(n * (ntiles + 1), cap / 4));
+    if ((rc = dev_alloc(&clist, std::max<int64_t>(last[0] + last[1], 1))) == LGE_OK) {
+      rc = dev_alloc(&toff, toff_len);
+      if (rc == LGE_ENOMEM && toff_len > 2 * n) {  // one tile per pass
+        toff_len = 2 * n;
+        rc = dev_alloc(&toff, toff_len);
+      }
+    }
+    if (rc != LGE_OK) {
       release();
       return rc;
     }
