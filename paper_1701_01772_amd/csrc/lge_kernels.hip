@@ -793,13 +793,16 @@ __global__ __launch_bounds__(kRowNT) void k_codeg_rows(const int32_t *__restrict
 // column are first listed as columns, in increasing order (columns go by
 // vertex id, and the adjacency lists are sorted); the tile's part of x's list
 // is then one segment, whose ends a separate pass finds once per (x, tile)
-// (k_rows_offsets).  One 32-bit LDS counter per column (packing them 4 or 2
-// to a word measured slower); the tile is then written out once as entries
-// of `width` bytes.  A wave reads the segment ends of 64 x at once; a lane
+// (k_rows_offsets).  Two 16-bit LDS counters per word, so a tile spans
+// 65,536 columns (an entry never exceeds the unranked vertex's degree, at
+// most 65,535; one counter per word took 20 % longer on Chung-Lu 1M, four
+// byte counters per word 30 % longer); the tile is then written out once as
+// entries of `width` bytes.  A wave reads the segment ends of 64 x at once; a lane
 // walks its own x's segment when it is short, and the wave walks the long
 // ones one after another, lanes striding each.
 constexpr int kTileNT = 1024;
-constexpr int kTileWords = 32768;  // 128 KB of LDS counters
+constexpr int kTileWords = 32768;        // 128 KB of LDS counters
+constexpr int kTileCols = 2 * kTileWords;  // columns per tile: 16-bit halves
 
 __device__ __forceinline__ int64_t lower_pos(const int32_t *__restrict__ a, int64_t lo, int64_t hi, int32_t v) {
   while (lo < hi) {
@@ -853,7 +856,7 @@ __global__ __launch_bounds__(256) void k_col_fill(const int32_t *__restrict__ rp
 }
 
 // toff[x * (nb + 1) + i] = first position of x's column list at or above
-// column (t0 + i) * kTileWords, for every vertex x and i in [0, nb]
+// column (t0 + i) * kTileCols, for every vertex x and i in [0, nb]
 __global__ __launch_bounds__(256) void k_rows_offsets(const int64_t *__restrict__ off, const int64_t *__restrict__ cnt,
                                                       const int32_t *__restrict__ clist, int64_t n, int64_t t0,
                                                       int64_t nb, int32_t *__restrict__ toff) {
@@ -861,7 +864,7 @@ __global__ __launch_bounds__(256) void k_rows_offsets(const int64_t *__restrict_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t x = i / per, k = i - x * per;
     const int64_t lo = off[x];
-    toff[i] = (int32_t)lower_pos(clist, lo, lo + cnt[x], (int32_t)((t0 + k) * kTileWords));
+    toff[i] = (int32_t)lower_pos(clist, lo, lo + cnt[x], (int32_t)((t0 + k) * kTileCols));
   }
 }
 
@@ -874,7 +877,9 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
                                                        int64_t ncol, int64_t stride, int width,
                                                        uint8_t *__restrict__ rows) {
   __shared__ uint32_t c[kTileWords];
-  const int64_t T = kTileWords;  // columns per tile
+  const int64_t T = kTileCols;
+  // column q of the tile: the 16-bit half q & 1 of word q >> 1
+  auto bump = [&](int32_t q) { atomicAdd(&c[q >> 1], 1u << ((q & 1) << 4)); };
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int kWaves = kTileNT / kWave;
   const int64_t per = nb + 1;
@@ -882,7 +887,8 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
     const int64_t h = wi / nb, tt = wi % nb, t = t0 + tt;
     const int32_t y = hubs[h];
     const int64_t c0 = t * T, c1 = c0 + T < ncol ? c0 + T : ncol;
-    const int64_t words = c1 - c0;
+    const int64_t cols = c1 - c0;
+    const int64_t words = (cols + 1) >> 1;
     const int32_t base = (int32_t)c0;
     for (int64_t i = threadIdx.x; i < words; i += kTileNT) c[i] = 0u;
     __syncthreads();
@@ -902,7 +908,7 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
         for (int u = 0; u < 4; ++u) cs[u] = k + u < hi ? clist[k + u] : -1;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (cs[u] >= 0) atomicAdd(&c[cs[u] - base], 1u);
+          if (cs[u] >= 0) bump(cs[u] - base);
       }
       uint64_t lm = __ballot(!own);
       while (lm) {  // uniform per wave
@@ -915,16 +921,17 @@ __global__ __launch_bounds__(kTileNT) void k_rows_fill(const int32_t *__restrict
           for (int u = 0; u < kCoopUnroll; ++u) cs[u] = k0 + u * kWave < hq ? clist[k0 + u * kWave] : -1;
 #pragma unroll
           for (int u = 0; u < kCoopUnroll; ++u)
-            if (cs[u] >= 0) atomicAdd(&c[cs[u] - base], 1u);
+            if (cs[u] >= 0) bump(cs[u] - base);
         }
       }
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < words; i += kTileNT) {
+    for (int64_t i = threadIdx.x; i < cols; i += kTileNT) {
+      const uint32_t v = (c[i >> 1] >> ((i & 1) << 4)) & 0xFFFFu;
       if (width == 1)
-        rows[h * stride + c0 + i] = (uint8_t)c[i];
+        rows[h * stride + c0 + i] = (uint8_t)v;
       else
-        reinterpret_cast<uint16_t *>(rows)[h * stride + c0 + i] = (uint16_t)c[i];
+        reinterpret_cast<uint16_t *>(rows)[h * stride + c0 + i] = (uint16_t)v;
     }
     __syncthreads();
   }
@@ -2842,7 +2849,7 @@ hipError_t launch_arc_rank(const int32_t *col, const int4 *vinfo, int64_t nnz, u
   return hipGetLastError();
 }
 
-int64_t rows_tile_entries(int) { return kTileWords; }
+int64_t rows_tile_entries(int) { return kTileCols; }
 
 hipError_t launch_col_count(const int32_t *row_ptr, const uint32_t *arh, int64_t n, int64_t *cnt, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -2860,7 +2867,7 @@ hipError_t launch_col_fill(const int32_t *row_ptr, const uint32_t *arh, int64_t 
 hipError_t launch_rows_fill(const int32_t *row_ptr, const int32_t *col, const int64_t *coff, const int64_t *ccnt,
                             const int32_t *clist, const int32_t *hubs, int64_t nh, int64_t ncol, int64_t stride,
                             int width, uint8_t *rows, int64_t n, int32_t *toff, int64_t toff_len, hipStream_t s) {
-  const int64_t ntiles = (ncol + kTileWords - 1) / kTileWords;
+  const int64_t ntiles = (ncol + kTileCols - 1) / kTileCols;
   if (nh <= 0 || ntiles <= 0) return hipSuccess;
   if (n <= 0 || toff_len < 2 * n) return hipErrorInvalidValue;
   // tiles per pass: as many as the segment-end buffer holds

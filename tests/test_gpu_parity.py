@@ -293,10 +293,10 @@ def test_table_budgets_change_state_not_results(ctx):
 
 
 def test_row_tiles_in_passes(ctx):
-    # co-degree rows over several 32,768-column tiles, built with the
+    # co-degree rows over several 65,536-column tiles, built with the
     # segment-end scratch at its minimum (one tile per pass) and in one pass:
     # the same state, and the same integers as a graph with hub tables only
-    g = inputs.chung_lu(200000, 16.0, 2.1, 5e4, 77)
+    g = inputs.chung_lu(300000, 16.0, 2.1, 5e4, 77)
     deg = np.diff(np.asarray(g.row_ptr, dtype=np.int64))
     made = []
     try:
@@ -307,9 +307,9 @@ def test_row_tiles_in_passes(ctx):
         made.append(lge.lge_graph_create_host(ctx, g.row_ptr, g.col, lge.LGE_FLAG_NO_TABLES))
         i0, i1 = lge.lge_graph_query(made[0]), lge.lge_graph_query(made[1])
         ncol = int((deg > i0["rows_floor"]).sum()) - i0["ranked"]
-        _say("row tiles: %d rows x %d columns (%d tiles), %d ranked" % (i0["rows"], ncol, -(-ncol // 32768),
+        _say("row tiles: %d rows x %d columns (%d tiles), %d ranked" % (i0["rows"], ncol, -(-ncol // 65536),
                                                                         i0["ranked"]))
-        assert i0["rows"] > 0 and ncol > 2 * 32768
+        assert i0["rows"] > 0 and ncol > 2 * 65536
         for k in ("rows", "ranked", "rows_floor", "rows_width", "state_bytes"):
             assert i1[k] == i0[k], k
         for p, seed in ((1.0, 5), (0.1, 6)):
