@@ -824,6 +824,7 @@ static void graph_free(lge_graph *g) {
   dev_free(g->arh);
   dev_free(g->t_arc);
   dev_free(g->tri);
+  dev_free(g->t_slot);
   dev_free(g->mred);
   dev_free(g->core);
   dev_free(g->wlevel[0]);
@@ -960,6 +961,7 @@ extern "C" int lge_graph_query(const lge_graph *g, lge_graph_info *out) {
   if (g->nrows > 0) b += g->nrows * g->rows_stride * g->rows_w;
   if (g->t_arc) b += 8 * m;
   if (g->tri) b += 8 * n;
+  if (g->t_slot) b += 4 * g->htab_len;
   if (g->core) b += 4 * n;
   for (int k = 0; k < 2; ++k)
     if (g->wlevel[k]) b += m;
@@ -1621,12 +1623,16 @@ static int ensure_micro(lge_ctx *ctx, lge_graph *g) {
   if (g->mred) return LGE_OK;
   dev_free(g->t_arc);  // left over from a failed earlier attempt
   dev_free(g->tri);
+  dev_free(g->t_slot);
   int rc;
   if ((rc = dev_alloc(&g->t_arc, std::max<int64_t>(2 * g->m, 1))) != LGE_OK) return rc;
   if ((rc = dev_alloc(&g->tri, std::max<int64_t>(g->n, 1))) != LGE_OK) return rc;
+  if ((rc = dev_alloc(&g->t_slot, std::max<int64_t>(g->htab_len, 1))) != LGE_OK) return rc;
   hipStream_t s = ctx->stream;
   LGE_HIP(launch_micro_arc_tri(g->row_ptr, g->col, g->edges, g->hoff, g->htab, g->m, g->t_arc, s));
   LGE_HIP(launch_micro_vertex_tri(g->row_ptr, g->t_arc, g->n, g->tri, s));
+  if (g->htab_len > 0)
+    LGE_HIP(launch_micro_slot_tri(g->row_ptr, g->col, g->n, g->hoff, g->htab, g->t_arc, g->t_slot, s));
   LGE_HIP(hipStreamSynchronize(s));
   if ((rc = dev_alloc(&g->mred, 32)) != LGE_OK) return rc;  // last: marks the cache complete
   return LGE_OK;
@@ -1653,8 +1659,8 @@ extern "C" int lge_micro(lge_ctx *ctx, const lge_graph *gc, int64_t e0, int64_t 
   LGE_HIP(launch_zero_u64(g->mred, 32, s));
   int *err = reinterpret_cast<int *>(g->mred + 24);
   LGE_HIP(hipEventRecord(ctx->ev[6], s));
-  LGE_HIP(launch_micro_rows(g->row_ptr, g->col, g->edges, g->vol2, g->t_arc, g->tri, g->n, g->m, e0, e1, rows,
-                            g->mred, err, ctx->num_cu * 8, s));
+  LGE_HIP(launch_micro_rows(g->row_ptr, g->col, g->edges, g->vol2, g->hoff, g->htab, g->t_slot, g->t_arc, g->tri,
+                            g->n, g->m, e0, e1, rows, g->mred, err, ctx->num_cu * 8, s));
   LGE_HIP(hipEventRecord(ctx->ev[7], s));
   unsigned long long h[32];
   LGE_HIP(hipMemcpyAsync(h, g->mred, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -2283,6 +2283,29 @@ __global__ __launch_bounds__(256) void k_micro_vertex_tri(const int32_t *__restr
   }
 }
 
+// t of every arc (u, x) of a vertex u with a hub table, stored at x's slot
+// of that table: the micro rows read t(b, x) with the membership test of x
+// in Gamma(b) (one probe instead of a binary search for x's position)
+__global__ __launch_bounds__(256) void k_micro_slot_tri(const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col, int64_t n,
+                                                        const int64_t *__restrict__ hoff,
+                                                        const uint32_t *__restrict__ htab,
+                                                        const int32_t *__restrict__ t_arc,
+                                                        int32_t *__restrict__ t_slot) {
+  for (int64_t u = blockIdx.x; u < n; u += gridDim.x) {
+    const int32_t beg = row_ptr[u], end = row_ptr[u + 1];
+    const int d = end - beg;
+    if (!has_table(d)) continue;  // uniform per block
+    const int lg = table_log(d);
+    const uint32_t *tab = htab + hoff[u];
+    int32_t *ts = t_slot + hoff[u];
+    for (int32_t j = beg + threadIdx.x; j < end; j += blockDim.x) {
+      const int sl = table_find(tab, lg, (uint32_t)col[j]);
+      if (sl >= 0) ts[sl] = t_arc[j];
+    }
+  }
+}
+
 // sentinel -1 in the columns the counting kernels fill
 __global__ __launch_bounds__(256) void k_micro_mark(long long *__restrict__ out, int64_t rows) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
@@ -2306,6 +2329,9 @@ __device__ __forceinline__ long long micro_pick(int c, const long long *y) {
 __global__ __launch_bounds__(256) void k_micro_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                    const uint64_t *__restrict__ edges,
                                                    const int64_t *__restrict__ vol2,
+                                                   const int64_t *__restrict__ hoff,
+                                                   const uint32_t *__restrict__ htab,
+                                                   const int32_t *__restrict__ t_slot,
                                                    const int32_t *__restrict__ t_arc,
                                                    const int64_t *__restrict__ tri, int64_t n, int64_t m, int64_t e0,
                                                    int64_t e1, long long *__restrict__ out,
@@ -2325,16 +2351,29 @@ __global__ __launch_bounds__(256) void k_micro_rows(const int32_t *__restrict__ 
     const int32_t a = us ? u : v, b = us ? v : u;
     const int32_t abeg = us ? ub : vb, da = us ? du : dv;
     const int32_t bbeg = us ? vb : ub, db = us ? dv : du;
+    // x in Gamma(a) n Gamma(b) with t(a, x) and t(b, x): b's hub table and
+    // the t stored at its slots, else a binary search of b's list
+    const bool hb = has_table(db);
+    const uint32_t *btab = hb ? htab + hoff[b] : nullptr;
+    const int32_t *bts = hb ? t_slot + hoff[b] : nullptr;
+    const int blg = table_log(db);
     long long st = 0, sdt = 0, ta = 0, tb = 0;
     for (int i = gl; i < da; i += kMicroGroup) {
       const int32_t x = col[abeg + i];
       if (x == b) continue;
-      const int k = row_lower(col + bbeg, db, x);
-      if (k < db && col[bbeg + k] == x) {
+      int32_t tbx = -1;
+      if (hb) {
+        const int sl = table_find(btab, blg, (uint32_t)x);
+        if (sl >= 0) tbx = bts[sl];
+      } else {
+        const int k = row_lower(col + bbeg, db, x);
+        if (k < db && col[bbeg + k] == x) tbx = t_arc[bbeg + k];
+      }
+      if (tbx >= 0) {
         st += 1;
         sdt += rp[x + 1] - rp[x];
         ta += t_arc[abeg + i];
-        tb += t_arc[bbeg + k];
+        tb += tbx;
       }
     }
     st = group_sum(st);
@@ -2955,13 +2994,22 @@ hipError_t launch_micro_mark(long long *out, int64_t rows, hipStream_t s) {
 }
 
 hipError_t launch_micro_rows(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges, const int64_t *vol2,
-                             const int32_t *t_arc, const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1,
-                             long long *out, unsigned long long *colmax, int *err, int grid, hipStream_t s) {
+                             const int64_t *hoff, const uint32_t *htab, const int32_t *t_slot, const int32_t *t_arc,
+                             const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1, long long *out,
+                             unsigned long long *colmax, int *err, int grid, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
   const int need = grid_for(e1 - e0, 256 / kMicroGroup, 1 << 20);
   const int g = need < grid ? need : grid;
-  hipLaunchKernelGGL(k_micro_rows, dim3(g), dim3(256), 0, s, row_ptr, col, edges, vol2, t_arc, tri, n, m, e0, e1,
-                     out, colmax, err);
+  hipLaunchKernelGGL(k_micro_rows, dim3(g), dim3(256), 0, s, row_ptr, col, edges, vol2, hoff, htab, t_slot, t_arc,
+                     tri, n, m, e0, e1, out, colmax, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_micro_slot_tri(const int32_t *row_ptr, const int32_t *col, int64_t n, const int64_t *hoff,
+                                 const uint32_t *htab, const int32_t *t_arc, int32_t *t_slot, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_micro_slot_tri, dim3(grid_for(n, 1, 65536)), dim3(256), 0, s, row_ptr, col, n, hoff, htab,
+                     t_arc, t_slot);
   return hipGetLastError();
 }
 

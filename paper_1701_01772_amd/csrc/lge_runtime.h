@@ -54,9 +54,11 @@ struct lge_graph {
   std::vector<double> work_pref;
   double build_ms = 0.0;     // preprocessing wall time (after validation and the edge list)
   // micro statistics, built on first use: t of every arc, triangles per
-  // vertex, and a small reduction buffer (column maxima, error flag)
+  // vertex, the arcs' t at the hub-table slots, and a small reduction buffer
+  // (column maxima, error flag)
   int32_t *t_arc = nullptr;
   int64_t *tri = nullptr;
+  int32_t *t_slot = nullptr;  // htab_len: t of every arc at its head's slot of the tail's hub table
   unsigned long long *mred = nullptr;
   // weighted sampling, built on first use: k-core numbers, and per weight
   // mode (1 degree, 2 k-core) the class of every edge and the class sizes
