@@ -1659,8 +1659,8 @@ extern "C" int lge_micro(lge_ctx *ctx, const lge_graph *gc, int64_t e0, int64_t 
   LGE_HIP(launch_zero_u64(g->mred, 32, s));
   int *err = reinterpret_cast<int *>(g->mred + 24);
   LGE_HIP(hipEventRecord(ctx->ev[6], s));
-  LGE_HIP(launch_micro_rows(g->row_ptr, g->col, g->edges, g->vol2, g->hoff, g->htab, g->t_slot, g->t_arc, g->tri,
-                            g->n, g->m, e0, e1, rows, g->mred, err, ctx->num_cu * 8, s));
+  LGE_HIP(launch_micro_rows(g->row_ptr, g->col, g->edges, g->vol2, g->hoff, g->htab, g->t_slot, g->vinfo, g->t_arc,
+                            g->tri, g->n, g->m, e0, e1, rows, g->mred, err, ctx->num_cu * 8, s));
   LGE_HIP(hipEventRecord(ctx->ev[7], s));
   unsigned long long h[32];
   LGE_HIP(hipMemcpyAsync(h, g->mred, sizeof(h), hipMemcpyDeviceToHost, s));

@@ -293,8 +293,8 @@ hipError_t launch_micro_mark(long long *out, int64_t rows, hipStream_t s);
 hipError_t launch_micro_slot_tri(const int32_t *row_ptr, const int32_t *col, int64_t n, const int64_t *hoff,
                                  const uint32_t *htab, const int32_t *t_arc, int32_t *t_slot, hipStream_t s);
 hipError_t launch_micro_rows(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges, const int64_t *vol2,
-                             const int64_t *hoff, const uint32_t *htab, const int32_t *t_slot, const int32_t *t_arc,
-                             const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1, long long *out,
-                             unsigned long long *colmax, int *err, int grid, hipStream_t s);
+                             const int64_t *hoff, const uint32_t *htab, const int32_t *t_slot, const int4 *vinfo,
+                             const int32_t *t_arc, const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1,
+                             long long *out, unsigned long long *colmax, int *err, int grid, hipStream_t s);
 
 }  // namespace lge

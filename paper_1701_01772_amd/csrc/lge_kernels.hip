@@ -2218,6 +2218,7 @@ __device__ __forceinline__ int row_lower(const int32_t *__restrict__ a, int len,
 }
 
 constexpr int kMicroGroup = 16;  // lanes per edge
+constexpr int kMicroUnroll = 4;  // positions a lane of the micro rows reads at a time
 
 template <typename T>
 __device__ __forceinline__ T group_sum(T v) {
@@ -2332,6 +2333,7 @@ __global__ __launch_bounds__(256) void k_micro_rows(const int32_t *__restrict__ 
                                                    const int64_t *__restrict__ hoff,
                                                    const uint32_t *__restrict__ htab,
                                                    const int32_t *__restrict__ t_slot,
+                                                   const int4 *__restrict__ vinfo,
                                                    const int32_t *__restrict__ t_arc,
                                                    const int64_t *__restrict__ tri, int64_t n, int64_t m, int64_t e0,
                                                    int64_t e1, long long *__restrict__ out,
@@ -2351,29 +2353,59 @@ __global__ __launch_bounds__(256) void k_micro_rows(const int32_t *__restrict__ 
     const int32_t a = us ? u : v, b = us ? v : u;
     const int32_t abeg = us ? ub : vb, da = us ? du : dv;
     const int32_t bbeg = us ? vb : ub, db = us ? dv : du;
-    // x in Gamma(a) n Gamma(b) with t(a, x) and t(b, x): b's hub table and
-    // the t stored at its slots, else a binary search of b's list
+    // x in Gamma(a) n Gamma(b) with t(a, x), t(b, x) and d_x: b's hub table
+    // and the t stored at its slots, else a binary search of b's list.  A
+    // lane takes kMicroUnroll positions at a time, each step's reads of all
+    // of them in flight together (positions, first probes, then t and the
+    // degrees)
     const bool hb = has_table(db);
     const uint32_t *btab = hb ? htab + hoff[b] : nullptr;
     const int32_t *bts = hb ? t_slot + hoff[b] : nullptr;
     const int blg = table_log(db);
+    const uint32_t bmask = (1u << blg) - 1u;
     long long st = 0, sdt = 0, ta = 0, tb = 0;
-    for (int i = gl; i < da; i += kMicroGroup) {
-      const int32_t x = col[abeg + i];
-      if (x == b) continue;
-      int32_t tbx = -1;
-      if (hb) {
-        const int sl = table_find(btab, blg, (uint32_t)x);
-        if (sl >= 0) tbx = bts[sl];
-      } else {
-        const int k = row_lower(col + bbeg, db, x);
-        if (k < db && col[bbeg + k] == x) tbx = t_arc[bbeg + k];
+    for (int i0 = gl; i0 < da; i0 += kMicroUnroll * kMicroGroup) {
+      int32_t xs[kMicroUnroll], tas[kMicroUnroll], tbx[kMicroUnroll];
+#pragma unroll
+      for (int u = 0; u < kMicroUnroll; ++u) {
+        const int i = i0 + u * kMicroGroup;
+        const int32_t x = i < da ? col[abeg + i] : -1;
+        xs[u] = x == b ? -1 : x;
+        tas[u] = i < da ? t_arc[abeg + i] : 0;
       }
-      if (tbx >= 0) {
-        st += 1;
-        sdt += rp[x + 1] - rp[x];
-        ta += t_arc[abeg + i];
-        tb += tbx;
+      if (hb) {
+        uint32_t h[kMicroUnroll], k[kMicroUnroll];
+#pragma unroll
+        for (int u = 0; u < kMicroUnroll; ++u) {
+          h[u] = xs[u] >= 0 ? hash_slot((uint32_t)xs[u], blg) : 0u;
+          k[u] = xs[u] >= 0 ? btab[h[u]] : kEmpty;
+        }
+#pragma unroll
+        for (int u = 0; u < kMicroUnroll; ++u) {
+          while (k[u] != kEmpty && (k[u] & kIdMask) != (uint32_t)xs[u]) {  // linear probing
+            h[u] = (h[u] + 1u) & bmask;
+            k[u] = btab[h[u]];
+          }
+          tbx[u] = k[u] != kEmpty ? bts[h[u]] : -1;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kMicroUnroll; ++u) {
+          tbx[u] = -1;
+          if (xs[u] >= 0) {
+            const int kk = row_lower(col + bbeg, db, xs[u]);
+            if (kk < db && col[bbeg + kk] == xs[u]) tbx[u] = t_arc[bbeg + kk];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kMicroUnroll; ++u) {
+        if (tbx[u] >= 0) {
+          st += 1;
+          sdt += vinfo[xs[u]].y;
+          ta += tas[u];
+          tb += tbx[u];
+        }
       }
     }
     st = group_sum(st);
@@ -2994,14 +3026,14 @@ hipError_t launch_micro_mark(long long *out, int64_t rows, hipStream_t s) {
 }
 
 hipError_t launch_micro_rows(const int32_t *row_ptr, const int32_t *col, const uint64_t *edges, const int64_t *vol2,
-                             const int64_t *hoff, const uint32_t *htab, const int32_t *t_slot, const int32_t *t_arc,
-                             const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1, long long *out,
-                             unsigned long long *colmax, int *err, int grid, hipStream_t s) {
+                             const int64_t *hoff, const uint32_t *htab, const int32_t *t_slot, const int4 *vinfo,
+                             const int32_t *t_arc, const int64_t *tri, int64_t n, int64_t m, int64_t e0, int64_t e1,
+                             long long *out, unsigned long long *colmax, int *err, int grid, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
   const int need = grid_for(e1 - e0, 256 / kMicroGroup, 1 << 20);
   const int g = need < grid ? need : grid;
-  hipLaunchKernelGGL(k_micro_rows, dim3(g), dim3(256), 0, s, row_ptr, col, edges, vol2, hoff, htab, t_slot, t_arc,
-                     tri, n, m, e0, e1, out, colmax, err);
+  hipLaunchKernelGGL(k_micro_rows, dim3(g), dim3(256), 0, s, row_ptr, col, edges, vol2, hoff, htab, t_slot, vinfo,
+                     t_arc, tri, n, m, e0, e1, out, colmax, err);
   return hipGetLastError();
 }
 
