@@ -282,10 +282,26 @@ def build_report(lge, ctx, g, h, create_s, p, seed, step_ms, min_steps=1):
 # the headline and large power-law legs
 # ---------------------------------------------------------------------------
 
+def tune_report(lge, ctx, h, p, seed, steps):
+    """lge_autotune's options for this graph class and p (the tuning time
+    reported, not timed with the steps), K steps with them against K steps
+    with the library defaults."""
+    t0 = time.perf_counter()
+    opts = lge.lge_autotune(ctx, h, p)
+    tune_s = time.perf_counter() - t0
+    tuned = time_steps(lge, ctx, h, p, seed, steps, opts)
+    base = time_steps(lge, ctx, h, p, seed, steps)
+    return {"seconds": tune_s, "options": lge.opts_dict(opts), "tuned_ms_per_step": tuned["ms_per_step"],
+            "default_ms_per_step": base["ms_per_step"], "tuned_value": tuned["value"],
+            "tuned_vs_default": base["ms_per_step"] / tuned["ms_per_step"]}
+
+
 def estimate_leg(lge, ctx, g, wname, workload, p, seed, steps, warmup, h=None, create_s=None, cpu_s=0.0,
-                 want_build=True):
+                 want_build=True, want_tune=False):
     """One workload at one p: cold estimate (if the graph is new), warm-up,
-    K timed steps, roofline, build report, CPU oracle baseline."""
+    K timed steps with the default options (the leg's value), roofline,
+    autotuned options against the defaults, build report, CPU oracle
+    baseline."""
     out = {"workload": wname, "n": g.n, "m": g.m, "p": p}
     own = h is None
     if own:
@@ -302,6 +318,11 @@ def estimate_leg(lge, ctx, g, wname, workload, p, seed, steps, warmup, h=None, c
                 "ms_per_step": st["ms_per_step"], "seed0": seed + 100, "device_ms": device_ms,
                 "class_edges": [sum(t["class_edges"][c] for t in st["tim"]) // k for c in range(3)],
                 "host_waits": max(t["host_waits"] for t in st["tim"]), "roofline": roof})
+    if want_tune:
+        out["autotune"] = tune_report(lge, ctx, h, p, seed + 500, steps)
+        log("%s p=%g autotune: %.2f vs %.2f ms per step (%.1f s of tuning)" % (
+            wname, p, out["autotune"]["tuned_ms_per_step"], out["autotune"]["default_ms_per_step"],
+            out["autotune"]["seconds"]))
     if want_build:
         out["build"] = build_report(lge, ctx, g, h, create_s, p, seed + 200, st["ms_per_step"])
         log("%s build: %.2f s, %.1f GB state, break-even %s estimates" % (
@@ -326,17 +347,7 @@ def rmat_leg(lge, ctx, args, g):
         for p, steps in ((0.1, args.rmat_steps), (0.01, 3 * args.rmat_steps)):
             leg = estimate_leg(lge, ctx, g, wname, "rmat", p, args.seed, steps, 1, h=h, create_s=create_s,
                                cpu_s=args.rmat_cpu_seconds if not args.no_cpu_baseline else 0.0,
-                               want_build=(p == 0.01))
-            t0 = time.perf_counter()
-            opts = lge.lge_autotune(ctx, h, p)
-            tune_s = time.perf_counter() - t0
-            tuned = time_steps(lge, ctx, h, p, args.seed + 500, steps, opts)
-            base = time_steps(lge, ctx, h, p, args.seed + 500, steps)
-            leg["autotune"] = {"seconds": tune_s, "options": lge.opts_dict(opts),
-                               "tuned_ms_per_step": tuned["ms_per_step"], "default_ms_per_step": base["ms_per_step"],
-                               "tuned_vs_default": base["ms_per_step"] / tuned["ms_per_step"]}
-            log("%s p=%g autotune: %.1f vs %.1f ms per step (%.1f s of tuning)" % (
-                wname, p, tuned["ms_per_step"], base["ms_per_step"], tune_s))
+                               want_build=(p == 0.01), want_tune=True)
             out["p%g" % p] = leg
     finally:
         lge.lge_graph_destroy(h)
@@ -740,7 +751,7 @@ def main():
     log("graph n=%d m=%d" % (g.n, g.m))
     ctx = lge.lge_open(0)
     head = estimate_leg(lge, ctx, g, wname, args.workload, p, args.seed, args.steps, args.warmup,
-                        cpu_s=0.0, want_build=not args.quick)
+                        cpu_s=0.0, want_build=not args.quick, want_tune=not args.quick)
     # the other legs' inputs are drawn on host threads (not while steps or
     # the CPU baseline are timed: they would compete for host cores)
     bg_rmat = Background(inputs.rmat_22) if full else None
@@ -767,6 +778,8 @@ def main():
         "cold": head["cold"],
         "roofline": head["roofline"],
     }
+    if "autotune" in head:
+        result["autotune"] = head["autotune"]
     if "build" in head:
         result["build"] = head["build"]
     if args.copy_calibration:
