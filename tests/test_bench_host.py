@@ -70,3 +70,35 @@ def test_roofline_traffic_only_from_a_profile_of_the_same_source():
         # is committed at p / 3)
         _, other = bench.roofline_of(tim, wl, pmc["p"] / 3)
         assert other["traffic"] is None
+
+
+def test_tune_report_times_tuned_and_default_options_alike(monkeypatch):
+    # a stand-in for the library: lge_autotune returns fixed options, and an
+    # estimate "takes" 2 ms with them and 3 ms with the defaults (opts None);
+    # the report must time both with the same steps and seeds and compare
+    # the per-step times, the tuning time kept apart
+    import types
+    import bench
+    calls = []
+
+    class R:
+        sampled_edges = 100
+
+    def est(ctx, h, p, seed, opts=None, raw=False, out=None):
+        calls.append((seed, opts))
+        bench.time.sleep(0.002 if opts is not None else 0.003)
+        return R()
+
+    fake = types.SimpleNamespace(
+        Result=R, lge_estimate=est, lge_last_timing=lambda ctx: {},
+        lge_autotune=lambda ctx, h, p: {"probe_ratio": 8},
+        opts_dict=lambda o: dict(o))
+    import torch  # time_steps brackets the steps with device synchronisations
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    rep = bench.tune_report(fake, None, None, 0.1, 500, 5)
+    assert rep["options"] == {"probe_ratio": 8}
+    assert [s for s, o in calls if o is not None] == [500 + i for i in range(5)]
+    assert [s for s, o in calls if o is None] == [500 + i for i in range(5)]
+    assert rep["tuned_ms_per_step"] < rep["default_ms_per_step"]
+    assert rep["tuned_vs_default"] == rep["default_ms_per_step"] / rep["tuned_ms_per_step"]
+    assert rep["seconds"] >= 0.0
